@@ -1,0 +1,467 @@
+// HashWave CPU oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// Only the test suite, the package smoke check and the benchmark's CPU-baseline
+// leg may load this library.  The GPU library never links, loads or calls it, and
+// this file includes nothing from the GPU library: every rule below is written
+// out again here from the paper and from the documented readings of it.
+//
+// Three parts:
+//
+//  1. The semantic map.  The paper's API (Section 5.1, "Hash table API") defines
+//     Upsert(key, value, callback), Query(key, &value) and Erase(key) on a map
+//     from keys to values; Section 4.1 requires concurrent operations to be
+//     serialisable.  The oracle is that definition written out: a standard
+//     library hash map, with a batch applied one operation at a time in input
+//     order.  Insert is Upsert with the "insert if unique" callback (Section
+//     5.1).  Sentinel keys are rejected (reading: the paper never names its
+//     empty/tombstone/reservation patterns; the GPU tables reserve the top three
+//     64-bit values, or the top two 32-bit values).
+//
+//  2. The layout checker.  Given a raw image of a GPU table (slots, tags, lock
+//     bits) it re-derives every key's candidate buckets from the documented hash
+//     rule (MurmurHash3's 64-bit finaliser of key XOR a fixed salt) and checks the
+//     design invariants: no duplicate key, no reservation marker left, every key
+//     in one of its candidate buckets, for double hashing every key before the
+//     first bucket on its sequence that holds an empty slot, every tag equal to the
+//     tag of its key (Section 4.3), every lock bit clear.  It also counts probes
+//     (Section 5.1: unique 128-byte lines an operation touches).
+//
+//  3. A sequential layout simulator: the placement rule of each design applied
+//     one key at a time (double hashing: first bucket on the sequence with a free
+//     slot, Section 2.2; power-of-two-choice: less loaded of two buckets, with the
+//     75% shortcut, Section 2.2).  Its probe counts are pinned to the paper's
+//     Table 1 by the tests, which is what ties the checker's model to the paper.
+//
+// Every function is a plain C ABI for ctypes.
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <unordered_map>
+#include <unordered_set>
+#include <utility>
+#include <vector>
+
+extern "C" {
+
+// ---------------------------------------------------------------------------
+// 1. Semantic map
+// ---------------------------------------------------------------------------
+
+// Operation codes of a batch (Section 5.1).
+enum { ORC_QUERY = 0, ORC_INSERT = 1, ORC_UPSERT = 2, ORC_ERASE = 3 };
+// Upsert callbacks offered as an enum (Section 5.1 gives "insert if unique" and
+// atomic accumulation as examples; replace/min/max are the same kind of callback).
+enum { ORC_SUM = 0, ORC_KEEP = 1, ORC_REPLACE = 2, ORC_MIN = 3, ORC_MAX = 4 };
+// Per-operation status codes.
+enum { ORC_MISS = 0, ORC_DONE = 1, ORC_EXISTED = 2, ORC_FULL = 3, ORC_INVALID = 4 };
+
+struct orc_map {
+  int key_bits;
+  uint64_t capacity;  // 0 = unbounded; else inserting past it gives ORC_FULL
+  std::unordered_map<uint64_t, uint64_t> m;
+};
+
+static uint64_t width_mask(int bits) { return bits == 64 ? ~0ull : ((1ull << bits) - 1); }
+
+static bool is_sentinel(const orc_map* h, uint64_t k) {
+  uint64_t top = width_mask(h->key_bits);
+  int n_reserved = h->key_bits == 64 ? 3 : 2;
+  return k > top - (uint64_t)n_reserved;
+}
+
+orc_map* orc_map_new(int key_bits, uint64_t capacity) {
+  if (key_bits != 64 && key_bits != 32) return nullptr;
+  orc_map* h = new orc_map;
+  h->key_bits = key_bits;
+  h->capacity = capacity;
+  return h;
+}
+
+void orc_map_free(orc_map* h) { delete h; }
+
+uint64_t orc_map_size(const orc_map* h) { return (uint64_t)h->m.size(); }
+
+static uint64_t combine(int op, uint64_t old, uint64_t v, uint64_t mask) {
+  switch (op) {
+    case ORC_SUM: return (old + v) & mask;
+    case ORC_KEEP: return old;
+    case ORC_REPLACE: return v & mask;
+    case ORC_MIN: return std::min(old, v & mask);
+    case ORC_MAX: return std::max(old, v & mask);
+  }
+  return old;
+}
+
+// Applies n operations in input order.  `ops` may be NULL (then every op is
+// `default_op`).  `vals` may be NULL for queries/erases.  Outputs: status[i] and,
+// for queries, vals_out[i] = stored value if found else 0 (0 for other ops).
+// Either output may be NULL.  Returns 0, or -1 on a bad argument.
+int orc_map_apply(orc_map* h, uint64_t n, const uint8_t* ops, int default_op,
+                  const uint64_t* keys, const uint64_t* vals, int combine_op,
+                  uint8_t* status, uint64_t* vals_out) {
+  if (!h || (n && !keys)) return -1;
+  const uint64_t mask = width_mask(h->key_bits);
+  for (uint64_t i = 0; i < n; i++) {
+    int op = ops ? ops[i] : default_op;
+    uint64_t k = keys[i];
+    uint64_t v = vals ? (vals[i] & mask) : 0;
+    uint8_t st = ORC_MISS;
+    uint64_t out = 0;
+    if (k > mask || is_sentinel(h, k)) {
+      st = ORC_INVALID;
+    } else if (op == ORC_QUERY) {
+      auto it = h->m.find(k);
+      if (it != h->m.end()) { st = ORC_DONE; out = it->second; }
+    } else if (op == ORC_INSERT || op == ORC_UPSERT) {
+      int c = op == ORC_INSERT ? ORC_KEEP : combine_op;
+      auto it = h->m.find(k);
+      if (it != h->m.end()) {
+        it->second = combine(c, it->second, v, mask);
+        st = ORC_EXISTED;
+      } else if (h->capacity && h->m.size() >= h->capacity) {
+        st = ORC_FULL;
+      } else {
+        h->m.emplace(k, v);
+        st = ORC_DONE;
+      }
+    } else if (op == ORC_ERASE) {
+      st = h->m.erase(k) ? ORC_DONE : ORC_MISS;
+    } else {
+      return -1;
+    }
+    if (status) status[i] = st;
+    if (vals_out) vals_out[i] = out;
+  }
+  return 0;
+}
+
+// Writes all (key, value) pairs sorted by key.  Arrays must hold orc_map_size().
+void orc_map_dump(const orc_map* h, uint64_t* keys, uint64_t* vals) {
+  std::vector<std::pair<uint64_t, uint64_t>> v(h->m.begin(), h->m.end());
+  std::sort(v.begin(), v.end());
+  for (size_t i = 0; i < v.size(); i++) {
+    keys[i] = v[i].first;
+    if (vals) vals[i] = v[i].second;
+  }
+}
+
+// Order-independent digest of the map contents (sum and xor of a per-pair mix),
+// used to compare two maps cheaply.
+void orc_map_digest(const orc_map* h, uint64_t* sum_out, uint64_t* xor_out) {
+  uint64_t s = 0, x = 0;
+  for (auto& kv : h->m) {
+    uint64_t z = kv.first * 0x9E3779B97F4A7C15ull ^ (kv.second + 0x632BE59BD9B4E019ull);
+    z ^= z >> 29;
+    s += z;
+    x ^= z;
+  }
+  *sum_out = s;
+  *xor_out = x;
+}
+
+// ---------------------------------------------------------------------------
+// 2. Hash rule, probe model and layout checker (independent re-statement)
+// ---------------------------------------------------------------------------
+//
+// Reading of the paper's silent hash functions (Section 2.2 names two hash
+// functions for double hashing and two choices for power-of-two-choice, nothing
+// more):  h = fmix64(key XOR 0x6a09e667f3bcc909), fmix64 being the 64-bit
+// finaliser of Appleby's MurmurHash3.  Primary bucket = low 32 bits of h mod nb;
+// second hash = high 32 bits of h.  Double hashing visits (b1 + i*step) mod nb
+// with step = (second mod nb) | 1 (odd, so the sequence covers all nb buckets, nb
+// a power of two).  Power-of-two-choice's alternate bucket = second mod nb.
+// Tag (Section 5.1: the low 16 bits of the key) with the two top patterns
+// reserved for empty (0xFFFF) and tombstone (0xFFFE): such keys take low16 - 2.
+
+enum { ORC_DOUBLE = 0, ORC_DOUBLE_M = 1, ORC_P2 = 2, ORC_P2_M = 3 };
+
+static uint64_t orc_fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+static const uint64_t ORC_SALT = 0x6a09e667f3bcc909ull;
+
+struct orc_hash {
+  uint64_t b1, second;
+};
+
+static orc_hash orc_hash_key(uint64_t key, uint64_t nb) {
+  uint64_t h = orc_fmix64(key ^ ORC_SALT);
+  orc_hash r;
+  r.b1 = (uint64_t)(uint32_t)h % nb;
+  r.second = (uint64_t)(uint32_t)(h >> 32);
+  return r;
+}
+
+static uint64_t orc_double_bucket(const orc_hash& h, uint64_t nb, uint64_t i) {
+  uint64_t step = (h.second % nb) | 1;
+  return (h.b1 + i * step) % nb;
+}
+
+static uint64_t orc_p2_alt(const orc_hash& h, uint64_t nb) { return h.second % nb; }
+
+uint16_t orc_tag(uint64_t key) {
+  uint16_t t = (uint16_t)(key & 0xFFFF);
+  return t >= 0xFFFE ? (uint16_t)(t - 2) : t;
+}
+
+// Candidate-bucket helpers exported for tests.
+uint64_t orc_primary_bucket(uint64_t key, uint64_t nb) { return orc_hash_key(key, nb).b1; }
+uint64_t orc_double_probe(uint64_t key, uint64_t nb, uint64_t i) {
+  return orc_double_bucket(orc_hash_key(key, nb), nb, i);
+}
+uint64_t orc_p2_alternate(uint64_t key, uint64_t nb) { return orc_p2_alt(orc_hash_key(key, nb), nb); }
+
+static bool design_has_tags(int d) { return d == ORC_DOUBLE_M || d == ORC_P2_M; }
+static bool design_is_double(int d) { return d == ORC_DOUBLE || d == ORC_DOUBLE_M; }
+
+// A table image in host memory.  Slots are (key, value) pairs of key_bits each,
+// bucket-major: slot s = bucket * bucket_slots + j.
+struct orc_image {
+  int design, key_bits;
+  uint64_t nb, bucket_slots;
+  const uint8_t* slots;
+  const uint16_t* tags;
+  uint64_t key(uint64_t s) const {
+    if (key_bits == 64) { uint64_t k; memcpy(&k, slots + 16 * s, 8); return k; }
+    uint32_t k; memcpy(&k, slots + 8 * s, 4); return k;
+  }
+  uint64_t value(uint64_t s) const {
+    if (key_bits == 64) { uint64_t v; memcpy(&v, slots + 16 * s + 8, 8); return v; }
+    uint32_t v; memcpy(&v, slots + 8 * s + 4, 4); return v;
+  }
+  uint64_t empty_key() const { return key_bits == 64 ? ~0ull : 0xFFFFFFFFull; }
+  uint64_t tomb_key() const { return empty_key() - 1; }
+  uint64_t reserved_key() const { return empty_key() - 2; }  // 64-bit only
+  uint64_t slot_bytes() const { return key_bits == 64 ? 16 : 8; }
+};
+
+static bool bucket_has_empty(const orc_image& im, uint64_t b) {
+  for (uint64_t j = 0; j < im.bucket_slots; j++) {
+    uint64_t s = b * im.bucket_slots + j;
+    if (design_has_tags(im.design)) {
+      if (im.tags[s] == 0xFFFF) return true;
+    } else if (im.key(s) == im.empty_key()) {
+      return true;
+    }
+  }
+  return false;
+}
+
+// 128-byte lines spanned by a bucket's slots, and by its tags.
+static uint64_t lines_of(uint64_t bytes) { return (bytes + 127) / 128; }
+
+struct orc_layout_report {
+  uint64_t live, tombs, empties, reserved;
+  uint64_t duplicate_keys;   // extra copies beyond the first
+  uint64_t misplaced;        // key outside its candidate buckets / past an empty-holding bucket
+  uint64_t tag_mismatch;     // tag disagrees with its slot (tag designs)
+  uint64_t locks_held;       // lock bits still set
+  uint64_t in_alternate;     // power-of-two-choice: keys in their alternate bucket
+  double pos_probe_sum;      // sum over live keys of the positive-query probe count
+  double neg_probe_sum;      // sum over `neg_keys` of the negative-query probe count
+  uint64_t neg_count;
+  uint64_t max_seq_index;    // double hashing: largest sequence index of a live key
+};
+
+// Positive-query probe count of a key found at sequence position `pos_bucket`
+// (0 = primary / first bucket) in slot j of that bucket, in the paper's unit (unique
+// 128-byte lines touched, Section 5.1).  Model:
+//   double hashing, no tags: each visited bucket's lines are read one tile-width at a
+//     time; a tile reads `tile_bytes` per step; the found bucket is read up to j.
+//   tag designs: one tag-bucket read per visited bucket (lines of 2*bucket bytes) plus
+//     one line for the key/value slot.
+//   power-of-two-choice, no tags: primary read fully when the key is in the alternate.
+static double probe_pos(const orc_image& im, uint64_t pos_bucket, uint64_t j, uint64_t tile_bytes) {
+  const uint64_t sb = im.slot_bytes();
+  if (design_has_tags(im.design)) {
+    return (double)(pos_bucket + 1) * (double)lines_of(2 * im.bucket_slots) + 1.0;
+  }
+  uint64_t bucket_lines = lines_of(im.bucket_slots * sb);
+  uint64_t step_lines = std::max<uint64_t>(1, tile_bytes / 128);
+  uint64_t found_lines = std::min<uint64_t>(bucket_lines, ((j * sb) / 128) / step_lines * step_lines + step_lines);
+  return (double)(pos_bucket * bucket_lines + found_lines);
+}
+
+// Negative-query probe count for a key absent from the table.
+static double probe_neg(const orc_image& im, uint64_t key) {
+  const uint64_t sb = im.slot_bytes();
+  orc_hash h = orc_hash_key(key, im.nb);
+  uint64_t per_bucket = design_has_tags(im.design) ? lines_of(2 * im.bucket_slots)
+                                                   : lines_of(im.bucket_slots * sb);
+  if (design_is_double(im.design)) {
+    for (uint64_t i = 0; i < im.nb; i++) {
+      uint64_t b = orc_double_bucket(h, im.nb, i);
+      if (bucket_has_empty(im, b)) return (double)((i + 1) * per_bucket);
+    }
+    return (double)(im.nb * per_bucket);
+  }
+  uint64_t b2 = orc_p2_alt(h, im.nb);
+  return (double)((b2 == h.b1 ? 1 : 2) * per_bucket);
+}
+
+// Checks a quiescent table image.  `tags` may be NULL for designs without tags;
+// `locks` (nlock_words 64-bit words, bit b%64 of word b/64 = bucket b) may be NULL.
+// `neg_keys` (may be NULL) are keys known absent, for negative probe counts.
+// Returns the number of invariant violations found (0 = consistent).
+uint64_t orc_layout_check(int design, int key_bits, uint64_t nb, uint64_t bucket_slots,
+                          const void* slots, const uint16_t* tags, const uint64_t* locks,
+                          uint64_t nlock_words, const uint64_t* neg_keys, uint64_t n_neg,
+                          uint64_t tile_bytes, orc_layout_report* rep) {
+  orc_image im{design, key_bits, nb, bucket_slots, (const uint8_t*)slots, tags};
+  orc_layout_report r;
+  memset(&r, 0, sizeof r);
+  if (design_has_tags(design) && !tags) { r.tag_mismatch = 1; *rep = r; return 1; }
+  const uint64_t nslots = nb * bucket_slots;
+  std::unordered_set<uint64_t> seen;
+  seen.reserve(nslots);
+  for (uint64_t b = 0; b < nb; b++) {
+    for (uint64_t j = 0; j < bucket_slots; j++) {
+      uint64_t s = b * bucket_slots + j;
+      uint64_t k = im.key(s);
+      uint16_t t = tags ? tags[s] : 0;
+      if (k == im.empty_key()) {
+        r.empties++;
+        if (tags && t != 0xFFFF) r.tag_mismatch++;
+        continue;
+      }
+      if (k == im.tomb_key()) {
+        r.tombs++;
+        // Erase writes the tombstone tag in double hashing designs; tags of
+        // power-of-two-choice designs return to empty (no tombstones are used).
+        if (tags && t != 0xFFFE) r.tag_mismatch++;
+        if (!design_is_double(design)) r.misplaced++;
+        continue;
+      }
+      if (key_bits == 64 && k == im.reserved_key()) { r.reserved++; continue; }
+      r.live++;
+      if (!seen.insert(k).second) r.duplicate_keys++;
+      if (tags && t != orc_tag(k)) r.tag_mismatch++;
+      orc_hash h = orc_hash_key(k, nb);
+      if (design_is_double(design)) {
+        // Key must sit on its sequence, with no empty-holding bucket before it.
+        uint64_t i = 0;
+        bool ok = false;
+        for (; i < nb; i++) {
+          uint64_t bi = orc_double_bucket(h, nb, i);
+          if (bi == b) { ok = true; break; }
+          if (bucket_has_empty(im, bi)) break;
+        }
+        if (!ok) { r.misplaced++; continue; }
+        r.max_seq_index = std::max(r.max_seq_index, i);
+        r.pos_probe_sum += probe_pos(im, i, j, tile_bytes);
+      } else {
+        uint64_t b2 = orc_p2_alt(h, nb);
+        if (b == h.b1) {
+          r.pos_probe_sum += probe_pos(im, 0, j, tile_bytes);
+        } else if (b == b2) {
+          r.in_alternate++;
+          r.pos_probe_sum += probe_pos(im, 1, j, tile_bytes);
+        } else {
+          r.misplaced++;
+        }
+      }
+    }
+  }
+  if (locks) {
+    for (uint64_t w = 0; w < nlock_words; w++) r.locks_held += (uint64_t)__builtin_popcountll(locks[w]);
+  }
+  for (uint64_t i = 0; i < n_neg; i++) {
+    r.neg_probe_sum += probe_neg(im, neg_keys[i]);
+    r.neg_count++;
+  }
+  *rep = r;
+  return r.duplicate_keys + r.misplaced + r.tag_mismatch + r.locks_held + r.reserved;
+}
+
+// Live (key, value) pairs of an image, in slot order.  Returns the count.
+uint64_t orc_image_pairs(int key_bits, uint64_t nslots, const void* slots, uint64_t* keys,
+                         uint64_t* vals) {
+  orc_image im{0, key_bits, 1, nslots, (const uint8_t*)slots, nullptr};
+  uint64_t c = 0;
+  for (uint64_t s = 0; s < nslots; s++) {
+    uint64_t k = im.key(s);
+    if (k == im.empty_key() || k == im.tomb_key()) continue;
+    if (key_bits == 64 && k == im.reserved_key()) continue;
+    keys[c] = k;
+    vals[c] = im.value(s);
+    c++;
+  }
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// 3. Sequential layout simulator (placement rules of Section 2.2)
+// ---------------------------------------------------------------------------
+//
+// Inserts `n` distinct keys one at a time into an empty image (slots and tags
+// pre-filled with the empty pattern by this function).  Within a bucket the
+// lowest-index free slot is taken.
+//   double hashing: first bucket along the sequence with a free slot.
+//   power-of-two-choice: if `shortcut` and the primary holds fewer than 3/4 of
+//     bucket_slots keys, the primary; else the less loaded of primary and
+//     alternate, ties to the primary; full when both are full.
+// Returns the number of keys that could not be placed.
+uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_slots,
+                        void* slots, uint16_t* tags, const uint64_t* keys, const uint64_t* vals,
+                        uint64_t n, int shortcut, int init) {
+  const uint64_t nslots = nb * bucket_slots;
+  const uint64_t sb = key_bits == 64 ? 16 : 8;
+  uint8_t* S = (uint8_t*)slots;
+  if (init) {
+    memset(S, 0xFF, nslots * sb);
+    if (tags) memset(tags, 0xFF, nslots * 2);
+  }
+  std::vector<uint32_t> fill(nb, 0);
+  if (!init) {
+    orc_image im{design, key_bits, nb, bucket_slots, S, tags};
+    for (uint64_t b = 0; b < nb; b++)
+      for (uint64_t j = 0; j < bucket_slots; j++)
+        if (im.key(b * bucket_slots + j) != im.empty_key()) fill[b]++;
+  }
+  const uint64_t empty = key_bits == 64 ? ~0ull : 0xFFFFFFFFull;
+  auto slot_key = [&](uint64_t s) -> uint64_t {
+    if (key_bits == 64) { uint64_t k; memcpy(&k, S + 16 * s, 8); return k; }
+    uint32_t k; memcpy(&k, S + 8 * s, 4); return k;
+  };
+  auto put = [&](uint64_t b, uint64_t key, uint64_t val) {
+    for (uint64_t j = 0; j < bucket_slots; j++) {
+      uint64_t s = b * bucket_slots + j;
+      if (slot_key(s) != empty) continue;
+      if (key_bits == 64) { memcpy(S + 16 * s, &key, 8); memcpy(S + 16 * s + 8, &val, 8); }
+      else { uint32_t k = (uint32_t)key, v = (uint32_t)val; memcpy(S + 8 * s, &k, 4); memcpy(S + 8 * s + 4, &v, 4); }
+      if (tags) tags[s] = orc_tag(key);
+      fill[b]++;
+      return;
+    }
+  };
+  uint64_t failed = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    orc_hash h = orc_hash_key(keys[i], nb);
+    uint64_t v = vals ? vals[i] : 0;
+    if (design_is_double(design)) {
+      bool placed = false;
+      for (uint64_t p = 0; p < nb; p++) {
+        uint64_t b = orc_double_bucket(h, nb, p);
+        if (fill[b] < bucket_slots) { put(b, keys[i], v); placed = true; break; }
+      }
+      if (!placed) failed++;
+    } else {
+      uint64_t b1 = h.b1, b2 = orc_p2_alt(h, nb);
+      if (shortcut && 4 * fill[b1] < 3 * bucket_slots) { put(b1, keys[i], v); continue; }
+      uint64_t b = fill[b2] < fill[b1] ? b2 : b1;
+      if (fill[b] >= bucket_slots) { failed++; continue; }
+      put(b, keys[i], v);
+    }
+  }
+  return failed;
+}
+
+}  // extern "C"

@@ -1,0 +1,327 @@
+"""Seeded synthetic input generators shared by the tests, the benchmark and the oracle runs.
+
+This module holds no hash-table arithmetic: it only draws numbers.  Every
+random quantity a workload needs (keys, values, shuffles, Zipf ranks, arrival
+times) is produced here from named, published generators and handed to both
+sides as plain arrays.
+
+* splitmix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+  generators", OOPSLA 2014): state advances by the odd constant
+  0x9E3779B97F4A7C15 and each output is a bijective mix of the state, so the
+  outputs of one stream at distinct counters are distinct.  A stream is fully
+  described by its 64-bit seed; element i of the stream is the output after
+  i+1 advances.
+* Zipf(theta) ranks by the closed-form inversion of Gray, Sundaresan,
+  Englert, Baclawski and Weinberger, "Quickly generating billion-record
+  synthetic databases", SIGMOD 1994 (the method the YCSB client uses).
+* Fisher-Yates shuffles driven by a splitmix64 stream.
+
+The workload recipes (which stream feeds which array) follow the evaluation
+setups of the paper's load benchmark (Section 6.3) and mixed-operation aging
+benchmark (Section 6.5); they are documented with each function below.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_S30 = np.uint64(30)
+_S27 = np.uint64(27)
+_S31 = np.uint64(31)
+
+U64_MAX = (1 << 64) - 1
+
+# Largest chunk materialised at once, to bound host memory on 2^28-key workloads.
+_CHUNK = 1 << 24
+
+
+def stream_seed(config: int, purpose: int) -> int:
+    """Seed of the splitmix64 stream for (workload config id, purpose id)."""
+    return ((config & 0xFFFFFFFF) << 32) | (purpose & 0xFFFFFFFF)
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Elements [start, start+count) of the splitmix64 stream with the given seed (uint64)."""
+    out = np.empty(count, dtype=np.uint64)
+    s0 = np.uint64(seed & U64_MAX)
+    with np.errstate(over="ignore"):
+        for c0 in range(0, count, _CHUNK):
+            c1 = min(count, c0 + _CHUNK)
+            ctr = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.uint64)
+            z = s0 + ctr * GAMMA
+            z = (z ^ (z >> _S30)) * _M1
+            z = (z ^ (z >> _S27)) * _M2
+            out[c0:c1] = z ^ (z >> _S31)
+    return out
+
+
+def distinct_keys(seed: int, count: int, key_bits: int = 64, n_reserved: int = 3,
+                  skip: int = 0) -> np.ndarray:
+    """`count` distinct keys: a splitmix64 stream with the top `n_reserved` values of the
+    key range removed (those are the table's reserved key patterns).
+
+    Keys are taken in stream order after dropping the first `skip` accepted keys, so
+    `distinct_keys(s, a)` followed by `distinct_keys(s, b, skip=a)` continues the same
+    stream: the two arrays are disjoint (splitmix64 is a bijection of its counter).
+    For key_bits=32 the stream output is truncated to its low 32 bits and duplicates
+    are removed by keeping first occurrences (in stream order).
+    """
+    if key_bits == 64:
+        limit = U64_MAX - n_reserved  # keys must be <= limit
+        need = skip + count
+        # reserved values appear with probability ~3/2^64: draw, filter, top up.
+        raw = splitmix64(seed, 0, need)
+        ok = raw <= np.uint64(limit)
+        pos = need
+        while int(ok.sum()) < need:
+            extra = splitmix64(seed, pos, need - int(ok.sum()))
+            pos += len(extra)
+            raw = np.concatenate([raw[ok], extra])
+            ok = raw <= np.uint64(limit)
+        return raw[ok][skip:need].copy()
+    if key_bits == 32:
+        limit = (1 << 32) - 1 - n_reserved
+        need = skip + count
+        got = np.empty(0, dtype=np.uint64)
+        pos = 0
+        while len(got) < need:
+            batch = splitmix64(seed, pos, max(need - len(got), 1024) + (need >> 4))
+            pos += len(batch)
+            cand = batch & np.uint64(0xFFFFFFFF)
+            cand = cand[cand <= np.uint64(limit)]
+            allk = np.concatenate([got, cand])
+            _, first = np.unique(allk, return_index=True)
+            first.sort()
+            got = allk[first]
+        return got[skip:need].copy()
+    raise ValueError("key_bits must be 32 or 64")
+
+
+def uniform_below(seed: int, start: int, count: int, bound: int) -> np.ndarray:
+    """`count` integers uniform in [0, bound) from a splitmix64 stream (multiply-shift
+    reduction of the high 32 bits; bound < 2^32)."""
+    assert 0 < bound < (1 << 32)
+    r = splitmix64(seed, start, count) >> np.uint64(32)
+    with np.errstate(over="ignore"):
+        return ((r * np.uint64(bound)) >> np.uint64(32)).astype(np.int64)
+
+
+def unit_float(seed: int, start: int, count: int) -> np.ndarray:
+    """`count` doubles uniform in [0, 1): top 53 bits of a splitmix64 stream."""
+    r = splitmix64(seed, start, count) >> np.uint64(11)
+    return r.astype(np.float64) * (1.0 / (1 << 53))
+
+
+def permutation(seed: int, n: int) -> np.ndarray:
+    """Fisher-Yates permutation of range(n) driven by a splitmix64 stream.
+
+    Step i (from n-1 down to 1) swaps position i with j = floor(u_i * (i+1)), u_i the
+    i-th stream double.  Vectorised draws, sequential swaps in chunks for big n.
+    """
+    p = np.arange(n, dtype=np.int64)
+    if n <= 1:
+        return p
+    u = unit_float(seed, 0, n - 1)  # u[k] drives step i = n-1-k
+    idx = np.arange(n - 1, 0, -1, dtype=np.int64)
+    j = np.minimum((u * (idx + 1)).astype(np.int64), idx)
+    _swap_loop(p, idx, j)
+    return p
+
+
+def _swap_loop(p, idx, j):
+    """Sequential Fisher-Yates swaps (numpy has no vectorised form); a compiled
+    loop takes over for large n."""
+    n = len(idx)
+    if n > 200000:
+        _swap_loop_fast(p, idx, j)
+        return
+    for k in range(n):
+        a = idx[k]
+        b = j[k]
+        p[a], p[b] = p[b], p[a]
+
+
+_fast = None
+
+
+def _swap_loop_fast(p, idx, j):
+    """Sequential swap loop compiled once with the host C compiler (ctypes)."""
+    global _fast
+    if _fast is None:
+        _fast = _build_swap_helper()
+    import ctypes
+    _fast(p.ctypes.data_as(ctypes.c_void_p), idx.ctypes.data_as(ctypes.c_void_p),
+          j.ctypes.data_as(ctypes.c_void_p), ctypes.c_int64(len(idx)))
+
+
+def _build_swap_helper():
+    import ctypes
+    import hashlib
+    import os
+    import subprocess
+    import tempfile
+    src = (
+        "#include <stdint.h>\n"
+        "void fy_swaps(int64_t* p, const int64_t* idx, const int64_t* j, int64_t n){\n"
+        "  for (int64_t k = 0; k < n; k++) { int64_t a = idx[k], b = j[k];\n"
+        "    int64_t t = p[a]; p[a] = p[b]; p[b] = t; } }\n"
+    )
+    tag = hashlib.sha1(src.encode()).hexdigest()[:12]
+    d = os.path.join(tempfile.gettempdir(), "hw_workloads_%d" % os.getuid())
+    os.makedirs(d, exist_ok=True)
+    so = os.path.join(d, "fy_%s.so" % tag)
+    if not os.path.exists(so):
+        c = os.path.join(d, "fy_%s.c" % tag)
+        with open(c, "w") as f:
+            f.write(src)
+        tmp = so + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", c, "-o", tmp])
+        os.replace(tmp, so)
+    lib = ctypes.CDLL(so)
+    fn = lib.fy_swaps
+    fn.restype = None
+    fn.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64]
+    return fn
+
+
+class Zipf:
+    """Zipf(theta) ranks in [0, n) by the Gray et al. (1994) inversion.
+
+    zeta(n) = sum_{i=1..n} i^-theta; alpha = 1/(1-theta);
+    eta = (1 - (2/n)^(1-theta)) / (1 - zeta(2)/zeta(n)).
+    For u uniform in [0,1): uz = u*zeta(n); rank 0 if uz < 1, rank 1 if uz < 1 + 0.5^theta,
+    else floor(n * (eta*u - eta + 1)^alpha).
+    """
+
+    def __init__(self, n: int, theta: float = 0.99):
+        assert n >= 2 and 0 < theta < 1
+        self.n = int(n)
+        self.theta = float(theta)
+        zn = 0.0
+        for c0 in range(1, n + 1, _CHUNK):
+            c1 = min(n + 1, c0 + _CHUNK)
+            zn += float(np.sum(np.arange(c0, c1, dtype=np.float64) ** (-theta)))
+        self.zetan = zn
+        zeta2 = 1.0 + 0.5 ** theta
+        self.alpha = 1.0 / (1.0 - theta)
+        self.eta = (1.0 - (2.0 / n) ** (1.0 - theta)) / (1.0 - zeta2 / zn)
+        self.half_pow = 0.5 ** theta
+
+    def ranks(self, seed: int, start: int, count: int) -> np.ndarray:
+        u = unit_float(seed, start, count)
+        uz = u * self.zetan
+        r = np.floor(self.n * np.power(self.eta * u - self.eta + 1.0, self.alpha))
+        r = np.minimum(r, self.n - 1).astype(np.int64)
+        r = np.where(uz < 1.0 + self.half_pow, 1, r)
+        r = np.where(uz < 1.0, 0, r)
+        return r
+
+
+# ---------------------------------------------------------------------------
+# Workload recipes.  Each returns plain numpy arrays; nothing here knows how the
+# table stores or finds keys.
+# ---------------------------------------------------------------------------
+
+def value_of(keys: np.ndarray, key_bits: int = 64) -> np.ndarray:
+    """Value convention of the load benchmarks: v = 3k + 1 (wrapping)."""
+    with np.errstate(over="ignore"):
+        v = keys * np.uint64(3) + np.uint64(1)
+    if key_bits == 32:
+        v &= np.uint64(0xFFFFFFFF)
+    return v
+
+
+def load_then_query(capacity: int, load: float, config_id: int = 1):
+    """Insert floor(load*capacity) distinct keys (v = 3k+1), then query them plus the
+    same number of absent keys (continuation of the key stream), shuffled.
+
+    Returns dict(keys, vals, qkeys, expect_found) where expect_found marks the
+    positive queries.  Absent keys are guaranteed distinct from inserted ones.
+    """
+    n = int(load * capacity)
+    s_keys = stream_seed(config_id, 1)
+    keys = distinct_keys(s_keys, n)
+    absent = distinct_keys(s_keys, n, skip=n)
+    q = np.concatenate([keys, absent])
+    perm = permutation(stream_seed(config_id, 2), len(q))
+    qkeys = q[perm]
+    expect_found = perm < n
+    return dict(keys=keys, vals=value_of(keys), qkeys=qkeys, expect_found=expect_found)
+
+
+def load_phases(capacity: int, fractions=(0.5, 0.75, 0.9), config_id: int = 2):
+    """Distinct-key insert phases filling a table to each fraction of `capacity`.
+
+    Phase p inserts keys [floor(f_{p-1} * cap), floor(f_p * cap)) of one stream.
+    Returns (all_keys, bounds) with bounds[p] = cumulative count after phase p.
+    """
+    bounds = [int(f * capacity) for f in fractions]
+    keys = distinct_keys(stream_seed(config_id, 1), bounds[-1])
+    return keys, bounds
+
+
+def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99,
+                  frac_upsert: float = 0.3, frac_erase: float = 0.2, config_id: int = 3,
+                  preload_fraction: float = 1.0):
+    """Generator of deterministic mixed batches over a Zipf-distributed key universe.
+
+    The universe is `universe` distinct keys (stream (config,1)); Zipf ranks index it.
+    Per batch of `batch` ops:
+      * erase keys: Zipf draws, repeats rejected, until floor(frac_erase*batch) distinct;
+      * upsert keys: Zipf draws with erase keys rejected (repeats allowed);
+      * query keys: Zipf draws with erase and upsert keys rejected;
+      * upsert values: a splitmix64 stream; op order shuffled.
+    Because erase and upsert keys are disjoint and queries avoid both, every output is
+    the same under any serialisation of the batch.
+    Yields dict(ops, keys, vals) with ops coded 0 query, 2 upsert, 3 erase.
+    """
+    ukeys = distinct_keys(stream_seed(config_id, 1), universe)
+    z = Zipf(universe, theta)
+    n_up = int(frac_upsert * batch)
+    n_er = int(frac_erase * batch)
+    n_q = batch - n_up - n_er
+    zs = stream_seed(config_id, 3)
+    zpos = 0
+    for b in range(n_batches):
+        def draw(count):
+            nonlocal zpos
+            r = z.ranks(zs, zpos, count)
+            zpos += count
+            return r
+        # erase: distinct ranks
+        er = np.empty(0, dtype=np.int64)
+        while len(er) < n_er:
+            r = draw(2 * (n_er - len(er)) + 1024)
+            allr = np.concatenate([er, r])
+            _, first = np.unique(allr, return_index=True)
+            first.sort()
+            er = allr[first][:n_er]
+        er_set = np.zeros(universe, dtype=bool)
+        er_set[er] = True
+        up = np.empty(0, dtype=np.int64)
+        while len(up) < n_up:
+            r = draw(n_up - len(up) + 1024)
+            r = r[~er_set[r]]
+            up = np.concatenate([up, r])[:n_up]
+        bad = er_set.copy()
+        bad[up] = True
+        qr = np.empty(0, dtype=np.int64)
+        while len(qr) < n_q:
+            r = draw(n_q - len(qr) + 1024)
+            r = r[~bad[r]]
+            qr = np.concatenate([qr, r])[:n_q]
+        ops = np.concatenate([np.zeros(n_q, np.uint8), np.full(n_up, 2, np.uint8),
+                              np.full(n_er, 3, np.uint8)])
+        ranks = np.concatenate([qr, up, er])
+        vals = np.zeros(batch, dtype=np.uint64)
+        vals[n_q:n_q + n_up] = splitmix64(stream_seed(config_id, 4), b * batch, n_up)
+        perm = permutation(stream_seed(config_id, 1000 + b), batch)
+        yield dict(ops=ops[perm], keys=ukeys[ranks[perm]], vals=vals[perm], ranks=ranks[perm])
+
+
+def universe_keys(universe: int, config_id: int = 3) -> np.ndarray:
+    """The key universe used by `mixed_batches` (same stream)."""
+    return distinct_keys(stream_seed(config_id, 1), universe)

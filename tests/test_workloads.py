@@ -1,0 +1,80 @@
+"""Seeded input generators (CPU only): each checked against an independent
+restatement of its published definition or a property that must hold."""
+import numpy as np
+
+from paper_2509_16407_amd import workloads as w
+
+MASK = (1 << 64) - 1
+
+
+def _splitmix_py(seed, n):
+    """splitmix64 with Python integers (Steele, Lea, Flood 2014)."""
+    s = seed
+    out = []
+    for _ in range(n):
+        s = (s + 0x9E3779B97F4A7C15) & MASK
+        z = s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def test_splitmix64_matches_integer_definition():
+    for seed in (0, 1, 1234567, w.stream_seed(2, 1), MASK):
+        assert w.splitmix64(seed, 0, 50).tolist() == _splitmix_py(seed, 50)
+    # offset access equals the tail of a longer draw
+    assert w.splitmix64(99, 17, 10).tolist() == _splitmix_py(99, 27)[17:]
+
+
+def test_distinct_keys_and_continuation_disjoint():
+    a = w.distinct_keys(w.stream_seed(1, 1), 200000)
+    b = w.distinct_keys(w.stream_seed(1, 1), 200000, skip=200000)
+    assert len(np.unique(a)) == len(a) == 200000
+    assert len(np.intersect1d(a, b)) == 0
+    assert (a <= np.uint64(MASK - 3)).all()
+    both = w.distinct_keys(w.stream_seed(1, 1), 400000)
+    assert (both[:200000] == a).all() and (both[200000:] == b).all()
+
+
+def test_distinct_keys_32():
+    k = w.distinct_keys(77, 300000, key_bits=32)
+    assert len(np.unique(k)) == len(k) == 300000
+    assert (k <= np.uint64(0xFFFFFFFF - 3)).all()
+
+
+def test_permutation_is_a_permutation():
+    for n in (0, 1, 2, 1000, 300001):
+        p = w.permutation(5, n)
+        assert np.array_equal(np.sort(p), np.arange(n))
+    assert not np.array_equal(w.permutation(5, 1000), np.arange(1000))
+    assert np.array_equal(w.permutation(5, 300001), w.permutation(5, 300001))
+
+
+def test_zipf_rank_frequencies():
+    """P(rank r) of Zipf(theta) over n ranks is (r+1)^-theta / zeta(n)."""
+    n, theta = 1 << 16, 0.99
+    z = w.Zipf(n, theta)
+    r = z.ranks(123, 0, 2_000_000)
+    assert r.min() >= 0 and r.max() < n
+    zeta = np.sum(np.arange(1, n + 1, dtype=np.float64) ** -theta)
+    for rank in (0, 1):
+        p = (rank + 1) ** -theta / zeta
+        obs = np.mean(r == rank)
+        assert abs(obs - p) < 5 * np.sqrt(p * (1 - p) / len(r)), (rank, obs, p)
+
+
+def test_mixed_batches_are_deterministic_and_disjoint():
+    gen = w.mixed_batches(1 << 14, 1 << 12, 2, config_id=3)
+    for b in gen:
+        ops, keys = b["ops"], b["keys"]
+        er = keys[ops == 3]
+        up = keys[ops == 2]
+        q = keys[ops == 0]
+        assert len(np.unique(er)) == len(er) == int(0.2 * 4096)
+        assert len(up) == int(0.3 * 4096)
+        assert len(np.intersect1d(er, up)) == 0
+        assert len(np.intersect1d(q, np.concatenate([er, up]))) == 0
+    g1 = next(w.mixed_batches(1 << 14, 1 << 12, 1, config_id=3))
+    g2 = next(w.mixed_batches(1 << 14, 1 << 12, 1, config_id=3))
+    assert all(np.array_equal(g1[k], g2[k]) for k in g1)
