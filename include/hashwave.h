@@ -1,0 +1,194 @@
+/*
+ * hashwave.h -- C-ABI of HashWave, concurrent open-addressing hash tables for
+ * AMD MI355X (gfx950).
+ *
+ * The operations follow the paper's hash-table API (Section 5.1, "Hash table
+ * API"): Upsert(key, value, callback), Query(key, &value) and Erase(key), here
+ * in bulk form over device arrays, enqueued on a HIP stream.  The callback of
+ * Upsert is offered as a fixed set of combine operations (hwave_combine),
+ * because a C-ABI cannot carry a device function pointer.  Insert is Upsert with
+ * the "insert if unique" callback (Section 5.1).
+ *
+ * Designs (Section 2.2 and Section 5): bucketed double hashing and
+ * power-of-two-choice hashing, each with an optional 16-bit fingerprint
+ * ("metadata", Section 4.3) array.  Every write operation takes the lock bit of
+ * the key's primary bucket (Section 4.1); queries take no lock (Section 4.2).
+ *
+ * Conventions for every call below:
+ *  - Pointers named d_* are device pointers (hipMalloc or torch CUDA tensors) on
+ *    the table's device; the caller owns them and keeps them alive until the
+ *    enqueued work completes.  Element width of keys and values is the table's
+ *    kv_bits (uint64_t or uint32_t elements); status/found arrays are uint8_t.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls are asynchronous; nothing blocks except hwave_destroy and the
+ *    *_sync helpers.
+ *  - Return value: HWAVE_OK (0) once the work is enqueued, or a negative
+ *    HWAVE_E* code; on an error nothing was enqueued.  n == 0 is a no-op.
+ *  - The table is concurrent: calls on different streams may overlap and the
+ *    result equals some serialisation of all their operations.  Calls within
+ *    one batch are concurrent with each other (any serialisation).
+ */
+#ifndef HASHWAVE_H
+#define HASHWAVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hwave_table hwave_table;
+
+/* Table designs (Section 2.2, configurations of Section 5). */
+typedef enum {
+  HWAVE_DOUBLE = 0,   /* bucketed double hashing; default bucket 8, tile 8     */
+  HWAVE_DOUBLE_M = 1, /* double hashing with 16-bit tags; bucket 32, tile 4    */
+  HWAVE_P2 = 2,       /* power-of-two-choice; bucket 32, tile 8                */
+  HWAVE_P2_M = 3      /* power-of-two-choice with 16-bit tags; bucket 32, tile 4 */
+} hwave_design;
+
+/* Upsert callbacks (Section 5.1): SUM accumulates with wrap-around modulo
+ * 2^kv_bits, KEEP is "insert if unique", REPLACE overwrites, MIN/MAX keep the
+ * unsigned minimum/maximum. */
+typedef enum { HWAVE_SUM = 0, HWAVE_KEEP = 1, HWAVE_REPLACE = 2, HWAVE_MIN = 3, HWAVE_MAX = 4 } hwave_combine;
+
+/* Opcodes of hwave_mixed. */
+typedef enum { HWAVE_OP_QUERY = 0, HWAVE_OP_INSERT = 1, HWAVE_OP_UPSERT = 2, HWAVE_OP_ERASE = 3 } hwave_op;
+
+/* Per-operation status codes written to d_status / d_found. */
+enum {
+  HWAVE_ST_MISS = 0,     /* query/erase: key absent                               */
+  HWAVE_ST_DONE = 1,     /* insert/upsert: inserted; query: found; erase: erased   */
+  HWAVE_ST_EXISTED = 2,  /* insert/upsert: key present, combine applied           */
+  HWAVE_ST_FULL = 3,     /* insert/upsert: no free slot among the key's buckets   */
+  HWAVE_ST_INVALID = 4   /* key equals a reserved pattern; the op had no effect   */
+};
+
+/* Return codes. */
+enum {
+  HWAVE_OK = 0,
+  HWAVE_EINVAL = -1,      /* bad argument (null pointer, size, unsupported value)  */
+  HWAVE_ENOMEM = -2,      /* device allocation failed or buffer too small          */
+  HWAVE_EDEVICE = -3,     /* a HIP call failed; see hwave_last_hip_error()         */
+  HWAVE_EUNSUPPORTED = -4 /* no kernel instance for this design/width/bucket/tile  */
+};
+
+/* Flags of hwave_config.flags. */
+enum {
+  HWAVE_F_NO_SHORTCUT = 1 /* power-of-two-choice: never take the 75% shortcut     */
+};
+
+/* Table configuration.  Zero fields take the design's defaults (the
+ * configurations of Section 5).  Supported (kv_bits, design, bucket, tile):
+ *   64-bit keys/values: DOUBLE bucket 8/16/32, tile 4/8 (tile <= bucket);
+ *                       DOUBLE_M, P2_M bucket 32, tile 4/8;
+ *                       P2 bucket 32, tile 4/8/16.
+ *   32-bit keys/values: every design, bucket 16/32, tile 4/8/16 (tile <= bucket).
+ * Reserved key patterns (rejected with HWAVE_ST_INVALID): 64-bit keys
+ * 0xFFFFFFFFFFFFFFFF (empty), ...FE (tombstone), ...FD (reservation marker);
+ * 32-bit keys 0xFFFFFFFF and 0xFFFFFFFE. */
+typedef struct {
+  uint32_t kv_bits;      /* 64 or 32                                          */
+  uint32_t bucket_slots; /* slots per bucket                                  */
+  uint32_t tile;         /* lanes cooperating on one operation                */
+  uint32_t probe_cap;    /* double hashing: max buckets visited (0 = all)      */
+  uint32_t flags;        /* HWAVE_F_*                                         */
+} hwave_config;
+
+/* Fills *out with the design's defaults.  Returns HWAVE_OK or HWAVE_EINVAL. */
+int hwave_config_default(hwave_design design, hwave_config* out);
+
+/* Device bytes a table needs (slots + tags + lock bits + control word) for a
+ * capacity rounded up to bucket_slots * 2^k slots.  Host-only arithmetic. */
+int hwave_table_bytes(uint64_t capacity_slots, hwave_design design, const hwave_config* cfg,
+                      uint64_t* bytes);
+
+/* Creates an empty table of at least capacity_slots slots (rounded up to
+ * bucket_slots * 2^k; hwave_capacity() reports the result).  Memory comes from
+ * hipMalloc and is owned by the table.  The table is initialised on `stream`.
+ * Capacity is fixed for the table's life (Section 3.2: no resizing). */
+int hwave_create(hwave_table** out, uint64_t capacity_slots, hwave_design design,
+                 const hwave_config* cfg, void* stream);
+
+/* Same as hwave_create but in caller-owned device memory (e.g. a torch tensor)
+ * of buffer_bytes >= hwave_table_bytes(); d_buffer must be 256-byte aligned and
+ * outlive the table. */
+int hwave_create_in(hwave_table** out, void* d_buffer, uint64_t buffer_bytes,
+                    uint64_t capacity_slots, hwave_design design, const hwave_config* cfg,
+                    void* stream);
+
+/* Synchronises the device, then frees the table (and its memory if owned). */
+int hwave_destroy(hwave_table* t);
+
+/* Empties the table (every slot empty, tags empty, locks clear) on `stream`. */
+int hwave_clear(hwave_table* t, void* stream);
+
+/* Insert = Upsert with KEEP (Section 5.1).  d_vals may not be NULL.  d_status
+ * (nullable): DONE (inserted), EXISTED (left unchanged), FULL or INVALID. */
+int hwave_insert(hwave_table* t, const void* d_keys, const void* d_vals, uint64_t n,
+                 uint8_t* d_status, void* stream);
+
+/* Upsert (Section 5.1): absent key -> inserted with its value (DONE); present
+ * key -> value = combine(stored, value) atomically (EXISTED). */
+int hwave_upsert(hwave_table* t, const void* d_keys, const void* d_vals, uint64_t n,
+                 hwave_combine combine, uint8_t* d_status, void* stream);
+
+/* Query (Section 5.1), lock-free (Section 4.2).  d_vals_out[i] = stored value
+ * or 0 when absent; d_found[i] = DONE / MISS / INVALID.  Either output may be
+ * NULL. */
+int hwave_query(hwave_table* t, const void* d_keys, uint64_t n, void* d_vals_out,
+                uint8_t* d_found, void* stream);
+
+/* Erase (Section 5.1): d_found[i] = DONE (erased) / MISS (absent, table
+ * unchanged) / INVALID.  d_found may be NULL. */
+int hwave_erase(hwave_table* t, const void* d_keys, uint64_t n, uint8_t* d_found, void* stream);
+
+/* One launch running a different operation per element (the paper runs all
+ * operations of an aging iteration concurrently in one kernel, Section 6.5).
+ * d_ops[i] is a hwave_op; upserts use `combine`; d_vals is read for inserts and
+ * upserts (nullable when there are none); d_vals_out (nullable) receives query
+ * results (0 for other ops); d_status (nullable) the per-op status. */
+int hwave_mixed(hwave_table* t, const uint8_t* d_ops, const void* d_keys, const void* d_vals,
+                uint64_t n, hwave_combine combine, void* d_vals_out, uint8_t* d_status,
+                void* stream);
+
+/* Writes the number of live keys to *d_count (one uint64_t on the device). */
+int hwave_size(hwave_table* t, uint64_t* d_count, void* stream);
+
+/* Copies every live (key, value) pair to d_keys/d_vals (capacity elements
+ * each, in slot order) and their number to *d_count.  Meant for a quiescent
+ * table (checkpoint dump, tests). */
+int hwave_export(hwave_table* t, void* d_keys, void* d_vals, uint64_t* d_count, void* stream);
+
+/* Number of buckets (host call), and the primary bucket of each key (device
+ * call): the two hooks of the paper's adversarial benchmark (Section 4.1). */
+uint64_t hwave_num_buckets(const hwave_table* t);
+int hwave_primary_bucket(hwave_table* t, const void* d_keys, uint64_t n, uint64_t* d_out,
+                         void* stream);
+
+/* Slot capacity after rounding. */
+uint64_t hwave_capacity(const hwave_table* t);
+
+/* Device pointers and geometry of a table, for tests that inspect its raw image. */
+typedef struct {
+  void* slots;          /* capacity slots of (key, value), bucket-major            */
+  uint16_t* tags;       /* capacity 16-bit tags, or NULL without tags             */
+  uint32_t* locks;      /* lock bits: bit b%32 of word b/32 is bucket b's lock    */
+  uint64_t n_lock_words;
+  uint64_t num_buckets;
+  uint32_t bucket_slots, tile, kv_bits, design;
+} hwave_raw_view;
+int hwave_raw(const hwave_table* t, hwave_raw_view* out);
+
+/* Text of a return code; HIP error code of the last failing HIP call. */
+const char* hwave_strerror(int code);
+int hwave_last_hip_error(void);
+
+/* Blocks until all work on `stream` is done (HIP error -> HWAVE_EDEVICE). */
+int hwave_stream_sync(void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HASHWAVE_H */

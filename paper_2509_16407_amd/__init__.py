@@ -1,0 +1,249 @@
+"""HashWave: concurrent GPU hash tables for MI355X (gfx950).
+
+Thin ctypes binding over `libhashwave.so` (C-ABI in include/hashwave.h).  It
+only marshals arguments: every table operation runs in the library's HIP
+kernels.  PyTorch provides device memory (tables are created inside a torch
+uint8 buffer with `hwave_create_in`) and the current stream.  Keys and values
+travel as int64 / int32 tensors holding the unsigned bit patterns.
+
+There is no fallback: if the shared library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Table", "lib", "DESIGNS", "COMBINES", "OPS", "HashWaveError"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhashwave.so")
+
+DESIGNS = {"DOUBLE": 0, "DOUBLE_M": 1, "P2": 2, "P2_M": 3}
+COMBINES = {"sum": 0, "keep": 1, "replace": 2, "min": 3, "max": 4}
+OPS = {"query": 0, "insert": 1, "upsert": 2, "erase": 3}
+ST_MISS, ST_DONE, ST_EXISTED, ST_FULL, ST_INVALID = 0, 1, 2, 3, 4
+F_NO_SHORTCUT = 1
+
+
+class HashWaveError(RuntimeError):
+    pass
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("kv_bits", ctypes.c_uint32), ("bucket_slots", ctypes.c_uint32),
+                ("tile", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class _Raw(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_void_p), ("tags", ctypes.c_void_p), ("locks", ctypes.c_void_p),
+                ("n_lock_words", ctypes.c_uint64), ("num_buckets", ctypes.c_uint64),
+                ("bucket_slots", ctypes.c_uint32), ("tile", ctypes.c_uint32),
+                ("kv_bits", ctypes.c_uint32), ("design", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HashWaveError("%s is missing: build it with __graft_entry__.build() "
+                                "(no CPU fallback exists)" % LIB_PATH)
+        _lib = _bind(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _bind(L):
+    P, U64, I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "hwave_config_default": (I, [I, ctypes.POINTER(_Config)]),
+        "hwave_table_bytes": (I, [U64, I, ctypes.POINTER(_Config), ctypes.POINTER(U64)]),
+        "hwave_create": (I, [ctypes.POINTER(P), U64, I, ctypes.POINTER(_Config), P]),
+        "hwave_create_in": (I, [ctypes.POINTER(P), P, U64, U64, I, ctypes.POINTER(_Config), P]),
+        "hwave_destroy": (I, [P]),
+        "hwave_clear": (I, [P, P]),
+        "hwave_insert": (I, [P, P, P, U64, P, P]),
+        "hwave_upsert": (I, [P, P, P, U64, I, P, P]),
+        "hwave_query": (I, [P, P, U64, P, P, P]),
+        "hwave_erase": (I, [P, P, U64, P, P]),
+        "hwave_mixed": (I, [P, P, P, P, U64, I, P, P, P]),
+        "hwave_size": (I, [P, P, P]),
+        "hwave_export": (I, [P, P, P, P, P]),
+        "hwave_num_buckets": (U64, [P]),
+        "hwave_capacity": (U64, [P]),
+        "hwave_primary_bucket": (I, [P, P, U64, P, P]),
+        "hwave_raw": (I, [P, ctypes.POINTER(_Raw)]),
+        "hwave_strerror": (ctypes.c_char_p, [I]),
+        "hwave_last_hip_error": (I, []),
+        "hwave_stream_sync": (I, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        L = lib()
+        raise HashWaveError("%s (code %d, hip error %d)" % (
+            L.hwave_strerror(rc).decode(), rc, L.hwave_last_hip_error()))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Table:
+    """One hash table in device memory.
+
+    design: "DOUBLE" | "DOUBLE_M" | "P2" | "P2_M"; kv_bits 64 or 32; bucket/tile 0 =
+    the design default (Section 5 configurations).  Keys/values are int64 tensors
+    (kv_bits=64) or int32 tensors (kv_bits=32) on the table's device.
+    """
+
+    def __init__(self, capacity: int, design: str = "P2_M", kv_bits: int = 64, bucket: int = 0,
+                 tile: int = 0, probe_cap: int = 0, flags: int = 0, device=None, stream=None):
+        import torch
+        L = lib()
+        self.design = design
+        self.design_id = DESIGNS[design]
+        self.cfg = _Config(kv_bits, bucket, tile, probe_cap, flags)
+        nbytes = ctypes.c_uint64()
+        _check(L.hwave_table_bytes(capacity, self.design_id, ctypes.byref(self.cfg),
+                                   ctypes.byref(nbytes)))
+        dv = torch.device(device if device is not None else "cuda")
+        if dv.index is None:
+            dv = torch.device("cuda", torch.cuda.current_device())
+        self.device = dv
+        self.buffer = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.hwave_create_in(ctypes.byref(h), _ptr(self.buffer), nbytes.value, capacity,
+                                     self.design_id, ctypes.byref(self.cfg), _stream(stream)))
+        self.h = h
+        self.kv_bits = kv_bits
+        self.dtype = torch.int64 if kv_bits == 64 else torch.int32
+        raw = _Raw()
+        _check(L.hwave_raw(self.h, ctypes.byref(raw)))
+        self._raw = raw
+        self.capacity = int(L.hwave_capacity(self.h))
+        self.num_buckets = int(L.hwave_num_buckets(self.h))
+        self.bucket_slots = int(raw.bucket_slots)
+        self.tile = int(raw.tile)
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hwave_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers
+    def _empty(self, n, dtype=None):
+        import torch
+        return torch.empty(n, dtype=dtype or self.dtype, device=self.device)
+
+    def _u8(self, n):
+        import torch
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def _keys(self, t):
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
+            raise HashWaveError("keys/values must be contiguous %s tensors on %s" % (self.dtype, self.device))
+        return t
+
+    # -- operations (asynchronous on the current or given stream)
+    def clear(self, stream=None):
+        _check(lib().hwave_clear(self.h, _stream(stream)))
+
+    def insert(self, keys, vals, status=None, stream=None):
+        n = keys.numel()
+        status = self._u8(n) if status is None else status
+        _check(lib().hwave_insert(self.h, _ptr(self._keys(keys)), _ptr(self._keys(vals)), n,
+                                  _ptr(status), _stream(stream)))
+        return status
+
+    def upsert(self, keys, vals, combine="sum", status=None, stream=None):
+        n = keys.numel()
+        status = self._u8(n) if status is None else status
+        _check(lib().hwave_upsert(self.h, _ptr(self._keys(keys)), _ptr(self._keys(vals)), n,
+                                  COMBINES[combine], _ptr(status), _stream(stream)))
+        return status
+
+    def query(self, keys, out=None, found=None, stream=None):
+        n = keys.numel()
+        out = self._empty(n) if out is None else out
+        found = self._u8(n) if found is None else found
+        _check(lib().hwave_query(self.h, _ptr(self._keys(keys)), n, _ptr(out), _ptr(found),
+                                 _stream(stream)))
+        return found, out
+
+    def erase(self, keys, found=None, stream=None):
+        n = keys.numel()
+        found = self._u8(n) if found is None else found
+        _check(lib().hwave_erase(self.h, _ptr(self._keys(keys)), n, _ptr(found), _stream(stream)))
+        return found
+
+    def mixed(self, ops, keys, vals, combine="sum", out=None, status=None, stream=None):
+        n = keys.numel()
+        out = self._empty(n) if out is None else out
+        status = self._u8(n) if status is None else status
+        _check(lib().hwave_mixed(self.h, _ptr(ops), _ptr(self._keys(keys)),
+                                 None if vals is None else _ptr(self._keys(vals)), n,
+                                 COMBINES[combine], _ptr(out), _ptr(status), _stream(stream)))
+        return status, out
+
+    def size(self, stream=None) -> int:
+        import torch
+        c = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().hwave_size(self.h, _ptr(c), _stream(stream)))
+        return int(c.item())
+
+    def export(self, stream=None):
+        """(keys, vals) of every live pair, unordered."""
+        import torch
+        k = self._empty(self.capacity)
+        v = self._empty(self.capacity)
+        c = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().hwave_export(self.h, _ptr(k), _ptr(v), _ptr(c), _stream(stream)))
+        n = int(c.item())
+        return k[:n], v[:n]
+
+    def primary_bucket(self, keys, stream=None):
+        n = keys.numel()
+        out = self._empty(n, dtype=__import__("torch").int64)
+        _check(lib().hwave_primary_bucket(self.h, _ptr(self._keys(keys)), n, _ptr(out),
+                                          _stream(stream)))
+        return out
+
+    def raw(self):
+        """Views of the raw device image: dict(slots=uint8, tags=int16 or None, locks=int32)."""
+        import torch
+        base = self.buffer.data_ptr()
+        r = self._raw
+        slot_bytes = self.capacity * (16 if self.kv_bits == 64 else 8)
+        out = {"slots": self.buffer[r.slots - base: r.slots - base + slot_bytes]}
+        if r.tags:
+            off = r.tags - base
+            out["tags"] = self.buffer[off: off + 2 * self.capacity].view(torch.int16)
+        else:
+            out["tags"] = None
+        off = r.locks - base
+        out["locks"] = self.buffer[off: off + 4 * r.n_lock_words].view(torch.int32)
+        return out

@@ -1,0 +1,433 @@
+// C-ABI of HashWave (declared in include/hashwave.h): table creation and
+// layout, argument checks, dispatch to the kernel instance of the table's
+// (key width, design, bucket, tile), and the design-independent kernels
+// (initialisation, counting, export, primary-bucket lookup).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "hashwave.h"
+#include "hw_launch.hpp"
+
+using namespace hw;
+
+struct hwave_table {
+  int device;
+  hwave_design design;
+  hwave_config cfg;
+  uint64_t nb, capacity, bytes;
+  uint64_t n_lock_words;
+  void* base;
+  bool owns;
+  const KernelSet* ks;
+  LaunchArgs la;
+};
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip_error = (int)e;
+  return HWAVE_EDEVICE;
+}
+
+constexpr uint64_t ALIGN = 256;
+uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  uint64_t nb, capacity;
+  uint64_t off_tags, off_locks, off_ctrl, total;
+  uint64_t n_lock_words;
+};
+
+bool design_tags(int d) { return d == HWAVE_DOUBLE_M || d == HWAVE_P2_M; }
+
+const std::vector<const KernelSet*>& registry() {
+  static std::vector<const KernelSet*> all;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const KernelSet* (*fns[])(size_t*) = {sets_u64_double, sets_u64_p2, sets_u32_double, sets_u32_p2};
+    for (auto f : fns) {
+      size_t n = 0;
+      const KernelSet* s = f(&n);
+      for (size_t i = 0; i < n; i++) all.push_back(s + i);
+    }
+  });
+  return all;
+}
+
+const KernelSet* find_set(int kv_bits, int design, int bucket, int tile) {
+  for (const KernelSet* s : registry())
+    if (s->kv_bits == kv_bits && s->design == design && s->bucket == bucket && s->tile == tile) return s;
+  return nullptr;
+}
+
+// Paper configurations (Section 5) for 64-bit keys; 32-bit keys keep the same
+// bucket byte span with 8-byte slots where a design's default bucket is small.
+void defaults_for(hwave_design design, uint32_t kv_bits, hwave_config* c) {
+  memset(c, 0, sizeof *c);
+  c->kv_bits = kv_bits;
+  c->bucket_slots = design == HWAVE_DOUBLE ? (kv_bits == 64 ? 8 : 16) : 32;
+  c->tile = design_tags(design) ? 4 : 8;
+}
+
+int resolve_config(hwave_design design, const hwave_config* in, hwave_config* out) {
+  if ((int)design < HWAVE_DOUBLE || (int)design > HWAVE_P2_M) return HWAVE_EINVAL;
+  const uint32_t kv = in && in->kv_bits ? in->kv_bits : 64;
+  if (kv != 64 && kv != 32) return HWAVE_EINVAL;
+  hwave_config c;
+  defaults_for(design, kv, &c);
+  if (in) {
+    if (in->bucket_slots) c.bucket_slots = in->bucket_slots;
+    if (in->tile) c.tile = in->tile;
+    c.probe_cap = in->probe_cap;
+    c.flags = in->flags;
+  }
+  *out = c;
+  return HWAVE_OK;
+}
+
+int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Layout* L) {
+  if (capacity == 0 || c.bucket_slots == 0) return HWAVE_EINVAL;
+  const uint64_t B = c.bucket_slots;
+  uint64_t want = (capacity + B - 1) / B;
+  uint64_t nb = 1;
+  while (nb < want) nb <<= 1;
+  if (nb > (1ull << 32)) return HWAVE_EINVAL;
+  const uint64_t slot_bytes = c.kv_bits / 4;  // two words
+  L->nb = nb;
+  L->capacity = nb * B;
+  uint64_t off = round_up(L->capacity * slot_bytes, ALIGN);
+  L->off_tags = off;
+  if (design_tags(design)) off += round_up(L->capacity * 2, ALIGN);
+  L->off_locks = off;
+  L->n_lock_words = (nb + 31) / 32;
+  off += round_up(L->n_lock_words * 4, ALIGN);
+  L->off_ctrl = off;
+  off += ALIGN;
+  L->total = off;
+  return HWAVE_OK;
+}
+
+__global__ void k_fill16(uint4* p, uint64_t n16, uint32_t word) {
+  const uint4 v = make_uint4(word, word, word, word);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename K>
+__global__ void k_count(const K* __restrict__ slots, uint64_t nslots, uint64_t* count) {
+  uint64_t c = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    c += slots[2 * i] < Keys<K>::FIRST_INVALID;
+  // wave reduction, one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd((unsigned long long*)count, (unsigned long long)c);
+}
+
+template <typename K>
+__global__ void k_export(const K* __restrict__ slots, uint64_t nslots, K* __restrict__ okeys,
+                         K* __restrict__ ovals, uint64_t* count) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const K k = slots[2 * i];
+    if (k < Keys<K>::FIRST_INVALID) {
+      const uint64_t at = atomicAdd((unsigned long long*)count, 1ull);
+      okeys[at] = k;
+      ovals[at] = slots[2 * i + 1];
+    }
+  }
+}
+
+__global__ void k_zero_u64(uint64_t* p) { *p = 0; }
+
+template <typename K>
+__global__ void k_primary(const K* __restrict__ keys, uint64_t n, uint32_t mask, uint64_t* __restrict__ out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = hash_key((uint64_t)keys[i], mask).b1;
+}
+
+unsigned max_blocks_for(int device) {
+  static unsigned cache[64] = {0};
+  if (device >= 0 && device < 64 && cache[device]) return cache[device];
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+    cus = 256;
+  unsigned v = (unsigned)cus * 32;
+  if (device >= 0 && device < 64) cache[device] = v;
+  return v;
+}
+
+unsigned stream_grid(uint64_t n, int device) {
+  uint64_t blocks = (n + 255) / 256;
+  uint64_t cap = max_blocks_for(device);
+  if (blocks > cap) blocks = cap;
+  return (unsigned)(blocks ? blocks : 1);
+}
+
+int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwave_design design,
+               const hwave_config& c, const KernelSet* ks, void* stream) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  t->device = dev;
+  t->design = design;
+  t->cfg = c;
+  t->nb = L.nb;
+  t->capacity = L.capacity;
+  t->bytes = bytes;
+  t->n_lock_words = L.n_lock_words;
+  t->base = base;
+  t->ks = ks;
+  uint8_t* b = (uint8_t*)base;
+  TableDev& tv = t->la.tv;
+  tv.slots = b;
+  tv.tagw = design_tags(design) ? (uint32_t*)(b + L.off_tags) : nullptr;
+  tv.locks = (uint32_t*)(b + L.off_locks);
+  tv.ctrl = (uint32_t*)(b + L.off_ctrl);
+  tv.bucket_mask = (uint32_t)(L.nb - 1);
+  uint64_t cap = c.probe_cap ? c.probe_cap : L.nb;
+  if (cap > L.nb) cap = L.nb;
+  tv.probe_cap = (uint32_t)(cap > 0xFFFFFFFFull ? 0xFFFFFFFFull : cap);
+  tv.shortcut = (c.flags & HWAVE_F_NO_SHORTCUT) ? 0u : 1u;
+  tv.pad = 0;
+  t->la.max_blocks = max_blocks_for(dev);
+  return hwave_clear(t, stream);
+}
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+int hwave_config_default(hwave_design design, hwave_config* out) {
+  if (!out || (int)design < HWAVE_DOUBLE || (int)design > HWAVE_P2_M) return HWAVE_EINVAL;
+  defaults_for(design, 64, out);
+  return HWAVE_OK;
+}
+
+int hwave_table_bytes(uint64_t capacity, hwave_design design, const hwave_config* cfg, uint64_t* bytes) {
+  if (!bytes) return HWAVE_EINVAL;
+  hwave_config c;
+  int rc = resolve_config(design, cfg, &c);
+  if (rc) return rc;
+  if (!find_set(c.kv_bits, design, c.bucket_slots, c.tile)) return HWAVE_EUNSUPPORTED;
+  Layout L;
+  rc = layout_of(capacity, design, c, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return HWAVE_OK;
+}
+
+int hwave_create(hwave_table** out, uint64_t capacity, hwave_design design, const hwave_config* cfg,
+                 void* stream) {
+  if (!out) return HWAVE_EINVAL;
+  *out = nullptr;
+  hwave_config c;
+  int rc = resolve_config(design, cfg, &c);
+  if (rc) return rc;
+  const KernelSet* ks = find_set(c.kv_bits, design, c.bucket_slots, c.tile);
+  if (!ks) return HWAVE_EUNSUPPORTED;
+  Layout L;
+  rc = layout_of(capacity, design, c, &L);
+  if (rc) return rc;
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, L.total);
+  if (e != hipSuccess) {
+    g_last_hip_error = (int)e;
+    (void)hipGetLastError();
+    return HWAVE_ENOMEM;
+  }
+  hwave_table* t = new hwave_table;
+  t->owns = true;
+  rc = init_table(t, base, L.total, L, design, c, ks, stream);
+  if (rc) {
+    (void)hipFree(base);
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return HWAVE_OK;
+}
+
+int hwave_create_in(hwave_table** out, void* d_buffer, uint64_t buffer_bytes, uint64_t capacity,
+                    hwave_design design, const hwave_config* cfg, void* stream) {
+  if (!out || !d_buffer || ((uintptr_t)d_buffer % ALIGN)) return HWAVE_EINVAL;
+  *out = nullptr;
+  hwave_config c;
+  int rc = resolve_config(design, cfg, &c);
+  if (rc) return rc;
+  const KernelSet* ks = find_set(c.kv_bits, design, c.bucket_slots, c.tile);
+  if (!ks) return HWAVE_EUNSUPPORTED;
+  Layout L;
+  rc = layout_of(capacity, design, c, &L);
+  if (rc) return rc;
+  if (buffer_bytes < L.total) return HWAVE_ENOMEM;
+  hwave_table* t = new hwave_table;
+  t->owns = false;
+  rc = init_table(t, d_buffer, L.total, L, design, c, ks, stream);
+  if (rc) {
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return HWAVE_OK;
+}
+
+int hwave_destroy(hwave_table* t) {
+  if (!t) return HWAVE_EINVAL;
+  hipError_t e = hipDeviceSynchronize();
+  int rc = e == hipSuccess ? HWAVE_OK : hip_fail(e);
+  if (t->owns) {
+    e = hipFree(t->base);
+    if (e != hipSuccess && rc == HWAVE_OK) rc = hip_fail(e);
+  }
+  delete t;
+  return rc;
+}
+
+int hwave_clear(hwave_table* t, void* stream) {
+  if (!t) return HWAVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  // Every region size is a multiple of 256 bytes.  Slots and tags: all-ones
+  // (empty); locks and control word: zero.
+  const uint64_t fill_end = (uint64_t)((uint8_t*)t->la.tv.locks - (uint8_t*)t->base);
+  hipLaunchKernelGGL(k_fill16, dim3(stream_grid(fill_end / 16, t->device)), dim3(256), 0, s,
+                     (uint4*)t->base, fill_end / 16, 0xFFFFFFFFu);
+  const uint64_t zero_bytes = t->bytes - fill_end;
+  hipLaunchKernelGGL(k_fill16, dim3(stream_grid(zero_bytes / 16, t->device)), dim3(256), 0, s,
+                     (uint4*)t->la.tv.locks, zero_bytes / 16, 0u);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_insert(hwave_table* t, const void* d_keys, const void* d_vals, uint64_t n, uint8_t* d_status,
+                 void* stream) {
+  return hwave_upsert(t, d_keys, d_vals, n, HWAVE_KEEP, d_status, stream);
+}
+
+int hwave_upsert(hwave_table* t, const void* d_keys, const void* d_vals, uint64_t n, hwave_combine combine,
+                 uint8_t* d_status, void* stream) {
+  if (!t || (int)combine < HWAVE_SUM || (int)combine > HWAVE_MAX) return HWAVE_EINVAL;
+  if (n == 0) return HWAVE_OK;
+  if (bad_ptr(d_keys) || bad_ptr(d_vals)) return HWAVE_EINVAL;
+  hipError_t e = t->ks->upsert(t->la, d_keys, d_vals, n, (int)combine, d_status, (hipStream_t)stream);
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_query(hwave_table* t, const void* d_keys, uint64_t n, void* d_vals_out, uint8_t* d_found,
+                void* stream) {
+  if (!t) return HWAVE_EINVAL;
+  if (n == 0) return HWAVE_OK;
+  if (bad_ptr(d_keys)) return HWAVE_EINVAL;
+  hipError_t e = t->ks->query(t->la, d_keys, n, d_vals_out, d_found, (hipStream_t)stream);
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_erase(hwave_table* t, const void* d_keys, uint64_t n, uint8_t* d_found, void* stream) {
+  if (!t) return HWAVE_EINVAL;
+  if (n == 0) return HWAVE_OK;
+  if (bad_ptr(d_keys)) return HWAVE_EINVAL;
+  hipError_t e = t->ks->erase(t->la, d_keys, n, d_found, (hipStream_t)stream);
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_mixed(hwave_table* t, const uint8_t* d_ops, const void* d_keys, const void* d_vals, uint64_t n,
+                hwave_combine combine, void* d_vals_out, uint8_t* d_status, void* stream) {
+  if (!t || (int)combine < HWAVE_SUM || (int)combine > HWAVE_MAX) return HWAVE_EINVAL;
+  if (n == 0) return HWAVE_OK;
+  if (bad_ptr(d_ops) || bad_ptr(d_keys)) return HWAVE_EINVAL;
+  // Values are read only for inserts/upserts; a batch without them may pass NULL,
+  // in which case the keys array stands in (never dereferenced for other ops).
+  const void* vals = d_vals ? d_vals : d_keys;
+  hipError_t e = t->ks->mixed(t->la, d_ops, d_keys, vals, n, (int)combine, d_vals_out, d_status,
+                              (hipStream_t)stream);
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_size(hwave_table* t, uint64_t* d_count, void* stream) {
+  if (!t || !d_count) return HWAVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_count);
+  const unsigned g = stream_grid(t->capacity, t->device);
+  if (t->cfg.kv_bits == 64)
+    hipLaunchKernelGGL(k_count<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)t->base, t->capacity, d_count);
+  else
+    hipLaunchKernelGGL(k_count<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)t->base, t->capacity, d_count);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_export(hwave_table* t, void* d_keys, void* d_vals, uint64_t* d_count, void* stream) {
+  if (!t || !d_keys || !d_vals || !d_count) return HWAVE_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_count);
+  const unsigned g = stream_grid(t->capacity, t->device);
+  if (t->cfg.kv_bits == 64)
+    hipLaunchKernelGGL(k_export<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)t->base, t->capacity,
+                       (uint64_t*)d_keys, (uint64_t*)d_vals, d_count);
+  else
+    hipLaunchKernelGGL(k_export<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)t->base, t->capacity,
+                       (uint32_t*)d_keys, (uint32_t*)d_vals, d_count);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+uint64_t hwave_num_buckets(const hwave_table* t) { return t ? t->nb : 0; }
+uint64_t hwave_capacity(const hwave_table* t) { return t ? t->capacity : 0; }
+
+int hwave_primary_bucket(hwave_table* t, const void* d_keys, uint64_t n, uint64_t* d_out, void* stream) {
+  if (!t || (n && (!d_keys || !d_out))) return HWAVE_EINVAL;
+  if (n == 0) return HWAVE_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned g = stream_grid(n, t->device);
+  if (t->cfg.kv_bits == 64)
+    hipLaunchKernelGGL(k_primary<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)d_keys, n,
+                       t->la.tv.bucket_mask, d_out);
+  else
+    hipLaunchKernelGGL(k_primary<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)d_keys, n,
+                       t->la.tv.bucket_mask, d_out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_raw(const hwave_table* t, hwave_raw_view* out) {
+  if (!t || !out) return HWAVE_EINVAL;
+  out->slots = t->la.tv.slots;
+  out->tags = (uint16_t*)t->la.tv.tagw;
+  out->locks = t->la.tv.locks;
+  out->n_lock_words = t->n_lock_words;
+  out->num_buckets = t->nb;
+  out->bucket_slots = t->cfg.bucket_slots;
+  out->tile = t->cfg.tile;
+  out->kv_bits = t->cfg.kv_bits;
+  out->design = (uint32_t)t->design;
+  return HWAVE_OK;
+}
+
+const char* hwave_strerror(int code) {
+  switch (code) {
+    case HWAVE_OK: return "ok";
+    case HWAVE_EINVAL: return "invalid argument";
+    case HWAVE_ENOMEM: return "out of device memory or buffer too small";
+    case HWAVE_EDEVICE: return "HIP error (see hwave_last_hip_error)";
+    case HWAVE_EUNSUPPORTED: return "no kernel instance for this configuration";
+  }
+  return "unknown error";
+}
+
+int hwave_last_hip_error(void) { return g_last_hip_error; }
+
+int hwave_stream_sync(void* stream) {
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+}  // extern "C"

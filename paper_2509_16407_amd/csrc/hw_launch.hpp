@@ -1,0 +1,161 @@
+// Bulk kernels and their host launchers, one template instance per
+// (key width, design, bucket slots, tile lanes).
+//
+// Each kernel maps one operation to one tile; tiles of a wave take consecutive
+// operations, so the op-batch reads and status writes are coalesced.  A
+// grid-stride loop keeps the grid near full occupancy for any batch size.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "hw_ops.hpp"
+
+namespace hw {
+
+constexpr int BLOCK = 256;
+
+template <class C>
+__global__ void __launch_bounds__(BLOCK)
+k_upsert(TableDev tv, const typename C::K* __restrict__ keys, const typename C::K* __restrict__ vals,
+         uint64_t n, int combine, uint8_t* __restrict__ status) {
+  using K = typename C::K;
+  const Tile<C::T> tile;
+  const uint64_t stride = (uint64_t)gridDim.x * (BLOCK / C::T);
+  for (uint64_t i = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / C::T; i < n; i += stride) {
+    const K key = keys[i];
+    const K val = vals[i];
+    const uint8_t st = Ops<C>::upsert(tv, tile, key, val, combine);
+    if (status && tile.leader()) status[i] = st;
+  }
+}
+
+template <class C>
+__global__ void __launch_bounds__(BLOCK)
+k_query(TableDev tv, const typename C::K* __restrict__ keys, uint64_t n, typename C::K* __restrict__ out,
+        uint8_t* __restrict__ found) {
+  using K = typename C::K;
+  const Tile<C::T> tile;
+  const uint64_t stride = (uint64_t)gridDim.x * (BLOCK / C::T);
+  for (uint64_t i = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / C::T; i < n; i += stride) {
+    K v;
+    const uint8_t st = Ops<C>::query(tv, tile, keys[i], &v);
+    if (tile.leader()) {
+      if (out) out[i] = v;
+      if (found) found[i] = st;
+    }
+  }
+}
+
+template <class C>
+__global__ void __launch_bounds__(BLOCK)
+k_erase(TableDev tv, const typename C::K* __restrict__ keys, uint64_t n, uint8_t* __restrict__ found) {
+  const Tile<C::T> tile;
+  const uint64_t stride = (uint64_t)gridDim.x * (BLOCK / C::T);
+  for (uint64_t i = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / C::T; i < n; i += stride) {
+    const uint8_t st = Ops<C>::erase(tv, tile, keys[i]);
+    if (found && tile.leader()) found[i] = st;
+  }
+}
+
+// One operation per element, all kinds in one launch (Section 6.5 runs an aging
+// iteration's inserts, queries and deletes concurrently in one kernel).
+template <class C>
+__global__ void __launch_bounds__(BLOCK)
+k_mixed(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __restrict__ keys,
+        const typename C::K* __restrict__ vals, uint64_t n, int combine, typename C::K* __restrict__ out,
+        uint8_t* __restrict__ status) {
+  using K = typename C::K;
+  const Tile<C::T> tile;
+  const uint64_t stride = (uint64_t)gridDim.x * (BLOCK / C::T);
+  for (uint64_t i = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / C::T; i < n; i += stride) {
+    const int op = ops[i];
+    const K key = keys[i];
+    K v = 0;
+    uint8_t st;
+    if (op == OP_QUERY) {
+      st = Ops<C>::query(tv, tile, key, &v);
+    } else if (op == OP_ERASE) {
+      st = Ops<C>::erase(tv, tile, key);
+    } else if (op == OP_INSERT || op == OP_UPSERT) {
+      st = Ops<C>::upsert(tv, tile, key, vals[i], op == OP_INSERT ? C_KEEP : combine);
+    } else {
+      st = ST_INVALID;
+    }
+    if (tile.leader()) {
+      if (out) out[i] = v;
+      if (status) status[i] = st;
+    }
+  }
+}
+
+// Host side ------------------------------------------------------------------
+
+struct LaunchArgs {
+  TableDev tv;
+  unsigned max_blocks;  // grid cap (device-dependent)
+};
+
+inline unsigned grid_for(uint64_t n, int T, unsigned max_blocks) {
+  const uint64_t per_block = BLOCK / T;
+  uint64_t blocks = (n + per_block - 1) / per_block;
+  if (blocks > max_blocks) blocks = max_blocks;
+  return (unsigned)(blocks ? blocks : 1);
+}
+
+typedef hipError_t (*upsert_fn)(const LaunchArgs&, const void*, const void*, uint64_t, int, uint8_t*,
+                                hipStream_t);
+typedef hipError_t (*query_fn)(const LaunchArgs&, const void*, uint64_t, void*, uint8_t*, hipStream_t);
+typedef hipError_t (*erase_fn)(const LaunchArgs&, const void*, uint64_t, uint8_t*, hipStream_t);
+typedef hipError_t (*mixed_fn)(const LaunchArgs&, const uint8_t*, const void*, const void*, uint64_t,
+                               int, void*, uint8_t*, hipStream_t);
+
+struct KernelSet {
+  int kv_bits, design, bucket, tile;
+  upsert_fn upsert;
+  query_fn query;
+  erase_fn erase;
+  mixed_fn mixed;
+};
+
+template <class C>
+struct Launch {
+  using K = typename C::K;
+  static hipError_t upsert(const LaunchArgs& a, const void* keys, const void* vals, uint64_t n,
+                           int combine, uint8_t* status, hipStream_t s) {
+    hipLaunchKernelGGL((k_upsert<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
+                       (const K*)keys, (const K*)vals, n, combine, status);
+    return hipGetLastError();
+  }
+  static hipError_t query(const LaunchArgs& a, const void* keys, uint64_t n, void* out, uint8_t* found,
+                          hipStream_t s) {
+    hipLaunchKernelGGL((k_query<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
+                       (const K*)keys, n, (K*)out, found);
+    return hipGetLastError();
+  }
+  static hipError_t erase(const LaunchArgs& a, const void* keys, uint64_t n, uint8_t* found,
+                          hipStream_t s) {
+    hipLaunchKernelGGL((k_erase<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
+                       (const K*)keys, n, found);
+    return hipGetLastError();
+  }
+  static hipError_t mixed(const LaunchArgs& a, const uint8_t* ops, const void* keys, const void* vals,
+                          uint64_t n, int combine, void* out, uint8_t* status, hipStream_t s) {
+    hipLaunchKernelGGL((k_mixed<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
+                       ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+    return hipGetLastError();
+  }
+};
+
+template <class C>
+constexpr KernelSet make_set() {
+  return KernelSet{(int)sizeof(typename C::K) * 8, C::DESIGN, C::B, C::T, &Launch<C>::upsert,
+                   &Launch<C>::query, &Launch<C>::erase, &Launch<C>::mixed};
+}
+
+// Instance tables, one per translation unit.
+const KernelSet* sets_u64_double(size_t* n);
+const KernelSet* sets_u64_p2(size_t* n);
+const KernelSet* sets_u32_double(size_t* n);
+const KernelSet* sets_u32_p2(size_t* n);
+
+}  // namespace hw

@@ -1,0 +1,503 @@
+// Per-operation device logic of the four open-addressing designs.
+//
+// One operation is carried out by one tile of T lanes (Section 3.2).  Upsert and
+// erase hold the lock bit of the key's primary bucket for their whole critical
+// section (Section 4.1: with associativity above one, two writers of the same
+// key must be serialised or the key can be duplicated).  Query takes no lock
+// (Section 4.2).  A new key's slot is first claimed atomically -- by a
+// compare-and-swap of its key word to the reservation marker, or of its tag in
+// the fingerprint designs (the tag is written first, Section 4.3, Fig. 3) -- then
+// the value is stored and the key is published last.  A reader that matches the
+// key therefore also sees its value.  Keys never move once stored (stability,
+// Section 2.1), which makes the in-place combine of an upsert safe.
+//
+// Probing (Section 2.2):
+//  * double hashing visits buckets b1, b1+s, b1+2s, ... (s odd) and stops at the
+//    first bucket holding an empty slot: the empty pattern never comes back,
+//    because erase leaves a tombstone, so a key is never stored past such a
+//    bucket.  Inserts take the first free (empty or tombstone) slot on the way;
+//  * power-of-two-choice inserts into the less loaded of its two buckets (ties
+//    to the primary), or straight into the primary while that holds fewer than
+//    3/4 of its slots ("shortcutting").  Erase returns slots to empty.
+//
+// Shortcut safety (a reading; the paper is silent): after an erase, a key can sit
+// in its alternate bucket while its primary has dropped below 3/4, and the
+// shortcut would then insert a second copy.  A per-table flag records that an
+// erase has happened; the shortcut is used only while it is clear.  An erase
+// sets it (and waits for the store) before removing anything; an insert reads it
+// after reading the primary bucket, so whoever observes a removal also observes
+// the flag.
+#pragma once
+
+#include "hw_device.hpp"
+
+namespace hw {
+
+enum : uint8_t { ST_MISS = 0, ST_DONE = 1, ST_EXISTED = 2, ST_FULL = 3, ST_INVALID = 4 };
+enum : int { C_SUM = 0, C_KEEP = 1, C_REPLACE = 2, C_MIN = 3, C_MAX = 4 };
+enum : int { OP_QUERY = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_ERASE = 3 };
+enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3 };
+
+// Device view of one table (passed by value to kernels).
+struct TableDev {
+  void* slots;           // (key, value) pairs, bucket-major
+  uint32_t* tagw;        // 16-bit tags viewed as 32-bit words; null without tags
+  uint32_t* locks;       // one bit per bucket
+  uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice)
+  uint32_t bucket_mask;  // buckets - 1 (a power of two minus one)
+  uint32_t probe_cap;    // double hashing: most buckets visited
+  uint32_t shortcut;     // power-of-two-choice shortcut enabled
+  uint32_t pad;
+};
+
+template <typename K_, int DESIGN_, int B_, int T_>
+struct Cfg {
+  using K = K_;
+  static constexpr int DESIGN = DESIGN_;
+  static constexpr bool TAGS = DESIGN == D_DOUBLE_M || DESIGN == D_P2_M;
+  static constexpr bool DOUBLE = DESIGN == D_DOUBLE || DESIGN == D_DOUBLE_M;
+  static constexpr int B = B_;
+  static constexpr int T = T_;
+  static constexpr int SLOT_BYTES = 2 * (int)sizeof(K);
+  static constexpr int SPL = 16 / SLOT_BYTES;   // slots per lane per 16-byte load
+  static constexpr int STEPS = B / (T * SPL);   // slot loads per bucket (no tags)
+  static constexpr int TPL = B / T;             // tags per lane (tag designs)
+  static_assert(TAGS || (B % (T * SPL) == 0 && STEPS >= 1), "bucket must be a multiple of the tile's load");
+  static_assert(!TAGS || TPL == 1 || TPL == 2 || TPL == 4 || TPL == 8 || TPL == 16, "tags per lane");
+};
+
+template <typename K>
+struct BucketScan {
+  int32_t hit;     // slot (within the bucket) holding the key, -1 if none
+  int32_t free;    // first free slot (empty or tombstone), -1 if none
+  uint32_t fill;   // slots not free (valid only when hit < 0)
+  bool has_empty;  // bucket holds an empty slot
+  K val;           // value at `hit`
+};
+
+template <class C>
+struct Ops {
+  using K = typename C::K;
+  static constexpr int B = C::B, T = C::T, SPL = C::SPL, TPL = C::TPL;
+  static constexpr K EMPTY = Keys<K>::EMPTY;
+  static constexpr K TOMB = Keys<K>::TOMB;
+
+  __device__ static __forceinline__ K* key_ptr(const TableDev& tv, uint64_t s) {
+    return (K*)tv.slots + 2 * s;
+  }
+  __device__ static __forceinline__ K* val_ptr(const TableDev& tv, uint64_t s) {
+    return (K*)tv.slots + 2 * s + 1;
+  }
+
+  // Coherent read of one whole slot.
+  __device__ static __forceinline__ void load_slot(const TableDev& tv, uint64_t s, K& k, K& v) {
+    if constexpr (sizeof(K) == 8) {
+      u32x4 w = ld16(key_ptr(tv, s));
+      k = (uint64_t)w.x | ((uint64_t)w.y << 32);
+      v = (uint64_t)w.z | ((uint64_t)w.w << 32);
+    } else {
+      uint64_t w = ld((const uint64_t*)key_ptr(tv, s));
+      k = (uint32_t)w;
+      v = (uint32_t)(w >> 32);
+    }
+  }
+
+  // Sum over the tile of a per-lane count.
+  __device__ static __forceinline__ uint32_t tile_sum(uint32_t x) {
+#pragma unroll
+    for (int o = 1; o < T; o <<= 1) x += __shfl_xor(x, o, 64);
+    return x;
+  }
+
+  // First set bit, in tile order, of per-lane masks of W bits each.
+  template <int W>
+  __device__ static __forceinline__ int32_t first_in_tile(const Tile<T>& tile, uint32_t m) {
+    uint64_t lanes = tile.ballot(m != 0);
+    if (!lanes) return -1;
+    int src = ffs64(lanes);
+    uint32_t mm = tile.bcast(m, src);
+    return src * W + (__ffs(mm) - 1);
+  }
+
+  // ---------------------------------------------------------------- scans
+
+  // Scans bucket b for `key` (FIND) and gathers its free/empty/fill state.
+  // Slot designs read the bucket one tile-width at a time and stop at a hit;
+  // tag designs read the tag bucket once and check each tag match against the
+  // full key (tags are lossy, Section 4.3).
+  template <bool FIND>
+  __device__ static BucketScan<K> scan(const TableDev& tv, const Tile<T>& tile, uint32_t b, K key,
+                                       uint32_t tag) {
+    BucketScan<K> r;
+    r.hit = -1;
+    r.free = -1;
+    r.fill = 0;
+    r.has_empty = false;
+    r.val = 0;
+    const uint64_t base = (uint64_t)b * B;
+    if constexpr (!C::TAGS) {
+      uint32_t occ = 0;
+#pragma unroll 1
+      for (int s = 0; s < C::STEPS; ++s) {
+        const uint64_t first = base + (uint64_t)s * T * SPL + (uint64_t)tile.tl * SPL;
+        K k[SPL], v[SPL];
+        if constexpr (SPL == 1) {
+          load_slot(tv, first, k[0], v[0]);
+        } else {
+          u32x4 w = ld16(key_ptr(tv, first));
+          k[0] = (K)w.x; v[0] = (K)w.y; k[1] = (K)w.z; v[1] = (K)w.w;
+        }
+        uint32_t m_hit = 0, m_free = 0, m_empty = 0;
+#pragma unroll
+        for (int j = 0; j < SPL; ++j) {
+          m_hit |= (uint32_t)(FIND && k[j] == key) << j;
+          m_free |= (uint32_t)(k[j] == EMPTY || k[j] == TOMB) << j;
+          m_empty |= (uint32_t)(k[j] == EMPTY) << j;
+        }
+        if constexpr (FIND) {
+          uint64_t lh = tile.ballot(m_hit != 0);
+          if (lh) {
+            int src = ffs64(lh);
+            uint32_t mm = tile.bcast(m_hit, src);
+            int j = __ffs(mm) - 1;
+            K vv = v[0];
+            if constexpr (SPL == 2) vv = j ? v[1] : v[0];
+            r.val = tile.bcast(vv, src);
+            r.hit = s * T * SPL + src * SPL + j;
+            return r;
+          }
+        }
+        if (r.free < 0) {
+          int32_t f = first_in_tile<SPL>(tile, m_free);
+          if (f >= 0) r.free = s * T * SPL + f;
+        }
+        r.has_empty |= tile.ballot(m_empty != 0) != 0;
+        occ += (uint32_t)__popc(~m_free & ((1u << SPL) - 1));
+      }
+      r.fill = tile_sum(occ);
+    } else {
+      uint32_t tw[(TPL + 1) / 2];
+      const uint32_t* tp = tv.tagw + (base + (uint64_t)tile.tl * TPL) / 2;
+      if constexpr (TPL == 16) {
+        u32x4 a = ld16(tp), c = ld16(tp + 4);
+        tw[0] = a.x; tw[1] = a.y; tw[2] = a.z; tw[3] = a.w;
+        tw[4] = c.x; tw[5] = c.y; tw[6] = c.z; tw[7] = c.w;
+      } else if constexpr (TPL == 8) {
+        u32x4 a = ld16(tp);
+        tw[0] = a.x; tw[1] = a.y; tw[2] = a.z; tw[3] = a.w;
+      } else if constexpr (TPL == 4) {
+        uint64_t a = ld((const uint64_t*)tp);
+        tw[0] = (uint32_t)a; tw[1] = (uint32_t)(a >> 32);
+      } else if constexpr (TPL == 2) {
+        tw[0] = ld(tp);
+      } else {
+        tw[0] = ld((const uint16_t*)tv.tagw + base + tile.tl);
+      }
+      uint32_t m_hit = 0, m_free = 0, m_empty = 0;
+#pragma unroll
+      for (int i = 0; i < TPL; ++i) {
+        uint32_t t = (tw[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+        m_hit |= (uint32_t)(t == tag) << i;
+        m_free |= (uint32_t)(t >= TAG_TOMB) << i;
+        m_empty |= (uint32_t)(t == TAG_EMPTY) << i;
+      }
+      if constexpr (FIND) {
+        uint64_t lanes = tile.ballot(m_hit != 0);
+        while (lanes) {
+          int src = ffs64(lanes);
+          lanes &= lanes - 1;
+          uint32_t mm = tile.bcast(m_hit, src);
+          while (mm) {
+            int j = __ffs(mm) - 1;
+            mm &= mm - 1;
+            K k, v;
+            load_slot(tv, base + src * TPL + j, k, v);
+            if (k == key) {
+              r.hit = src * TPL + j;
+              r.val = v;
+              return r;
+            }
+          }
+        }
+      }
+      r.free = first_in_tile<TPL>(tile, m_free);
+      r.has_empty = tile.ballot(m_empty != 0) != 0;
+      constexpr uint32_t lane_bits = TPL == 32 ? 0xFFFFFFFFu : ((1u << TPL) - 1);
+      r.fill = tile_sum((uint32_t)__popc(~m_free & lane_bits));
+    }
+    return r;
+  }
+
+  // ---------------------------------------------------------------- writes
+
+  // Claims slot s for a new key and publishes (key, value).  Leader lane only
+  // touches memory; the result is broadcast.
+  __device__ static bool claim(const TableDev& tv, const Tile<T>& tile, uint64_t s, K key, K val,
+                               uint32_t tag) {
+    bool ok = false;
+    if (tile.leader()) {
+      if constexpr (C::TAGS) {
+        uint32_t* wp = tv.tagw + (s >> 1);
+        const uint32_t sh = (uint32_t)(s & 1) * 16;
+        uint32_t cur = ld(wp);
+        while (((cur >> sh) & 0xFFFFu) >= TAG_TOMB) {
+          uint32_t want = (cur & ~(0xFFFFu << sh)) | (tag << sh);
+          uint32_t old = cas(wp, cur, want);
+          if (old == cur) { ok = true; break; }
+          cur = old;
+        }
+        if (ok) {
+          if constexpr (sizeof(K) == 8) {
+            st(val_ptr(tv, s), val);
+            wait_mem();
+            st(key_ptr(tv, s), key);
+          } else {
+            st((uint64_t*)key_ptr(tv, s), (uint64_t)key | ((uint64_t)val << 32));
+          }
+        }
+      } else if constexpr (sizeof(K) == 8) {
+        K* kp = key_ptr(tv, s);
+        K cur = EMPTY;
+        for (int a = 0; a < 2; ++a) {
+          K old = cas(kp, cur, (K)Keys<K>::RESERVED);
+          if (old == cur) { ok = true; break; }
+          if (old != TOMB) break;
+          cur = TOMB;
+        }
+        if (ok) {
+          st(val_ptr(tv, s), val);
+          wait_mem();
+          st(kp, key);
+        }
+      } else {
+        uint64_t* sp = (uint64_t*)key_ptr(tv, s);
+        uint64_t cur = ld(sp);
+        const uint64_t want = (uint64_t)key | ((uint64_t)val << 32);
+        while ((K)cur == EMPTY || (K)cur == TOMB) {
+          uint64_t old = cas(sp, cur, want);
+          if (old == cur) { ok = true; break; }
+          cur = old;
+        }
+      }
+    }
+    return tile.bcast((uint32_t)ok, 0) != 0;
+  }
+
+  // Upsert callback applied to a present key (Section 5.1).
+  __device__ static void combine_at(const TableDev& tv, const Tile<T>& tile, uint64_t s, K val,
+                                    int combine) {
+    if (tile.leader()) {
+      K* vp = val_ptr(tv, s);
+      switch (combine) {
+        case C_SUM: __hip_atomic_fetch_add(vp, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+        case C_REPLACE: st(vp, val); break;
+        case C_MIN: __hip_atomic_fetch_min(vp, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+        case C_MAX: __hip_atomic_fetch_max(vp, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); break;
+        default: break;
+      }
+    }
+  }
+
+  // Removes the key in slot s: the key word first (the linearisation point),
+  // then, once that store has completed, the tag (a reading; the paper does not
+  // state the erase order).
+  __device__ static void remove(const TableDev& tv, const Tile<T>& tile, uint64_t s, uint32_t tag) {
+    if (tile.leader()) {
+      st(key_ptr(tv, s), C::DOUBLE ? TOMB : EMPTY);
+      if constexpr (C::TAGS) {
+        wait_mem();
+        uint32_t* wp = tv.tagw + (s >> 1);
+        const uint32_t sh = (uint32_t)(s & 1) * 16;
+        if constexpr (C::DOUBLE) {
+          __hip_atomic_fetch_xor(wp, (tag ^ TAG_TOMB) << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          __hip_atomic_fetch_or(wp, 0xFFFFu << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+  }
+
+  // Claims the first free slot of bucket b, rescanning after lost races.
+  // Returns the slot or -1 when the bucket is full.
+  __device__ static int64_t claim_in_bucket(const TableDev& tv, const Tile<T>& tile, uint32_t b,
+                                            int32_t free_hint, K key, K val, uint32_t tag) {
+    int32_t f = free_hint;
+    while (f >= 0) {
+      const uint64_t s = (uint64_t)b * B + f;
+      if (claim(tv, tile, s, key, val, tag)) return (int64_t)s;
+      f = scan<false>(tv, tile, b, key, tag).free;
+    }
+    return -1;
+  }
+
+  // ---------------------------------------------------------------- operations
+
+  __device__ static __forceinline__ uint32_t step_of(const TableDev& tv, const Hashed& h) {
+    return (h.h2 & tv.bucket_mask) | 1u;
+  }
+
+  // Upsert: lock primary, find or insert, unlock.  Status per hwave.h.
+  __device__ static uint8_t upsert(const TableDev& tv, const Tile<T>& tile, K key, K val,
+                                   int combine) {
+    if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
+    const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
+    const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
+    uint8_t status = ST_FULL;
+    bool pending = true;
+    while (pending) {
+      if (try_lock(tv.locks, h.b1, tile)) {
+        if constexpr (C::DOUBLE)
+          status = upsert_double_locked(tv, tile, h, key, val, tag, combine);
+        else
+          status = upsert_p2_locked(tv, tile, h, key, val, tag, combine);
+        unlock(tv.locks, h.b1, tile);
+        pending = false;
+      }
+    }
+    return status;
+  }
+
+  __device__ static uint8_t upsert_double_locked(const TableDev& tv, const Tile<T>& tile,
+                                                 const Hashed& h, K key, K val, uint32_t tag,
+                                                 int combine) {
+    const uint32_t step = step_of(tv, h);
+    int64_t free_slot = -1;
+    uint32_t free_i = 0, free_b = 0;
+    uint32_t b = h.b1;
+    for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
+      BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
+      if (r.hit >= 0) {
+        combine_at(tv, tile, (uint64_t)b * B + r.hit, val, combine);
+        return ST_EXISTED;
+      }
+      if (free_slot < 0 && r.free >= 0) {
+        free_slot = (uint64_t)b * B + r.free;
+        free_i = i;
+        free_b = b;
+      }
+      if (r.has_empty) break;
+    }
+    // Absent: claim the first free slot met, moving on along the sequence when
+    // other writers take the free slots first.
+    if (free_slot < 0) return ST_FULL;
+    int32_t f = (int32_t)(free_slot - (uint64_t)free_b * B);
+    b = free_b;
+    for (uint32_t i = free_i; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
+      if (i != free_i) f = scan<false>(tv, tile, b, key, tag).free;
+      if (claim_in_bucket(tv, tile, b, f, key, val, tag) >= 0) return ST_DONE;
+    }
+    return ST_FULL;
+  }
+
+  __device__ static uint8_t upsert_p2_locked(const TableDev& tv, const Tile<T>& tile,
+                                             const Hashed& h, K key, K val, uint32_t tag,
+                                             int combine) {
+    const uint32_t b1 = h.b1;
+    const uint32_t b2 = h.h2 & tv.bucket_mask;
+    BucketScan<K> r1 = scan<true>(tv, tile, b1, key, tag);
+    if (r1.hit >= 0) {
+      combine_at(tv, tile, (uint64_t)b1 * B + r1.hit, val, combine);
+      return ST_EXISTED;
+    }
+    if (tv.shortcut && 4 * r1.fill < 3 * (uint32_t)B) {
+      uint32_t erased = tile.leader() ? ld(tv.ctrl) : 0u;
+      if (tile.bcast(erased, 0) == 0) {
+        if (claim_in_bucket(tv, tile, b1, r1.free, key, val, tag) >= 0) return ST_DONE;
+        r1 = scan<false>(tv, tile, b1, key, tag);  // filled up meanwhile: full path
+      }
+    }
+    if (b2 == b1) {
+      return claim_in_bucket(tv, tile, b1, r1.free, key, val, tag) >= 0 ? ST_DONE : ST_FULL;
+    }
+    BucketScan<K> r2 = scan<true>(tv, tile, b2, key, tag);
+    if (r2.hit >= 0) {
+      combine_at(tv, tile, (uint64_t)b2 * B + r2.hit, val, combine);
+      return ST_EXISTED;
+    }
+    const bool alt_first = r2.fill < r1.fill;
+    const uint32_t bf = alt_first ? b2 : b1, bs = alt_first ? b1 : b2;
+    const int32_t ff = alt_first ? r2.free : r1.free, fs = alt_first ? r1.free : r2.free;
+    if (claim_in_bucket(tv, tile, bf, ff, key, val, tag) >= 0) return ST_DONE;
+    if (claim_in_bucket(tv, tile, bs, fs, key, val, tag) >= 0) return ST_DONE;
+    return ST_FULL;
+  }
+
+  // Lock-free query (Section 4.2).  Returns ST_DONE/ST_MISS/ST_INVALID, value in *out.
+  __device__ static uint8_t query(const TableDev& tv, const Tile<T>& tile, K key, K* out) {
+    *out = 0;
+    if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
+    const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
+    const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
+    if constexpr (C::DOUBLE) {
+      const uint32_t step = step_of(tv, h);
+      uint32_t b = h.b1;
+      for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
+        BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
+        if (r.hit >= 0) { *out = r.val; return ST_DONE; }
+        if (r.has_empty) break;
+      }
+      return ST_MISS;
+    } else {
+      BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
+      if (r.hit >= 0) { *out = r.val; return ST_DONE; }
+      const uint32_t b2 = h.h2 & tv.bucket_mask;
+      if (b2 != h.b1) {
+        r = scan<true>(tv, tile, b2, key, tag);
+        if (r.hit >= 0) { *out = r.val; return ST_DONE; }
+      }
+      return ST_MISS;
+    }
+  }
+
+  // Erase under the primary lock.  ST_DONE if removed, ST_MISS if absent.
+  __device__ static uint8_t erase(const TableDev& tv, const Tile<T>& tile, K key) {
+    if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
+    const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
+    const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
+    if constexpr (!C::DOUBLE) {
+      if (tile.leader() && ld(tv.ctrl) == 0) {
+        st(tv.ctrl, 1u);
+        wait_mem();
+      }
+    }
+    uint8_t status = ST_MISS;
+    bool pending = true;
+    while (pending) {
+      if (try_lock(tv.locks, h.b1, tile)) {
+        if constexpr (C::DOUBLE) {
+          const uint32_t step = step_of(tv, h);
+          uint32_t b = h.b1;
+          for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
+            BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
+            if (r.hit >= 0) {
+              remove(tv, tile, (uint64_t)b * B + r.hit, tag);
+              status = ST_DONE;
+              break;
+            }
+            if (r.has_empty) break;
+          }
+        } else {
+          BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
+          if (r.hit >= 0) {
+            remove(tv, tile, (uint64_t)h.b1 * B + r.hit, tag);
+            status = ST_DONE;
+          } else {
+            const uint32_t b2 = h.h2 & tv.bucket_mask;
+            if (b2 != h.b1) {
+              r = scan<true>(tv, tile, b2, key, tag);
+              if (r.hit >= 0) {
+                remove(tv, tile, (uint64_t)b2 * B + r.hit, tag);
+                status = ST_DONE;
+              }
+            }
+          }
+        }
+        unlock(tv.locks, h.b1, tile);
+        pending = false;
+      }
+    }
+    return status;
+  }
+};
+
+}  // namespace hw

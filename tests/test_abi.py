@@ -1,0 +1,79 @@
+"""The C-ABI library (CPU only): it loads, exports every function the header
+declares, and its host-only calls (sizes, defaults, error text) behave.  No
+kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2509_16407_amd as hw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hashwave.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hwave_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    so = ctypes.CDLL(hw.LIB_PATH)
+    missing = [n for n in names if not hasattr(so, n)]
+    assert not missing, missing
+
+
+def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0):
+    c = hw._Config(kv_bits, bucket, tile, 0, 0)
+    b = ctypes.c_uint64()
+    rc = hw.lib().hwave_table_bytes(capacity, design, ctypes.byref(c), ctypes.byref(b))
+    return rc, b.value
+
+
+@pytest.mark.parametrize("design,per_slot", [(0, 16), (1, 18), (2, 16), (3, 18)])
+def test_space_per_slot_matches_section_6_1(design, per_slot):
+    """16 bytes per key-value slot, plus 2 bytes of tag in the metadata designs;
+    lock bits and the control word add < 0.01 byte per slot at 2^28 slots."""
+    rc, b = _bytes(1 << 28, design)
+    assert rc == 0
+    assert abs(b / (1 << 28) - per_slot) < 0.02
+
+
+def test_capacity_rounds_up_to_power_of_two_buckets():
+    rc, b1 = _bytes(1000, 0)
+    rc2, b2 = _bytes(1024, 0)
+    assert rc == rc2 == 0 and b1 == b2  # 1000 slots -> 128 buckets of 8
+    rc3, b3 = _bytes(1025, 0)
+    assert b3 > b2
+
+
+def test_bad_arguments_rejected_on_host():
+    L = hw.lib()
+    assert _bytes(0, 0)[0] == -1                      # capacity 0
+    assert _bytes(1024, 7)[0] == -1                   # no such design
+    assert _bytes(1024, 0, kv_bits=16)[0] == -1       # key width
+    assert _bytes(1024, 0, bucket=8, tile=16)[0] == -4  # no kernel instance
+    assert L.hwave_table_bytes(1024, 0, None, None) == -1
+    c = hw._Config()
+    assert L.hwave_config_default(9, ctypes.byref(c)) == -1
+    assert L.hwave_config_default(3, ctypes.byref(c)) == 0
+    assert (c.kv_bits, c.bucket_slots, c.tile) == (64, 32, 4)
+    assert L.hwave_num_buckets(None) == 0 and L.hwave_capacity(None) == 0
+    assert L.hwave_destroy(None) == -1
+    for code in (0, -1, -2, -3, -4):
+        assert L.hwave_strerror(code)
+
+
+def test_paper_default_configurations():
+    """Section 5: double hashing bucket 8 / tile 8; its metadata variant bucket 32 /
+    tile 4; power-of-two-choice bucket 32 / tile 8; its metadata variant 32 / 4."""
+    L = hw.lib()
+    expect = {0: (8, 8), 1: (32, 4), 2: (32, 8), 3: (32, 4)}
+    for d, (b, t) in expect.items():
+        c = hw._Config()
+        assert L.hwave_config_default(d, ctypes.byref(c)) == 0
+        assert (c.bucket_slots, c.tile) == (b, t)

@@ -1,0 +1,290 @@
+"""GPU parity: every HIP-path result against the CPU oracle, element by element.
+
+Batches are built so that every compared output is the same under any
+serialisation of the concurrent batch (distinct keys per insert/erase batch,
+equal values for duplicate inserts, commutative sums for duplicate upserts);
+where the order decides a status among duplicates, per-key counts are compared.
+Sizes span many tiles with a ragged tail.  Every test also runs the oracle's
+layout checker on the raw table image (no duplicate key, every key in a
+candidate bucket, tags consistent, no reservation marker, all locks released).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_16407_amd as hw
+from paper_2509_16407_amd import workloads as w
+from gpu_util import dev, host, image, per_key_counts, u8
+
+pytestmark = pytest.mark.gpu
+
+ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M}
+
+
+def check_layout(t, neg_keys=None, tile_bytes=None):
+    slots, tags, locks = image(t)
+    tb = tile_bytes or (t.tile * 16)
+    nv, rep = oracle.layout_check(ODESIGN[t.design], t.kv_bits, t.num_buckets, t.bucket_slots,
+                                  slots, tags, locks, neg_keys=neg_keys, tile_bytes=tb)
+    assert nv == 0, rep
+    return rep
+
+
+def p2_full_is_genuine(t, full_keys):
+    """Power-of-two-choice reports FULL only when both candidate buckets are full
+    (checked on the final image of an insert-only table)."""
+    slots, tags, _ = image(t)
+    if t.kv_bits == 64:
+        kw = slots.view(np.uint64)[0::2]
+        free = kw >= np.uint64((1 << 64) - 2)
+    else:
+        kw = slots.view(np.uint32)[0::2]
+        free = kw >= np.uint32(0xFFFFFFFE)
+    occ = (~free).reshape(t.num_buckets, t.bucket_slots).sum(axis=1)
+    for k in np.unique(full_keys).tolist():
+        b1 = oracle.primary_bucket(k, t.num_buckets)
+        b2 = oracle.p2_alternate(k, t.num_buckets)
+        assert occ[b1] == t.bucket_slots and occ[b2] == t.bucket_slots, (k, occ[b1], occ[b2])
+
+
+def check_dump(t, om):
+    k, v = t.export()
+    k, v = host(k, t.kv_bits), host(v, t.kv_bits)
+    order = np.argsort(k)
+    ok, ov = om.dump()
+    assert len(k) == len(ok)
+    assert np.array_equal(k[order], ok)
+    assert np.array_equal(v[order], ov)
+    assert t.size() == len(ok)
+
+
+# ------------------------------------------------------------------ load benchmark (config 1)
+
+def test_config1_double_hashing_2p20():
+    """2^20-slot double hashing, bucket 8: insert 943,718 keys (v = 3k+1), query them
+    and 943,718 absent keys; all outputs, the dump and the layout against the oracle."""
+    d = w.load_then_query(1 << 20, 0.9, config_id=1)
+    t = hw.Table(1 << 20, "DOUBLE")
+    assert t.capacity == 1 << 20 and t.num_buckets == 1 << 17
+    om = oracle.OracleMap()
+    st = u8(t.insert(dev(d["keys"]), dev(d["vals"])))
+    assert np.array_equal(st, om.insert(d["keys"], d["vals"]))
+    found, vals = t.query(dev(d["qkeys"]))
+    ost, oval = om.query(d["qkeys"])
+    assert np.array_equal(u8(found), ost)
+    assert np.array_equal(host(vals), oval)
+    check_dump(t, om)
+    neg = d["qkeys"][~d["expect_found"]][:100000]
+    rep = check_layout(t, neg_keys=neg)
+    # Table 1 (load probes, query): 1.22 unique lines per positive query
+    assert abs(rep["pos_probe_sum"] / rep["live"] - 1.22) < 0.02
+
+
+# ------------------------------------------------------------------ every design, all ops
+
+CASES = [
+    ("DOUBLE", 64, 8, 8), ("DOUBLE", 64, 8, 4), ("DOUBLE", 64, 16, 8), ("DOUBLE", 64, 32, 16),
+    ("DOUBLE_M", 64, 32, 4), ("DOUBLE_M", 64, 32, 8), ("DOUBLE_M", 64, 16, 4), ("DOUBLE_M", 64, 64, 8),
+    ("P2", 64, 32, 8), ("P2", 64, 32, 4), ("P2", 64, 32, 32), ("P2", 64, 16, 8),
+    ("P2_M", 64, 32, 4), ("P2_M", 64, 32, 8), ("P2_M", 64, 32, 16), ("P2_M", 64, 64, 8),
+    ("DOUBLE", 32, 16, 8), ("DOUBLE_M", 32, 32, 4), ("P2", 32, 32, 8), ("P2_M", 32, 32, 4),
+    ("P2_M", 32, 32, 32), ("DOUBLE", 32, 64, 32),
+]
+
+
+@pytest.mark.parametrize("design,bits,bucket,tile", CASES,
+                         ids=["%s-u%d-b%d-t%d" % c for c in CASES])
+def test_all_ops_against_oracle(design, bits, bucket, tile):
+    cap = 1 << 16
+    t = hw.Table(cap, design, kv_bits=bits, bucket=bucket, tile=tile)
+    assert t.capacity == cap
+    om = oracle.OracleMap(key_bits=bits)
+    seed = w.stream_seed(100 + ODESIGN[design], bits * 1000 + bucket * 10 + tile)
+    pool = w.distinct_keys(seed, int(1.3 * cap), key_bits=bits)
+    absent = w.distinct_keys(seed, 20000, key_bits=bits, skip=len(pool))
+    vals_of = lambda k: w.value_of(k, bits)
+    # (a) first load: 0.55 of capacity, ragged batch size
+    n1 = int(0.55 * cap) + 7
+    k1 = pool[:n1]
+    st = u8(t.insert(dev(k1, bits), dev(vals_of(k1), bits)))
+    assert np.array_equal(st, om.insert(k1, vals_of(k1)))
+    # (b) insert again: half present (EXISTED, value kept), half new
+    k2 = np.concatenate([pool[: n1 // 2], pool[n1: n1 + 9001]])
+    v2 = vals_of(k2) ^ np.uint64(1)  # present keys must keep their old value
+    perm = w.permutation(seed + 1, len(k2))
+    k2, v2 = k2[perm], v2[perm]
+    st = u8(t.insert(dev(k2, bits), dev(v2, bits)))
+    assert np.array_equal(st, om.insert(k2, v2))
+    # (c) queries: present and absent, shuffled
+    q = np.concatenate([pool[: n1 + 9001: 3], absent])
+    q = q[w.permutation(seed + 2, len(q))]
+    f, v = t.query(dev(q, bits))
+    of, ov = om.query(q)
+    assert np.array_equal(u8(f), of) and np.array_equal(host(v, bits), ov)
+    # (d) SUM upserts with duplicates: existing keys and new keys, each 1-3 times
+    base = np.concatenate([pool[1000:4000], pool[n1 + 9001: n1 + 12001]])
+    reps = w.uniform_below(seed + 3, 0, len(base), 3) + 1
+    ku = np.repeat(base, reps)
+    vu = w.splitmix64(seed + 4, 0, len(ku))
+    if bits == 32:
+        vu &= np.uint64(0xFFFFFFFF)
+    p = w.permutation(seed + 5, len(ku))
+    ku, vu = ku[p], vu[p]
+    st = u8(t.upsert(dev(ku, bits), dev(vu, bits), combine="sum"))
+    ost = om.upsert(ku, vu)
+    # who inserts among duplicates of a new key is racy: compare per-key counts
+    assert per_key_counts(ku, st, 1) == per_key_counts(ku, ost, 1)
+    assert per_key_counts(ku, st, 2) == per_key_counts(ku, ost, 2)
+    assert not np.isin(st, [3, 4]).any()
+    # (e) erase: distinct keys, some absent
+    ke = np.concatenate([pool[2000:2000 + 15000:2], absent[:3000]])
+    ke = ke[w.permutation(seed + 6, len(ke))]
+    st = u8(t.erase(dev(ke, bits)))
+    assert np.array_equal(st, om.erase(ke))
+    # (f) refill past the first load (reuses freed slots), then re-query everything
+    lim = 0.8 if design.startswith("P2") else 0.9
+    n_more = int(lim * cap) - om.size()
+    k3 = pool[n1 + 12001: n1 + 12001 + n_more]
+    st = u8(t.insert(dev(k3, bits), dev(vals_of(k3), bits)))
+    assert np.array_equal(st, om.insert(k3, vals_of(k3)))
+    q = np.concatenate([pool, absent])
+    f, v = t.query(dev(q, bits))
+    of, ov = om.query(q)
+    assert np.array_equal(u8(f), of) and np.array_equal(host(v, bits), ov)
+    # (g) other combines on present keys (distinct keys per batch)
+    for comb, code in (("replace", oracle.REPLACE), ("min", oracle.MIN), ("max", oracle.MAX),
+                       ("keep", oracle.KEEP)):
+        kc = pool[5000:9000]
+        vc = w.splitmix64(seed + 10 + code, 0, len(kc))
+        if bits == 32:
+            vc &= np.uint64(0xFFFFFFFF)
+        st = u8(t.upsert(dev(kc, bits), dev(vc, bits), combine=comb))
+        assert np.array_equal(st, om.upsert(kc, vc, combine=code))
+    check_dump(t, om)
+    check_layout(t)
+
+
+# ------------------------------------------------------------------ mixed batches (config 3 shape)
+
+@pytest.mark.parametrize("design", ["DOUBLE_M", "P2_M", "DOUBLE", "P2"])
+def test_mixed_batches_against_oracle(design):
+    """Preload a 2^k-key universe to load 0.5, then mixed batches (50% query, 30% SUM
+    upsert, 20% erase, Zipf 0.99 keys; erase and upsert keys disjoint, queries avoid
+    both): query outputs, erase flags, per-key upsert statuses and the dump after
+    every batch match the oracle."""
+    cap = 1 << 18
+    universe = cap // 2
+    t = hw.Table(cap, design)
+    om = oracle.OracleMap()
+    uk = w.universe_keys(universe, config_id=3)
+    st = u8(t.insert(dev(uk), dev(w.value_of(uk))))
+    assert np.array_equal(st, om.insert(uk, w.value_of(uk)))
+    for b in w.mixed_batches(universe, 1 << 15, 4, config_id=3):
+        ops = b["ops"]
+        import torch
+        s, v = t.mixed(torch.from_numpy(ops).cuda(), dev(b["keys"]), dev(b["vals"]), combine="sum")
+        s, v = u8(s), host(v)
+        os_, ov = om.apply(b["keys"], b["vals"], ops=ops, combine=oracle.SUM)
+        det = ops != 2  # query and erase outputs are serialisation-independent
+        assert np.array_equal(s[det], os_[det])
+        assert np.array_equal(v[det], ov[det])
+        up = ops == 2
+        assert per_key_counts(b["keys"][up], s[up], 1) == per_key_counts(b["keys"][up], os_[up], 1)
+        assert per_key_counts(b["keys"][up], s[up], 2) == per_key_counts(b["keys"][up], os_[up], 2)
+        check_dump(t, om)
+    check_layout(t)
+
+
+# ------------------------------------------------------------------ 32-bit group-by (config 4 shape)
+
+@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+@pytest.mark.parametrize("logcap", [10, 14, 17])
+def test_u32_groupby_sum(design, logcap):
+    """Group-by hash aggregation: D = 0.85 * capacity distinct uint32 keys, each upserted
+    once plus D extra uniform repeats; result = wrapping sums per key.  In tiny
+    power-of-two-choice tables a key may find both buckets full: that FULL is
+    accepted only when the final image shows both buckets full."""
+    cap = 1 << logcap
+    t = hw.Table(cap, design, kv_bits=32)
+    cap = t.capacity
+    D = int(0.85 * cap)
+    seed = w.stream_seed(4, logcap * 8 + ODESIGN[design])
+    keys = w.distinct_keys(seed, D, key_bits=32)
+    extra = keys[w.uniform_below(seed + 1, 0, D, D)]
+    ops_k = np.concatenate([keys, extra])
+    ops_k = ops_k[w.permutation(seed + 2, len(ops_k))]
+    ops_v = w.splitmix64(seed + 3, 0, len(ops_k)) & np.uint64(0xFFFFFFFF)
+    st = u8(t.upsert(dev(ops_k, 32), dev(ops_v, 32), combine="sum"))
+    full = st == hw.ST_FULL
+    if full.any():
+        assert design.startswith("P2"), "double hashing reported FULL below capacity"
+        p2_full_is_genuine(t, ops_k[full])
+        # a key that never got in is absent from the table: drop all its ops
+        lost = np.setdiff1d(ops_k[full], ops_k[st == hw.ST_DONE])
+        keep = ~np.isin(ops_k, lost)
+        keep &= ~full
+        ops_k, ops_v, st = ops_k[keep], ops_v[keep], st[keep]
+    om = oracle.OracleMap(key_bits=32)
+    ost = om.upsert(ops_k, ops_v)
+    assert per_key_counts(ops_k, st, 1) == per_key_counts(ops_k, ost, 1)
+    check_dump(t, om)
+    check_layout(t)
+
+
+# ------------------------------------------------------------------ edge cases
+
+@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+def test_sentinels_and_empty_batches(design):
+    import torch
+    t = hw.Table(1 << 12, design)
+    top = (1 << 64) - 1
+    bad = np.array([top, top - 1, top - 2], np.uint64)
+    st = u8(t.insert(dev(bad), dev(bad)))
+    assert (st == hw.ST_INVALID).all()
+    f, v = t.query(dev(bad))
+    assert (u8(f) == hw.ST_INVALID).all() and (host(v) == 0).all()
+    assert (u8(t.erase(dev(bad))) == hw.ST_INVALID).all()
+    assert (u8(t.upsert(dev(bad), dev(bad))) == hw.ST_INVALID).all()
+    assert t.size() == 0
+    ok = np.array([top - 3, 0, 1], np.uint64)
+    assert (u8(t.insert(dev(ok), dev(ok))) == hw.ST_DONE).all()
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    t.insert(e, e)
+    t.query(e)
+    t.erase(e)
+    t.upsert(e, e)
+    assert t.size() == 3
+    check_layout(t)
+
+
+@pytest.mark.parametrize("design,bucket", [("DOUBLE", 8), ("DOUBLE_M", 32)])
+def test_double_hashing_fills_every_slot(design, bucket):
+    """Double hashing visits every bucket, so FULL happens exactly when all
+    capacity slots hold keys: 1100 distinct inserts into 1024 slots give 1024
+    inserted and 76 FULL; after erasing one key, one more insert succeeds."""
+    t = hw.Table(1024, design)
+    keys = w.distinct_keys(77, 1100)
+    st = u8(t.insert(dev(keys), dev(w.value_of(keys))))
+    assert (st == hw.ST_DONE).sum() == 1024 and (st == hw.ST_FULL).sum() == 76
+    inserted = keys[st == hw.ST_DONE]
+    om = oracle.OracleMap(capacity=1024)
+    om.insert(inserted, w.value_of(inserted))
+    check_dump(t, om)
+    rep = check_layout(t)
+    assert rep["live"] == 1024 and rep["empties"] == 0
+    full = keys[st == hw.ST_FULL]
+    assert (u8(t.erase(dev(inserted[:1]))) == hw.ST_DONE).all()
+    st2 = u8(t.insert(dev(full[:2]), dev(w.value_of(full[:2]))))
+    assert sorted(st2.tolist()) == [hw.ST_DONE, hw.ST_FULL]
+    check_layout(t)
+
+
+def test_primary_bucket_hook_matches_oracle():
+    """The adversarial benchmark's device hook (Section 4.1) agrees with the oracle's
+    independent restatement of the hash rule."""
+    t = hw.Table(1 << 20, "P2_M")
+    keys = w.distinct_keys(5, 10000)
+    got = t.primary_bucket(dev(keys)).cpu().numpy()
+    exp = np.array([oracle.primary_bucket(int(k), t.num_buckets) for k in keys[:2000]])
+    assert np.array_equal(got[:2000], exp)
+    assert got.max() < t.num_buckets
