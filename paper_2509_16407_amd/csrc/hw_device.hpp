@@ -121,6 +121,19 @@ __device__ __forceinline__ u32x4 ld16(const void* p) {
   return r;
 }
 
+// 16-byte agent-coherent store (one global_store_dwordx4 with the sc1 policy):
+// publishes a whole (key, value) slot in one request, the counterpart of the
+// paper's 128-bit release store (Section 4.2).  Completion is awaited by the
+// caller's next wait_mem().
+__device__ __forceinline__ void st16(void* p, uint64_t lo, uint64_t hi) {
+  u32x4 v;
+  v.x = (uint32_t)lo;
+  v.y = (uint32_t)(lo >> 32);
+  v.z = (uint32_t)hi;
+  v.w = (uint32_t)(hi >> 32);
+  asm volatile("global_store_dwordx4 %0, %1, off sc1" : : "v"(p), "v"(v) : "memory");
+}
+
 template <typename X>
 __device__ __forceinline__ X ld(const X* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -156,6 +169,18 @@ __device__ __forceinline__ bool try_lock(uint32_t* locks, uint32_t b, const Tile
   old = tile.bcast(old, 0);
   return (old & bit) == 0;
 }
+
+// Backoff between failed lock attempts.  Waiting tiles re-issue their atomic
+// only after a pause that doubles up to ~55 us (256 x 512 cycles): with many
+// thousands of tiles waiting on one bucket (a hot key), back-to-back atomics on
+// the lock word would queue the holder's unlock behind all of them.
+struct Backoff {
+  uint32_t n = 0;
+  __device__ __forceinline__ void pause() {
+    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(8);
+  }
+  __device__ __forceinline__ void grow() { n = n ? (n < 256 ? 2 * n : 256) : 1; }
+};
 
 // Releases bucket b after every write of the critical section has completed.
 template <int T>

@@ -68,11 +68,14 @@ struct Cfg {
 
 template <typename K>
 struct BucketScan {
-  int32_t hit;     // slot (within the bucket) holding the key, -1 if none
-  int32_t free;    // first free slot (empty or tombstone), -1 if none
-  uint32_t fill;   // slots not free (valid only when hit < 0)
-  bool has_empty;  // bucket holds an empty slot
-  K val;           // value at `hit`
+  int32_t hit;         // slot (within the bucket) holding the key, -1 if none
+  int32_t free;        // first free slot (empty or tombstone), -1 if none
+  uint32_t fill;       // slots not free (valid only when hit < 0)
+  bool has_empty;      // bucket holds an empty slot
+  K val;               // value at `hit`
+  uint64_t free_word;  // as read: the free slot's tag word (tag designs), its key
+                       // (64-bit slots) or its whole slot (32-bit slots); the
+                       // expected value of the claiming compare-and-swap
 };
 
 template <class C>
@@ -109,16 +112,6 @@ struct Ops {
     return x;
   }
 
-  // First set bit, in tile order, of per-lane masks of W bits each.
-  template <int W>
-  __device__ static __forceinline__ int32_t first_in_tile(const Tile<T>& tile, uint32_t m) {
-    uint64_t lanes = tile.ballot(m != 0);
-    if (!lanes) return -1;
-    int src = ffs64(lanes);
-    uint32_t mm = tile.bcast(m, src);
-    return src * W + (__ffs(mm) - 1);
-  }
-
   // ---------------------------------------------------------------- scans
 
   // Scans bucket b for `key` (FIND) and gathers its free/empty/fill state.
@@ -134,6 +127,7 @@ struct Ops {
     r.fill = 0;
     r.has_empty = false;
     r.val = 0;
+    r.free_word = 0;
     const uint64_t base = (uint64_t)b * B;
     if constexpr (!C::TAGS) {
       uint32_t occ = 0;
@@ -168,8 +162,16 @@ struct Ops {
           }
         }
         if (r.free < 0) {
-          int32_t f = first_in_tile<SPL>(tile, m_free);
-          if (f >= 0) r.free = s * T * SPL + f;
+          uint64_t lanes = tile.ballot(m_free != 0);
+          if (lanes) {
+            int src = ffs64(lanes);
+            int j = __ffs(tile.bcast(m_free, src)) - 1;
+            uint64_t word;
+            if constexpr (SPL == 1) word = (uint64_t)k[0];
+            else word = j ? ((uint64_t)k[1] | ((uint64_t)v[1] << 32)) : ((uint64_t)k[0] | ((uint64_t)v[0] << 32));
+            r.free_word = tile.bcast(word, src);
+            r.free = s * T * SPL + src * SPL + j;
+          }
         }
         r.has_empty |= tile.ballot(m_empty != 0) != 0;
         occ += (uint32_t)__popc(~m_free & ((1u << SPL) - 1));
@@ -220,7 +222,24 @@ struct Ops {
           }
         }
       }
-      r.free = first_in_tile<TPL>(tile, m_free);
+      {
+        uint64_t lanes = tile.ballot(m_free != 0);
+        if (lanes) {
+          int src = ffs64(lanes);
+          int j = __ffs(tile.bcast(m_free, src)) - 1;
+          uint32_t word = tw[0];
+#pragma unroll
+          for (int i = 1; i < (TPL + 1) / 2; ++i)
+            if ((j >> 1) == i) word = tw[i];
+          if constexpr (TPL == 1) {
+            // one tag per lane: the 32-bit word pairs this lane's tag with its neighbour's
+            const uint32_t other = __shfl_xor(tw[0], 1, 64) & 0xFFFFu;
+            word = (tile.tl & 1) ? ((tw[0] & 0xFFFFu) << 16) | other : (other << 16) | (tw[0] & 0xFFFFu);
+          }
+          r.free_word = tile.bcast(word, src);
+          r.free = src * TPL + j;
+        }
+      }
       r.has_empty = tile.ballot(m_empty != 0) != 0;
       constexpr uint32_t lane_bits = TPL == 32 ? 0xFFFFFFFFu : ((1u << TPL) - 1);
       r.fill = tile_sum((uint32_t)__popc(~m_free & lane_bits));
@@ -230,48 +249,38 @@ struct Ops {
 
   // ---------------------------------------------------------------- writes
 
-  // Claims slot s for a new key and publishes (key, value).  Leader lane only
-  // touches memory; the result is broadcast.
-  __device__ static bool claim(const TableDev& tv, const Tile<T>& tile, uint64_t s, K key, K val,
-                               uint32_t tag) {
+  // Claims slot s for a new key and publishes (key, value).  `seen` is the
+  // free slot's word as the scan read it (see BucketScan::free_word): the
+  // compare-and-swap expects it, and retries with whatever it finds for as
+  // long as the slot stays free.  Leader lane only touches memory; the result
+  // is broadcast.
+  __device__ static bool claim(const TableDev& tv, const Tile<T>& tile, uint64_t s, uint64_t seen,
+                               K key, K val, uint32_t tag) {
     bool ok = false;
     if (tile.leader()) {
       if constexpr (C::TAGS) {
         uint32_t* wp = tv.tagw + (s >> 1);
         const uint32_t sh = (uint32_t)(s & 1) * 16;
-        uint32_t cur = ld(wp);
+        uint32_t cur = (uint32_t)seen;
         while (((cur >> sh) & 0xFFFFu) >= TAG_TOMB) {
           uint32_t want = (cur & ~(0xFFFFu << sh)) | (tag << sh);
           uint32_t old = cas(wp, cur, want);
           if (old == cur) { ok = true; break; }
           cur = old;
         }
-        if (ok) {
-          if constexpr (sizeof(K) == 8) {
-            st(val_ptr(tv, s), val);
-            wait_mem();
-            st(key_ptr(tv, s), key);
-          } else {
-            st((uint64_t*)key_ptr(tv, s), (uint64_t)key | ((uint64_t)val << 32));
-          }
-        }
+        if (ok) publish(tv, s, key, val);
       } else if constexpr (sizeof(K) == 8) {
         K* kp = key_ptr(tv, s);
-        K cur = EMPTY;
-        for (int a = 0; a < 2; ++a) {
+        K cur = (K)seen;
+        while (cur == EMPTY || cur == TOMB) {
           K old = cas(kp, cur, (K)Keys<K>::RESERVED);
           if (old == cur) { ok = true; break; }
-          if (old != TOMB) break;
-          cur = TOMB;
+          cur = old;
         }
-        if (ok) {
-          st(val_ptr(tv, s), val);
-          wait_mem();
-          st(kp, key);
-        }
+        if (ok) publish(tv, s, key, val);
       } else {
         uint64_t* sp = (uint64_t*)key_ptr(tv, s);
-        uint64_t cur = ld(sp);
+        uint64_t cur = seen;
         const uint64_t want = (uint64_t)key | ((uint64_t)val << 32);
         while ((K)cur == EMPTY || (K)cur == TOMB) {
           uint64_t old = cas(sp, cur, want);
@@ -281,6 +290,24 @@ struct Ops {
       }
     }
     return tile.bcast((uint32_t)ok, 0) != 0;
+  }
+
+  // Writes (key, value) into a slot this operation has claimed.  64-bit slots:
+  // one 16-byte store, or with -DHW_SPLIT_PUBLISH the value first and the key
+  // once the value store has completed.  32-bit slots (tag designs): one 8-byte
+  // store.
+  __device__ static __forceinline__ void publish(const TableDev& tv, uint64_t s, K key, K val) {
+    if constexpr (sizeof(K) == 8) {
+#ifdef HW_SPLIT_PUBLISH
+      st(val_ptr(tv, s), val);
+      wait_mem();
+      st(key_ptr(tv, s), key);
+#else
+      st16(key_ptr(tv, s), (uint64_t)key, (uint64_t)val);
+#endif
+    } else {
+      st((uint64_t*)key_ptr(tv, s), (uint64_t)key | ((uint64_t)val << 32));
+    }
   }
 
   // Upsert callback applied to a present key (Section 5.1).
@@ -317,15 +344,14 @@ struct Ops {
     }
   }
 
-  // Claims the first free slot of bucket b, rescanning after lost races.
-  // Returns the slot or -1 when the bucket is full.
+  // Claims the first free slot of bucket b (as found by scan `r`), rescanning
+  // after lost races.  Returns the slot or -1 when the bucket is full.
   __device__ static int64_t claim_in_bucket(const TableDev& tv, const Tile<T>& tile, uint32_t b,
-                                            int32_t free_hint, K key, K val, uint32_t tag) {
-    int32_t f = free_hint;
-    while (f >= 0) {
-      const uint64_t s = (uint64_t)b * B + f;
-      if (claim(tv, tile, s, key, val, tag)) return (int64_t)s;
-      f = scan<false>(tv, tile, b, key, tag).free;
+                                            BucketScan<K> r, K key, K val, uint32_t tag) {
+    while (r.free >= 0) {
+      const uint64_t s = (uint64_t)b * B + r.free;
+      if (claim(tv, tile, s, r.free_word, key, val, tag)) return (int64_t)s;
+      r = scan<false>(tv, tile, b, key, tag);
     }
     return -1;
   }
@@ -344,7 +370,12 @@ struct Ops {
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
     uint8_t status = ST_FULL;
     bool pending = true;
+    Backoff bo;
+    // The critical section runs inside the retry loop: a tile that wins the
+    // lock finishes and releases it in the same iteration, so tiles of one wave
+    // waiting on each other cannot deadlock (lanes of a wave run in lockstep).
     while (pending) {
+      bo.pause();
       if (try_lock(tv.locks, h.b1, tile)) {
         if constexpr (C::DOUBLE)
           status = upsert_double_locked(tv, tile, h, key, val, tag, combine);
@@ -352,6 +383,8 @@ struct Ops {
           status = upsert_p2_locked(tv, tile, h, key, val, tag, combine);
         unlock(tv.locks, h.b1, tile);
         pending = false;
+      } else {
+        bo.grow();
       }
     }
     return status;
@@ -361,7 +394,8 @@ struct Ops {
                                                  const Hashed& h, K key, K val, uint32_t tag,
                                                  int combine) {
     const uint32_t step = step_of(tv, h);
-    int64_t free_slot = -1;
+    BucketScan<K> first_free;
+    first_free.free = -1;
     uint32_t free_i = 0, free_b = 0;
     uint32_t b = h.b1;
     for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
@@ -370,8 +404,8 @@ struct Ops {
         combine_at(tv, tile, (uint64_t)b * B + r.hit, val, combine);
         return ST_EXISTED;
       }
-      if (free_slot < 0 && r.free >= 0) {
-        free_slot = (uint64_t)b * B + r.free;
+      if (first_free.free < 0 && r.free >= 0) {
+        first_free = r;
         free_i = i;
         free_b = b;
       }
@@ -379,12 +413,12 @@ struct Ops {
     }
     // Absent: claim the first free slot met, moving on along the sequence when
     // other writers take the free slots first.
-    if (free_slot < 0) return ST_FULL;
-    int32_t f = (int32_t)(free_slot - (uint64_t)free_b * B);
+    if (first_free.free < 0) return ST_FULL;
     b = free_b;
+    BucketScan<K> r = first_free;
     for (uint32_t i = free_i; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
-      if (i != free_i) f = scan<false>(tv, tile, b, key, tag).free;
-      if (claim_in_bucket(tv, tile, b, f, key, val, tag) >= 0) return ST_DONE;
+      if (i != free_i) r = scan<false>(tv, tile, b, key, tag);
+      if (claim_in_bucket(tv, tile, b, r, key, val, tag) >= 0) return ST_DONE;
     }
     return ST_FULL;
   }
@@ -402,12 +436,12 @@ struct Ops {
     if (tv.shortcut && 4 * r1.fill < 3 * (uint32_t)B) {
       uint32_t erased = tile.leader() ? ld(tv.ctrl) : 0u;
       if (tile.bcast(erased, 0) == 0) {
-        if (claim_in_bucket(tv, tile, b1, r1.free, key, val, tag) >= 0) return ST_DONE;
+        if (claim_in_bucket(tv, tile, b1, r1, key, val, tag) >= 0) return ST_DONE;
         r1 = scan<false>(tv, tile, b1, key, tag);  // filled up meanwhile: full path
       }
     }
     if (b2 == b1) {
-      return claim_in_bucket(tv, tile, b1, r1.free, key, val, tag) >= 0 ? ST_DONE : ST_FULL;
+      return claim_in_bucket(tv, tile, b1, r1, key, val, tag) >= 0 ? ST_DONE : ST_FULL;
     }
     BucketScan<K> r2 = scan<true>(tv, tile, b2, key, tag);
     if (r2.hit >= 0) {
@@ -415,10 +449,10 @@ struct Ops {
       return ST_EXISTED;
     }
     const bool alt_first = r2.fill < r1.fill;
-    const uint32_t bf = alt_first ? b2 : b1, bs = alt_first ? b1 : b2;
-    const int32_t ff = alt_first ? r2.free : r1.free, fs = alt_first ? r1.free : r2.free;
-    if (claim_in_bucket(tv, tile, bf, ff, key, val, tag) >= 0) return ST_DONE;
-    if (claim_in_bucket(tv, tile, bs, fs, key, val, tag) >= 0) return ST_DONE;
+    if (claim_in_bucket(tv, tile, alt_first ? b2 : b1, alt_first ? r2 : r1, key, val, tag) >= 0)
+      return ST_DONE;
+    if (claim_in_bucket(tv, tile, alt_first ? b1 : b2, alt_first ? r1 : r2, key, val, tag) >= 0)
+      return ST_DONE;
     return ST_FULL;
   }
 
@@ -462,7 +496,9 @@ struct Ops {
     }
     uint8_t status = ST_MISS;
     bool pending = true;
+    Backoff bo;
     while (pending) {
+      bo.pause();
       if (try_lock(tv.locks, h.b1, tile)) {
         if constexpr (C::DOUBLE) {
           const uint32_t step = step_of(tv, h);
@@ -494,6 +530,8 @@ struct Ops {
         }
         unlock(tv.locks, h.b1, tile);
         pending = false;
+      } else {
+        bo.grow();
       }
     }
     return status;

@@ -265,10 +265,11 @@ def load_phases(capacity: int, fractions=(0.5, 0.75, 0.9), config_id: int = 2):
 
 def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99,
                   frac_upsert: float = 0.3, frac_erase: float = 0.2, config_id: int = 3,
-                  preload_fraction: float = 1.0):
+                  ukeys: np.ndarray | None = None):
     """Generator of deterministic mixed batches over a Zipf-distributed key universe.
 
-    The universe is `universe` distinct keys (stream (config,1)); Zipf ranks index it.
+    The universe is `universe` distinct keys (stream (config,1), or the given `ukeys`);
+    Zipf ranks index it.
     Per batch of `batch` ops:
       * erase keys: Zipf draws, repeats rejected, until floor(frac_erase*batch) distinct;
       * upsert keys: Zipf draws with erase keys rejected (repeats allowed);
@@ -278,7 +279,9 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
     the same under any serialisation of the batch.
     Yields dict(ops, keys, vals) with ops coded 0 query, 2 upsert, 3 erase.
     """
-    ukeys = distinct_keys(stream_seed(config_id, 1), universe)
+    if ukeys is None:
+        ukeys = distinct_keys(stream_seed(config_id, 1), universe)
+    assert len(ukeys) == universe
     z = Zipf(universe, theta)
     n_up = int(frac_upsert * batch)
     n_er = int(frac_erase * batch)
@@ -320,6 +323,18 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
         vals[n_q:n_q + n_up] = splitmix64(stream_seed(config_id, 4), b * batch, n_up)
         perm = permutation(stream_seed(config_id, 1000 + b), batch)
         yield dict(ops=ops[perm], keys=ukeys[ranks[perm]], vals=vals[perm], ranks=ranks[perm])
+
+
+def sample_without_replacement(seed: int, n: int, k: int) -> np.ndarray:
+    """k distinct indices of range(n), uniform without replacement, in increasing order:
+    the k smallest of n splitmix64 doubles (ties impossible in practice; broken by index)."""
+    assert 0 <= k <= n
+    if k == n:
+        return np.arange(n, dtype=np.int64)
+    u = unit_float(seed, 0, n)
+    thr = np.partition(u, k - 1)[k - 1] if k else -1.0
+    idx = np.nonzero(u <= thr)[0]
+    return idx[:k].astype(np.int64)
 
 
 def universe_keys(universe: int, config_id: int = 3) -> np.ndarray:
