@@ -246,6 +246,9 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-log2cap", type=int, default=24)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB read + 1 GiB write elementwise kernel first "
+                         "(reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -267,6 +270,15 @@ def main():
     if not args.no_verify:
         verify_step(step, d)
         log("full-size closed-form verification passed")
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 1, out=dst)  # reads 2^30 bytes, writes 2^30 bytes
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy done (1 GiB read, 1 GiB written)")
 
     for _ in range(args.warmup):
         step.run()

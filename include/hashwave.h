@@ -75,7 +75,12 @@ enum {
 
 /* Flags of hwave_config.flags. */
 enum {
-  HWAVE_F_NO_SHORTCUT = 1 /* power-of-two-choice: never take the 75% shortcut     */
+  HWAVE_F_NO_SHORTCUT = 1, /* power-of-two-choice: never take the 75% shortcut    */
+  HWAVE_F_NO_ERASE = 2     /* the table never erases: hwave_erase returns
+                              HWAVE_EINVAL, erase ops of hwave_mixed get
+                              HWAVE_ST_INVALID, and upserts of present keys are
+                              combined in place without taking the bucket lock
+                              (stable slots are never reused; Section 2.1)    */
 };
 
 /* Table configuration.  Zero fields take the design's defaults (the
@@ -140,7 +145,8 @@ int hwave_query(hwave_table* t, const void* d_keys, uint64_t n, void* d_vals_out
                 uint8_t* d_found, void* stream);
 
 /* Erase (Section 5.1): d_found[i] = DONE (erased) / MISS (absent, table
- * unchanged) / INVALID.  d_found may be NULL. */
+ * unchanged) / INVALID.  d_found may be NULL.  HWAVE_EINVAL on a table created
+ * with HWAVE_F_NO_ERASE. */
 int hwave_erase(hwave_table* t, const void* d_keys, uint64_t n, uint8_t* d_found, void* stream);
 
 /* One launch running a different operation per element (the paper runs all

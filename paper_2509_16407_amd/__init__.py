@@ -23,6 +23,7 @@ COMBINES = {"sum": 0, "keep": 1, "replace": 2, "min": 3, "max": 4}
 OPS = {"query": 0, "insert": 1, "upsert": 2, "erase": 3}
 ST_MISS, ST_DONE, ST_EXISTED, ST_FULL, ST_INVALID = 0, 1, 2, 3, 4
 F_NO_SHORTCUT = 1
+F_NO_ERASE = 2
 
 
 class HashWaveError(RuntimeError):

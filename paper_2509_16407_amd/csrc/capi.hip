@@ -196,7 +196,7 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   if (cap > L.nb) cap = L.nb;
   tv.probe_cap = (uint32_t)(cap > 0xFFFFFFFFull ? 0xFFFFFFFFull : cap);
   tv.shortcut = (c.flags & HWAVE_F_NO_SHORTCUT) ? 0u : 1u;
-  tv.pad = 0;
+  tv.no_erase = (c.flags & HWAVE_F_NO_ERASE) ? 1u : 0u;
   t->la.max_blocks = max_blocks_for(dev);
   return hwave_clear(t, stream);
 }
@@ -332,7 +332,7 @@ int hwave_query(hwave_table* t, const void* d_keys, uint64_t n, void* d_vals_out
 }
 
 int hwave_erase(hwave_table* t, const void* d_keys, uint64_t n, uint8_t* d_found, void* stream) {
-  if (!t) return HWAVE_EINVAL;
+  if (!t || t->la.tv.no_erase) return HWAVE_EINVAL;
   if (n == 0) return HWAVE_OK;
   if (bad_ptr(d_keys)) return HWAVE_EINVAL;
   hipError_t e = t->ks->erase(t->la, d_keys, n, d_found, (hipStream_t)stream);

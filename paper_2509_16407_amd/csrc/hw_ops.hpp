@@ -47,7 +47,7 @@ struct TableDev {
   uint32_t bucket_mask;  // buckets - 1 (a power of two minus one)
   uint32_t probe_cap;    // double hashing: most buckets visited
   uint32_t shortcut;     // power-of-two-choice shortcut enabled
-  uint32_t pad;
+  uint32_t no_erase;     // table never erases: present keys are combined without the lock
 };
 
 template <typename K_, int DESIGN_, int B_, int T_>
@@ -362,7 +362,41 @@ struct Ops {
     return (h.h2 & tv.bucket_mask) | 1u;
   }
 
+  // Lock-free search (Section 4.2): the slot holding `key`, or -1.  Value in *val.
+  __device__ static int64_t find(const TableDev& tv, const Tile<T>& tile, const Hashed& h, K key,
+                                 uint32_t tag, K* val) {
+    if constexpr (C::DOUBLE) {
+      const uint32_t step = step_of(tv, h);
+      uint32_t b = h.b1;
+      for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
+        BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
+        if (r.hit >= 0) { *val = r.val; return (int64_t)b * B + r.hit; }
+        if (r.has_empty) break;
+      }
+      return -1;
+    } else {
+      BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
+      if (r.hit >= 0) { *val = r.val; return (int64_t)h.b1 * B + r.hit; }
+      const uint32_t b2 = h.h2 & tv.bucket_mask;
+      if (b2 != h.b1) {
+        r = scan<true>(tv, tile, b2, key, tag);
+        if (r.hit >= 0) { *val = r.val; return (int64_t)b2 * B + r.hit; }
+      }
+      return -1;
+    }
+  }
+
   // Upsert: lock primary, find or insert, unlock.  Status per hwave.h.
+  //
+  // Waiting for the lock: after a failed attempt a tile backs off, then polls
+  // the lock word with a load and tries the atomic only when the bit reads
+  // clear -- or on every 64th attempt regardless, so progress never depends on
+  // how soon a load observes the release.  In a table that never erases, a slot
+  // once filled keeps its key for good (stability, Section 2.1), so a present
+  // key is combined in place without the lock (as the paper does for sparse
+  // tensor contraction, Section 6.7), and a waiting tile looks for its key
+  // again before each attempt: once another tile has inserted it, the waiter
+  // finishes without the lock.
   __device__ static uint8_t upsert(const TableDev& tv, const Tile<T>& tile, K key, K val,
                                    int combine) {
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
@@ -371,12 +405,25 @@ struct Ops {
     uint8_t status = ST_FULL;
     bool pending = true;
     Backoff bo;
+    uint32_t attempt = 0;
     // The critical section runs inside the retry loop: a tile that wins the
     // lock finishes and releases it in the same iteration, so tiles of one wave
     // waiting on each other cannot deadlock (lanes of a wave run in lockstep).
     while (pending) {
       bo.pause();
-      if (try_lock(tv.locks, h.b1, tile)) {
+      if (tv.no_erase) {
+        K cur;
+        const int64_t s = find(tv, tile, h, key, tag, &cur);
+        if (s >= 0) {
+          combine_at(tv, tile, (uint64_t)s, val, combine);
+          status = ST_EXISTED;
+          pending = false;
+          continue;
+        }
+      }
+      const bool go = (attempt & 63) == 0 || lock_looks_free(tv.locks, h.b1, tile);
+      ++attempt;
+      if (go && try_lock(tv.locks, h.b1, tile)) {
         if constexpr (C::DOUBLE)
           status = upsert_double_locked(tv, tile, h, key, val, tag, combine);
         else
@@ -462,30 +509,12 @@ struct Ops {
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
     const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
-    if constexpr (C::DOUBLE) {
-      const uint32_t step = step_of(tv, h);
-      uint32_t b = h.b1;
-      for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
-        BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
-        if (r.hit >= 0) { *out = r.val; return ST_DONE; }
-        if (r.has_empty) break;
-      }
-      return ST_MISS;
-    } else {
-      BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
-      if (r.hit >= 0) { *out = r.val; return ST_DONE; }
-      const uint32_t b2 = h.h2 & tv.bucket_mask;
-      if (b2 != h.b1) {
-        r = scan<true>(tv, tile, b2, key, tag);
-        if (r.hit >= 0) { *out = r.val; return ST_DONE; }
-      }
-      return ST_MISS;
-    }
+    return find(tv, tile, h, key, tag, out) >= 0 ? ST_DONE : ST_MISS;
   }
 
   // Erase under the primary lock.  ST_DONE if removed, ST_MISS if absent.
   __device__ static uint8_t erase(const TableDev& tv, const Tile<T>& tile, K key) {
-    if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
+    if (key >= Keys<K>::FIRST_INVALID || tv.no_erase) return ST_INVALID;
     const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
     if constexpr (!C::DOUBLE) {
@@ -497,9 +526,12 @@ struct Ops {
     uint8_t status = ST_MISS;
     bool pending = true;
     Backoff bo;
+    uint32_t attempt = 0;
     while (pending) {
       bo.pause();
-      if (try_lock(tv.locks, h.b1, tile)) {
+      const bool go = (attempt & 63) == 0 || lock_looks_free(tv.locks, h.b1, tile);
+      ++attempt;
+      if (go && try_lock(tv.locks, h.b1, tile)) {
         if constexpr (C::DOUBLE) {
           const uint32_t step = step_of(tv, h);
           uint32_t b = h.b1;

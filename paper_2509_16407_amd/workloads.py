@@ -46,15 +46,16 @@ def stream_seed(config: int, purpose: int) -> int:
 def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
     """Elements [start, start+count) of the splitmix64 stream with the given seed (uint64)."""
     out = np.empty(count, dtype=np.uint64)
+    if count >= 4096:
+        _helper().sm64_fill(_c_u64(seed & U64_MAX), _c_u64(start), _c_u64(count), _cptr(out))
+        return out
     s0 = np.uint64(seed & U64_MAX)
     with np.errstate(over="ignore"):
-        for c0 in range(0, count, _CHUNK):
-            c1 = min(count, c0 + _CHUNK)
-            ctr = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.uint64)
-            z = s0 + ctr * GAMMA
-            z = (z ^ (z >> _S30)) * _M1
-            z = (z ^ (z >> _S27)) * _M2
-            out[c0:c1] = z ^ (z >> _S31)
+        ctr = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = s0 + ctr * GAMMA
+        z = (z ^ (z >> _S30)) * _M1
+        z = (z ^ (z >> _S27)) * _M2
+        out[:] = z ^ (z >> _S31)
     return out
 
 
@@ -144,47 +145,80 @@ def _swap_loop(p, idx, j):
         p[a], p[b] = p[b], p[a]
 
 
-_fast = None
+_lib = None
+
+
+def _c_u64(x):
+    import ctypes
+    return ctypes.c_uint64(int(x))
+
+
+def _cptr(a):
+    import ctypes
+    return a.ctypes.data_as(ctypes.c_void_p)
 
 
 def _swap_loop_fast(p, idx, j):
-    """Sequential swap loop compiled once with the host C compiler (ctypes)."""
-    global _fast
-    if _fast is None:
-        _fast = _build_swap_helper()
     import ctypes
-    _fast(p.ctypes.data_as(ctypes.c_void_p), idx.ctypes.data_as(ctypes.c_void_p),
-          j.ctypes.data_as(ctypes.c_void_p), ctypes.c_int64(len(idx)))
+    _helper().fy_swaps(_cptr(p), _cptr(idx), _cptr(j), ctypes.c_int64(len(idx)))
 
 
-def _build_swap_helper():
-    import ctypes
-    import hashlib
-    import os
-    import subprocess
-    import tempfile
-    src = (
-        "#include <stdint.h>\n"
-        "void fy_swaps(int64_t* p, const int64_t* idx, const int64_t* j, int64_t n){\n"
-        "  for (int64_t k = 0; k < n; k++) { int64_t a = idx[k], b = j[k];\n"
-        "    int64_t t = p[a]; p[a] = p[b]; p[b] = t; } }\n"
-    )
-    tag = hashlib.sha1(src.encode()).hexdigest()[:12]
-    d = os.path.join(tempfile.gettempdir(), "hw_workloads_%d" % os.getuid())
-    os.makedirs(d, exist_ok=True)
-    so = os.path.join(d, "fy_%s.so" % tag)
-    if not os.path.exists(so):
-        c = os.path.join(d, "fy_%s.c" % tag)
-        with open(c, "w") as f:
-            f.write(src)
-        tmp = so + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", c, "-o", tmp])
-        os.replace(tmp, so)
-    lib = ctypes.CDLL(so)
-    fn = lib.fy_swaps
-    fn.restype = None
-    fn.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64]
-    return fn
+_HELPER_SRC = r"""
+#include <stdint.h>
+static inline uint64_t sm64_at(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+void sm64_fill(uint64_t seed, uint64_t start, uint64_t count, uint64_t* out) {
+  for (uint64_t i = 0; i < count; i++) out[i] = sm64_at(seed, start + i);
+}
+uint64_t select_s(uint64_t seed, uint64_t n, uint64_t k, int64_t* out) {
+  uint64_t got = 0;
+  for (uint64_t i = 0; i < n && got < k; i++) {
+    double u = (double)(sm64_at(seed, i) >> 11) * (1.0 / 9007199254740992.0);
+    if ((double)(n - i) * u < (double)(k - got)) out[got++] = (int64_t)i;
+  }
+  return got;
+}
+void fy_swaps(int64_t* p, const int64_t* idx, const int64_t* j, int64_t n) {
+  for (int64_t k = 0; k < n; k++) { int64_t a = idx[k], b = j[k];
+    int64_t t = p[a]; p[a] = p[b]; p[b] = t; }
+}
+"""
+
+
+def _helper():
+    """The generators' inner loops compiled once with the host C compiler."""
+    global _lib
+    if _lib is None:
+        import ctypes
+        import hashlib
+        import os
+        import subprocess
+        import tempfile
+        tag = hashlib.sha1(_HELPER_SRC.encode()).hexdigest()[:12]
+        d = os.path.join(tempfile.gettempdir(), "hw_workloads_%d" % os.getuid())
+        os.makedirs(d, exist_ok=True)
+        so = os.path.join(d, "gen_%s.so" % tag)
+        if not os.path.exists(so):
+            c = os.path.join(d, "gen_%s.c" % tag)
+            with open(c, "w") as f:
+                f.write(_HELPER_SRC)
+            tmp = so + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", c, "-o", tmp])
+            os.replace(tmp, so)
+        lib = ctypes.CDLL(so)
+        P, U = ctypes.c_void_p, ctypes.c_uint64
+        lib.sm64_fill.argtypes = [U, U, U, P]
+        lib.sm64_fill.restype = None
+        lib.select_s.argtypes = [U, U, U, P]
+        lib.select_s.restype = U
+        lib.fy_swaps.argtypes = [P, P, P, ctypes.c_int64]
+        lib.fy_swaps.restype = None
+        _lib = lib
+    return _lib
 
 
 class Zipf:
@@ -302,19 +336,17 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
             _, first = np.unique(allr, return_index=True)
             first.sort()
             er = allr[first][:n_er]
-        er_set = np.zeros(universe, dtype=bool)
-        er_set[er] = True
+        er_sorted = np.sort(er)
         up = np.empty(0, dtype=np.int64)
         while len(up) < n_up:
             r = draw(n_up - len(up) + 1024)
-            r = r[~er_set[r]]
+            r = r[~np.isin(r, er_sorted, assume_unique=False)]
             up = np.concatenate([up, r])[:n_up]
-        bad = er_set.copy()
-        bad[up] = True
+        bad = np.union1d(er_sorted, up)
         qr = np.empty(0, dtype=np.int64)
         while len(qr) < n_q:
             r = draw(n_q - len(qr) + 1024)
-            r = r[~bad[r]]
+            r = r[~np.isin(r, bad)]
             qr = np.concatenate([qr, r])[:n_q]
         ops = np.concatenate([np.zeros(n_q, np.uint8), np.full(n_up, 2, np.uint8),
                               np.full(n_er, 3, np.uint8)])
@@ -326,15 +358,17 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
 
 
 def sample_without_replacement(seed: int, n: int, k: int) -> np.ndarray:
-    """k distinct indices of range(n), uniform without replacement, in increasing order:
-    the k smallest of n splitmix64 doubles (ties impossible in practice; broken by index)."""
+    """k distinct indices of range(n), uniform without replacement, increasing.
+
+    Selection sampling (Knuth, TAOCP vol. 2, 3.4.2, Algorithm S; Fan, Muller and
+    Rezucha 1962): index i is taken when (n - i) * u_i < k - (taken so far), u_i the
+    i-th double of the splitmix64 stream `seed`."""
     assert 0 <= k <= n
-    if k == n:
-        return np.arange(n, dtype=np.int64)
-    u = unit_float(seed, 0, n)
-    thr = np.partition(u, k - 1)[k - 1] if k else -1.0
-    idx = np.nonzero(u <= thr)[0]
-    return idx[:k].astype(np.int64)
+    out = np.empty(k, dtype=np.int64)
+    if k:
+        got = _helper().select_s(_c_u64(seed & U64_MAX), _c_u64(n), _c_u64(k), _cptr(out))
+        assert got == k
+    return out
 
 
 def universe_keys(universe: int, config_id: int = 3) -> np.ndarray:

@@ -141,6 +141,35 @@ def test_same_key_storm_one_lock(design, bits):
 
 @pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
 @pytest.mark.parametrize("bits", [64, 32])
+def test_hot_keys_no_erase_table(design, bits):
+    """Hot keys on a table that never erases: 2^14 SUM upserts over 16 keys sharing
+    one primary bucket.  Present keys are combined without the lock, so only the 16
+    first inserts serialise on it; sums and statuses are exact."""
+    t = hw.Table(1 << 14, design, kv_bits=bits, flags=hw.F_NO_ERASE)
+    cand = w.distinct_keys(w.stream_seed(58, ODESIGN[design] + bits), 200000, key_bits=bits)
+    prim = t.primary_bucket(dev(cand, bits)).cpu().numpy()
+    b0 = np.bincount(prim).argmax()
+    keys16 = cand[prim == b0][:16]
+    assert len(keys16) == 16
+    n = 1 << 14
+    ks = keys16[w.uniform_below(w.stream_seed(59, bits), 0, n, 16)]
+    vs = w.splitmix64(w.stream_seed(60, bits), 0, n)
+    if bits == 32:
+        vs &= np.uint64(0xFFFFFFFF)
+    st = u8(t.upsert(dev(ks, bits), dev(vs, bits), combine="sum"))
+    om = oracle.OracleMap(key_bits=bits)
+    om.upsert(ks, vs)
+    assert (st == hw.ST_DONE).sum() == 16 and (st == hw.ST_EXISTED).sum() == n - 16
+    k, v = t.export()
+    k, v = host(k, bits), host(v, bits)
+    o = np.argsort(k)
+    ok, ov = om.dump()
+    assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov)
+    _layout_ok(t)
+
+
+@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+@pytest.mark.parametrize("bits", [64, 32])
 def test_publish_litmus_insert_vs_query(design, bits):
     t = hw.Table(1 << 20, design, kv_bits=bits)
     seed = w.stream_seed(55, ODESIGN[design] * 100 + bits)

@@ -197,15 +197,16 @@ def test_mixed_batches_against_oracle(design):
 
 # ------------------------------------------------------------------ 32-bit group-by (config 4 shape)
 
+@pytest.mark.parametrize("flags", [0, hw.F_NO_ERASE], ids=["locked", "noerase"])
 @pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
 @pytest.mark.parametrize("logcap", [10, 14, 17])
-def test_u32_groupby_sum(design, logcap):
+def test_u32_groupby_sum(design, logcap, flags):
     """Group-by hash aggregation: D = 0.85 * capacity distinct uint32 keys, each upserted
     once plus D extra uniform repeats; result = wrapping sums per key.  In tiny
     power-of-two-choice tables a key may find both buckets full: that FULL is
     accepted only when the final image shows both buckets full."""
     cap = 1 << logcap
-    t = hw.Table(cap, design, kv_bits=32)
+    t = hw.Table(cap, design, kv_bits=32, flags=flags)
     cap = t.capacity
     D = int(0.85 * cap)
     seed = w.stream_seed(4, logcap * 8 + ODESIGN[design])
@@ -288,3 +289,19 @@ def test_primary_bucket_hook_matches_oracle():
     exp = np.array([oracle.primary_bucket(int(k), t.num_buckets) for k in keys[:2000]])
     assert np.array_equal(got[:2000], exp)
     assert got.max() < t.num_buckets
+
+
+@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+def test_no_erase_table_rejects_erase(design):
+    import torch
+    t = hw.Table(1 << 12, design, flags=hw.F_NO_ERASE)
+    k = w.distinct_keys(3, 100)
+    assert (u8(t.insert(dev(k), dev(k))) == hw.ST_DONE).all()
+    with pytest.raises(hw.HashWaveError):
+        t.erase(dev(k))
+    ops = torch.full((100,), 3, dtype=torch.uint8, device="cuda")
+    st, _ = t.mixed(ops, dev(k), dev(k))
+    assert (u8(st) == hw.ST_INVALID).all()
+    assert t.size() == 100
+    f, v = t.query(dev(k))
+    assert (u8(f) == hw.ST_DONE).all() and np.array_equal(host(v), k)

@@ -25,6 +25,9 @@ def test_splitmix64_matches_integer_definition():
         assert w.splitmix64(seed, 0, 50).tolist() == _splitmix_py(seed, 50)
     # offset access equals the tail of a longer draw
     assert w.splitmix64(99, 17, 10).tolist() == _splitmix_py(99, 27)[17:]
+    # the compiled path (long draws) agrees with the definition too
+    long = w.splitmix64(12345, 100, 6000)
+    assert long.tolist() == _splitmix_py(12345, 6100)[100:]
 
 
 def test_distinct_keys_and_continuation_disjoint():
@@ -78,3 +81,16 @@ def test_mixed_batches_are_deterministic_and_disjoint():
     g1 = next(w.mixed_batches(1 << 14, 1 << 12, 1, config_id=3))
     g2 = next(w.mixed_batches(1 << 14, 1 << 12, 1, config_id=3))
     assert all(np.array_equal(g1[k], g2[k]) for k in g1)
+
+
+def test_selection_sample_exact_size_and_uniform():
+    """Algorithm S returns exactly k distinct increasing indices; every index is
+    taken with probability k/n (checked on per-decile counts)."""
+    n, k = 1_000_000, 300_000
+    idx = w.sample_without_replacement(7, n, k)
+    assert len(idx) == k and np.all(np.diff(idx) > 0) and idx[0] >= 0 and idx[-1] < n
+    counts = np.bincount(idx * 10 // n, minlength=10)
+    exp = k / 10
+    assert np.all(np.abs(counts - exp) < 5 * np.sqrt(exp))
+    assert len(w.sample_without_replacement(7, 10, 10)) == 10
+    assert len(w.sample_without_replacement(7, 10, 0)) == 0
