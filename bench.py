@@ -214,23 +214,66 @@ def cpu_baseline(cap_log2: int):
                        % (cap_log2 - 1, cap_log2, n_ops, dt))
 
 
-def load_traffic(dominant: str, n_ops: int):
-    """HBM bytes per launch of the dominant kernel from committed rocprofv3 counter
-    summaries, if they were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_OF = {"insert_0.5": "k_upsert", "insert_0.75": "k_upsert", "insert_0.9": "k_upsert",
+             "upsert": "k_upsert", "query_pos": "k_query", "query_neg": "k_query",
+             "requery_pos": "k_query", "requery_neg": "k_query", "erase": "k_erase",
+             "mixed": "k_mixed"}
+
+
+def algo_kind(phase: str) -> str:
+    return "insert" if phase.startswith("insert") else phase
+
+
+def load_traffic():
+    """Measured HBM bytes per launch, per phase, from the committed rocprofv3 counter
+    summary -- only if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_p2m_2p28.txt")
     if not os.path.exists(path):
         return None
-    try:
-        with open(path) as f:
-            rec = json.load(f)
-    except Exception:
-        return None
+    rec, phases = {}, {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("phase "):
+                parts = line.split()
+                kv = dict(x.split("=", 1) for x in parts[3:])
+                phases.setdefault(parts[1], float(kv["hbm_bytes"]))
+            elif "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                rec[k] = v
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    ph = rec.get("phases", {}).get(dominant)
-    if not ph:
-        return None
-    return ph.get("hbm_bytes_per_launch")
+    return phases
+
+
+def roofline(phase_ms: dict, per_step_ops: dict, steps: int, traffic_by_phase):
+    """Roofline object of the dominant kernel (largest total time per step):
+    algorithmic bytes of all its launches in a step / their total time, against the
+    8 TB/s HBM peak; `traffic` = measured HBM bytes per launch (or None)."""
+    kern_ms, kern_bytes, kern_launch, kern_meas = {}, {}, {}, {}
+    for ph, lst in phase_ms.items():
+        k = KERNEL_OF[ph]
+        kern_ms[k] = kern_ms.get(k, 0.0) + float(np.sum(lst)) / steps
+        n_launch = len(lst) // steps
+        kern_launch[k] = kern_launch.get(k, 0) + n_launch
+        kern_bytes[k] = kern_bytes.get(k, 0.0) + ALGO_BYTES[algo_kind(ph)] * per_step_ops[ph] * n_launch
+        if traffic_by_phase is not None and ph in traffic_by_phase:
+            kern_meas[k] = kern_meas.get(k, 0.0) + traffic_by_phase[ph] * n_launch
+    dom = max(kern_ms, key=kern_ms.get)
+    avg_launch_ms = kern_ms[dom] / kern_launch[dom]
+    bytes_per_launch = kern_bytes[dom] / kern_launch[dom]
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    traffic = None
+    if traffic_by_phase is not None and dom in kern_meas:
+        traffic = round(kern_meas[dom] / kern_launch[dom])
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": dom, "launches_per_step": kern_launch[dom],
+            "algo_bytes_per_launch": round(bytes_per_launch), "avg_launch_ms": round(avg_launch_ms, 4)}
+    if traffic is not None:
+        roof["traffic_GBps"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
+        roof["traffic_frac"] = round(roof["traffic_GBps"] / HBM_PEAK_GBS, 4)
+    return roof
 
 
 def main():
@@ -309,20 +352,10 @@ def main():
     else:
         p50 = p99 = None
 
-    # dominant kernel (largest total time per step) and its roofline fraction
-    tot = {k: float(np.sum(v)) for k, v in phase_ms.items()}
-    dom = max(tot, key=tot.get)
-    dom_ops = step.ops.get(dom, (step.mixed_ops // max(1, len(step.mixed))))
-    dom_ms = float(np.mean(phase_ms[dom]))
-    kind = "insert" if dom.startswith("insert") else dom
-    algo_bytes = ALGO_BYTES[kind] * dom_ops
-    achieved = algo_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = load_traffic(dom, dom_ops)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "%s (%s)" % (dom, "k_query" if "query" in dom else "k_upsert" if dom.startswith(("insert", "upsert")) else "k_" + kind),
-            "algo_bytes_per_op": ALGO_BYTES[kind], "ops_per_launch": dom_ops,
-            "avg_launch_ms": round(dom_ms, 4)}
+    per_step_ops = dict(step.ops)
+    if step.mixed:
+        per_step_ops["mixed"] = step.mixed_ops // len(step.mixed)
+    roof = roofline(phase_ms, per_step_ops, args.steps, load_traffic())
 
     cpu = None
     if not args.no_cpu:
