@@ -186,6 +186,72 @@ typedef struct {
 } hwave_raw_view;
 int hwave_raw(const hwave_table* t, hwave_raw_view* out);
 
+/* ------------------------------------------------------------------------
+ * Batched form: one persistent launch over many tables.
+ *
+ * A hwave_multi groups tables of one key width (any designs and sizes whose
+ * configuration is in the multi-table menu: hwave_multi_supported).  Each call
+ * takes a list of work items over shared device arrays; item i applies its
+ * operation to ops [begin, end) of the arrays on table `table`.  All items run
+ * in ONE kernel launch whose waves pull chunks of items from per-XCD queues.
+ * Items on different tables are independent; items on the same table are
+ * concurrent (any serialisation), like one batch.
+ */
+typedef struct hwave_multi hwave_multi;
+
+typedef struct {
+  uint32_t table; /* index into the tables given to hwave_multi_create          */
+  uint32_t op;    /* hwave_op | (hwave_combine << 8) for HWAVE_OP_UPSERT         */
+  uint64_t begin; /* first op of this item in the shared arrays                  */
+  uint64_t end;   /* one past the last                                            */
+} hwave_item;
+
+/* 1 if a table with this (kv_bits, design, bucket, tile) can join a hwave_multi. */
+int hwave_multi_supported(uint32_t kv_bits, hwave_design design, uint32_t bucket_slots, uint32_t tile);
+
+/* Creates a group over n_tables existing tables (same device and key width).
+ * The tables must outlive the group.  Uploads their descriptors on `stream`. */
+int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n_tables, void* stream);
+int hwave_multi_destroy(hwave_multi* m);
+
+/* Runs n_items host-described items in one launch.  d_vals is read by insert
+ * and upsert items (nullable if there are none); d_vals_out (nullable) receives
+ * query values; d_status (nullable) one status byte per op.  Blocks only until
+ * the host item list has been copied out of the group's staging buffer from
+ * the previous call. */
+int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items, const void* d_keys,
+                    const void* d_vals, void* d_vals_out, uint8_t* d_status, void* stream);
+
+/* Empties every table of the group in one launch on `stream`. */
+int hwave_multi_clear(hwave_multi* m, void* stream);
+
+/* Convenience: table i receives ops [h_offsets[i], h_offsets[i+1]) as one upsert
+ * with `combine` (h_offsets has n_tables + 1 entries). */
+int hwave_multi_upsert(hwave_multi* m, const uint64_t* h_offsets, const void* d_keys, const void* d_vals,
+                       hwave_combine combine, uint8_t* d_status, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Autotuner (the paper picks bucket and tile size per design by exhaustive
+ * search, Section 5): times every multi-table menu configuration whose design
+ * bit is set in design_mask (1 << hwave_design) for tables of `capacity` slots,
+ * on a synthetic group-by SUM-upsert batch that fills them to `load`, spread
+ * over enough tables of that class to fill the GPU and run through the
+ * persistent multi-table kernel.  `flags` are the tables' HWAVE_F_* flags.
+ * Writes up to results_cap timings to `results` (their count to *n_results) and
+ * the fastest to *best.  Allocates and frees its own device memory; blocks.
+ */
+typedef struct {
+  uint32_t design;       /* hwave_design                        */
+  uint32_t bucket_slots;
+  uint32_t tile;
+  uint32_t kv_bits;
+  double gops;           /* measured upserts per ns (G ops/s)   */
+} hwave_tune_result;
+
+int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, double load, uint32_t reps,
+                   uint32_t flags, hwave_tune_result* results, uint32_t results_cap, uint32_t* n_results,
+                   hwave_tune_result* best, void* stream);
+
 /* Text of a return code; HIP error code of the last failing HIP call. */
 const char* hwave_strerror(int code);
 int hwave_last_hip_error(void);

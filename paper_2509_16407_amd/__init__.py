@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Table", "lib", "DESIGNS", "COMBINES", "OPS", "HashWaveError"]
+__all__ = ["Table", "Multi", "lib", "autotune", "DESIGNS", "COMBINES", "OPS", "HashWaveError"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhashwave.so")
@@ -34,6 +34,16 @@ class _Config(ctypes.Structure):
     _fields_ = [("kv_bits", ctypes.c_uint32), ("bucket_slots", ctypes.c_uint32),
                 ("tile", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32)]
+
+
+class _Item(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_uint32), ("op", ctypes.c_uint32), ("begin", ctypes.c_uint64),
+                ("end", ctypes.c_uint64)]
+
+
+class _Tune(ctypes.Structure):
+    _fields_ = [("design", ctypes.c_uint32), ("bucket_slots", ctypes.c_uint32), ("tile", ctypes.c_uint32),
+                ("kv_bits", ctypes.c_uint32), ("gops", ctypes.c_double)]
 
 
 class _Raw(ctypes.Structure):
@@ -80,6 +90,15 @@ def _bind(L):
         "hwave_strerror": (ctypes.c_char_p, [I]),
         "hwave_last_hip_error": (I, []),
         "hwave_stream_sync": (I, [P]),
+        "hwave_multi_supported": (I, [ctypes.c_uint32, I, ctypes.c_uint32, ctypes.c_uint32]),
+        "hwave_multi_create": (I, [ctypes.POINTER(P), P, ctypes.c_uint32, P]),
+        "hwave_multi_destroy": (I, [P]),
+        "hwave_multi_run": (I, [P, P, ctypes.c_uint32, P, P, P, P, P]),
+        "hwave_multi_clear": (I, [P, P]),
+        "hwave_multi_upsert": (I, [P, P, P, P, I, P, P]),
+        "hwave_autotune": (I, [ctypes.c_uint32, U64, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32,
+                               ctypes.c_uint32, ctypes.POINTER(_Tune), ctypes.c_uint32,
+                               ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_Tune), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -248,3 +267,98 @@ class Table:
         off = r.locks - base
         out["locks"] = self.buffer[off: off + 4 * r.n_lock_words].view(torch.int32)
         return out
+
+
+class Multi:
+    """A group of tables (one key width) served by one persistent kernel per call."""
+
+    def __init__(self, tables, stream=None):
+        self.tables = list(tables)
+        if not self.tables:
+            raise HashWaveError("empty table group")
+        self.kv_bits = self.tables[0].kv_bits
+        arr = (ctypes.c_void_p * len(self.tables))(*[t.h.value for t in self.tables])
+        h = ctypes.c_void_p()
+        _check(lib().hwave_multi_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p),
+                                        len(self.tables), _stream(stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hwave_multi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clear(self, stream=None):
+        _check(lib().hwave_multi_clear(self.h, _stream(stream)))
+
+    def run(self, items, keys, vals=None, out=None, status=None, stream=None):
+        """items: sequence of (table, op, begin, end) with op an int (OPS value |
+        combine << 8).  Returns (status, out) tensors."""
+        import torch
+        n = keys.numel()
+        dt = keys.dtype
+        out = torch.empty(n, dtype=dt, device=keys.device) if out is None else out
+        status = torch.empty(n, dtype=torch.uint8, device=keys.device) if status is None else status
+        arr = (_Item * len(items))(*[_Item(int(a), int(b), int(c), int(d)) for a, b, c, d in items])
+        _check(lib().hwave_multi_run(self.h, ctypes.cast(arr, ctypes.c_void_p), len(items), _ptr(keys),
+                                     _ptr(vals), _ptr(out), _ptr(status), _stream(stream)))
+        return status, out
+
+    def upsert(self, offsets, keys, vals, combine="sum", status=None, stream=None):
+        import torch
+        n = keys.numel()
+        status = torch.empty(n, dtype=torch.uint8, device=keys.device) if status is None else status
+        offs = (ctypes.c_uint64 * len(offsets))(*[int(x) for x in offsets])
+        _check(lib().hwave_multi_upsert(self.h, ctypes.cast(offs, ctypes.c_void_p), _ptr(keys), _ptr(vals),
+                                        COMBINES[combine], _ptr(status), _stream(stream)))
+        return status
+
+
+def multi_supported(kv_bits, design, bucket, tile) -> bool:
+    return bool(lib().hwave_multi_supported(kv_bits, DESIGNS[design], bucket, tile))
+
+
+def autotune(kv_bits: int, capacity: int, designs=("DOUBLE", "DOUBLE_M", "P2", "P2_M"), load=0.85,
+             reps=3, flags=0, stream=None):
+    """Times every multi-table menu configuration of `designs` for tables of
+    `capacity` slots (C-ABI hwave_autotune).  Returns (best, all) as dicts."""
+    mask = 0
+    for d in designs:
+        mask |= 1 << DESIGNS[d]
+    res = (_Tune * 64)()
+    n = ctypes.c_uint32()
+    best = _Tune()
+    _check(lib().hwave_autotune(kv_bits, capacity, mask, load, reps, flags, res, 64, ctypes.byref(n),
+                                ctypes.byref(best), _stream(stream)))
+    names = {v: k for k, v in DESIGNS.items()}
+
+    def as_dict(r):
+        return {"design": names[r.design], "bucket": r.bucket_slots, "tile": r.tile,
+                "kv_bits": r.kv_bits, "gops": r.gops}
+    return as_dict(best), [as_dict(res[i]) for i in range(min(n.value, 64))]
+
+
+def tune_classes(kv_bits: int, exponents, path=None, **kw):
+    """Autotunes each capacity class 2^e and (optionally) saves {e: best} as JSON."""
+    import json
+    table = {}
+    for e in exponents:
+        best, _ = autotune(kv_bits, 1 << e, **kw)
+        table[str(e)] = best
+    if path:
+        with open(path, "w") as f:
+            json.dump({"kv_bits": kv_bits, "classes": table}, f, indent=1)
+    return table
+
+
+def load_tuning(path):
+    import json
+    with open(path) as f:
+        rec = json.load(f)
+    return {int(k): v for k, v in rec["classes"].items()}

@@ -14,8 +14,8 @@ OUT = os.path.join(HERE, "libhashwave.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = ["capi.hip", "inst_u64_double.hip", "inst_u64_p2.hip", "inst_u32_double.hip",
-           "inst_u32_p2.hip"]
-HEADERS = ["hw_device.hpp", "hw_ops.hpp", "hw_launch.hpp"]
+           "inst_u32_p2.hip", "inst_multi.hip", "autotune.hip"]
+HEADERS = ["hw_device.hpp", "hw_ops.hpp", "hw_launch.hpp", "hw_multi.hpp"]
 
 ARCH = os.environ.get("HWAVE_ARCH", "gfx950")
 FLAGS = [

@@ -1,0 +1,165 @@
+// Autotuner: picks a table configuration (design, bucket size, tile width) for a
+// capacity class by timing every candidate of the multi-table menu on the work
+// it will run -- a group-by SUM upsert batch that fills tables of that class to
+// the requested load, spread over enough tables of the class to fill the GPU,
+// through the persistent multi-table kernel.  The paper tunes bucket and tile
+// size by exhaustive search per design (Section 5); this does the same per
+// capacity class, at run time.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "hashwave.h"
+#include "hw_multi.hpp"
+
+using namespace hw;
+
+namespace {
+
+// Bijective 64-bit and 32-bit mixers (the splitmix64 output function, and
+// Wellons' "lowbias32"): distinct indices give distinct synthetic keys.
+__device__ __forceinline__ uint64_t bij64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint32_t bij32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Group-by batch for n_tab tables: table t gets ops [t*2D, (t+1)*2D): its D
+// distinct keys interleaved with D repeats drawn from them; values pseudo-random.
+template <typename K>
+__global__ void k_gen_groupby(K* keys, K* vals, uint32_t n_tab, uint64_t D, uint64_t seed) {
+  const uint64_t total = (uint64_t)n_tab * 2 * D;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t t = i / (2 * D), j = i % (2 * D);
+    const uint64_t idx = (j & 1) ? bij64(seed ^ (i * 0x9E3779B97F4A7C15ull)) % D : (j >> 1);
+    K k;
+    if constexpr (sizeof(K) == 8) {
+      k = bij64(idx + t * 0x100000000ull + seed);
+      if (k >= Keys<uint64_t>::FIRST_INVALID) k >>= 1;
+    } else {
+      k = bij32((uint32_t)(idx + (uint32_t)seed));
+      if (k >= Keys<uint32_t>::FIRST_INVALID) k >>= 1;
+    }
+    keys[i] = k;
+    vals[i] = (K)bij64(i + seed * 3);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, double load, uint32_t reps,
+                   uint32_t flags, hwave_tune_result* results, uint32_t results_cap, uint32_t* n_results,
+                   hwave_tune_result* best, void* stream) {
+  if ((kv_bits != 32 && kv_bits != 64) || capacity == 0 || !(load > 0.0 && load <= 1.0) || !best)
+    return HWAVE_EINVAL;
+  if (n_results) *n_results = 0;
+  hipStream_t s = (hipStream_t)stream;
+  int n_menu = 0;
+  const MenuEntry* menu = kv_bits == 64 ? menu_entries(MenuU64{}, &n_menu) : menu_entries(MenuU32{}, &n_menu);
+  if (reps == 0) reps = 3;
+  // enough tables of this class to give the launch at least ~4M slots of work
+  uint64_t n_tab64 = (4ull << 20) / capacity;
+  if (n_tab64 < 1) n_tab64 = 1;
+  if (n_tab64 > 8192) n_tab64 = 8192;
+  const uint32_t n_tab = (uint32_t)n_tab64;
+  best->gops = -1.0;
+  uint32_t nres = 0;
+  const size_t kb = kv_bits / 8;
+  for (int c = 0; c < n_menu; c++) {
+    const hwave_design d = (hwave_design)menu[c].design;
+    if (!(design_mask & (1u << d))) continue;
+    hwave_config cfg;
+    memset(&cfg, 0, sizeof cfg);
+    cfg.kv_bits = kv_bits;
+    cfg.bucket_slots = (uint32_t)menu[c].bucket;
+    cfg.tile = (uint32_t)menu[c].tile;
+    cfg.flags = flags;
+    uint64_t tb = 0;
+    int rc = hwave_table_bytes(capacity, d, &cfg, &tb);
+    if (rc == HWAVE_EUNSUPPORTED) continue;
+    if (rc) return rc;
+    const uint64_t real_cap = [&] {
+      uint64_t nb = 1, want = (capacity + cfg.bucket_slots - 1) / cfg.bucket_slots;
+      while (nb < want) nb <<= 1;
+      return nb * cfg.bucket_slots;
+    }();
+    const uint64_t D = (uint64_t)(load * (double)real_cap);
+    if (D == 0) continue;
+    const uint64_t n_ops = (uint64_t)n_tab * 2 * D;
+    uint8_t* region = nullptr;
+    void *keys = nullptr, *vals = nullptr;
+    hipError_t e = hipMalloc(&region, tb * n_tab);
+    if (e == hipSuccess) e = hipMalloc(&keys, n_ops * kb);
+    if (e == hipSuccess) e = hipMalloc(&vals, n_ops * kb);
+    if (e != hipSuccess) {
+      if (region) (void)hipFree(region);
+      if (keys) (void)hipFree(keys);
+      if (vals) (void)hipFree(vals);
+      return HWAVE_ENOMEM;
+    }
+    std::vector<hwave_table*> tabs(n_tab, nullptr);
+    for (uint32_t t = 0; t < n_tab && rc == HWAVE_OK; t++)
+      rc = hwave_create_in(&tabs[t], region + tb * t, tb, capacity, d, &cfg, stream);
+    hwave_multi* m = nullptr;
+    if (rc == HWAVE_OK) rc = hwave_multi_create(&m, tabs.data(), n_tab, stream);
+    std::vector<uint64_t> offs(n_tab + 1);
+    for (uint32_t t = 0; t <= n_tab; t++) offs[t] = (uint64_t)t * 2 * D;
+    float total_ms = 0.f;
+    if (rc == HWAVE_OK) {
+      if (kv_bits == 64)
+        hipLaunchKernelGGL(k_gen_groupby<uint64_t>, dim3(2048), dim3(256), 0, s, (uint64_t*)keys, (uint64_t*)vals,
+                           n_tab, D, 0x5eedull + c);
+      else
+        hipLaunchKernelGGL(k_gen_groupby<uint32_t>, dim3(2048), dim3(256), 0, s, (uint32_t*)keys, (uint32_t*)vals,
+                           n_tab, D, 0x5eedull + c);
+      hipEvent_t a, b;
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      for (uint32_t r = 0; r <= reps && rc == HWAVE_OK; r++) {  // r == 0: warmup
+        rc = hwave_multi_clear(m, stream);
+        if (rc) break;
+        (void)hipEventRecord(a, s);
+        rc = hwave_multi_upsert(m, offs.data(), keys, vals, HWAVE_SUM, nullptr, stream);
+        (void)hipEventRecord(b, s);
+        if (hipEventSynchronize(b) != hipSuccess) rc = HWAVE_EDEVICE;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (r > 0) total_ms += ms;
+      }
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+    if (m) hwave_multi_destroy(m);
+    for (auto* t : tabs)
+      if (t) hwave_destroy(t);
+    (void)hipFree(region);
+    (void)hipFree(keys);
+    (void)hipFree(vals);
+    if (rc) return rc;
+    hwave_tune_result res;
+    res.design = (uint32_t)d;
+    res.bucket_slots = cfg.bucket_slots;
+    res.tile = cfg.tile;
+    res.kv_bits = kv_bits;
+    res.gops = (double)n_ops * reps / ((double)total_ms * 1e6);
+    if (results && nres < results_cap) results[nres] = res;
+    nres++;
+    if (res.gops > best->gops) *best = res;
+  }
+  if (n_results) *n_results = nres;
+  return best->gops > 0 ? HWAVE_OK : HWAVE_EUNSUPPORTED;
+}
+
+}  // extern "C"

@@ -10,6 +10,7 @@
 
 #include "hashwave.h"
 #include "hw_launch.hpp"
+#include "hw_multi.hpp"
 
 using namespace hw;
 
@@ -424,6 +425,193 @@ const char* hwave_strerror(int code) {
 }
 
 int hwave_last_hip_error(void) { return g_last_hip_error; }
+
+// ---------------------------------------------------------------- multi-table
+
+}  // extern "C"
+
+struct hwave_multi {
+  int device;
+  int kv_bits;
+  uint32_t n_tables;
+  std::vector<uint64_t> table_bytes;  // footprint per table (queue placement)
+  MultiTable* d_tables = nullptr;
+  uint32_t* d_heads = nullptr;
+  MultiItem* d_items = nullptr;
+  size_t items_cap = 0;
+  MultiItem* h_stage = nullptr;  // pinned staging of the item list
+  size_t stage_cap = 0;
+  hipEvent_t staged = nullptr;   // recorded after the last item upload
+  bool staged_pending = false;
+  unsigned grid = 0;
+  std::vector<MultiItem> build;  // host scratch
+  std::vector<uint32_t> qcount;
+};
+
+namespace {
+
+// Items longer than this many ops are split, so the queues balance big tables.
+constexpr uint64_t MULTI_CHUNK = 16384;
+// Tables whose footprint fits comfortably in one XCD's L2 keep all their items on
+// one queue.
+constexpr uint64_t L2_RESIDENT_BYTES = 2ull << 20;
+
+int multi_reserve(hwave_multi* m, size_t n) {
+  if (n <= m->items_cap && n <= m->stage_cap) return HWAVE_OK;
+  size_t cap = 1024;
+  while (cap < n) cap <<= 1;
+  hipError_t e = hipDeviceSynchronize();  // the old buffers may still be read by a launch
+  if (e != hipSuccess) return hip_fail(e);
+  if (m->d_items) (void)hipFree(m->d_items);
+  if (m->h_stage) (void)hipHostFree(m->h_stage);
+  m->d_items = nullptr;
+  m->h_stage = nullptr;
+  m->items_cap = m->stage_cap = 0;
+  e = hipMalloc(&m->d_items, cap * sizeof(MultiItem));
+  if (e != hipSuccess) { g_last_hip_error = (int)e; return HWAVE_ENOMEM; }
+  e = hipHostMalloc((void**)&m->h_stage, cap * sizeof(MultiItem), hipHostMallocDefault);
+  if (e != hipSuccess) { g_last_hip_error = (int)e; return HWAVE_ENOMEM; }
+  m->items_cap = m->stage_cap = cap;
+  m->staged_pending = false;
+  return HWAVE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hwave_multi_supported(uint32_t kv_bits, hwave_design design, uint32_t bucket_slots, uint32_t tile) {
+  return multi_menu_index((int)kv_bits, (int)design, (int)bucket_slots, (int)tile) >= 0 ? 1 : 0;
+}
+
+int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n_tables, void* stream) {
+  if (!out || !tables || n_tables == 0) return HWAVE_EINVAL;
+  *out = nullptr;
+  const int kv = (int)tables[0]->cfg.kv_bits;
+  const int dev = tables[0]->device;
+  std::vector<MultiTable> h(n_tables);
+  for (uint32_t i = 0; i < n_tables; i++) {
+    const hwave_table* t = tables[i];
+    if (!t || (int)t->cfg.kv_bits != kv || t->device != dev) return HWAVE_EINVAL;
+    int cls = multi_menu_index(kv, (int)t->design, (int)t->cfg.bucket_slots, (int)t->cfg.tile);
+    if (cls < 0) return HWAVE_EUNSUPPORTED;
+    h[i].tv = t->la.tv;
+    h[i].cls = (uint32_t)cls;
+    h[i].pad = 0;
+    const uint64_t locks_off = (uint64_t)((uint8_t*)t->la.tv.locks - (uint8_t*)t->base);
+    h[i].fill_words = locks_off / 16;
+    h[i].zero_words = (t->bytes - locks_off) / 16;
+  }
+  hwave_multi* m = new hwave_multi;
+  m->device = dev;
+  m->kv_bits = kv;
+  m->n_tables = n_tables;
+  for (uint32_t i = 0; i < n_tables; i++) m->table_bytes.push_back(tables[i]->bytes);
+  hipError_t e = hipMalloc(&m->d_tables, n_tables * sizeof(MultiTable));
+  if (e == hipSuccess) e = hipMalloc(&m->d_heads, 64 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemcpyAsync(m->d_tables, h.data(), n_tables * sizeof(MultiTable),
+                                          hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&m->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    hwave_multi_destroy(m);
+    return hip_fail(e);
+  }
+  // Persistent grid: full occupancy of the multi-table kernel.
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  m->grid = (unsigned)cus * (4 * HW_MULTI_WAVES * 64 / BLOCK);
+  *out = m;
+  return HWAVE_OK;
+}
+
+int hwave_multi_destroy(hwave_multi* m) {
+  if (!m) return HWAVE_EINVAL;
+  (void)hipDeviceSynchronize();
+  if (m->d_tables) (void)hipFree(m->d_tables);
+  if (m->d_heads) (void)hipFree(m->d_heads);
+  if (m->d_items) (void)hipFree(m->d_items);
+  if (m->h_stage) (void)hipHostFree(m->h_stage);
+  if (m->staged) (void)hipEventDestroy(m->staged);
+  delete m;
+  return HWAVE_OK;
+}
+
+int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items, const void* d_keys,
+                    const void* d_vals, void* d_vals_out, uint8_t* d_status, void* stream) {
+  if (!m || (n_items && (!h_items || !d_keys))) return HWAVE_EINVAL;
+  if (n_items == 0) return HWAVE_OK;
+  // Split items into chunks and deal them to queues: small tables to queue
+  // table % NQ, big tables' chunks round-robin over all queues.
+  m->build.clear();
+  std::vector<std::vector<MultiItem>> per_q(NQ);
+  uint32_t rr = 0;
+  for (uint32_t i = 0; i < n_items; i++) {
+    const hwave_item& it = h_items[i];
+    if (it.table >= m->n_tables || it.end < it.begin) return HWAVE_EINVAL;
+    const int op = (int)(it.op & 0xFF);
+    if (op > HWAVE_OP_ERASE || ((it.op >> 8) & 0xFF) > HWAVE_MAX) return HWAVE_EINVAL;
+    if ((op == HWAVE_OP_INSERT || op == HWAVE_OP_UPSERT) && !d_vals) return HWAVE_EINVAL;
+    const bool small = m->table_bytes[it.table] <= L2_RESIDENT_BYTES;
+    for (uint64_t b = it.begin; b < it.end; b += MULTI_CHUNK) {
+      MultiItem c;
+      c.table = it.table;
+      c.op = it.op;
+      c.begin = b;
+      c.end = b + MULTI_CHUNK < it.end ? b + MULTI_CHUNK : it.end;
+      const uint32_t q = small ? it.table % NQ : (rr++ % NQ);
+      per_q[q].push_back(c);
+    }
+  }
+  size_t total = 0;
+  for (auto& v : per_q) total += v.size();
+  if (total == 0) return HWAVE_OK;
+  if (total > 0xFFFFFFFFull) return HWAVE_EINVAL;
+  int rc = multi_reserve(m, total);
+  if (rc) return rc;
+  // the staging buffer may still be in flight from the previous call
+  if (m->staged_pending) {
+    hipError_t e = hipEventSynchronize(m->staged);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  MultiQueues qs;
+  size_t at = 0;
+  for (int q = 0; q < NQ; q++) {
+    qs.start[q] = (uint32_t)at;
+    memcpy(m->h_stage + at, per_q[q].data(), per_q[q].size() * sizeof(MultiItem));
+    at += per_q[q].size();
+    qs.end[q] = (uint32_t)at;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(m->d_items, m->h_stage, total * sizeof(MultiItem), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(m->staged, s);
+  if (e != hipSuccess) return hip_fail(e);
+  m->staged_pending = true;
+  e = launch_multi(m->kv_bits, m->grid, m->d_tables, m->d_items, qs, m->d_heads, d_keys,
+                   d_vals ? d_vals : d_keys, d_vals_out, d_status, s);
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_multi_clear(hwave_multi* m, void* stream) {
+  if (!m) return HWAVE_EINVAL;
+  const unsigned grid = m->n_tables < 4096 ? m->n_tables : 4096;
+  hipError_t e = launch_multi_clear(grid, m->d_tables, m->n_tables, (hipStream_t)stream);
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_multi_upsert(hwave_multi* m, const uint64_t* h_offsets, const void* d_keys, const void* d_vals,
+                       hwave_combine combine, uint8_t* d_status, void* stream) {
+  if (!m || !h_offsets || (int)combine < HWAVE_SUM || (int)combine > HWAVE_MAX) return HWAVE_EINVAL;
+  std::vector<hwave_item> items;
+  items.reserve(m->n_tables);
+  for (uint32_t i = 0; i < m->n_tables; i++) {
+    if (h_offsets[i + 1] < h_offsets[i]) return HWAVE_EINVAL;
+    if (h_offsets[i + 1] == h_offsets[i]) continue;
+    items.push_back(hwave_item{i, (uint32_t)HWAVE_OP_UPSERT | ((uint32_t)combine << 8), h_offsets[i],
+                               h_offsets[i + 1]});
+  }
+  return hwave_multi_run(m, items.data(), (uint32_t)items.size(), d_keys, d_vals, nullptr, d_status, stream);
+}
 
 int hwave_stream_sync(void* stream) {
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);

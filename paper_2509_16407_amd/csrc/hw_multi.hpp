@@ -1,0 +1,141 @@
+// One persistent launch serving many tables of uneven capacities and configurations.
+//
+// Work is a list of items (table, operation kind, op range [begin, end)) over shared
+// key / value / output arrays.  Items are spread over NQ queues, each a slice of the
+// item array with its own head counter, so popping never funnels through a single
+// atomic address.  A wave starts at its home queue (block index mod NQ: workgroups
+// are dealt to the XCDs round-robin, so items of small tables, which the host puts
+// on queue table mod NQ, stay near one XCD's L2) and then takes work from the other
+// queues until every queue is empty; each wave visits each queue at most once after
+// finding it empty, so every wave exits.
+//
+// Per item, a wave-uniform switch selects the table's compiled configuration from a
+// menu and runs the same per-operation code as the single-table kernels, with the
+// wave's 64 lanes split into tiles of that configuration's width.
+#pragma once
+
+#include "hw_launch.hpp"
+
+namespace hw {
+
+constexpr int NQ = 8;
+
+#ifndef HW_MULTI_WAVES
+#define HW_MULTI_WAVES 6  // occupancy target of the multi-table kernel (waves per SIMD)
+#endif
+
+struct MultiItem {
+  uint32_t table;
+  uint32_t op;     // low byte: OP_*; bits 8..15: combine for OP_UPSERT
+  uint64_t begin;  // ops [begin, end) of the shared arrays
+  uint64_t end;
+};
+
+struct MultiTable {
+  TableDev tv;
+  uint32_t cls;          // index in the key width's configuration menu
+  uint32_t pad;
+  uint64_t fill_words;   // 16-byte words of slots + tags (all-ones when empty)
+  uint64_t zero_words;   // 16-byte words of locks + control (zero when empty)
+};
+
+struct MultiQueues {
+  uint32_t start[NQ];  // item index where queue q starts
+  uint32_t end[NQ];
+};
+
+template <class... Cs>
+struct Menu {
+  static constexpr int N = sizeof...(Cs);
+};
+
+// Runs ops [m.begin, m.end) of one table with configuration C on this wave.
+template <class C>
+__device__ __forceinline__ void run_item(const TableDev& tv, const MultiItem& m, const typename C::K* __restrict__ keys,
+                         const typename C::K* __restrict__ vals, typename C::K* __restrict__ out,
+                         uint8_t* __restrict__ status) {
+  using K = typename C::K;
+  const Tile<C::T> tile;
+  const uint32_t lane = __lane_id();
+  const int op = (int)(m.op & 0xFF);
+  const int combine = op == OP_INSERT ? C_KEEP : (int)((m.op >> 8) & 0xFF);
+  for (uint64_t i = m.begin + lane / C::T; i < m.end; i += 64 / C::T) {
+    const K key = keys[i];
+    uint8_t st;
+    if (op == OP_QUERY) {
+      K v;
+      st = Ops<C>::query(tv, tile, key, &v);
+      if (out && tile.leader()) out[i] = v;
+    } else if (op == OP_ERASE) {
+      st = Ops<C>::erase(tv, tile, key);
+    } else {
+      st = Ops<C>::upsert(tv, tile, key, vals[i], combine);
+    }
+    if (status && tile.leader()) status[i] = st;
+  }
+}
+
+template <class... Cs>
+__device__ __forceinline__ void dispatch(uint32_t cls, const TableDev& tv, const MultiItem& m,
+                                         const void* keys, const void* vals, void* out, uint8_t* status,
+                                         Menu<Cs...>) {
+  uint32_t i = 0;
+  (void)((cls == i++ ? (run_item<Cs>(tv, m, (const typename Cs::K*)keys, (const typename Cs::K*)vals,
+                                     (typename Cs::K*)out, status),
+                        true)
+                     : false) ||
+         ...);
+}
+
+template <class M>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HW_MULTI_WAVES, 8)))
+k_multi(const MultiTable* __restrict__ tables, const MultiItem* __restrict__ items, MultiQueues qs,
+        uint32_t* heads, const void* keys, const void* vals, void* out, uint8_t* status) {
+  const uint32_t lane = __lane_id();
+  const uint32_t home = blockIdx.x % NQ;
+  for (uint32_t k = 0; k < NQ; ++k) {
+    const uint32_t q = (home + k) % NQ;
+    const uint32_t qlen = qs.end[q] - qs.start[q];
+    while (true) {
+      uint32_t idx = 0;
+      if (lane == 0) idx = __hip_atomic_fetch_add(heads + q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      idx = __builtin_amdgcn_readfirstlane(idx);
+      if (idx >= qlen) break;
+      const MultiItem m = items[qs.start[q] + idx];
+      const MultiTable& t = tables[m.table];
+      dispatch(__builtin_amdgcn_readfirstlane(t.cls), t.tv, m, keys, vals, out, status, M{});
+    }
+  }
+}
+
+// Configuration menus of the multi-table kernel (one per key width).  The
+// autotuner chooses among these.
+using MenuU64 = Menu<Cfg<uint64_t, D_DOUBLE, 8, 8>, Cfg<uint64_t, D_DOUBLE, 16, 8>,
+                     Cfg<uint64_t, D_DOUBLE_M, 32, 4>, Cfg<uint64_t, D_DOUBLE_M, 32, 8>,
+                     Cfg<uint64_t, D_P2, 32, 8>, Cfg<uint64_t, D_P2_M, 32, 4>,
+                     Cfg<uint64_t, D_P2_M, 32, 8>, Cfg<uint64_t, D_P2_M, 64, 8>>;
+using MenuU32 = Menu<Cfg<uint32_t, D_DOUBLE, 16, 4>, Cfg<uint32_t, D_DOUBLE, 16, 8>,
+                     Cfg<uint32_t, D_DOUBLE, 32, 16>, Cfg<uint32_t, D_DOUBLE, 64, 32>,
+                     Cfg<uint32_t, D_DOUBLE, 128, 64>, Cfg<uint32_t, D_DOUBLE_M, 32, 4>,
+                     Cfg<uint32_t, D_P2, 32, 8>, Cfg<uint32_t, D_P2_M, 16, 4>,
+                     Cfg<uint32_t, D_P2_M, 32, 4>, Cfg<uint32_t, D_P2_M, 32, 8>>;
+
+struct MenuEntry {
+  int design, bucket, tile;
+};
+
+template <class... Cs>
+inline const MenuEntry* menu_entries(Menu<Cs...>, int* n) {
+  static const MenuEntry e[] = {MenuEntry{Cs::DESIGN, Cs::B, Cs::T}...};
+  *n = (int)sizeof...(Cs);
+  return e;
+}
+
+// Host launchers (inst_multi.hip).
+hipError_t launch_multi_clear(unsigned grid, const MultiTable* tables, uint32_t n_tables, hipStream_t s);
+hipError_t launch_multi(int kv_bits, unsigned grid, const MultiTable* tables, const MultiItem* items,
+                        const MultiQueues& qs, uint32_t* heads, const void* keys, const void* vals, void* out,
+                        uint8_t* status, hipStream_t s);
+int multi_menu_index(int kv_bits, int design, int bucket, int tile);
+
+}  // namespace hw

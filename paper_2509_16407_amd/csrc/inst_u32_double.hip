@@ -7,6 +7,7 @@ const KernelSet* sets_u32_double(size_t* n) {
       make_set<Cfg<uint32_t, D_DOUBLE, 8, 4>>(),    make_set<Cfg<uint32_t, D_DOUBLE, 16, 4>>(),
       make_set<Cfg<uint32_t, D_DOUBLE, 16, 8>>(),   make_set<Cfg<uint32_t, D_DOUBLE, 32, 8>>(),
       make_set<Cfg<uint32_t, D_DOUBLE, 32, 16>>(),  make_set<Cfg<uint32_t, D_DOUBLE, 64, 32>>(),
+      make_set<Cfg<uint32_t, D_DOUBLE, 128, 64>>(),
       make_set<Cfg<uint32_t, D_DOUBLE_M, 16, 4>>(), make_set<Cfg<uint32_t, D_DOUBLE_M, 32, 4>>(),
       make_set<Cfg<uint32_t, D_DOUBLE_M, 32, 8>>(), make_set<Cfg<uint32_t, D_DOUBLE_M, 32, 16>>(),
       make_set<Cfg<uint32_t, D_DOUBLE_M, 64, 8>>(),

@@ -182,6 +182,33 @@ uint64_t select_s(uint64_t seed, uint64_t n, uint64_t k, int64_t* out) {
   }
   return got;
 }
+/* 4-round Feistel permutation of 32-bit values (Luby-Rackoff), round function
+   = low 16 bits of splitmix64 keyed by (key, round): distinct x give distinct y. */
+static inline uint32_t feistel32(uint64_t key, uint32_t x) {
+  uint32_t L = x >> 16, R = x & 0xFFFFu;
+  for (int r = 0; r < 4; r++) {
+    uint32_t F = (uint32_t)(sm64_at(key ^ ((uint64_t)r << 56), R) & 0xFFFFu);
+    uint32_t nl = R;
+    R = L ^ F;
+    L = nl;
+  }
+  return (L << 16) | R;
+}
+/* Group-by batch of one table: D distinct 32-bit keys (top two patterns skipped)
+   at even positions, each followed by a uniform repeat of one of them; values
+   from a second stream.  keys/vals hold 2D entries. */
+void groupby_fill(uint64_t seed, uint64_t D, uint32_t* keys, uint32_t* vals) {
+  uint64_t got = 0;
+  uint32_t x = 0;
+  while (got < D) {
+    uint32_t k = feistel32(seed, x++);
+    if (k >= 0xFFFFFFFEu) continue;
+    keys[2 * got] = k;
+    got++;
+  }
+  for (uint64_t i = 0; i < D; i++) keys[2 * i + 1] = keys[2 * (sm64_at(seed ^ 0x5bd1e9955bd1e995ull, i) % D)];
+  for (uint64_t j = 0; j < 2 * D; j++) vals[j] = (uint32_t)sm64_at(seed ^ 0x6c62272e07bb0142ull, j);
+}
 void fy_swaps(int64_t* p, const int64_t* idx, const int64_t* j, int64_t n) {
   for (int64_t k = 0; k < n; k++) { int64_t a = idx[k], b = j[k];
     int64_t t = p[a]; p[a] = p[b]; p[b] = t; }
@@ -217,6 +244,8 @@ def _helper():
         lib.select_s.restype = U
         lib.fy_swaps.argtypes = [P, P, P, ctypes.c_int64]
         lib.fy_swaps.restype = None
+        lib.groupby_fill.argtypes = [U, U, P, P]
+        lib.groupby_fill.restype = None
         _lib = lib
     return _lib
 
@@ -374,3 +403,32 @@ def sample_without_replacement(seed: int, n: int, k: int) -> np.ndarray:
 def universe_keys(universe: int, config_id: int = 3) -> np.ndarray:
     """The key universe used by `mixed_batches` (same stream)."""
     return distinct_keys(stream_seed(config_id, 1), universe)
+
+
+def groupby_tables(exponents, load: float = 0.85, config_id: int = 4):
+    """Group-by aggregation batches for tables of capacity 2^e (e in `exponents`):
+    table t gets D_t = floor(load * 2^e) distinct uint32 keys, each followed by a
+    uniform repeat of one of them, with uint32 values.  Returns (offsets, keys,
+    vals): table t's ops are [offsets[t], offsets[t+1]) of the uint32 arrays."""
+    ds = [int(load * (1 << int(e))) for e in exponents]
+    offsets = np.zeros(len(ds) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([2 * d for d in ds])
+    keys = np.empty(int(offsets[-1]), dtype=np.uint32)
+    vals = np.empty(int(offsets[-1]), dtype=np.uint32)
+    h = _helper()
+
+    def fill(t):
+        a, d = int(offsets[t]), ds[t]
+        h.groupby_fill(_c_u64(stream_seed(config_id, 1 << 20 | t)), _c_u64(d),
+                       _cptr(keys[a: a + 2 * d]), _cptr(vals[a: a + 2 * d]))
+
+    import concurrent.futures as cf
+    import os
+    with cf.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(fill, range(len(ds))))
+    return offsets, keys, vals
+
+
+def table_exponents(n_tables: int, e_min: int, e_max: int, config_id: int = 4) -> np.ndarray:
+    """Capacity exponents uniform in [e_min, e_max] (log-uniform capacities)."""
+    return uniform_below(stream_seed(config_id, 2), 0, n_tables, e_max - e_min + 1) + e_min

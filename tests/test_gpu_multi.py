@@ -1,0 +1,118 @@
+"""The batched form: one persistent launch over many tables of uneven
+capacities and configurations, compared bit-exactly with one plain launch per
+table and with the oracle; plus the autotuner."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_16407_amd as hw
+from paper_2509_16407_amd import workloads as w
+from gpu_util import dev, host, u8
+
+pytestmark = pytest.mark.gpu
+
+MENU32 = [("DOUBLE", 16, 4), ("DOUBLE", 16, 8), ("DOUBLE", 32, 16), ("DOUBLE", 64, 32),
+          ("DOUBLE", 128, 64), ("DOUBLE_M", 32, 4), ("P2", 32, 8), ("P2_M", 16, 4), ("P2_M", 32, 4),
+          ("P2_M", 32, 8)]
+MENU64 = [("DOUBLE", 8, 8), ("DOUBLE", 16, 8), ("DOUBLE_M", 32, 4), ("DOUBLE_M", 32, 8), ("P2", 32, 8),
+          ("P2_M", 32, 4), ("P2_M", 32, 8), ("P2_M", 64, 8)]
+
+
+def _dump(t):
+    k, v = t.export()
+    k, v = host(k, t.kv_bits), host(v, t.kv_bits)
+    o = np.argsort(k)
+    return k[o], v[o]
+
+
+def test_menus_match_library():
+    for d, b, t in MENU32:
+        assert hw.multi_supported(32, d, b, t)
+    for d, b, t in MENU64:
+        assert hw.multi_supported(64, d, b, t)
+    assert not hw.multi_supported(32, "P2", 64, 32)
+
+
+@pytest.mark.parametrize("flags", [0, hw.F_NO_ERASE], ids=["locked", "noerase"])
+def test_multi_groupby_equals_plain_and_oracle(flags):
+    n = 2 * len(MENU32) * 3
+    exps = w.table_exponents(n, 9, 14, config_id=41)
+    cfgs = [MENU32[i % len(MENU32)] for i in range(n)]
+    # power-of-two-choice tables get a lower fill so no key finds both buckets full
+    offsets, keys, vals = w.groupby_tables(exps, 0.65, config_id=41)
+    A = [hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t, flags=flags) for e, (d, b, t) in zip(exps, cfgs)]
+    B = [hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t, flags=flags) for e, (d, b, t) in zip(exps, cfgs)]
+    m = hw.Multi(A)
+    kd = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    st = u8(m.upsert(offsets, kd, vd, combine="sum"))
+    for i, t in enumerate(B):  # plain form: one launch per table
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        t.upsert(kd[a:b], vd[a:b], combine="sum")
+    for i in range(n):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        kk = keys[a:b].astype(np.uint64)
+        vv = vals[a:b].astype(np.uint64)
+        om = oracle.OracleMap(key_bits=32)
+        ost = om.upsert(kk, vv)
+        assert (st[a:b] == hw.ST_DONE).sum() == (ost == oracle.DONE).sum(), i
+        assert not (st[a:b] == hw.ST_FULL).any(), i
+        ok, ov = om.dump()
+        ka, va = _dump(A[i])
+        kb, vb = _dump(B[i])
+        assert np.array_equal(ka, ok) and np.array_equal(va, ov), i
+        assert np.array_equal(kb, ok) and np.array_equal(vb, ov), i
+    m.clear()
+    assert all(t.size() == 0 for t in A)
+
+
+def test_multi_mixed_items_u64():
+    """Items of every kind across tables of every u64 menu configuration; at most
+    one writing item per table per launch, so every output is deterministic."""
+    tabs = [hw.Table(1 << 14, d, bucket=b, tile=t) for d, b, t in MENU64]
+    oms = [oracle.OracleMap() for _ in tabs]
+    m = hw.Multi(tabs)
+    pool = [w.distinct_keys(w.stream_seed(42, i), 20000) for i in range(len(tabs))]
+    # launch 1: insert 10000 keys per table
+    keys = np.concatenate([p[:10000] for p in pool])
+    vals = w.value_of(keys)
+    items = [(i, hw.OPS["insert"], i * 10000, (i + 1) * 10000) for i in range(len(tabs))]
+    st, _ = m.run(items, dev(keys), dev(vals))
+    st = u8(st)
+    for i, om in enumerate(oms):
+        assert np.array_equal(st[i * 10000:(i + 1) * 10000], om.insert(pool[i][:10000], w.value_of(pool[i][:10000])))
+    # launch 2: per table either a query item (present + absent keys) or an upsert item
+    segs, items, pos = [], [], 0
+    for i in range(len(tabs)):
+        if i % 2 == 0:
+            k = np.concatenate([pool[i][:5000], pool[i][15000:18000]])
+            op = hw.OPS["query"]
+        else:
+            k = np.concatenate([pool[i][2000:6000], pool[i][10000:12000]])
+            op = hw.OPS["upsert"] | (hw.COMBINES["sum"] << 8)
+        segs.append(k)
+        items.append((i, op, pos, pos + len(k)))
+        pos += len(k)
+    keys = np.concatenate(segs)
+    vals = w.splitmix64(43, 0, len(keys))
+    st, out = m.run(items, dev(keys), dev(vals))
+    st, out = u8(st), host(out)
+    for i, (t, op, a, b) in enumerate(items):
+        if op == hw.OPS["query"]:
+            os_, ov = oms[i].query(keys[a:b])
+            assert np.array_equal(st[a:b], os_) and np.array_equal(out[a:b], ov)
+        else:
+            os_ = oms[i].upsert(keys[a:b], vals[a:b])
+            assert np.array_equal(st[a:b], os_)
+    for i, t in enumerate(tabs):
+        ok, ov = oms[i].dump()
+        k, v = _dump(t)
+        assert np.array_equal(k, ok) and np.array_equal(v, ov)
+
+
+def test_autotune_small_class():
+    best, alls = hw.autotune(32, 1 << 12, reps=1)
+    assert len(alls) == len(MENU32)
+    assert (best["design"], best["bucket"], best["tile"]) in MENU32
+    assert best["gops"] == max(a["gops"] for a in alls) and best["gops"] > 0
