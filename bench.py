@@ -186,6 +186,171 @@ def verify_step(step: Step, d) -> None:
     del exp
 
 
+def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_reps=2, n_verify=16):
+    """The batched form (SURVEY config 4): n_tables uint32 tables with capacities 2^e,
+    e uniform in [e_min, e_max], each receiving a group-by SUM-upsert batch that
+    fills it to `load`.  Times one persistent multi-table launch (configuration
+    autotuned per capacity class) against one plain launch per table (same
+    configurations) and against one persistent launch with a fixed default
+    configuration.  Verifies every table's size and a sample against the oracle."""
+    import torch
+    import paper_2509_16407_amd as hw
+    from paper_2509_16407_amd import workloads as w
+    t0 = time.time()
+    exps = w.table_exponents(n_tables, e_min, e_max, config_id=4)
+    offsets, keys, vals = w.groupby_tables(exps, load, config_id=4)
+    n_ops = int(offsets[-1])
+    log("batched: %d tables, %d ops generated in %.1f s" % (n_tables, n_ops, time.time() - t0))
+    t0 = time.time()
+    classes = sorted(set(int(e) for e in exps))
+    tuned = {e: hw.autotune(32, 1 << e, load=load, reps=tune_reps)[0] for e in classes}
+    log("batched: autotuned %d classes in %.1f s" % (len(classes), time.time() - t0))
+    kd = torch.from_numpy(keys.view(np.int32)).cuda()
+    vd = torch.from_numpy(vals.view(np.int32)).cuda()
+    st = torch.empty(n_ops, dtype=torch.uint8, device="cuda")
+
+    def make(cfg_of):
+        tabs = []
+        for e in exps:
+            d, b, t = cfg_of(int(e))
+            tabs.append(hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t))
+        return tabs, hw.Multi(tabs)
+
+    def timed(fn, clear):
+        ms = []
+        for r in range(reps + 1):
+            clear()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            if r:
+                ms.append(a.elapsed_time(b))
+        return float(np.median(ms))
+
+    tabs, m = make(lambda e: (tuned[e]["design"], tuned[e]["bucket"], tuned[e]["tile"]))
+    ms_batched = timed(lambda: m.upsert(offsets, kd, vd, status=st), m.clear)
+
+    def plain():
+        for i, t in enumerate(tabs):
+            a, b = int(offsets[i]), int(offsets[i + 1])
+            t.upsert(kd[a:b], vd[a:b], status=st[a:b])
+    ms_plain = timed(plain, m.clear)
+    # verification on the last (plain) run's final state: sizes, and a sample vs the oracle
+    import oracle
+    ds = (offsets[1:] - offsets[:-1]) // 2
+    sizes = [t.size() for t in tabs]
+    assert sizes == [int(x) for x in ds], "table sizes"
+    pick = w.sample_without_replacement(w.stream_seed(4, 9), n_tables, min(n_verify, n_tables))
+    for i in pick.tolist():
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        om = oracle.OracleMap(key_bits=32)
+        om.upsert(keys[a:b].astype(np.uint64), vals[a:b].astype(np.uint64))
+        k, v = tabs[i].export()
+        k = k.cpu().numpy().view(np.uint32).astype(np.uint64)
+        v = v.cpu().numpy().view(np.uint32).astype(np.uint64)
+        o = np.argsort(k)
+        ok, ov = om.dump()
+        assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov), "table %d vs oracle" % i
+    log("batched: verified sizes of all tables and %d tables against the oracle" % len(pick))
+    del m, tabs
+    torch.cuda.empty_cache()
+    tabs_d, m_d = make(lambda e: ("P2_M", 32, 4))
+    ms_default = timed(lambda: m_d.upsert(offsets, kd, vd, status=st), m_d.clear)
+    del m_d, tabs_d, kd, vd, st
+    torch.cuda.empty_cache()
+    gops = lambda ms: round(n_ops / ms / 1e6, 3)
+    return {"workload": "%d uint32 tables, capacities 2^e (e uniform %d..%d), group-by SUM upserts to %.2f load"
+                        % (n_tables, e_min, e_max, load),
+            "ops": n_ops, "slots": int((1 << exps.astype(np.int64)).sum()),
+            "batched_ms": round(ms_batched, 3), "batched_gops": gops(ms_batched),
+            "plain_ms": round(ms_plain, 3), "plain_gops": gops(ms_plain),
+            "default_cfg_batched_ms": round(ms_default, 3), "default_cfg_batched_gops": gops(ms_default),
+            "speedup_vs_plain": round(ms_plain / ms_batched, 3),
+            "tuning": {str(e): "%s/b%d/t%d %.2f" % (v["design"], v["bucket"], v["tile"], v["gops"])
+                       for e, v in tuned.items()}}
+
+
+def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):
+    """The served form (SURVEY config 5): n_tables resident P2HT(M) tables of 2^log2cap
+    slots, preloaded with half of a Zipf universe of floor(0.85 * capacity) keys;
+    n_req requests arriving as a Poisson process at `rate`/s (query / upsert /
+    insert 50/30/20, sizes 2^U, U ~ U[8, 20], Zipf 0.99 keys).  The same stream is
+    replayed through the batched server and through plain one-request launches on
+    identical tables; latency = completion - arrival."""
+    import torch
+    import paper_2509_16407_amd as hw
+    from paper_2509_16407_amd import workloads as w
+    cap = 1 << log2cap
+    universe = int(0.85 * cap)
+    t0 = time.time()
+    reqs = list(w.served_requests(n_tables, universe, n_req, rate, config_id=5))
+    n_ops = sum(len(r["keys"]) for r in reqs)
+    log("served: %d requests, %d ops generated in %.1f s" % (n_req, n_ops, time.time() - t0))
+    OP = {"query": hw.OPS["query"], "insert": hw.OPS["insert"],
+          "upsert": hw.OPS["upsert"] | (hw.COMBINES["sum"] << 8)}
+    # pinned request buffers, reused by both runs
+    bufs = []
+    for r in reqs:
+        k = torch.from_numpy(r["keys"].view(np.int64)).pin_memory()
+        v = None if r["vals"] is None else torch.from_numpy(r["vals"].view(np.int64)).pin_memory()
+        o = torch.empty(len(r["keys"]), dtype=torch.int64).pin_memory()
+        st = torch.empty(len(r["keys"]), dtype=torch.uint8).pin_memory()
+        bufs.append((k, v, o, st))
+    offs = [r["t"] for r in reqs]
+
+    def run(mode):
+        tabs = [hw.Table(cap, "P2_M") for _ in range(n_tables)]
+        pre_n = universe // 2
+        for t in range(n_tables):
+            pre = w.splitmix64(w.stream_seed(5, 100 + t), 0, pre_n)
+            kk = torch.from_numpy(pre.view(np.int64)).cuda()
+            tabs[t].insert(kk, kk * 3 + 1)
+            del kk
+        torch.cuda.synchronize()
+        srv = hw.Server(tabs, mode=mode, slots=slots, slot_ops=1 << 22)
+        rs = [hw.Server.request(r["table"], OP[r["kind"]], *b) for r, b in zip(reqs, bufs)]
+        srv.replay(rs, offs)
+        srv.drain()
+        st = srv.stats()
+        srv.close()
+        res = [(b[2].numpy().copy() if r["kind"] == "query" else None, b[3].numpy().copy())
+               for r, b in zip(reqs, bufs)]
+        del tabs
+        torch.cuda.empty_cache()
+        return st, res
+
+    st_b, res_b = run("batched")
+    log("served batched: %.2f Gops/s, p50 %.2f ms, p99 %.2f ms, %.1f requests/launch"
+        % (st_b["ops"] / st_b["wall_s"] / 1e9, st_b["p50_ms"], st_b["p99_ms"], st_b["mean_requests_per_batch"]))
+    st_p, res_p = run("plain")
+    log("served plain: %.2f Gops/s, p50 %.2f ms, p99 %.2f ms"
+        % (st_p["ops"] / st_p["wall_s"] / 1e9, st_p["p50_ms"], st_p["p99_ms"]))
+    # each request's results alone (plain, serial) and in the mix (batched) agree:
+    # query outputs exactly, write statuses as per-key counts
+    same = 0
+    for r, (ob, sb), (op_, sp) in zip(reqs, res_b, res_p):
+        if r["kind"] == "query":
+            ok = np.array_equal(ob, op_) and np.array_equal(sb, sp)
+        else:
+            ok = all(np.array_equal(np.unique(r["keys"][sb == c]), np.unique(r["keys"][sp == c]))
+                     and (sb == c).sum() == (sp == c).sum() for c in (1, 2))
+        same += int(ok)
+    assert same == len(reqs), "served results differ from the one-at-a-time replay"
+    log("served: all %d requests equal alone (plain replay) and in the mix" % len(reqs))
+    f = lambda st: {"gops": round(st["ops"] / st["wall_s"] / 1e9, 3), "p50_ms": round(st["p50_ms"], 3),
+                    "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                    "wall_s": round(st["wall_s"], 4), "requests_per_launch": round(st["mean_requests_per_batch"], 2)}
+    offered = n_ops / offs[-1] / 1e9
+    return {"workload": "%d P2HT(M) tables x 2^%d slots, %d Poisson requests at %.0f/s, sizes 2^U (U~U[8,20]), "
+                        "query/upsert/insert 50/30/20, Zipf 0.99" % (n_tables, log2cap, n_req, rate),
+            "ops": n_ops, "offered_gops": round(offered, 3), "batched": f(st_b), "plain": f(st_p),
+            "identical_results": True}
+
+
 def cpu_baseline(cap_log2: int):
     """The CPU oracle (single thread) on the same step recipe at a smaller size."""
     import oracle
@@ -287,6 +452,8 @@ def main():
     ap.add_argument("--bucket", type=int, default=0)
     ap.add_argument("--mixed-batches", type=int, default=16)
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the multi-table (batched) section")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving section")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-log2cap", type=int, default=24)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -357,6 +524,27 @@ def main():
         per_step_ops["mixed"] = step.mixed_ops // len(step.mixed)
     roof = roofline(phase_ms, per_step_ops, args.steps, load_traffic())
 
+    cfg = {"workload": "load benchmark at 2^%d slots on %s (bucket %d, tile %d): insert to "
+                       "0.5/0.75/0.9, 2^%d pos+neg queries, 2^%d SUM upserts, erase 50%%, "
+                       "re-query, %d mixed 2^20-op batches"
+                       % (args.log2cap, args.design, step.t.bucket_slots, step.t.tile,
+                          args.log2cap - 1, args.log2cap - 1, len(step.mixed)),
+           "slots": step.t.capacity, "ops_per_step": ops_per_step, "key_bits": 64,
+           "parallelism": "single GPU"}
+    batched = None
+    if not args.no_batched:
+        del step
+        torch.cuda.empty_cache()
+        batched = bench_batched()
+        log("batched: %.2f Gops/s in one launch vs %.2f Gops/s plain" % (batched["batched_gops"], batched["plain_gops"]))
+
+    served = None
+    if not args.no_served:
+        if args.no_batched:
+            del step
+        torch.cuda.empty_cache()
+        served = bench_served()
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) at 2^%d" % args.cpu_log2cap)
@@ -367,19 +555,14 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "load benchmark at 2^%d slots on %s (bucket %d, tile %d): insert to "
-                               "0.5/0.75/0.9, 2^%d pos+neg queries, 2^%d SUM upserts, erase 50%%, "
-                               "re-query, %d mixed 2^20-op batches"
-                               % (args.log2cap, args.design, step.t.bucket_slots, step.t.tile,
-                                  args.log2cap - 1, args.log2cap - 1, len(step.mixed)),
-                   "slots": step.t.capacity, "ops_per_step": ops_per_step, "key_bits": 64,
-                   "parallelism": "single GPU"},
+        "config": cfg,
         "phases": rates,
         "insert_0.9_gops": rates["insert_0.9"]["gops"], "query_gops": rates["query_pos"]["gops"],
         "upsert_gops": rates["upsert"]["gops"],
         "p50_batch_ms": None if p50 is None else round(p50, 4),
         "p99_batch_ms": None if p99 is None else round(p99, 4),
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "served": served,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(result), flush=True)

@@ -252,6 +252,70 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
                    uint32_t flags, hwave_tune_result* results, uint32_t results_cap, uint32_t* n_results,
                    hwave_tune_result* best, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Served form: a request loop over resident tables (continuous batching).
+ *
+ * A request is one operation kind on n keys of one table, with its arrays in
+ * host memory (pinned -- hipHostMalloc or torch pin_memory -- for asynchronous
+ * copies); they must stay valid until the request completes.  A worker thread
+ * admits pending requests into the next batch while their data fits a device
+ * staging slot of `slot_ops` operations (admission by memory), packs them into
+ * one persistent multi-table launch, and keeps up to `slots` batches in flight
+ * with copies and kernels overlapped on separate streams.  A request that
+ * writes a table never shares a launch with another request on that table and
+ * requests on a table are admitted in submission order, so each request's
+ * results equal those of a one-at-a-time replay in submission order.
+ * HWAVE_SERVE_PLAIN serves one request at a time with the single-table kernels,
+ * waiting for each: the baseline.
+ */
+typedef struct hwave_server hwave_server;
+
+enum { HWAVE_SERVE_BATCHED = 0, HWAVE_SERVE_PLAIN = 1 };
+
+typedef struct {
+  uint32_t table;      /* index into the server's tables                      */
+  uint32_t op;         /* hwave_op | (hwave_combine << 8)                      */
+  uint64_t n;          /* operations (1 .. slot_ops)                           */
+  const void* h_keys;  /* n keys                                               */
+  const void* h_vals;  /* n values (insert / upsert)                           */
+  void* h_vals_out;    /* n values out (query; nullable)                       */
+  uint8_t* h_status;   /* n status bytes out (nullable)                        */
+} hwave_request;
+
+typedef struct {
+  uint32_t mode;          /* HWAVE_SERVE_*                                     */
+  uint32_t slots;         /* batches in flight (batched mode)                  */
+  uint64_t slot_ops;      /* staging capacity per batch, in operations         */
+  uint32_t max_requests;  /* per batch (0 = 65536)                             */
+  int32_t device;
+} hwave_server_config;
+
+typedef struct {
+  uint64_t requests, ops, batches;
+  double mean_requests_per_batch;
+  double wall_s;                      /* first arrival to last completion     */
+  double p50_ms, p99_ms, max_ms, mean_ms; /* completion - arrival             */
+} hwave_serve_stats;
+
+/* The tables (same key width; in the multi-table menu for batched mode) must
+ * outlive the server. */
+int hwave_server_create(hwave_server** out, hwave_table* const* tables, uint32_t n_tables,
+                        const hwave_server_config* cfg);
+/* Queues a request; arrival_s (hwave_now() clock, 0 = now) is its arrival time
+ * for latency accounting.  *ticket identifies it for hwave_server_poll. */
+int hwave_server_submit(hwave_server* s, const hwave_request* r, double arrival_s, uint64_t* ticket);
+int hwave_server_poll(hwave_server* s, uint64_t ticket, int* done);
+/* Blocks until every submitted request has completed. */
+int hwave_server_drain(hwave_server* s);
+/* Load generator: submits reqs[i] at t0 + offsets_s[i] (t0 = now + 1 ms, written
+ * to *t0_out), sleeping between arrivals; returns when all are submitted. */
+int hwave_server_replay(hwave_server* s, const hwave_request* reqs, const double* offsets_s, uint64_t n,
+                        double* t0_out);
+int hwave_server_stats(hwave_server* s, hwave_serve_stats* out);
+int hwave_server_destroy(hwave_server* s);
+/* Seconds on the server's monotonic clock. */
+double hwave_now(void);
+
 /* Text of a return code; HIP error code of the last failing HIP call. */
 const char* hwave_strerror(int code);
 int hwave_last_hip_error(void);

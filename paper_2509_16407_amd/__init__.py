@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Table", "Multi", "lib", "autotune", "DESIGNS", "COMBINES", "OPS", "HashWaveError"]
+__all__ = ["Table", "Multi", "Server", "lib", "autotune", "DESIGNS", "COMBINES", "OPS", "HashWaveError"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhashwave.so")
@@ -44,6 +44,24 @@ class _Item(ctypes.Structure):
 class _Tune(ctypes.Structure):
     _fields_ = [("design", ctypes.c_uint32), ("bucket_slots", ctypes.c_uint32), ("tile", ctypes.c_uint32),
                 ("kv_bits", ctypes.c_uint32), ("gops", ctypes.c_double)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_uint32), ("op", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("h_keys", ctypes.c_void_p), ("h_vals", ctypes.c_void_p), ("h_vals_out", ctypes.c_void_p),
+                ("h_status", ctypes.c_void_p)]
+
+
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("slot_ops", ctypes.c_uint64),
+                ("max_requests", ctypes.c_uint32), ("device", ctypes.c_int32)]
+
+
+class _ServeStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("ops", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("mean_requests_per_batch", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double)]
 
 
 class _Raw(ctypes.Structure):
@@ -96,6 +114,14 @@ def _bind(L):
         "hwave_multi_run": (I, [P, P, ctypes.c_uint32, P, P, P, P, P]),
         "hwave_multi_clear": (I, [P, P]),
         "hwave_multi_upsert": (I, [P, P, P, P, I, P, P]),
+        "hwave_server_create": (I, [ctypes.POINTER(P), P, ctypes.c_uint32, ctypes.POINTER(_ServerCfg)]),
+        "hwave_server_submit": (I, [P, ctypes.POINTER(_Request), ctypes.c_double, ctypes.POINTER(U64)]),
+        "hwave_server_poll": (I, [P, U64, ctypes.POINTER(I)]),
+        "hwave_server_drain": (I, [P]),
+        "hwave_server_replay": (I, [P, P, P, U64, ctypes.POINTER(ctypes.c_double)]),
+        "hwave_server_stats": (I, [P, ctypes.POINTER(_ServeStats)]),
+        "hwave_server_destroy": (I, [P]),
+        "hwave_now": (ctypes.c_double, []),
         "hwave_autotune": (I, [ctypes.c_uint32, U64, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.POINTER(_Tune), ctypes.c_uint32,
                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_Tune), P]),
@@ -318,6 +344,67 @@ class Multi:
         _check(lib().hwave_multi_upsert(self.h, ctypes.cast(offs, ctypes.c_void_p), _ptr(keys), _ptr(vals),
                                         COMBINES[combine], _ptr(status), _stream(stream)))
         return status
+
+
+class Server:
+    """Request loop over resident tables (C-ABI hwave_server_*).
+
+    mode "batched": continuous batching into persistent multi-table launches;
+    mode "plain": one request at a time with single-table launches (baseline).
+    Request arrays are pinned CPU tensors (torch pin_memory) the caller keeps
+    alive until drain()."""
+
+    def __init__(self, tables, mode="batched", slots=3, slot_ops=1 << 22, max_requests=0, device=0):
+        self.tables = list(tables)
+        arr = (ctypes.c_void_p * len(self.tables))(*[t.h.value for t in self.tables])
+        cfg = _ServerCfg(0 if mode == "batched" else 1, slots, slot_ops, max_requests, device)
+        h = ctypes.c_void_p()
+        _check(lib().hwave_server_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p),
+                                         len(self.tables), ctypes.byref(cfg)))
+        self.h = h
+        self._keep = []
+
+    @staticmethod
+    def request(table, op, keys, vals=None, out=None, status=None):
+        n = keys.numel()
+        return _Request(int(table), int(op), n, keys.data_ptr(), 0 if vals is None else vals.data_ptr(),
+                        0 if out is None else out.data_ptr(), 0 if status is None else status.data_ptr())
+
+    def submit(self, table, op, keys, vals=None, out=None, status=None, arrival=0.0):
+        r = self.request(table, op, keys, vals, out, status)
+        t = ctypes.c_uint64()
+        _check(lib().hwave_server_submit(self.h, ctypes.byref(r), arrival, ctypes.byref(t)))
+        self._keep.append((keys, vals, out, status))
+        return t.value
+
+    def replay(self, requests, offsets_s):
+        """requests: list of _Request (see request()); offsets_s: arrival times (s)."""
+        arr = (_Request * len(requests))(*requests)
+        offs = (ctypes.c_double * len(offsets_s))(*[float(x) for x in offsets_s])
+        t0 = ctypes.c_double()
+        _check(lib().hwave_server_replay(self.h, ctypes.cast(arr, ctypes.c_void_p),
+                                         ctypes.cast(offs, ctypes.c_void_p), len(requests), ctypes.byref(t0)))
+        return t0.value
+
+    def drain(self):
+        _check(lib().hwave_server_drain(self.h))
+
+    def stats(self):
+        st = _ServeStats()
+        _check(lib().hwave_server_stats(self.h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in _ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hwave_server_destroy(self.h)
+            self.h = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def multi_supported(kv_bits, design, bucket, tile) -> bool:

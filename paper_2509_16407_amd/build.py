@@ -14,7 +14,8 @@ OUT = os.path.join(HERE, "libhashwave.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = ["capi.hip", "inst_u64_double.hip", "inst_u64_p2.hip", "inst_u32_double.hip",
-           "inst_u32_p2.hip", "inst_multi.hip", "autotune.hip"]
+           "inst_u32_p2.hip", "inst_multi.hip", "autotune.hip",
+           "server.hip"]
 HEADERS = ["hw_device.hpp", "hw_ops.hpp", "hw_launch.hpp", "hw_multi.hpp"]
 
 ARCH = os.environ.get("HWAVE_ARCH", "gfx950")
@@ -46,7 +47,7 @@ def build(extra_flags=(), out: str = OUT, jobs: int | None = None) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, list(extra_flags)), SOURCES))
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-lpthread", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)

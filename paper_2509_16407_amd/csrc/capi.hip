@@ -450,8 +450,11 @@ struct hwave_multi {
 
 namespace {
 
-// Items longer than this many ops are split, so the queues balance big tables.
+// Items are split into chunks of at most this many ops so the queues balance big
+// tables; the chunk shrinks (down to MULTI_CHUNK_MIN) when a launch has too little
+// work to give every wave of the persistent grid several chunks.
 constexpr uint64_t MULTI_CHUNK = 16384;
+constexpr uint64_t MULTI_CHUNK_MIN = 256;
 // Tables whose footprint fits comfortably in one XCD's L2 keep all their items on
 // one queue.
 constexpr uint64_t L2_RESIDENT_BYTES = 2ull << 20;
@@ -546,6 +549,13 @@ int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items,
   m->build.clear();
   std::vector<std::vector<MultiItem>> per_q(NQ);
   uint32_t rr = 0;
+  uint64_t total_ops = 0;
+  for (uint32_t i = 0; i < n_items; i++)
+    if (h_items[i].end > h_items[i].begin) total_ops += h_items[i].end - h_items[i].begin;
+  const uint64_t waves = (uint64_t)m->grid * (BLOCK / 64);
+  uint64_t chunk = total_ops / (4 * waves);
+  if (chunk > MULTI_CHUNK) chunk = MULTI_CHUNK;
+  if (chunk < MULTI_CHUNK_MIN) chunk = MULTI_CHUNK_MIN;
   for (uint32_t i = 0; i < n_items; i++) {
     const hwave_item& it = h_items[i];
     if (it.table >= m->n_tables || it.end < it.begin) return HWAVE_EINVAL;
@@ -553,12 +563,12 @@ int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items,
     if (op > HWAVE_OP_ERASE || ((it.op >> 8) & 0xFF) > HWAVE_MAX) return HWAVE_EINVAL;
     if ((op == HWAVE_OP_INSERT || op == HWAVE_OP_UPSERT) && !d_vals) return HWAVE_EINVAL;
     const bool small = m->table_bytes[it.table] <= L2_RESIDENT_BYTES;
-    for (uint64_t b = it.begin; b < it.end; b += MULTI_CHUNK) {
+    for (uint64_t b = it.begin; b < it.end; b += chunk) {
       MultiItem c;
       c.table = it.table;
       c.op = it.op;
       c.begin = b;
-      c.end = b + MULTI_CHUNK < it.end ? b + MULTI_CHUNK : it.end;
+      c.end = b + chunk < it.end ? b + chunk : it.end;
       const uint32_t q = small ? it.table % NQ : (rr++ % NQ);
       per_q[q].push_back(c);
     }

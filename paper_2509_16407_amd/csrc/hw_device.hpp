@@ -170,14 +170,16 @@ __device__ __forceinline__ bool try_lock(uint32_t* locks, uint32_t b, const Tile
   return (old & bit) == 0;
 }
 
-// Backoff between failed lock attempts: a pause that doubles up to ~55 us
-// (256 x 512 cycles).
+// Backoff between failed lock attempts: a pause that doubles from 128 cycles up
+// to ~3.4 us (64 x 128 cycles), about one critical section.  Waiters poll the
+// lock word with loads between attempts, so short pauses cost no atomics; long
+// pauses would leave a released lock idle while its waiters sleep.
 struct Backoff {
   uint32_t n = 0;
   __device__ __forceinline__ void pause() {
-    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(8);
+    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(2);
   }
-  __device__ __forceinline__ void grow() { n = n ? (n < 256 ? 2 * n : 256) : 1; }
+  __device__ __forceinline__ void grow() { n = n ? (n < 64 ? 2 * n : 64) : 1; }
 };
 
 // Whether bucket b's lock bit currently reads clear (a coherent load of the

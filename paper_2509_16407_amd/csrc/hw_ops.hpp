@@ -390,7 +390,7 @@ struct Ops {
   //
   // Waiting for the lock: after a failed attempt a tile backs off, then polls
   // the lock word with a load and tries the atomic only when the bit reads
-  // clear -- or on every 64th attempt regardless, so progress never depends on
+  // clear -- or on every 256th attempt regardless, so progress never depends on
   // how soon a load observes the release.  In a table that never erases, a slot
   // once filled keeps its key for good (stability, Section 2.1), so a present
   // key is combined in place without the lock (as the paper does for sparse
@@ -421,7 +421,7 @@ struct Ops {
           continue;
         }
       }
-      const bool go = (attempt & 63) == 0 || lock_looks_free(tv.locks, h.b1, tile);
+      const bool go = (attempt & 255) == 0 || lock_looks_free(tv.locks, h.b1, tile);
       ++attempt;
       if (go && try_lock(tv.locks, h.b1, tile)) {
         if constexpr (C::DOUBLE)
@@ -529,7 +529,7 @@ struct Ops {
     uint32_t attempt = 0;
     while (pending) {
       bo.pause();
-      const bool go = (attempt & 63) == 0 || lock_looks_free(tv.locks, h.b1, tile);
+      const bool go = (attempt & 255) == 0 || lock_looks_free(tv.locks, h.b1, tile);
       ++attempt;
       if (go && try_lock(tv.locks, h.b1, tile)) {
         if constexpr (C::DOUBLE) {

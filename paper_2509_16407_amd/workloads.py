@@ -174,6 +174,9 @@ static inline uint64_t sm64_at(uint64_t seed, uint64_t i) {
 void sm64_fill(uint64_t seed, uint64_t start, uint64_t count, uint64_t* out) {
   for (uint64_t i = 0; i < count; i++) out[i] = sm64_at(seed, start + i);
 }
+void sm64_gather(uint64_t seed, const int64_t* idx, uint64_t count, uint64_t* out) {
+  for (uint64_t i = 0; i < count; i++) out[i] = sm64_at(seed, (uint64_t)idx[i]);
+}
 uint64_t select_s(uint64_t seed, uint64_t n, uint64_t k, int64_t* out) {
   uint64_t got = 0;
   for (uint64_t i = 0; i < n && got < k; i++) {
@@ -240,6 +243,8 @@ def _helper():
         P, U = ctypes.c_void_p, ctypes.c_uint64
         lib.sm64_fill.argtypes = [U, U, U, P]
         lib.sm64_fill.restype = None
+        lib.sm64_gather.argtypes = [U, P, U, P]
+        lib.sm64_gather.restype = None
         lib.select_s.argtypes = [U, U, U, P]
         lib.select_s.restype = U
         lib.fy_swaps.argtypes = [P, P, P, ctypes.c_int64]
@@ -432,3 +437,42 @@ def groupby_tables(exponents, load: float = 0.85, config_id: int = 4):
 def table_exponents(n_tables: int, e_min: int, e_max: int, config_id: int = 4) -> np.ndarray:
     """Capacity exponents uniform in [e_min, e_max] (log-uniform capacities)."""
     return uniform_below(stream_seed(config_id, 2), 0, n_tables, e_max - e_min + 1) + e_min
+
+
+def splitmix64_at(seed: int, idx: np.ndarray) -> np.ndarray:
+    """Elements idx[i] of the splitmix64 stream `seed` (uint64)."""
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(len(idx), dtype=np.uint64)
+    if len(idx):
+        _helper().sm64_gather(_c_u64(seed & U64_MAX), _cptr(idx), _c_u64(len(idx)), _cptr(out))
+    return out
+
+
+def served_requests(n_tables: int, universe: int, n_req: int, rate_per_s: float, log2_min: float = 8,
+                    log2_max: float = 20, theta: float = 0.99, mix=(0.5, 0.3, 0.2), config_id: int = 5):
+    """Request stream of the served form: Poisson arrivals at `rate_per_s` (exponential
+    gaps), table uniform over n_tables, kind query / upsert / insert with
+    probabilities `mix`, size floor(2^U) with U uniform in [log2_min, log2_max], keys
+    Zipf(theta) ranks over a per-table universe whose rank-r key is element r of
+    stream (config, 100 + table).  Yields dicts (t_offset, table, kind, keys, vals);
+    insert values are 3k+1, upsert values a separate stream."""
+    u = unit_float(stream_seed(config_id, 1), 0, 4 * n_req)
+    z = Zipf(universe, theta)
+    t = 0.0
+    zpos = 0
+    for i in range(n_req):
+        t += -np.log(1.0 - u[4 * i]) / rate_per_s
+        table = min(int(u[4 * i + 1] * n_tables), n_tables - 1)
+        r = u[4 * i + 2]
+        kind = "query" if r < mix[0] else ("upsert" if r < mix[0] + mix[1] else "insert")
+        n = int(2.0 ** (log2_min + (log2_max - log2_min) * u[4 * i + 3]))
+        ranks = z.ranks(stream_seed(config_id, 2), zpos, n)
+        keys = splitmix64_at(stream_seed(config_id, 100 + table), ranks)
+        if kind == "insert":
+            vals = value_of(keys)
+        elif kind == "upsert":
+            vals = splitmix64(stream_seed(config_id, 3), zpos, n)
+        else:
+            vals = None
+        zpos += n
+        yield dict(t=t, table=table, kind=kind, keys=keys, vals=vals)

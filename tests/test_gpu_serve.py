@@ -1,0 +1,113 @@
+"""The served form: requests of uneven sizes arriving over time are batched
+continuously into multi-table launches; every request's outputs must equal a
+one-at-a-time replay in submission order (plain mode) and the oracle's."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_16407_amd as hw
+from paper_2509_16407_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+OPQ = hw.OPS["query"]
+OPI = hw.OPS["insert"]
+OPU = hw.OPS["upsert"] | (hw.COMBINES["sum"] << 8)
+
+
+def _pinned(a):
+    t = torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy())
+    return t.pin_memory()
+
+
+def _make_requests(n_tables, universe, n_req, seed):
+    """Zipf keys per table; op kinds query/upsert/insert 50/30/20; sizes 2^U, U ~ U[3, 11];
+    insert values 3k+1 so duplicate inserts are deterministic."""
+    uk = [w.distinct_keys(w.stream_seed(seed, 100 + t), universe) for t in range(n_tables)]
+    z = w.Zipf(universe, 0.99)
+    u = w.unit_float(w.stream_seed(seed, 1), 0, 3 * n_req)
+    reqs = []
+    zpos = 0
+    for i in range(n_req):
+        t = int(u[3 * i] * n_tables)
+        r = u[3 * i + 1]
+        op = OPQ if r < 0.5 else (OPU if r < 0.8 else OPI)
+        n = int(2 ** (3 + 8 * u[3 * i + 2]))
+        ranks = z.ranks(w.stream_seed(seed, 2), zpos, n)
+        zpos += n
+        keys = uk[t][ranks]
+        if op == OPI:
+            vals = w.value_of(keys)
+        elif op == OPU:
+            vals = w.splitmix64(w.stream_seed(seed, 3), zpos, n)
+        else:
+            vals = None
+        reqs.append((t, op, keys, vals))
+    return uk, reqs
+
+
+def _serve(tables, reqs, mode, gap_s):
+    srv = hw.Server(tables, mode=mode, slots=3, slot_ops=1 << 16)
+    bufs, rs = [], []
+    for t, op, keys, vals in reqs:
+        kt = _pinned(keys)
+        vt = None if vals is None else _pinned(vals)
+        out = torch.zeros(len(keys), dtype=torch.int64).pin_memory()
+        st = torch.zeros(len(keys), dtype=torch.uint8).pin_memory()
+        bufs.append((kt, vt, out, st))
+        rs.append(hw.Server.request(t, op, kt, vt, out, st))
+    offs = np.arange(len(reqs)) * gap_s
+    srv.replay(rs, offs)
+    srv.drain()
+    stats = srv.stats()
+    srv.close()
+    res = [(b[2].numpy().view(np.uint64).copy(), b[3].numpy().copy()) for b in bufs]
+    return res, stats
+
+
+def _counts(keys, st, code):
+    u, c = np.unique(keys[st == code], return_counts=True)
+    return dict(zip(u.tolist(), c.tolist()))
+
+
+@pytest.mark.parametrize("design", ["P2_M", "DOUBLE_M"])
+def test_served_results_equal_serial_replay_and_oracle(design):
+    n_tables, universe = 8, 1 << 14
+    uk, reqs = _make_requests(n_tables, universe, 600, seed=61)
+    A = [hw.Table(1 << 16, design) for _ in range(n_tables)]
+    B = [hw.Table(1 << 16, design) for _ in range(n_tables)]
+    oms = [oracle.OracleMap() for _ in range(n_tables)]
+    for t in range(n_tables):  # preload half of each universe
+        pre = uk[t][: universe // 2]
+        kk = torch.from_numpy(pre.view(np.int64).copy()).cuda()
+        vv = torch.from_numpy(w.value_of(pre).view(np.int64).copy()).cuda()
+        A[t].insert(kk, vv)
+        B[t].insert(kk, vv)
+        oms[t].insert(pre, w.value_of(pre))
+    torch.cuda.synchronize()
+    served, st_a = _serve(A, reqs, "batched", 20e-6)
+    plain, st_b = _serve(B, reqs, "plain", 20e-6)
+    assert st_a["requests"] == st_b["requests"] == len(reqs)
+    assert st_a["mean_requests_per_batch"] > 1.0  # batching really happened
+    for i, (t, op, keys, vals) in enumerate(reqs):
+        out_a, s_a = served[i]
+        out_b, s_b = plain[i]
+        if op == OPQ:
+            os_, ov = oms[t].query(keys)
+            assert np.array_equal(s_a, os_) and np.array_equal(out_a, ov), i
+            assert np.array_equal(s_b, os_) and np.array_equal(out_b, ov), i
+        else:
+            os_ = oms[t].apply(keys, vals, default_op=hw.OPS["insert"] if op == OPI else hw.OPS["upsert"],
+                               combine=oracle.SUM)[0]
+            for code in (1, 2):
+                assert _counts(keys, s_a, code) == _counts(keys, os_, code), i
+                assert _counts(keys, s_b, code) == _counts(keys, os_, code), i
+    for t in range(n_tables):
+        ok, ov = oms[t].dump()
+        for tab in (A[t], B[t]):
+            k, v = tab.export()
+            k = k.cpu().numpy().view(np.uint64)
+            v = v.cpu().numpy().view(np.uint64)
+            o = np.argsort(k)
+            assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov)
