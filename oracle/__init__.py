@@ -39,14 +39,15 @@ MISS, DONE, EXISTED, FULL, INVALID = 0, 1, 2, 3, 4
 DOUBLE, DOUBLE_M, P2, P2_M = 0, 1, 2, 3
 
 
-def build(force: bool = False, extra_flags=()) -> str:
+def build(force: bool = False, extra_flags=(), out: str | None = None) -> str:
     """Compile the oracle with the host C++ compiler; returns the library path."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
+    out = out or LIB
+    if force or out != LIB or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+        tmp = out + ".tmp%d" % os.getpid()
         cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", *extra_flags, SRC, "-o", tmp]
         subprocess.check_call(cmd)
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
 
 
 class _Report(ctypes.Structure):
@@ -61,11 +62,14 @@ _lib = None
 
 
 def load(path: str | None = None):
+    """The oracle library.  HW_ORACLE_LIB names an alternative build (used only by
+    the mutation test, which plants known mistakes in copies of the oracle)."""
     global _lib
     if path is not None:
         return _bind(ctypes.CDLL(path))
     if _lib is None:
-        _lib = _bind(ctypes.CDLL(build()))
+        alt = os.environ.get("HW_ORACLE_LIB")
+        _lib = _bind(ctypes.CDLL(alt if alt else build()))
     return _lib
 
 

@@ -33,6 +33,12 @@
 //     Table 1 by the tests, which is what ties the checker's model to the paper.
 //
 // Every function is a plain C ABI for ctypes.
+//
+// ORC_MUTANT (0 = none) plants one known mistake, so the test suite can show
+// that its pins catch it; the shipped build never sets it.
+#ifndef ORC_MUTANT
+#define ORC_MUTANT 0
+#endif
 
 #include <algorithm>
 #include <cstdint>
@@ -67,7 +73,7 @@ static uint64_t width_mask(int bits) { return bits == 64 ? ~0ull : ((1ull << bit
 
 static bool is_sentinel(const orc_map* h, uint64_t k) {
   uint64_t top = width_mask(h->key_bits);
-  int n_reserved = h->key_bits == 64 ? 3 : 2;
+  int n_reserved = h->key_bits == 64 ? (ORC_MUTANT == 2 ? 2 : 3) : 2;
   return k > top - (uint64_t)n_reserved;
 }
 
@@ -85,8 +91,8 @@ uint64_t orc_map_size(const orc_map* h) { return (uint64_t)h->m.size(); }
 
 static uint64_t combine(int op, uint64_t old, uint64_t v, uint64_t mask) {
   switch (op) {
-    case ORC_SUM: return (old + v) & mask;
-    case ORC_KEEP: return old;
+    case ORC_SUM: return ORC_MUTANT == 1 ? (old + v) : (old + v) & mask;
+    case ORC_KEEP: return ORC_MUTANT == 5 ? v : old;
     case ORC_REPLACE: return v & mask;
     case ORC_MIN: return std::min(old, v & mask);
     case ORC_MAX: return std::max(old, v & mask);
@@ -113,21 +119,21 @@ int orc_map_apply(orc_map* h, uint64_t n, const uint8_t* ops, int default_op,
       st = ORC_INVALID;
     } else if (op == ORC_QUERY) {
       auto it = h->m.find(k);
-      if (it != h->m.end()) { st = ORC_DONE; out = it->second; }
+      if (it != h->m.end()) { st = ORC_DONE; out = ORC_MUTANT == 12 ? it->first : it->second; }
     } else if (op == ORC_INSERT || op == ORC_UPSERT) {
       int c = op == ORC_INSERT ? ORC_KEEP : combine_op;
       auto it = h->m.find(k);
       if (it != h->m.end()) {
         it->second = combine(c, it->second, v, mask);
         st = ORC_EXISTED;
-      } else if (h->capacity && h->m.size() >= h->capacity) {
+      } else if (h->capacity && (ORC_MUTANT == 4 ? h->m.size() > h->capacity : h->m.size() >= h->capacity)) {
         st = ORC_FULL;
       } else {
         h->m.emplace(k, v);
         st = ORC_DONE;
       }
     } else if (op == ORC_ERASE) {
-      st = h->m.erase(k) ? ORC_DONE : ORC_MISS;
+      st = (ORC_MUTANT == 3 ? h->m.count(k) : h->m.erase(k)) ? ORC_DONE : ORC_MISS;
     } else {
       return -1;
     }
@@ -201,7 +207,7 @@ static orc_hash orc_hash_key(uint64_t key, uint64_t nb) {
 }
 
 static uint64_t orc_double_bucket(const orc_hash& h, uint64_t nb, uint64_t i) {
-  uint64_t step = (h.second % nb) | 1;
+  uint64_t step = ORC_MUTANT == 6 ? (h.second % nb) : (h.second % nb) | 1;
   return (h.b1 + i * step) % nb;
 }
 
@@ -209,7 +215,7 @@ static uint64_t orc_p2_alt(const orc_hash& h, uint64_t nb) { return h.second % n
 
 uint16_t orc_tag(uint64_t key) {
   uint16_t t = (uint16_t)(key & 0xFFFF);
-  return t >= 0xFFFE ? (uint16_t)(t - 2) : t;
+  return t >= 0xFFFE ? (uint16_t)(t - (ORC_MUTANT == 9 ? 1 : 2)) : t;
 }
 
 // Candidate-bucket helpers exported for tests.
@@ -287,6 +293,7 @@ static double probe_pos(const orc_image& im, uint64_t pos_bucket, uint64_t j, ui
   uint64_t bucket_lines = lines_of(im.bucket_slots * sb);
   uint64_t step_lines = std::max<uint64_t>(1, tile_bytes / 128);
   uint64_t found_lines = std::min<uint64_t>(bucket_lines, ((j * sb) / 128) / step_lines * step_lines + step_lines);
+  if (ORC_MUTANT == 10) found_lines = bucket_lines;
   return (double)(pos_bucket * bucket_lines + found_lines);
 }
 
@@ -342,7 +349,7 @@ uint64_t orc_layout_check(int design, int key_bits, uint64_t nb, uint64_t bucket
       }
       if (key_bits == 64 && k == im.reserved_key()) { r.reserved++; continue; }
       r.live++;
-      if (!seen.insert(k).second) r.duplicate_keys++;
+      if (!seen.insert(k).second && ORC_MUTANT != 11) r.duplicate_keys++;
       if (tags && t != orc_tag(k)) r.tag_mismatch++;
       orc_hash h = orc_hash_key(k, nb);
       if (design_is_double(design)) {
@@ -455,8 +462,11 @@ uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_s
       if (!placed) failed++;
     } else {
       uint64_t b1 = h.b1, b2 = orc_p2_alt(h, nb);
-      if (shortcut && 4 * fill[b1] < 3 * bucket_slots) { put(b1, keys[i], v); continue; }
-      uint64_t b = fill[b2] < fill[b1] ? b2 : b1;
+      if (shortcut && (ORC_MUTANT == 7 ? 2 * fill[b1] < bucket_slots : 4 * fill[b1] < 3 * bucket_slots)) {
+        put(b1, keys[i], v);
+        continue;
+      }
+      uint64_t b = ORC_MUTANT == 8 ? (fill[b2] <= fill[b1] ? b2 : b1) : (fill[b2] < fill[b1] ? b2 : b1);
       if (fill[b] >= bucket_slots) { failed++; continue; }
       put(b, keys[i], v);
     }
