@@ -11,8 +11,8 @@
  *
  * Designs (Section 2.2 and Section 5): bucketed double hashing and
  * power-of-two-choice hashing, each with an optional 16-bit fingerprint
- * ("metadata", Section 4.3) array.  Every write operation takes the lock bit of
- * the key's primary bucket (Section 4.1); queries take no lock (Section 4.2).
+ * ("metadata", Section 4.3) array.  Every write operation takes the lock of the
+ * key's primary bucket (Section 4.1); queries take no lock (Section 4.2).
  *
  * Conventions for every call below:
  *  - Pointers named d_* are device pointers (hipMalloc or torch CUDA tensors) on
@@ -103,7 +103,7 @@ typedef struct {
 /* Fills *out with the design's defaults.  Returns HWAVE_OK or HWAVE_EINVAL. */
 int hwave_config_default(hwave_design design, hwave_config* out);
 
-/* Device bytes a table needs (slots + tags + lock bits + control word) for a
+/* Device bytes a table needs (slots + tags + lock bytes + control word) for a
  * capacity rounded up to bucket_slots * 2^k slots.  Host-only arithmetic. */
 int hwave_table_bytes(uint64_t capacity_slots, hwave_design design, const hwave_config* cfg,
                       uint64_t* bytes);
@@ -179,7 +179,7 @@ uint64_t hwave_capacity(const hwave_table* t);
 typedef struct {
   void* slots;          /* capacity slots of (key, value), bucket-major            */
   uint16_t* tags;       /* capacity 16-bit tags, or NULL without tags             */
-  uint32_t* locks;      /* lock bits: bit b%32 of word b/32 is bucket b's lock    */
+  uint32_t* locks;      /* lock bytes: byte b is bucket b's lock (0 = free)       */
   uint64_t n_lock_words;
   uint64_t num_buckets;
   uint32_t bucket_slots, tile, kv_bits, design;

@@ -105,7 +105,7 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
   L->off_tags = off;
   if (design_tags(design)) off += round_up(L->capacity * 2, ALIGN);
   L->off_locks = off;
-  L->n_lock_words = (nb + 31) / 32;
+  L->n_lock_words = (nb + 3) / 4;  // one lock byte per bucket
   off += round_up(L->n_lock_words * 4, ALIGN);
   L->off_ctrl = off;
   off += ALIGN;

@@ -152,18 +152,27 @@ __device__ __forceinline__ X cas(X* p, X expected, X desired) {
 }
 
 // ------------------------------------------------------------------ locks
+//
+// One lock byte per bucket (the paper keeps one lock bit per bucket in an
+// external array, Section 5.1).  Taking the lock is an atomic OR of the bucket's
+// bit 0 on the 32-bit word holding four buckets' bytes; releasing it is a plain
+// agent-coherent store of the byte, which cannot disturb the neighbours' bytes.
+// A byte per bucket thus saves the atomic AND a bit-packed release needs: on this
+// chip the atomic unit, not HBM bandwidth, bounds the write operations.
 
-// Leader lane sets bucket b's bit; every lane of the tile learns whether the
+__device__ __forceinline__ uint32_t lock_bit(uint32_t b) { return 1u << ((b & 3) * 8); }
+
+// Leader lane sets bucket b's lock; every lane of the tile learns whether the
 // lock was free.  On success the caller owns the bucket until unlock().
 template <int T>
 __device__ __forceinline__ bool try_lock(uint32_t* locks, uint32_t b, const Tile<T>& tile) {
-  const uint32_t bit = 1u << (b & 31);
+  const uint32_t bit = lock_bit(b);
   uint32_t old = 0;
   if (tile.leader()) {
 #ifdef HW_STRICT_ORDER
-    old = __hip_atomic_fetch_or(locks + (b >> 5), bit, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    old = __hip_atomic_fetch_or(locks + (b >> 2), bit, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 #else
-    old = __hip_atomic_fetch_or(locks + (b >> 5), bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    old = __hip_atomic_fetch_or(locks + (b >> 2), bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #endif
   }
   old = tile.bcast(old, 0);
@@ -172,8 +181,8 @@ __device__ __forceinline__ bool try_lock(uint32_t* locks, uint32_t b, const Tile
 
 // Backoff between failed lock attempts: a pause that doubles from 128 cycles up
 // to ~3.4 us (64 x 128 cycles), about one critical section.  Waiters poll the
-// lock word with loads between attempts, so short pauses cost no atomics; long
-// pauses would leave a released lock idle while its waiters sleep.
+// lock with loads between attempts, so short pauses cost no atomics; long pauses
+// would leave a released lock idle while its waiters sleep.
 struct Backoff {
   uint32_t n = 0;
   __device__ __forceinline__ void pause() {
@@ -182,28 +191,27 @@ struct Backoff {
   __device__ __forceinline__ void grow() { n = n ? (n < 64 ? 2 * n : 64) : 1; }
 };
 
-// Whether bucket b's lock bit currently reads clear (a coherent load of the
-// lock word; no atomic).  Waiting tiles poll with this and only try the atomic
-// when the bit looks clear, so the lock word's atomic unit -- which serves one
-// address at ~80 M operations/s on MI355X -- is left to the holder's release.
+// Whether bucket b's lock currently reads clear (a coherent load; no atomic).
+// Waiting tiles poll with this and only try the atomic when it looks clear, so
+// the lock word's atomic unit -- which serves one address at ~80 M operations/s
+// on MI355X -- is left to the holders.
 template <int T>
 __device__ __forceinline__ bool lock_looks_free(const uint32_t* locks, uint32_t b, const Tile<T>& tile) {
   uint32_t w = 0;
-  if (tile.leader()) w = ld(locks + (b >> 5));
-  return (tile.bcast(w, 0) & (1u << (b & 31))) == 0;
+  if (tile.leader()) w = ld((const uint8_t*)locks + b);
+  return tile.bcast(w, 0) == 0;
 }
 
 // Releases bucket b after every write of the critical section has completed.
 template <int T>
 __device__ __forceinline__ void unlock(uint32_t* locks, uint32_t b, const Tile<T>& tile) {
-  wait_mem();
-  if (tile.leader()) {
 #ifdef HW_STRICT_ORDER
-    __hip_atomic_fetch_and(locks + (b >> 5), ~(1u << (b & 31)), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (tile.leader())
+    __hip_atomic_fetch_and(locks + (b >> 2), ~lock_bit(b), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 #else
-    __hip_atomic_fetch_and(locks + (b >> 5), ~(1u << (b & 31)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  wait_mem();
+  if (tile.leader()) st((uint8_t*)locks + b, (uint8_t)0);
 #endif
-  }
 }
 
 }  // namespace hw

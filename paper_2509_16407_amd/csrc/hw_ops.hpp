@@ -42,7 +42,7 @@ enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3 };
 struct TableDev {
   void* slots;           // (key, value) pairs, bucket-major
   uint32_t* tagw;        // 16-bit tags viewed as 32-bit words; null without tags
-  uint32_t* locks;       // one bit per bucket
+  uint32_t* locks;       // one byte per bucket (viewed as 32-bit words)
   uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice)
   uint32_t bucket_mask;  // buckets - 1 (a power of two minus one)
   uint32_t probe_cap;    // double hashing: most buckets visited
@@ -327,19 +327,15 @@ struct Ops {
 
   // Removes the key in slot s: the key word first (the linearisation point),
   // then, once that store has completed, the tag (a reading; the paper does not
-  // state the erase order).
+  // state the erase order).  The tag is freed with a 16-bit store: it leaves the
+  // other tag of its 32-bit word alone, and an inserter's compare-and-swap on that
+  // word that races with it simply fails and retries.
   __device__ static void remove(const TableDev& tv, const Tile<T>& tile, uint64_t s, uint32_t tag) {
     if (tile.leader()) {
       st(key_ptr(tv, s), C::DOUBLE ? TOMB : EMPTY);
       if constexpr (C::TAGS) {
         wait_mem();
-        uint32_t* wp = tv.tagw + (s >> 1);
-        const uint32_t sh = (uint32_t)(s & 1) * 16;
-        if constexpr (C::DOUBLE) {
-          __hip_atomic_fetch_xor(wp, (tag ^ TAG_TOMB) << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          __hip_atomic_fetch_or(wp, 0xFFFFu << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        st((uint16_t*)tv.tagw + s, (uint16_t)(C::DOUBLE ? TAG_TOMB : TAG_EMPTY));
       }
     }
   }

@@ -34,13 +34,15 @@ def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0):
     return rc, b.value
 
 
-@pytest.mark.parametrize("design,per_slot", [(0, 16), (1, 18), (2, 16), (3, 18)])
-def test_space_per_slot_matches_section_6_1(design, per_slot):
-    """16 bytes per key-value slot, plus 2 bytes of tag in the metadata designs;
-    lock bits and the control word add < 0.01 byte per slot at 2^28 slots."""
-    rc, b = _bytes(1 << 28, design)
+@pytest.mark.parametrize("design,per_slot,bucket", [(0, 16, 8), (1, 18, 32), (2, 16, 32), (3, 18, 32)])
+def test_space_per_slot_matches_section_6_1(design, per_slot, bucket):
+    """16 bytes per key-value slot, plus 2 bytes of tag in the metadata designs
+    (Section 6.1); on top, one lock byte per bucket and a 256-byte control word."""
+    slots = 1 << 28
+    rc, b = _bytes(slots, design)
     assert rc == 0
-    assert abs(b / (1 << 28) - per_slot) < 0.02
+    locks = slots // bucket
+    assert b == slots * per_slot + locks + 256
 
 
 def test_capacity_rounds_up_to_power_of_two_buckets():
