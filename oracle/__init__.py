@@ -19,7 +19,9 @@ Parity status per function (see the test files for the pins):
                    pinned through sim_insert against Table 1 and against the
                    uniform-probing closed form.
   sim_insert       pinned: Table 1 load probes (double hashing 1.22 / 2.05, power of
-                   two choice 2.83 / 2.13) and Knuth's uniform-probing formulas.
+                   two choice 2.83 / 2.13, iceberg 2.97 / 2.16) and Knuth's
+                   uniform-probing formulas; iceberg placement also pinned by its
+                   front-yard-first invariant on brute-force small images.
 """
 from __future__ import annotations
 
@@ -36,7 +38,7 @@ LIB = os.path.join(HERE, "libhw_oracle.so")
 QUERY, INSERT, UPSERT, ERASE = 0, 1, 2, 3
 SUM, KEEP, REPLACE, MIN, MAX = 0, 1, 2, 3, 4
 MISS, DONE, EXISTED, FULL, INVALID = 0, 1, 2, 3, 4
-DOUBLE, DOUBLE_M, P2, P2_M = 0, 1, 2, 3
+DOUBLE, DOUBLE_M, P2, P2_M, ICEBERG, ICEBERG_M = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = False, extra_flags=(), out: str | None = None) -> str:
@@ -55,7 +57,8 @@ class _Report(ctypes.Structure):
         "live", "tombs", "empties", "reserved", "duplicate_keys", "misplaced",
         "tag_mismatch", "locks_held", "in_alternate")] + [
         ("pos_probe_sum", ctypes.c_double), ("neg_probe_sum", ctypes.c_double),
-        ("neg_count", ctypes.c_uint64), ("max_seq_index", ctypes.c_uint64)]
+        ("neg_count", ctypes.c_uint64), ("max_seq_index", ctypes.c_uint64),
+        ("front_room", ctypes.c_uint64)]
 
 
 _lib = None
@@ -92,6 +95,9 @@ def _bind(lib):
         getattr(lib, f).argtypes = [U64, U64]
     lib.orc_double_probe.restype = U64
     lib.orc_double_probe.argtypes = [U64, U64, U64]
+    lib.orc_iceberg_front_buckets.restype = U64
+    lib.orc_iceberg_front_buckets.argtypes = [U64]
+    lib.orc_iceberg_buckets.argtypes = [U64, U64, ctypes.POINTER(U64)]
     lib.orc_layout_check.restype = U64
     lib.orc_layout_check.argtypes = [ctypes.c_int, ctypes.c_int, U64, U64, P, P, P, U64, P, U64,
                                      U64, ctypes.POINTER(_Report)]
@@ -209,7 +215,7 @@ def sim_insert(design, key_bits, nb, bucket_slots, keys, vals=None, shortcut=Tru
     init = slots is None
     if slots is None:
         slots = np.empty(nb * bucket_slots * sb, dtype=np.uint8)
-        if design in (DOUBLE_M, P2_M):
+        if design in (DOUBLE_M, P2_M, ICEBERG_M):
             tags = np.empty(nb * bucket_slots, dtype=np.uint16)
     keys = _u64(keys)
     vals = _u64(vals)
@@ -232,3 +238,14 @@ def double_probe(key: int, nb: int, i: int) -> int:
 
 def p2_alternate(key: int, nb: int) -> int:
     return int(load().orc_p2_alternate(key, nb))
+
+
+def iceberg_front_buckets(nb: int) -> int:
+    return int(load().orc_iceberg_front_buckets(nb))
+
+
+def iceberg_buckets(key: int, nb: int):
+    """(front bucket, first backyard choice, second backyard choice)."""
+    out = (ctypes.c_uint64 * 3)()
+    load().orc_iceberg_buckets(key, nb, out)
+    return int(out[0]), int(out[1]), int(out[2])

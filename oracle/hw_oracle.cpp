@@ -180,8 +180,16 @@ void orc_map_digest(const orc_map* h, uint64_t* sum_out, uint64_t* xor_out) {
 // a power of two).  Power-of-two-choice's alternate bucket = second mod nb.
 // Tag (Section 5.1: the low 16 bits of the key) with the two top patterns
 // reserved for empty (0xFFFF) and tombstone (0xFFFE): such keys take low16 - 2.
+//
+// Iceberg hashing (Section 2.2; the split is the evaluated one of Section 5, 83%
+// front yard and 17% backyard, not the 90/10 of the design overview): of nb
+// buckets the first nf = floor(83 nb / 100) (kept within 1 .. nb-1) form the front
+// yard and the other nb - nf the backyard.  Reading of the silent hashes: front
+// bucket = floor(lo32(h) * nf / 2^32); the two backyard choices are
+// nf + floor(hi32(h) * (nb-nf) / 2^32) and nf + floor(lo32(g) * (nb-nf) / 2^32),
+// with g = fmix64(key XOR 0xbb67ae8584caa73b).
 
-enum { ORC_DOUBLE = 0, ORC_DOUBLE_M = 1, ORC_P2 = 2, ORC_P2_M = 3 };
+enum { ORC_DOUBLE = 0, ORC_DOUBLE_M = 1, ORC_P2 = 2, ORC_P2_M = 3, ORC_ICEBERG = 4, ORC_ICEBERG_M = 5 };
 
 static uint64_t orc_fmix64(uint64_t k) {
   k ^= k >> 33;
@@ -213,6 +221,33 @@ static uint64_t orc_double_bucket(const orc_hash& h, uint64_t nb, uint64_t i) {
 
 static uint64_t orc_p2_alt(const orc_hash& h, uint64_t nb) { return h.second % nb; }
 
+static const uint64_t ORC_SALT_B = 0xbb67ae8584caa73bull;
+
+uint64_t orc_iceberg_front_buckets(uint64_t nb) {
+  uint64_t nf = nb * (ORC_MUTANT == 13 ? 90 : 83) / 100;
+  if (nf < 1) nf = 1;
+  if (nf > nb - 1) nf = nb - 1;
+  return nf;
+}
+
+struct orc_iceberg {
+  uint64_t front, back1, back2;
+};
+
+// floor(x * n / 2^32) for a 32-bit x: a uniform x gives a near-uniform index below n.
+static uint64_t orc_scale32(uint64_t x32, uint64_t n) { return (x32 * n) >> 32; }
+
+static orc_iceberg orc_iceberg_of(uint64_t key, uint64_t nb) {
+  const uint64_t nf = orc_iceberg_front_buckets(nb), nback = nb - nf;
+  const uint64_t h = orc_fmix64(key ^ ORC_SALT);
+  const uint64_t g = orc_fmix64(key ^ ORC_SALT_B);
+  orc_iceberg r;
+  r.front = orc_scale32(h & 0xFFFFFFFFull, nf);
+  r.back1 = nf + orc_scale32(h >> 32, nback);
+  r.back2 = nf + orc_scale32(g & 0xFFFFFFFFull, nback);
+  return r;
+}
+
 uint16_t orc_tag(uint64_t key) {
   uint16_t t = (uint16_t)(key & 0xFFFF);
   return t >= 0xFFFE ? (uint16_t)(t - (ORC_MUTANT == 9 ? 1 : 2)) : t;
@@ -224,9 +259,16 @@ uint64_t orc_double_probe(uint64_t key, uint64_t nb, uint64_t i) {
   return orc_double_bucket(orc_hash_key(key, nb), nb, i);
 }
 uint64_t orc_p2_alternate(uint64_t key, uint64_t nb) { return orc_p2_alt(orc_hash_key(key, nb), nb); }
+void orc_iceberg_buckets(uint64_t key, uint64_t nb, uint64_t* out3) {
+  orc_iceberg r = orc_iceberg_of(key, nb);
+  out3[0] = r.front;
+  out3[1] = r.back1;
+  out3[2] = r.back2;
+}
 
-static bool design_has_tags(int d) { return d == ORC_DOUBLE_M || d == ORC_P2_M; }
+static bool design_has_tags(int d) { return d == ORC_DOUBLE_M || d == ORC_P2_M || d == ORC_ICEBERG_M; }
 static bool design_is_double(int d) { return d == ORC_DOUBLE || d == ORC_DOUBLE_M; }
+static bool design_is_iceberg(int d) { return d == ORC_ICEBERG || d == ORC_ICEBERG_M; }
 
 // A table image in host memory.  Slots are (key, value) pairs of key_bits each,
 // bucket-major: slot s = bucket * bucket_slots + j.
@@ -270,11 +312,14 @@ struct orc_layout_report {
   uint64_t misplaced;        // key outside its candidate buckets / past an empty-holding bucket
   uint64_t tag_mismatch;     // tag disagrees with its slot (tag designs)
   uint64_t locks_held;       // lock bits still set
-  uint64_t in_alternate;     // power-of-two-choice: keys in their alternate bucket
+  uint64_t in_alternate;     // power-of-two-choice: keys in their alternate bucket;
+                             // iceberg: keys in the backyard
   double pos_probe_sum;      // sum over live keys of the positive-query probe count
   double neg_probe_sum;      // sum over `neg_keys` of the negative-query probe count
   uint64_t neg_count;
   uint64_t max_seq_index;    // double hashing: largest sequence index of a live key
+  uint64_t front_room;       // iceberg: backyard keys whose front bucket has an empty
+                             // slot (none in a table that has never erased)
 };
 
 // Positive-query probe count of a key found at sequence position `pos_bucket`
@@ -310,6 +355,13 @@ static double probe_neg(const orc_image& im, uint64_t key) {
     }
     return (double)(im.nb * per_bucket);
   }
+  if (design_is_iceberg(im.design)) {
+    // A table that has never erased keeps a key out of the backyard while its front
+    // bucket has room, so a query stops at a front bucket with an empty slot.
+    orc_iceberg ib = orc_iceberg_of(key, im.nb);
+    if (bucket_has_empty(im, ib.front)) return (double)per_bucket;
+    return (double)((ib.back1 == ib.back2 ? 2 : 3) * per_bucket);
+  }
   uint64_t b2 = orc_p2_alt(h, im.nb);
   return (double)((b2 == h.b1 ? 1 : 2) * per_bucket);
 }
@@ -342,7 +394,8 @@ uint64_t orc_layout_check(int design, int key_bits, uint64_t nb, uint64_t bucket
       if (k == im.tomb_key()) {
         r.tombs++;
         // Erase writes the tombstone tag in double hashing designs; tags of
-        // power-of-two-choice designs return to empty (no tombstones are used).
+        // power-of-two-choice and iceberg designs return to empty (no tombstones
+        // are used).
         if (tags && t != 0xFFFE) r.tag_mismatch++;
         if (!design_is_double(design)) r.misplaced++;
         continue;
@@ -364,6 +417,18 @@ uint64_t orc_layout_check(int design, int key_bits, uint64_t nb, uint64_t bucket
         if (!ok) { r.misplaced++; continue; }
         r.max_seq_index = std::max(r.max_seq_index, i);
         r.pos_probe_sum += probe_pos(im, i, j, tile_bytes);
+      } else if (design_is_iceberg(design)) {
+        // Front bucket, then the backyard choices in order (a repeated choice once).
+        orc_iceberg ib = orc_iceberg_of(k, nb);
+        if (b == ib.front) {
+          r.pos_probe_sum += probe_pos(im, 0, j, tile_bytes);
+        } else if (b == ib.back1 || b == ib.back2) {
+          r.in_alternate++;
+          r.pos_probe_sum += probe_pos(im, b == ib.back1 ? 1 : 2, j, tile_bytes);
+          if (bucket_has_empty(im, ib.front)) r.front_room++;
+        } else {
+          r.misplaced++;
+        }
       } else {
         uint64_t b2 = orc_p2_alt(h, nb);
         if (b == h.b1) {
@@ -415,6 +480,8 @@ uint64_t orc_image_pairs(int key_bits, uint64_t nslots, const void* slots, uint6
 //   power-of-two-choice: if `shortcut` and the primary holds fewer than 3/4 of
 //     bucket_slots keys, the primary; else the less loaded of primary and
 //     alternate, ties to the primary; full when both are full.
+//   iceberg: the front bucket while it has a free slot; else the less loaded of
+//     the two backyard choices, ties to the first; full when both are full.
 // Returns the number of keys that could not be placed.
 uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_slots,
                         void* slots, uint16_t* tags, const uint64_t* keys, const uint64_t* vals,
@@ -460,6 +527,16 @@ uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_s
         if (fill[b] < bucket_slots) { put(b, keys[i], v); placed = true; break; }
       }
       if (!placed) failed++;
+    } else if (design_is_iceberg(design)) {
+      orc_iceberg ib = orc_iceberg_of(keys[i], nb);
+      if (fill[ib.front] < bucket_slots) {
+        put(ib.front, keys[i], v);
+        continue;
+      }
+      uint64_t b = ORC_MUTANT == 14 ? (fill[ib.back2] <= fill[ib.back1] ? ib.back2 : ib.back1)
+                                    : (fill[ib.back2] < fill[ib.back1] ? ib.back2 : ib.back1);
+      if (fill[b] >= bucket_slots) { failed++; continue; }
+      put(b, keys[i], v);
     } else {
       uint64_t b1 = h.b1, b2 = orc_p2_alt(h, nb);
       if (shortcut && (ORC_MUTANT == 7 ? 2 * fill[b1] < bucket_slots : 4 * fill[b1] < 3 * bucket_slots)) {

@@ -172,7 +172,9 @@ def test_digest_is_order_independent():
 
 # ---------------------------------------------------------------- probe model vs paper
 
-DESIGNS = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M}
+DESIGNS = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M,
+           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M}
+ICEBERGS = (oracle.ICEBERG, oracle.ICEBERG_M)
 
 
 @pytest.mark.parametrize("row", _read_golden("table1_load_probes.txt"), ids=lambda r: r[0])
@@ -255,7 +257,16 @@ def _image(design, nb, bucket, keys, shortcut=True):
     return slots, tags
 
 
-@pytest.mark.parametrize("design", [oracle.DOUBLE, oracle.DOUBLE_M, oracle.P2, oracle.P2_M])
+def _candidates(design, key, nb):
+    """Every bucket a search for `key` may visit (before any early stop)."""
+    if design in ICEBERGS:
+        return set(oracle.iceberg_buckets(key, nb))
+    if design in (oracle.P2, oracle.P2_M):
+        return {oracle.primary_bucket(key, nb), oracle.p2_alternate(key, nb)}
+    return {oracle.double_probe(key, nb, i) for i in range(nb)}
+
+
+@pytest.mark.parametrize("design", sorted(DESIGNS.values()))
 def test_layout_checker_detects_planted_violations(design):
     nb, bucket = 64, 8 if design == oracle.DOUBLE else 32
     keys = w.distinct_keys(17, int(0.8 * nb * bucket))
@@ -267,7 +278,7 @@ def test_layout_checker_detects_planted_violations(design):
     empty = np.nonzero(s64[0::2] == np.uint64(U64))[0]
     # duplicate: copy a live key into an empty slot of one of its candidate buckets
     k0 = int(s64[2 * live[0]])
-    cand = [oracle.primary_bucket(k0, nb)]
+    cand = _candidates(design, k0, nb)
     s_dup = slots.copy()
     tg = None if tags is None else tags.copy()
     e = [s for s in empty if s // bucket in cand]
@@ -280,11 +291,9 @@ def test_layout_checker_detects_planted_violations(design):
     # misplaced: move a key to a bucket that is not a candidate
     s_mis = slots.copy()
     tg = None if tags is None else tags.copy()
-    kb = oracle.primary_bucket(k0, nb)
-    far = [s for s in empty if s // bucket not in (kb, oracle.p2_alternate(k0, nb))
-           and all(oracle.double_probe(k0, nb, i) != s // bucket for i in range(nb))]
+    far = [s for s in empty if s // bucket not in cand]
     if not far:
-        far = [s for s in empty if s // bucket not in (kb, oracle.p2_alternate(k0, nb))]
+        far = [s for s in empty if s // bucket != oracle.primary_bucket(k0, nb)]
     s_mis.view(np.uint64)[2 * far[0]] = k0
     s_mis.view(np.uint64)[2 * live[0]] = np.uint64(U64)
     if tg is not None:
@@ -292,6 +301,15 @@ def test_layout_checker_detects_planted_violations(design):
         tg[live[0]] = 0xFFFF
     nv, rep = oracle.layout_check(design, 64, nb, bucket, s_mis, tg)
     assert nv >= 1
+    # a tombstone where erase returns slots to empty
+    if design not in (oracle.DOUBLE, oracle.DOUBLE_M):
+        s_tomb = slots.copy()
+        s_tomb.view(np.uint64)[2 * empty[0]] = np.uint64(U64 - 1)
+        tg = None if tags is None else tags.copy()
+        if tg is not None:
+            tg[empty[0]] = 0xFFFE
+        nv, rep = oracle.layout_check(design, 64, nb, bucket, s_tomb, tg)
+        assert rep["tombs"] == 1 and rep["misplaced"] == 1 and nv == 1
     # reservation marker left behind
     s_res = slots.copy()
     s_res.view(np.uint64)[2 * empty[0]] = np.uint64(U64 - 2)
@@ -334,3 +352,65 @@ def test_image_pairs_roundtrip():
     k, v = oracle.image_pairs(64, slots)
     assert sorted(k.tolist()) == sorted(keys.tolist())
     assert (k == v).all()
+
+
+# ---------------------------------------------------------------- iceberg
+
+def test_iceberg_split_is_83_17():
+    """Section 5: the front yard takes 83% of the buckets, the backyard 17%."""
+    for nb in (2, 3, 7, 100, 1 << 10, 1 << 23):
+        nf = oracle.iceberg_front_buckets(nb)
+        assert nf == min(max(nb * 83 // 100, 1), nb - 1)
+    for key in w.distinct_keys(5, 2000).tolist():
+        f, b1, b2 = oracle.iceberg_buckets(key, 1 << 10)
+        nf = oracle.iceberg_front_buckets(1 << 10)
+        assert 0 <= f < nf <= b1 < 1 << 10 and nf <= b2 < 1 << 10
+
+
+@pytest.mark.parametrize("load", [0.8, 0.9])
+def test_iceberg_backyard_share_is_the_binomial_overflow(load):
+    """Keys go to the backyard only when their front bucket is full, so the
+    backyard holds the front yard's overflow: with n keys thrown uniformly into the
+    nf = floor(0.83 nb) front buckets of 32 slots, nf * E[(X - 32)+] keys for
+    X ~ Binomial(n, 1/nf), as long as the backyard itself does not run out."""
+    from scipy.stats import binom
+    nb, bucket = 1 << 16, 32
+    n = int(load * nb * bucket)
+    nf = nb * 83 // 100
+    x = np.arange(0, bucket)
+    expect = nf * (n / nf - bucket + np.sum((bucket - x) * binom.pmf(x, n, 1.0 / nf)))
+    keys = w.distinct_keys(w.stream_seed(42, int(load * 10)), n)
+    slots, tags, failed = oracle.sim_insert(oracle.ICEBERG_M, 64, nb, bucket, keys)
+    assert failed == 0
+    nv, rep = oracle.layout_check(oracle.ICEBERG_M, 64, nb, bucket, slots, tags)
+    assert nv == 0
+    assert abs(rep["in_alternate"] - expect) / expect < 0.02, (rep["in_alternate"], expect)
+
+
+def test_iceberg_front_yard_first():
+    """Without erases no backyard key has room in its front bucket; moving a
+    front-yard key into its backyard bucket while the front has room is reported
+    (but is no violation: after an erase it is a legal state)."""
+    nb, bucket = 256, 32
+    keys = w.distinct_keys(44, int(0.85 * nb * bucket))
+    slots, tags, failed = oracle.sim_insert(oracle.ICEBERG, 64, nb, bucket, keys)
+    assert failed == 0
+    nv, rep = oracle.layout_check(oracle.ICEBERG, 64, nb, bucket, slots, None)
+    assert nv == 0 and rep["front_room"] == 0 and rep["in_alternate"] > 0
+    s64 = slots.view(np.uint64)
+    for s in range(nb * bucket):
+        k = int(s64[2 * s])
+        if k >= U64 - 2:
+            continue
+        f, b1, _ = oracle.iceberg_buckets(k, nb)
+        if s // bucket != f:
+            continue
+        free_back = [t for t in range(b1 * bucket, (b1 + 1) * bucket) if int(s64[2 * t]) == U64]
+        if free_back:
+            moved = slots.copy()
+            moved.view(np.uint64)[2 * free_back[0]] = np.uint64(k)
+            moved.view(np.uint64)[2 * s] = np.uint64(U64)
+            nv, rep = oracle.layout_check(oracle.ICEBERG, 64, nb, bucket, moved, None)
+            assert nv == 0 and rep["front_room"] >= 1
+            return
+    pytest.fail("no movable key found")
