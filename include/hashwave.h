@@ -9,8 +9,8 @@
  * because a C-ABI cannot carry a device function pointer.  Insert is Upsert with
  * the "insert if unique" callback (Section 5.1).
  *
- * Designs (Section 2.2 and Section 5): bucketed double hashing and
- * power-of-two-choice hashing, each with an optional 16-bit fingerprint
+ * Designs (Section 2.2 and Section 5): bucketed double hashing,
+ * power-of-two-choice hashing and iceberg hashing, each with an optional 16-bit fingerprint
  * ("metadata", Section 4.3) array.  Every write operation takes the lock of the
  * key's primary bucket (Section 4.1); queries take no lock (Section 4.2).
  *
@@ -39,12 +39,18 @@ extern "C" {
 
 typedef struct hwave_table hwave_table;
 
-/* Table designs (Section 2.2, configurations of Section 5). */
+/* Table designs (Section 2.2, configurations of Section 5).  The lock a key's
+ * writers take is that of its primary bucket, for iceberg its front-yard
+ * bucket (hwave_primary_bucket reports it). */
 typedef enum {
   HWAVE_DOUBLE = 0,   /* bucketed double hashing; default bucket 8, tile 8     */
   HWAVE_DOUBLE_M = 1, /* double hashing with 16-bit tags; bucket 32, tile 4    */
   HWAVE_P2 = 2,       /* power-of-two-choice; bucket 32, tile 8                */
-  HWAVE_P2_M = 3      /* power-of-two-choice with 16-bit tags; bucket 32, tile 4 */
+  HWAVE_P2_M = 3,     /* power-of-two-choice with 16-bit tags; bucket 32, tile 4 */
+  HWAVE_ICEBERG = 4,  /* iceberg: 83% single-hash front yard, 17% power-of-two-
+                         choice backyard (Section 2.2, Section 5); bucket 32,
+                         tile 8; at least two buckets                          */
+  HWAVE_ICEBERG_M = 5 /* iceberg with 16-bit tags; bucket 32, tile 4           */
 } hwave_design;
 
 /* Upsert callbacks (Section 5.1): SUM accumulates with wrap-around modulo

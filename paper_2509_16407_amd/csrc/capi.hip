@@ -44,13 +44,24 @@ struct Layout {
   uint64_t n_lock_words;
 };
 
-bool design_tags(int d) { return d == HWAVE_DOUBLE_M || d == HWAVE_P2_M; }
+bool design_tags(int d) { return d == HWAVE_DOUBLE_M || d == HWAVE_P2_M || d == HWAVE_ICEBERG_M; }
+bool design_iceberg(int d) { return d == HWAVE_ICEBERG || d == HWAVE_ICEBERG_M; }
+
+// Iceberg front yard: 83% of the buckets (Section 5), at least one bucket in
+// each yard.
+uint64_t iceberg_front(uint64_t nb) {
+  uint64_t nf = nb * 83 / 100;
+  if (nf < 1) nf = 1;
+  if (nf > nb - 1) nf = nb - 1;
+  return nf;
+}
 
 const std::vector<const KernelSet*>& registry() {
   static std::vector<const KernelSet*> all;
   static std::once_flag once;
   std::call_once(once, [] {
-    const KernelSet* (*fns[])(size_t*) = {sets_u64_double, sets_u64_p2, sets_u32_double, sets_u32_p2};
+    const KernelSet* (*fns[])(size_t*) = {sets_u64_double, sets_u64_p2, sets_u64_iceberg,
+                                          sets_u32_double, sets_u32_p2, sets_u32_iceberg};
     for (auto f : fns) {
       size_t n = 0;
       const KernelSet* s = f(&n);
@@ -76,7 +87,7 @@ void defaults_for(hwave_design design, uint32_t kv_bits, hwave_config* c) {
 }
 
 int resolve_config(hwave_design design, const hwave_config* in, hwave_config* out) {
-  if ((int)design < HWAVE_DOUBLE || (int)design > HWAVE_P2_M) return HWAVE_EINVAL;
+  if ((int)design < HWAVE_DOUBLE || (int)design > HWAVE_ICEBERG_M) return HWAVE_EINVAL;
   const uint32_t kv = in && in->kv_bits ? in->kv_bits : 64;
   if (kv != 64 && kv != 32) return HWAVE_EINVAL;
   hwave_config c;
@@ -95,7 +106,7 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
   if (capacity == 0 || c.bucket_slots == 0) return HWAVE_EINVAL;
   const uint64_t B = c.bucket_slots;
   uint64_t want = (capacity + B - 1) / B;
-  uint64_t nb = 1;
+  uint64_t nb = design_iceberg(design) ? 2 : 1;  // iceberg: a bucket in each yard
   while (nb < want) nb <<= 1;
   if (nb > (1ull << 32)) return HWAVE_EINVAL;
   const uint64_t slot_bytes = c.kv_bits / 4;  // two words
@@ -147,11 +158,14 @@ __global__ void k_export(const K* __restrict__ slots, uint64_t nslots, K* __rest
 
 __global__ void k_zero_u64(uint64_t* p) { *p = 0; }
 
+// The bucket whose lock a key's writers take: primary bucket, or the front-yard
+// bucket of iceberg tables (nf != 0).
 template <typename K>
-__global__ void k_primary(const K* __restrict__ keys, uint64_t n, uint32_t mask, uint64_t* __restrict__ out) {
+__global__ void k_primary(const K* __restrict__ keys, uint64_t n, uint32_t mask, uint32_t nf,
+                          uint64_t* __restrict__ out) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
-    out[i] = hash_key((uint64_t)keys[i], mask).b1;
+    out[i] = nf ? front_bucket((uint64_t)keys[i], nf) : hash_key((uint64_t)keys[i], mask).b1;
 }
 
 unsigned max_blocks_for(int device) {
@@ -193,6 +207,8 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   tv.locks = (uint32_t*)(b + L.off_locks);
   tv.ctrl = (uint32_t*)(b + L.off_ctrl);
   tv.bucket_mask = (uint32_t)(L.nb - 1);
+  tv.nb_front = design_iceberg(design) ? (uint32_t)iceberg_front(L.nb) : (uint32_t)L.nb;
+  tv.nb_back = design_iceberg(design) ? (uint32_t)(L.nb - tv.nb_front) : 0u;
   uint64_t cap = c.probe_cap ? c.probe_cap : L.nb;
   if (cap > L.nb) cap = L.nb;
   tv.probe_cap = (uint32_t)(cap > 0xFFFFFFFFull ? 0xFFFFFFFFull : cap);
@@ -209,7 +225,7 @@ bool bad_ptr(const void* p) { return p == nullptr; }
 extern "C" {
 
 int hwave_config_default(hwave_design design, hwave_config* out) {
-  if (!out || (int)design < HWAVE_DOUBLE || (int)design > HWAVE_P2_M) return HWAVE_EINVAL;
+  if (!out || (int)design < HWAVE_DOUBLE || (int)design > HWAVE_ICEBERG_M) return HWAVE_EINVAL;
   defaults_for(design, 64, out);
   return HWAVE_OK;
 }
@@ -389,12 +405,13 @@ int hwave_primary_bucket(hwave_table* t, const void* d_keys, uint64_t n, uint64_
   if (n == 0) return HWAVE_OK;
   hipStream_t s = (hipStream_t)stream;
   const unsigned g = stream_grid(n, t->device);
+  const uint32_t nf = design_iceberg(t->design) ? t->la.tv.nb_front : 0u;
   if (t->cfg.kv_bits == 64)
     hipLaunchKernelGGL(k_primary<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)d_keys, n,
-                       t->la.tv.bucket_mask, d_out);
+                       t->la.tv.bucket_mask, nf, d_out);
   else
     hipLaunchKernelGGL(k_primary<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)d_keys, n,
-                       t->la.tv.bucket_mask, d_out);
+                       t->la.tv.bucket_mask, nf, d_out);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
 }

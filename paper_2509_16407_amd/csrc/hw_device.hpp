@@ -79,6 +79,28 @@ __device__ __forceinline__ Hashed hash_key(uint64_t key, uint32_t bucket_mask) {
   return Hashed{(uint32_t)h & bucket_mask, (uint32_t)(h >> 32)};
 }
 
+// Iceberg hashing (Section 2.2, split of Section 5): buckets [0, nf) are the
+// front yard, [nf, nf + nback) the backyard.  A 32-bit hash x is mapped to
+// [0, n) as floor(x * n / 2^32) (one multiply-high), so neither region has to
+// be a power of two.  The second backyard choice comes from an independently
+// salted hash.
+constexpr uint64_t HASH_SALT_B = 0xbb67ae8584caa73bull;
+
+struct Yard {
+  uint32_t front, back1, back2;
+};
+
+__device__ __forceinline__ uint32_t front_bucket(uint64_t key, uint32_t nf) {
+  return __umulhi((uint32_t)fmix64(key ^ HASH_SALT), nf);
+}
+
+__device__ __forceinline__ Yard yard_of(uint64_t key, uint32_t nf, uint32_t nback) {
+  const uint64_t h = fmix64(key ^ HASH_SALT);
+  const uint64_t g = fmix64(key ^ HASH_SALT_B);
+  return Yard{__umulhi((uint32_t)h, nf), nf + __umulhi((uint32_t)(h >> 32), nback),
+              nf + __umulhi((uint32_t)g, nback)};
+}
+
 // ------------------------------------------------------------------ tiles
 
 template <int T>

@@ -157,5 +157,7 @@ const KernelSet* sets_u64_double(size_t* n);
 const KernelSet* sets_u64_p2(size_t* n);
 const KernelSet* sets_u32_double(size_t* n);
 const KernelSet* sets_u32_p2(size_t* n);
+const KernelSet* sets_u64_iceberg(size_t* n);
+const KernelSet* sets_u32_iceberg(size_t* n);
 
 }  // namespace hw

@@ -19,6 +19,11 @@
 //  * power-of-two-choice inserts into the less loaded of its two buckets (ties
 //    to the primary), or straight into the primary while that holds fewer than
 //    3/4 of its slots ("shortcutting").  Erase returns slots to empty.
+//  * iceberg hashing keeps a key in its single front-yard bucket while that has
+//    a free slot, and otherwise in the less loaded of its two backyard buckets
+//    (ties to the first).  The front bucket's lock serialises the key's writers;
+//    front-yard slots are only ever claimed under that lock.  Erase returns
+//    slots to empty.
 //
 // Shortcut safety (a reading; the paper is silent): after an erase, a key can sit
 // in its alternate bucket while its primary has dropped below 3/4, and the
@@ -26,7 +31,10 @@
 // erase has happened; the shortcut is used only while it is clear.  An erase
 // sets it (and waits for the store) before removing anything; an insert reads it
 // after reading the primary bucket, so whoever observes a removal also observes
-// the flag.
+// the flag.  Iceberg uses the same flag: until an erase, a front bucket's fill
+// only grows, so a key was placed in the backyard only while its front bucket
+// was full and stays full; an insert that finds a free front slot claims it
+// without looking at the backyard, and a query that finds one stops there.
 #pragma once
 
 #include "hw_device.hpp"
@@ -36,15 +44,17 @@ namespace hw {
 enum : uint8_t { ST_MISS = 0, ST_DONE = 1, ST_EXISTED = 2, ST_FULL = 3, ST_INVALID = 4 };
 enum : int { C_SUM = 0, C_KEEP = 1, C_REPLACE = 2, C_MIN = 3, C_MAX = 4 };
 enum : int { OP_QUERY = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_ERASE = 3 };
-enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3 };
+enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, D_ICEBERG_M = 5 };
 
 // Device view of one table (passed by value to kernels).
 struct TableDev {
   void* slots;           // (key, value) pairs, bucket-major
   uint32_t* tagw;        // 16-bit tags viewed as 32-bit words; null without tags
   uint32_t* locks;       // one byte per bucket (viewed as 32-bit words)
-  uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice)
+  uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice, iceberg)
   uint32_t bucket_mask;  // buckets - 1 (a power of two minus one)
+  uint32_t nb_front;     // iceberg: front-yard buckets [0, nb_front)
+  uint32_t nb_back;      // iceberg: backyard buckets [nb_front, nb_front + nb_back)
   uint32_t probe_cap;    // double hashing: most buckets visited
   uint32_t shortcut;     // power-of-two-choice shortcut enabled
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
@@ -54,8 +64,9 @@ template <typename K_, int DESIGN_, int B_, int T_>
 struct Cfg {
   using K = K_;
   static constexpr int DESIGN = DESIGN_;
-  static constexpr bool TAGS = DESIGN == D_DOUBLE_M || DESIGN == D_P2_M;
+  static constexpr bool TAGS = DESIGN == D_DOUBLE_M || DESIGN == D_P2_M || DESIGN == D_ICEBERG_M;
   static constexpr bool DOUBLE = DESIGN == D_DOUBLE || DESIGN == D_DOUBLE_M;
+  static constexpr bool ICEBERG = DESIGN == D_ICEBERG || DESIGN == D_ICEBERG_M;
   static constexpr int B = B_;
   static constexpr int T = T_;
   static constexpr int SLOT_BYTES = 2 * (int)sizeof(K);
@@ -354,14 +365,51 @@ struct Ops {
 
   // ---------------------------------------------------------------- operations
 
-  __device__ static __forceinline__ uint32_t step_of(const TableDev& tv, const Hashed& h) {
+  // A key's buckets.  b1 is the bucket whose lock guards the key (primary; the
+  // front bucket for iceberg); h2 the second hash (double-hashing step,
+  // power-of-two-choice alternate) or, for iceberg, the first backyard choice;
+  // b3 the second backyard choice.
+  struct Home {
+    uint32_t b1, h2, b3;
+  };
+
+  __device__ static __forceinline__ Home home_of(const TableDev& tv, K key) {
+    if constexpr (C::ICEBERG) {
+      const Yard y = yard_of((uint64_t)key, tv.nb_front, tv.nb_back);
+      return Home{y.front, y.back1, y.back2};
+    } else {
+      const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
+      return Home{h.b1, h.h2, 0u};
+    }
+  }
+
+  // The erase flag, read by the leader and broadcast.
+  __device__ static __forceinline__ bool erased(const TableDev& tv, const Tile<T>& tile) {
+    const uint32_t e = tile.leader() ? ld(tv.ctrl) : 0u;
+    return tile.bcast(e, 0) != 0;
+  }
+
+  __device__ static __forceinline__ uint32_t step_of(const TableDev& tv, const Home& h) {
     return (h.h2 & tv.bucket_mask) | 1u;
   }
 
   // Lock-free search (Section 4.2): the slot holding `key`, or -1.  Value in *val.
-  __device__ static int64_t find(const TableDev& tv, const Tile<T>& tile, const Hashed& h, K key,
+  __device__ static int64_t find(const TableDev& tv, const Tile<T>& tile, const Home& h, K key,
                                  uint32_t tag, K* val) {
-    if constexpr (C::DOUBLE) {
+    if constexpr (C::ICEBERG) {
+      BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
+      if (r.hit >= 0) { *val = r.val; return (int64_t)h.b1 * B + r.hit; }
+      // The flag is read after the front bucket: a free slot seen there that an
+      // erase made is seen together with the flag the erase set first.
+      if (r.free >= 0 && !erased(tv, tile)) return -1;
+      r = scan<true>(tv, tile, h.h2, key, tag);
+      if (r.hit >= 0) { *val = r.val; return (int64_t)h.h2 * B + r.hit; }
+      if (h.b3 != h.h2) {
+        r = scan<true>(tv, tile, h.b3, key, tag);
+        if (r.hit >= 0) { *val = r.val; return (int64_t)h.b3 * B + r.hit; }
+      }
+      return -1;
+    } else if constexpr (C::DOUBLE) {
       const uint32_t step = step_of(tv, h);
       uint32_t b = h.b1;
       for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
@@ -396,7 +444,7 @@ struct Ops {
   __device__ static uint8_t upsert(const TableDev& tv, const Tile<T>& tile, K key, K val,
                                    int combine) {
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
-    const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
+    const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
     uint8_t status = ST_FULL;
     bool pending = true;
@@ -420,7 +468,9 @@ struct Ops {
       const bool go = (attempt & 255) == 0 || lock_looks_free(tv.locks, h.b1, tile);
       ++attempt;
       if (go && try_lock(tv.locks, h.b1, tile)) {
-        if constexpr (C::DOUBLE)
+        if constexpr (C::ICEBERG)
+          status = upsert_iceberg_locked(tv, tile, h, key, val, tag, combine);
+        else if constexpr (C::DOUBLE)
           status = upsert_double_locked(tv, tile, h, key, val, tag, combine);
         else
           status = upsert_p2_locked(tv, tile, h, key, val, tag, combine);
@@ -434,7 +484,7 @@ struct Ops {
   }
 
   __device__ static uint8_t upsert_double_locked(const TableDev& tv, const Tile<T>& tile,
-                                                 const Hashed& h, K key, K val, uint32_t tag,
+                                                 const Home& h, K key, K val, uint32_t tag,
                                                  int combine) {
     const uint32_t step = step_of(tv, h);
     BucketScan<K> first_free;
@@ -467,7 +517,7 @@ struct Ops {
   }
 
   __device__ static uint8_t upsert_p2_locked(const TableDev& tv, const Tile<T>& tile,
-                                             const Hashed& h, K key, K val, uint32_t tag,
+                                             const Home& h, K key, K val, uint32_t tag,
                                              int combine) {
     const uint32_t b1 = h.b1;
     const uint32_t b2 = h.h2 & tv.bucket_mask;
@@ -499,11 +549,49 @@ struct Ops {
     return ST_FULL;
   }
 
+  // Iceberg insert under the front bucket's lock: the front bucket if it has a
+  // free slot (after checking the backyard for the key once an erase has
+  // happened), else the less loaded backyard choice, ties to the first.
+  __device__ static uint8_t upsert_iceberg_locked(const TableDev& tv, const Tile<T>& tile,
+                                                  const Home& h, K key, K val, uint32_t tag,
+                                                  int combine) {
+    BucketScan<K> rf = scan<true>(tv, tile, h.b1, key, tag);
+    if (rf.hit >= 0) {
+      combine_at(tv, tile, (uint64_t)h.b1 * B + rf.hit, val, combine);
+      return ST_EXISTED;
+    }
+    if (rf.free >= 0 && !erased(tv, tile)) {
+      if (claim_in_bucket(tv, tile, h.b1, rf, key, val, tag) >= 0) return ST_DONE;
+      rf.free = -1;  // not reached: front slots are claimed only under this lock
+    }
+    BucketScan<K> r1 = scan<true>(tv, tile, h.h2, key, tag);
+    if (r1.hit >= 0) {
+      combine_at(tv, tile, (uint64_t)h.h2 * B + r1.hit, val, combine);
+      return ST_EXISTED;
+    }
+    BucketScan<K> r2 = r1;
+    if (h.b3 != h.h2) {
+      r2 = scan<true>(tv, tile, h.b3, key, tag);
+      if (r2.hit >= 0) {
+        combine_at(tv, tile, (uint64_t)h.b3 * B + r2.hit, val, combine);
+        return ST_EXISTED;
+      }
+    }
+    if (rf.free >= 0 && claim_in_bucket(tv, tile, h.b1, rf, key, val, tag) >= 0) return ST_DONE;
+    const bool second_first = h.b3 != h.h2 && r2.fill < r1.fill;
+    if (claim_in_bucket(tv, tile, second_first ? h.b3 : h.h2, second_first ? r2 : r1, key, val, tag) >= 0)
+      return ST_DONE;
+    if (h.b3 != h.h2 &&
+        claim_in_bucket(tv, tile, second_first ? h.h2 : h.b3, second_first ? r1 : r2, key, val, tag) >= 0)
+      return ST_DONE;
+    return ST_FULL;
+  }
+
   // Lock-free query (Section 4.2).  Returns ST_DONE/ST_MISS/ST_INVALID, value in *out.
   __device__ static uint8_t query(const TableDev& tv, const Tile<T>& tile, K key, K* out) {
     *out = 0;
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
-    const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
+    const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
     return find(tv, tile, h, key, tag, out) >= 0 ? ST_DONE : ST_MISS;
   }
@@ -511,7 +599,7 @@ struct Ops {
   // Erase under the primary lock.  ST_DONE if removed, ST_MISS if absent.
   __device__ static uint8_t erase(const TableDev& tv, const Tile<T>& tile, K key) {
     if (key >= Keys<K>::FIRST_INVALID || tv.no_erase) return ST_INVALID;
-    const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
+    const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
     if constexpr (!C::DOUBLE) {
       if (tile.leader() && ld(tv.ctrl) == 0) {
@@ -528,7 +616,19 @@ struct Ops {
       const bool go = (attempt & 255) == 0 || lock_looks_free(tv.locks, h.b1, tile);
       ++attempt;
       if (go && try_lock(tv.locks, h.b1, tile)) {
-        if constexpr (C::DOUBLE) {
+        if constexpr (C::ICEBERG) {
+          const uint32_t cand[3] = {h.b1, h.h2, h.b3};
+#pragma unroll 1
+          for (int i = 0; i < 3; ++i) {
+            if (i == 2 && h.b3 == h.h2) break;
+            BucketScan<K> r = scan<true>(tv, tile, cand[i], key, tag);
+            if (r.hit >= 0) {
+              remove(tv, tile, (uint64_t)cand[i] * B + r.hit, tag);
+              status = ST_DONE;
+              break;
+            }
+          }
+        } else if constexpr (C::DOUBLE) {
           const uint32_t step = step_of(tv, h);
           uint32_t b = h.b1;
           for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {

@@ -34,7 +34,8 @@ def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0):
     return rc, b.value
 
 
-@pytest.mark.parametrize("design,per_slot,bucket", [(0, 16, 8), (1, 18, 32), (2, 16, 32), (3, 18, 32)])
+@pytest.mark.parametrize("design,per_slot,bucket", [(0, 16, 8), (1, 18, 32), (2, 16, 32), (3, 18, 32),
+                                                    (4, 16, 32), (5, 18, 32)])
 def test_space_per_slot_matches_section_6_1(design, per_slot, bucket):
     """16 bytes per key-value slot, plus 2 bytes of tag in the metadata designs
     (Section 6.1); on top, one lock byte per bucket and a 256-byte control word."""
@@ -50,6 +51,15 @@ def test_capacity_rounds_up_to_power_of_two_buckets():
     rc2, b2 = _bytes(1024, 0)
     assert rc == rc2 == 0 and b1 == b2  # 1000 slots -> 128 buckets of 8
     rc3, b3 = _bytes(1025, 0)
+    assert b3 > b2
+
+
+def test_iceberg_has_a_bucket_in_each_yard():
+    """The smallest iceberg table holds two buckets: one front yard, one backyard."""
+    rc, b1 = _bytes(1, 4)
+    rc2, b2 = _bytes(64, 4)
+    assert rc == rc2 == 0 and b1 == b2
+    rc3, b3 = _bytes(65, 4)
     assert b3 > b2
 
 
@@ -72,9 +82,10 @@ def test_bad_arguments_rejected_on_host():
 
 def test_paper_default_configurations():
     """Section 5: double hashing bucket 8 / tile 8; its metadata variant bucket 32 /
-    tile 4; power-of-two-choice bucket 32 / tile 8; its metadata variant 32 / 4."""
+    tile 4; power-of-two-choice bucket 32 / tile 8; its metadata variant 32 / 4;
+    iceberg bucket 32 / tile 8; its metadata variant 32 / 4."""
     L = hw.lib()
-    expect = {0: (8, 8), 1: (32, 4), 2: (32, 8), 3: (32, 4)}
+    expect = {0: (8, 8), 1: (32, 4), 2: (32, 8), 3: (32, 4), 4: (32, 8), 5: (32, 4)}
     for d, (b, t) in expect.items():
         c = hw._Config()
         assert L.hwave_config_default(d, ctypes.byref(c)) == 0

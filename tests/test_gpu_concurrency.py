@@ -3,8 +3,8 @@ one launch.
 
 * Adversarial benchmark (Section 4.1, Fig. 2) adapted to buckets: every target
   bucket is full and holds X; in one launch X is erased while two operations
-  insert Y, whose primary is the same bucket and whose other candidate bucket
-  has room.  Exactly one copy of Y may result.
+  insert Y, whose primary (iceberg: front-yard) bucket is the same bucket and
+  whose other candidate bucket has room.  Exactly one copy of Y may result.
 * Same-key storm: 2^16 SUM upserts over 16 keys that all share one primary
   bucket (every tile of every wave contends for one lock bit): the launch ends
   and every sum is exact.
@@ -24,7 +24,9 @@ from gpu_util import dev, host, image, u8
 
 pytestmark = pytest.mark.gpu
 
-ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M}
+ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M,
+           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M}
+ALL = ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M"]
 OPQ, OPI, OPU, OPE = 0, 1, 2, 3
 
 
@@ -42,13 +44,16 @@ def _layout_ok(t):
     return rep
 
 
-@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+@pytest.mark.parametrize("design", ALL)
 def test_adversarial_erase_vs_duplicate_insert(design):
     t = hw.Table(1 << 16, design)
     nb, B = t.num_buckets, t.bucket_slots
     cand = w.distinct_keys(w.stream_seed(50, ODESIGN[design]), nb * B * 6)
     prim = t.primary_bucket(dev(cand)).cpu().numpy()
-    targets = np.arange(0, nb, 2)  # even buckets are filled; odd ones stay empty
+    # even buckets are filled; odd ones stay empty (iceberg: even front-yard
+    # buckets; the backyard stays empty)
+    top = oracle.iceberg_front_buckets(nb) if design.startswith("ICEBERG") else nb
+    targets = np.arange(0, top, 2)
     order = np.argsort(prim, kind="stable")
     ps = prim[order]
     slots_img = np.full((nb * B, 2), np.uint64((1 << 64) - 1), dtype=np.uint64)
@@ -65,7 +70,9 @@ def test_adversarial_erase_vs_duplicate_insert(design):
                     y = k
                     break
             else:
-                y = k  # second bucket on the sequence is b + odd step: an odd, empty bucket
+                # double hashing: the second bucket on the sequence is b + odd step,
+                # an odd, empty bucket; iceberg: the backyard is empty
+                y = k
                 break
         assert y is not None
         slots_img[b * B: (b + 1) * B, 0] = resident
@@ -139,7 +146,7 @@ def test_same_key_storm_one_lock(design, bits):
     _layout_ok(t)
 
 
-@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+@pytest.mark.parametrize("design", ALL)
 @pytest.mark.parametrize("bits", [64, 32])
 def test_hot_keys_no_erase_table(design, bits):
     """Hot keys on a table that never erases: 2^14 SUM upserts over 16 keys sharing
@@ -168,7 +175,7 @@ def test_hot_keys_no_erase_table(design, bits):
     _layout_ok(t)
 
 
-@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+@pytest.mark.parametrize("design", ALL)
 @pytest.mark.parametrize("bits", [64, 32])
 def test_publish_litmus_insert_vs_query(design, bits):
     t = hw.Table(1 << 20, design, kv_bits=bits)
@@ -195,7 +202,7 @@ def test_publish_litmus_insert_vs_query(design, bits):
     _layout_ok(t)
 
 
-@pytest.mark.parametrize("design", ["DOUBLE_M", "P2_M", "DOUBLE", "P2"])
+@pytest.mark.parametrize("design", ["DOUBLE_M", "P2_M", "DOUBLE", "P2", "ICEBERG_M", "ICEBERG"])
 def test_publish_litmus_replace_vs_query(design):
     """Present keys overwritten with REPLACE while other tiles read them: every read
     returns the old value or one of the values written in this launch."""

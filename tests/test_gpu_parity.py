@@ -18,7 +18,9 @@ from gpu_util import dev, host, image, per_key_counts, u8
 
 pytestmark = pytest.mark.gpu
 
-ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M}
+ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M,
+           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M}
+ALL = ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M"]
 
 
 def check_layout(t, neg_keys=None, tile_bytes=None):
@@ -31,8 +33,9 @@ def check_layout(t, neg_keys=None, tile_bytes=None):
 
 
 def p2_full_is_genuine(t, full_keys):
-    """Power-of-two-choice reports FULL only when both candidate buckets are full
-    (checked on the final image of an insert-only table)."""
+    """Power-of-two-choice reports FULL only when both candidate buckets are full,
+    iceberg only when its front bucket and both backyard choices are (checked on
+    the final image of an insert-only table)."""
     slots, tags, _ = image(t)
     if t.kv_bits == 64:
         kw = slots.view(np.uint64)[0::2]
@@ -42,9 +45,11 @@ def p2_full_is_genuine(t, full_keys):
         free = kw >= np.uint32(0xFFFFFFFE)
     occ = (~free).reshape(t.num_buckets, t.bucket_slots).sum(axis=1)
     for k in np.unique(full_keys).tolist():
-        b1 = oracle.primary_bucket(k, t.num_buckets)
-        b2 = oracle.p2_alternate(k, t.num_buckets)
-        assert occ[b1] == t.bucket_slots and occ[b2] == t.bucket_slots, (k, occ[b1], occ[b2])
+        if t.design.startswith("ICEBERG"):
+            cand = oracle.iceberg_buckets(k, t.num_buckets)
+        else:
+            cand = (oracle.primary_bucket(k, t.num_buckets), oracle.p2_alternate(k, t.num_buckets))
+        assert all(occ[b] == t.bucket_slots for b in cand), (k, [occ[b] for b in cand])
 
 
 def check_dump(t, om):
@@ -87,8 +92,11 @@ CASES = [
     ("DOUBLE_M", 64, 32, 4), ("DOUBLE_M", 64, 32, 8), ("DOUBLE_M", 64, 16, 4), ("DOUBLE_M", 64, 64, 8),
     ("P2", 64, 32, 8), ("P2", 64, 32, 4), ("P2", 64, 32, 32), ("P2", 64, 16, 8),
     ("P2_M", 64, 32, 4), ("P2_M", 64, 32, 8), ("P2_M", 64, 32, 16), ("P2_M", 64, 64, 8),
+    ("ICEBERG", 64, 32, 8), ("ICEBERG", 64, 32, 4), ("ICEBERG", 64, 32, 16),
+    ("ICEBERG_M", 64, 32, 4), ("ICEBERG_M", 64, 32, 8), ("ICEBERG_M", 64, 64, 8),
     ("DOUBLE", 32, 16, 8), ("DOUBLE_M", 32, 32, 4), ("P2", 32, 32, 8), ("P2_M", 32, 32, 4),
-    ("P2_M", 32, 32, 32), ("DOUBLE", 32, 64, 32),
+    ("P2_M", 32, 32, 32), ("DOUBLE", 32, 64, 32), ("ICEBERG", 32, 32, 8), ("ICEBERG", 32, 32, 4),
+    ("ICEBERG_M", 32, 32, 4), ("ICEBERG_M", 32, 32, 8),
 ]
 
 
@@ -166,7 +174,7 @@ def test_all_ops_against_oracle(design, bits, bucket, tile):
 
 # ------------------------------------------------------------------ mixed batches (config 3 shape)
 
-@pytest.mark.parametrize("design", ["DOUBLE_M", "P2_M", "DOUBLE", "P2"])
+@pytest.mark.parametrize("design", ["DOUBLE_M", "P2_M", "DOUBLE", "P2", "ICEBERG_M", "ICEBERG"])
 def test_mixed_batches_against_oracle(design):
     """Preload a 2^k-key universe to load 0.5, then mixed batches (50% query, 30% SUM
     upsert, 20% erase, Zipf 0.99 keys; erase and upsert keys disjoint, queries avoid
@@ -198,7 +206,7 @@ def test_mixed_batches_against_oracle(design):
 # ------------------------------------------------------------------ 32-bit group-by (config 4 shape)
 
 @pytest.mark.parametrize("flags", [0, hw.F_NO_ERASE], ids=["locked", "noerase"])
-@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+@pytest.mark.parametrize("design", ALL)
 @pytest.mark.parametrize("logcap", [10, 14, 17])
 def test_u32_groupby_sum(design, logcap, flags):
     """Group-by hash aggregation: D = 0.85 * capacity distinct uint32 keys, each upserted
@@ -218,7 +226,7 @@ def test_u32_groupby_sum(design, logcap, flags):
     st = u8(t.upsert(dev(ops_k, 32), dev(ops_v, 32), combine="sum"))
     full = st == hw.ST_FULL
     if full.any():
-        assert design.startswith("P2"), "double hashing reported FULL below capacity"
+        assert not design.startswith("DOUBLE"), "double hashing reported FULL below capacity"
         p2_full_is_genuine(t, ops_k[full])
         # a key that never got in is absent from the table: drop all its ops
         lost = np.setdiff1d(ops_k[full], ops_k[st == hw.ST_DONE])
@@ -234,7 +242,7 @@ def test_u32_groupby_sum(design, logcap, flags):
 
 # ------------------------------------------------------------------ edge cases
 
-@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+@pytest.mark.parametrize("design", ALL)
 def test_sentinels_and_empty_batches(design):
     import torch
     t = hw.Table(1 << 12, design)
@@ -289,9 +297,41 @@ def test_primary_bucket_hook_matches_oracle():
     exp = np.array([oracle.primary_bucket(int(k), t.num_buckets) for k in keys[:2000]])
     assert np.array_equal(got[:2000], exp)
     assert got.max() < t.num_buckets
+    # iceberg: the front-yard bucket (its lock guards the key)
+    t = hw.Table(1 << 20, "ICEBERG_M")
+    got = t.primary_bucket(dev(keys)).cpu().numpy()
+    exp = np.array([oracle.iceberg_buckets(int(k), t.num_buckets)[0] for k in keys[:2000]])
+    assert np.array_equal(got[:2000], exp)
+    assert got.max() < oracle.iceberg_front_buckets(t.num_buckets)
 
 
-@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M"])
+# ------------------------------------------------------------------ iceberg load
+
+@pytest.mark.parametrize("design,paper", [("ICEBERG", 2.97), ("ICEBERG_M", 2.16)])
+def test_iceberg_load_2p20(design, paper):
+    """2^20-slot iceberg table, one insert batch to 0.9 load and a query batch of
+    those keys plus as many absent ones: every output, the dump and the layout
+    against the oracle; no backyard key has room in its front bucket (the table
+    never erased); positive-query probes near Table 1's load-phase figure."""
+    d = w.load_then_query(1 << 20, 0.9, config_id=1)
+    t = hw.Table(1 << 20, design)
+    om = oracle.OracleMap()
+    st = u8(t.insert(dev(d["keys"]), dev(d["vals"])))
+    assert np.array_equal(st, om.insert(d["keys"], d["vals"]))
+    found, vals = t.query(dev(d["qkeys"]))
+    ost, oval = om.query(d["qkeys"])
+    assert np.array_equal(u8(found), ost)
+    assert np.array_equal(host(vals), oval)
+    check_dump(t, om)
+    neg = d["qkeys"][~d["expect_found"]][:100000]
+    rep = check_layout(t, neg_keys=neg)
+    assert rep["front_room"] == 0
+    # concurrent placement differs from the sequential one only in which of
+    # several equal choices a key takes
+    assert abs(rep["pos_probe_sum"] / rep["live"] - paper) < 0.03
+
+
+@pytest.mark.parametrize("design", ALL)
 def test_no_erase_table_rejects_erase(design):
     import torch
     t = hw.Table(1 << 12, design, flags=hw.F_NO_ERASE)
