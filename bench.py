@@ -8,6 +8,8 @@ One step = one pass of the whole hot path over one synthetic batch set:
   erase a seeded 50% of the keys; re-query the positive and negative sets;
   16 mixed batches of 2^20 ops (50% query / 30% SUM upsert / 20% erase, Zipf 0.99
   over the inserted keys).
+The same step is then run, verified and timed on the other designs (double
+hashing, power-of-two-choice and iceberg, with and without tags) for comparison.
 Inputs are resident in HBM before timing.  `value` = all operations of K steps /
 wall time of K steps.  Per-kernel durations come from HIP events on the stream
 the kernels run on; p50/p99 batch latency is over the mixed 2^20-op batches.
@@ -184,6 +186,41 @@ def verify_step(step: Step, d) -> None:
     assert bool(torch.where(kept_mask, v == exp + 1, v == 0).all()), "re-query values"
     torch.cuda.synchronize()
     del exp
+
+
+def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
+    """The same step on other table designs at the same size and inputs (the paper's
+    load benchmark compares designs, Section 6.3): per design, closed-form
+    verification at full size, then per-phase rates over `steps` timed steps."""
+    import torch
+    import paper_2509_16407_amd as hw
+    main_t = step.t
+    out = {}
+    for des in designs:
+        step.t = hw.Table(d["cap"], des)
+        if verify:
+            verify_step(step, d)
+        for _ in range(warmup):
+            step.run()
+        events = {}
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(steps):
+            step.run(events)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ph = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in events.items()}
+        rates = {n: round(step.ops[n] / ph[n] / 1e6, 3) for n in step.phase_names}
+        if "mixed" in ph:
+            rates["mixed"] = round(step.mixed_ops / len(step.mixed) / ph["mixed"] / 1e6, 3)
+        out[des] = {"bucket": step.t.bucket_slots, "tile": step.t.tile, "verified": bool(verify),
+                    "step_gops": round(step.ops_per_step() * steps / wall / 1e9, 4), "phase_gops": rates}
+        log("design %s: %.2f Gops/s per step (insert_0.9 %.2f, query+ %.2f, query- %.2f)"
+            % (des, out[des]["step_gops"], rates["insert_0.9"], rates["query_pos"], rates["query_neg"]))
+        step.t = None
+        torch.cuda.empty_cache()
+    step.t = main_t
+    return out
 
 
 def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_reps=2, n_verify=16):
@@ -455,6 +492,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-table (batched) section")
     ap.add_argument("--no-served", action="store_true", help="skip the serving section")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--compare", default="DOUBLE,DOUBLE_M,P2,ICEBERG,ICEBERG_M",
+                    help="other designs to run the same step on ('' to skip)")
     ap.add_argument("--cpu-log2cap", type=int, default=24)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel first "
@@ -531,6 +570,11 @@ def main():
                           args.log2cap - 1, args.log2cap - 1, len(step.mixed)),
            "slots": step.t.capacity, "ops_per_step": ops_per_step, "key_bits": 64,
            "parallelism": "single GPU"}
+    designs = None
+    cmp_list = [x for x in args.compare.split(",") if x and x != args.design]
+    if cmp_list:
+        designs = bench_designs(step, d, cmp_list, verify=not args.no_verify)
+
     batched = None
     if not args.no_batched:
         del step
@@ -561,7 +605,7 @@ def main():
         "upsert_gops": rates["upsert"]["gops"],
         "p50_batch_ms": None if p50 is None else round(p50, 4),
         "p99_batch_ms": None if p99 is None else round(p99, 4),
-        "roofline": roof, "cpu_baseline": cpu, "batched": batched,
+        "roofline": roof, "cpu_baseline": cpu, "designs": designs, "batched": batched,
         "served": served,
         "kernel_source_hash": kernel_source_hash(),
     }

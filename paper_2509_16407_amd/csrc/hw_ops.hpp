@@ -263,11 +263,21 @@ struct Ops {
   // Claims slot s for a new key and publishes (key, value).  `seen` is the
   // free slot's word as the scan read it (see BucketScan::free_word): the
   // compare-and-swap expects it, and retries with whatever it finds for as
-  // long as the slot stays free.  Leader lane only touches memory; the result
-  // is broadcast.
+  // long as the slot stays free.  `excl`: the slot's bucket is written only by
+  // holders of the lock this operation holds (an iceberg front-yard bucket), so
+  // the slot stays free and is taken with plain stores -- tag first, then the
+  // slot -- without the compare-and-swap.  Leader lane only touches memory;
+  // the result is broadcast.
   __device__ static bool claim(const TableDev& tv, const Tile<T>& tile, uint64_t s, uint64_t seen,
-                               K key, K val, uint32_t tag) {
+                               K key, K val, uint32_t tag, bool excl = false) {
     bool ok = false;
+    if (excl) {
+      if (tile.leader()) {
+        if constexpr (C::TAGS) st((uint16_t*)tv.tagw + s, (uint16_t)tag);
+        publish(tv, s, key, val);
+      }
+      return true;
+    }
     if (tile.leader()) {
       if constexpr (C::TAGS) {
         uint32_t* wp = tv.tagw + (s >> 1);
@@ -354,10 +364,11 @@ struct Ops {
   // Claims the first free slot of bucket b (as found by scan `r`), rescanning
   // after lost races.  Returns the slot or -1 when the bucket is full.
   __device__ static int64_t claim_in_bucket(const TableDev& tv, const Tile<T>& tile, uint32_t b,
-                                            BucketScan<K> r, K key, K val, uint32_t tag) {
+                                            BucketScan<K> r, K key, K val, uint32_t tag,
+                                            bool excl = false) {
     while (r.free >= 0) {
       const uint64_t s = (uint64_t)b * B + r.free;
-      if (claim(tv, tile, s, r.free_word, key, val, tag)) return (int64_t)s;
+      if (claim(tv, tile, s, r.free_word, key, val, tag, excl)) return (int64_t)s;
       r = scan<false>(tv, tile, b, key, tag);
     }
     return -1;
@@ -560,9 +571,10 @@ struct Ops {
       combine_at(tv, tile, (uint64_t)h.b1 * B + rf.hit, val, combine);
       return ST_EXISTED;
     }
+    // Front-yard slots are claimed only under this lock: plain stores suffice.
     if (rf.free >= 0 && !erased(tv, tile)) {
-      if (claim_in_bucket(tv, tile, h.b1, rf, key, val, tag) >= 0) return ST_DONE;
-      rf.free = -1;  // not reached: front slots are claimed only under this lock
+      claim_in_bucket(tv, tile, h.b1, rf, key, val, tag, true);
+      return ST_DONE;
     }
     BucketScan<K> r1 = scan<true>(tv, tile, h.h2, key, tag);
     if (r1.hit >= 0) {
@@ -577,7 +589,10 @@ struct Ops {
         return ST_EXISTED;
       }
     }
-    if (rf.free >= 0 && claim_in_bucket(tv, tile, h.b1, rf, key, val, tag) >= 0) return ST_DONE;
+    if (rf.free >= 0) {
+      claim_in_bucket(tv, tile, h.b1, rf, key, val, tag, true);
+      return ST_DONE;
+    }
     const bool second_first = h.b3 != h.h2 && r2.fill < r1.fill;
     if (claim_in_bucket(tv, tile, second_first ? h.b3 : h.h2, second_first ? r2 : r1, key, val, tag) >= 0)
       return ST_DONE;
