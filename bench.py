@@ -9,7 +9,8 @@ One step = one pass of the whole hot path over one synthetic batch set:
   16 mixed batches of 2^20 ops (50% query / 30% SUM upsert / 20% erase, Zipf 0.99
   over the inserted keys).
 The same step is then run, verified and timed on the other designs (double
-hashing, power-of-two-choice and iceberg, with and without tags) for comparison.
+hashing, power-of-two-choice and iceberg, with and without tags) for comparison,
+followed by the aging (churn) benchmark of Section 6.5 on every design.
 Inputs are resident in HBM before timing.  `value` = all operations of K steps /
 wall time of K steps.  Per-kernel durations come from HIP events on the stream
 the kernels run on; p50/p99 batch latency is over the mixed 2^20-op batches.
@@ -188,6 +189,53 @@ def verify_step(step: Step, d) -> None:
     del exp
 
 
+def bench_phased(step: Step, d, design: str, conc_rates: dict, reps=3):
+    """Cost of concurrency (Section 6.4): the load phases and the query sets on the
+    phased variant of `design` (no locks, plain cacheable loads in queries), against
+    the same phases of the concurrent table.  Outputs are checked by closed form."""
+    import torch
+    import paper_2509_16407_amd as hw
+    from paper_2509_16407_amd import workloads as w
+    t = hw.Table(d["cap"], design, flags=hw.F_BSP)
+    b0, b1, b2 = step.bounds
+    nq = step.qpos.numel()
+    ms = {}
+
+    def timed(name, fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        ms.setdefault(name, []).append((a, b))
+
+    for r in range(reps + 1):
+        t.clear()
+        timed("insert_0.5", lambda: t.insert(step.keys[:b0], step.vals[:b0], status=step.st[:b0]))
+        timed("insert_0.75", lambda: t.insert(step.keys[b0:b1], step.vals[b0:b1], status=step.st[:b1 - b0]))
+        timed("insert_0.9", lambda: t.insert(step.keys[b1:b2], step.vals[b1:b2], status=step.st[:b2 - b1]))
+        if r == 0:
+            assert t.size() == b2, "phased %s: size after the load phases" % design
+        timed("query_pos", lambda: t.query(step.qpos, out=step.out, found=step.st[:nq]))
+        if r == 0:
+            exp = to_dev(w.value_of(d["qpos"]))
+            assert bool((step.st[:nq] == 1).all()) and bool((step.out == exp).all()), "phased positives"
+            del exp
+        timed("query_neg", lambda: t.query(step.qneg, out=step.out, found=step.st[:nq]))
+        if r == 0:
+            assert bool((step.st[:nq] == 0).all()), "phased negatives"
+    torch.cuda.synchronize()
+    res = {}
+    for name, ev in ms.items():
+        m = float(np.mean([a.elapsed_time(b) for a, b in ev[1:]]))
+        g = step.ops[name] / m / 1e6
+        res[name] = {"gops": round(g, 3), "concurrent_gops": conc_rates[name],
+                     "overhead_pct": round(100.0 * (g - conc_rates[name]) / g, 2)}
+    del t
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
     """The same step on other table designs at the same size and inputs (the paper's
     load benchmark compares designs, Section 6.3): per design, closed-form
@@ -215,12 +263,77 @@ def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
             rates["mixed"] = round(step.mixed_ops / len(step.mixed) / ph["mixed"] / 1e6, 3)
         out[des] = {"bucket": step.t.bucket_slots, "tile": step.t.tile, "verified": bool(verify),
                     "step_gops": round(step.ops_per_step() * steps / wall / 1e9, 4), "phase_gops": rates}
-        log("design %s: %.2f Gops/s per step (insert_0.9 %.2f, query+ %.2f, query- %.2f)"
-            % (des, out[des]["step_gops"], rates["insert_0.9"], rates["query_pos"], rates["query_neg"]))
         step.t = None
         torch.cuda.empty_cache()
+        out[des]["phased"] = bench_phased(step, d, des, rates)
+        log("design %s: %.2f Gops/s per step (insert_0.9 %.2f, query+ %.2f, query- %.2f)"
+            % (des, out[des]["step_gops"], rates["insert_0.9"], rates["query_pos"], rates["query_neg"]))
     step.t = main_t
     return out
+
+
+def bench_aging(designs, log2cap=26, iters=1000, probe_cap_double=80):
+    """The aging (churn) benchmark (Section 6.5) on each design: fill 2^log2cap slots
+    to 0.85, then `iters` iterations, each ONE mixed launch inserting a new 1% slice,
+    erasing the oldest 1% and querying 1% live and 1% never-inserted keys.  Every
+    output of every iteration is checked on the device against its closed form
+    (inserts and erases succeed, positives return 3k+1, negatives miss).  Double
+    hashing runs with a probe cap of 80 buckets."""
+    import torch
+    import paper_2509_16407_amd as hw
+    from paper_2509_16407_amd import workloads as w
+    t0 = time.time()
+    plan = w.aging_plan(1 << log2cap, iters=iters, config_id=6)
+    n0, s = plan["n0"], plan["s"]
+    kd = to_dev(plan["keys"])
+    nd = to_dev(plan["negs"])
+    log("aging: plan of %d + %d x %d keys ready in %.1f s" % (n0, iters, s, time.time() - t0))
+    ops = torch.cat([torch.full((s,), 1, dtype=torch.uint8), torch.full((s,), 3, dtype=torch.uint8),
+                     torch.zeros(2 * s, dtype=torch.uint8)]).cuda()
+    kb = torch.empty(4 * s, dtype=torch.int64, device="cuda")
+    st = torch.empty(4 * s, dtype=torch.uint8, device="cuda")
+    out = torch.empty(4 * s, dtype=torch.int64, device="cuda")
+    res = {}
+    for des in designs:
+        cap = probe_cap_double if des.startswith("DOUBLE") else 0
+        t = hw.Table(1 << log2cap, des, probe_cap=cap)
+        pre = t.insert(kd[:n0], kd[:n0] * 3 + 1)
+        bad = (pre != 1).sum()
+        ev = []
+        for i in range(iters):
+            ps = int(plan["pos_start"][i])
+            torch.cat([kd[n0 + i * s: n0 + (i + 1) * s], kd[i * s: (i + 1) * s], kd[ps: ps + s],
+                       nd[i * s: (i + 1) * s]], out=kb)
+            vb = kb * 3 + 1
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            t.mixed(ops, kb, vb, combine="sum", out=out, status=st)
+            b.record()
+            ev.append((a, b))
+            bad += (st[: 3 * s] != 1).sum() + (st[3 * s:] != 0).sum()
+            bad += (out[2 * s: 3 * s] != vb[2 * s: 3 * s]).sum() + (out[3 * s:] != 0).sum()
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        g = 4 * s / ms / 1e6
+        nbad = int(bad.item())
+        assert nbad == 0, "aging %s: %d outputs differ from their closed form" % (des, nbad)
+        assert t.size() == n0, "aging %s: size" % des
+        res[des] = {"gops_mean": round(float(4 * s * iters / ms.sum() / 1e6), 3),
+                    "gops_first10": round(float(g[:10].mean()), 3),
+                    "gops_last100": round(float(g[-100:].mean()), 3),
+                    "gops_min": round(float(g.min()), 3),
+                    "gops_every100": [round(float(g[j: j + 100].mean()), 3) for j in range(0, iters, 100)],
+                    "probe_cap": cap or None, "verified": True}
+        log("aging %s: mean %.2f Gops/s, first 10 %.2f, last 100 %.2f"
+            % (des, res[des]["gops_mean"], res[des]["gops_first10"], res[des]["gops_last100"]))
+        del t
+        torch.cuda.empty_cache()
+    del kd, nd
+    torch.cuda.empty_cache()
+    return {"workload": "aging: 2^%d slots filled to 0.85, %d iterations of one mixed launch (insert new 1%%, "
+                        "erase oldest 1%%, query 1%% live + 1%% absent)" % (log2cap, iters),
+            "ops_per_iteration": 4 * s, "designs": res}
 
 
 def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_reps=2, n_verify=16):
@@ -492,6 +605,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-table (batched) section")
     ap.add_argument("--no-served", action="store_true", help="skip the serving section")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-aging", action="store_true", help="skip the aging (churn) section")
     ap.add_argument("--compare", default="DOUBLE,DOUBLE_M,P2,ICEBERG,ICEBERG_M",
                     help="other designs to run the same step on ('' to skip)")
     ap.add_argument("--cpu-log2cap", type=int, default=24)
@@ -574,6 +688,17 @@ def main():
     cmp_list = [x for x in args.compare.split(",") if x and x != args.design]
     if cmp_list:
         designs = bench_designs(step, d, cmp_list, verify=not args.no_verify)
+        main_t = step.t
+        designs[args.design] = {"bucket": step.t.bucket_slots, "tile": step.t.tile, "main": True,
+                                "phase_gops": {k: v["gops"] for k, v in rates.items()}}
+        step.t = None
+        torch.cuda.empty_cache()
+        designs[args.design]["phased"] = bench_phased(step, d, args.design, designs[args.design]["phase_gops"])
+        step.t = main_t
+
+    aging = None
+    if not args.no_aging:
+        aging = bench_aging(["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M"])
 
     batched = None
     if not args.no_batched:
@@ -605,7 +730,7 @@ def main():
         "upsert_gops": rates["upsert"]["gops"],
         "p50_batch_ms": None if p50 is None else round(p50, 4),
         "p99_batch_ms": None if p99 is None else round(p99, 4),
-        "roofline": roof, "cpu_baseline": cpu, "designs": designs, "batched": batched,
+        "roofline": roof, "cpu_baseline": cpu, "designs": designs, "aging": aging, "batched": batched,
         "served": served,
         "kernel_source_hash": kernel_source_hash(),
     }

@@ -86,7 +86,16 @@ enum {
                               HWAVE_EINVAL, erase ops of hwave_mixed get
                               HWAVE_ST_INVALID, and upserts of present keys are
                               combined in place without taking the bucket lock
-                              (stable slots are never reused; Section 2.1)    */
+                              (stable slots are never reused; Section 2.1)    */,
+  HWAVE_F_BSP = 4          /* phased (bulk-synchronous) variant, to measure what
+                              concurrency costs (Section 6.4): writes take no
+                              lock, queries read with plain cacheable loads.
+                              Results are defined only for phased use: the
+                              writes of one call are to distinct keys, and no
+                              call overlaps another that writes the keys it
+                              touches.  64-bit tables at the default bucket and
+                              tile of each design; not accepted by
+                              hwave_multi_create                               */
 };
 
 /* Table configuration.  Zero fields take the design's defaults (the

@@ -24,6 +24,7 @@ OPS = {"query": 0, "insert": 1, "upsert": 2, "erase": 3}
 ST_MISS, ST_DONE, ST_EXISTED, ST_FULL, ST_INVALID = 0, 1, 2, 3, 4
 F_NO_SHORTCUT = 1
 F_NO_ERASE = 2
+F_BSP = 4
 
 
 class HashWaveError(RuntimeError):

@@ -61,7 +61,7 @@ const std::vector<const KernelSet*>& registry() {
   static std::once_flag once;
   std::call_once(once, [] {
     const KernelSet* (*fns[])(size_t*) = {sets_u64_double, sets_u64_p2, sets_u64_iceberg,
-                                          sets_u32_double, sets_u32_p2, sets_u32_iceberg};
+                                          sets_u32_double, sets_u32_p2, sets_u32_iceberg, sets_u64_bsp};
     for (auto f : fns) {
       size_t n = 0;
       const KernelSet* s = f(&n);
@@ -71,9 +71,12 @@ const std::vector<const KernelSet*>& registry() {
   return all;
 }
 
-const KernelSet* find_set(int kv_bits, int design, int bucket, int tile) {
+const KernelSet* find_set(const hwave_config& c, int design) {
+  const bool bsp = (c.flags & HWAVE_F_BSP) != 0;
   for (const KernelSet* s : registry())
-    if (s->kv_bits == kv_bits && s->design == design && s->bucket == bucket && s->tile == tile) return s;
+    if (s->kv_bits == (int)c.kv_bits && s->design == design && s->bucket == (int)c.bucket_slots &&
+        s->tile == (int)c.tile && s->bsp == bsp)
+      return s;
   return nullptr;
 }
 
@@ -235,7 +238,7 @@ int hwave_table_bytes(uint64_t capacity, hwave_design design, const hwave_config
   hwave_config c;
   int rc = resolve_config(design, cfg, &c);
   if (rc) return rc;
-  if (!find_set(c.kv_bits, design, c.bucket_slots, c.tile)) return HWAVE_EUNSUPPORTED;
+  if (!find_set(c, design)) return HWAVE_EUNSUPPORTED;
   Layout L;
   rc = layout_of(capacity, design, c, &L);
   if (rc) return rc;
@@ -250,7 +253,7 @@ int hwave_create(hwave_table** out, uint64_t capacity, hwave_design design, cons
   hwave_config c;
   int rc = resolve_config(design, cfg, &c);
   if (rc) return rc;
-  const KernelSet* ks = find_set(c.kv_bits, design, c.bucket_slots, c.tile);
+  const KernelSet* ks = find_set(c, design);
   if (!ks) return HWAVE_EUNSUPPORTED;
   Layout L;
   rc = layout_of(capacity, design, c, &L);
@@ -281,7 +284,7 @@ int hwave_create_in(hwave_table** out, void* d_buffer, uint64_t buffer_bytes, ui
   hwave_config c;
   int rc = resolve_config(design, cfg, &c);
   if (rc) return rc;
-  const KernelSet* ks = find_set(c.kv_bits, design, c.bucket_slots, c.tile);
+  const KernelSet* ks = find_set(c, design);
   if (!ks) return HWAVE_EUNSUPPORTED;
   Layout L;
   rc = layout_of(capacity, design, c, &L);
@@ -513,6 +516,7 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
   for (uint32_t i = 0; i < n_tables; i++) {
     const hwave_table* t = tables[i];
     if (!t || (int)t->cfg.kv_bits != kv || t->device != dev) return HWAVE_EINVAL;
+    if (t->cfg.flags & HWAVE_F_BSP) return HWAVE_EUNSUPPORTED;
     int cls = multi_menu_index(kv, (int)t->design, (int)t->cfg.bucket_slots, (int)t->cfg.tile);
     if (cls < 0) return HWAVE_EUNSUPPORTED;
     h[i].tv = t->la.tv;

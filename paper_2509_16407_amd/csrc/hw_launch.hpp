@@ -111,6 +111,7 @@ typedef hipError_t (*mixed_fn)(const LaunchArgs&, const uint8_t*, const void*, c
 
 struct KernelSet {
   int kv_bits, design, bucket, tile;
+  bool bsp;  // phased variant (no locks, plain loads in queries)
   upsert_fn upsert;
   query_fn query;
   erase_fn erase;
@@ -148,7 +149,7 @@ struct Launch {
 
 template <class C>
 constexpr KernelSet make_set() {
-  return KernelSet{(int)sizeof(typename C::K) * 8, C::DESIGN, C::B, C::T, &Launch<C>::upsert,
+  return KernelSet{(int)sizeof(typename C::K) * 8, C::DESIGN, C::B, C::T, C::BSP, &Launch<C>::upsert,
                    &Launch<C>::query, &Launch<C>::erase, &Launch<C>::mixed};
 }
 
@@ -159,5 +160,6 @@ const KernelSet* sets_u32_double(size_t* n);
 const KernelSet* sets_u32_p2(size_t* n);
 const KernelSet* sets_u64_iceberg(size_t* n);
 const KernelSet* sets_u32_iceberg(size_t* n);
+const KernelSet* sets_u64_bsp(size_t* n);
 
 }  // namespace hw

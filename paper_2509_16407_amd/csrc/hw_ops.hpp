@@ -60,10 +60,15 @@ struct TableDev {
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
 };
 
-template <typename K_, int DESIGN_, int B_, int T_>
+// BSP_: the phased (bulk-synchronous) variant used to measure what concurrency
+// costs (Section 6.4): writes take no lock and queries read with plain cacheable
+// loads.  Correct only for phased use: the writes of one launch are to distinct
+// keys and no launch mixes writes and reads of one key.
+template <typename K_, int DESIGN_, int B_, int T_, bool BSP_ = false>
 struct Cfg {
   using K = K_;
   static constexpr int DESIGN = DESIGN_;
+  static constexpr bool BSP = BSP_;
   static constexpr bool TAGS = DESIGN == D_DOUBLE_M || DESIGN == D_P2_M || DESIGN == D_ICEBERG_M;
   static constexpr bool DOUBLE = DESIGN == D_DOUBLE || DESIGN == D_DOUBLE_M;
   static constexpr bool ICEBERG = DESIGN == D_ICEBERG || DESIGN == D_ICEBERG_M;
@@ -103,14 +108,28 @@ struct Ops {
     return (K*)tv.slots + 2 * s + 1;
   }
 
-  // Coherent read of one whole slot.
+  // Loads: agent-coherent, or plain cacheable ones (PLAIN: queries of the phased
+  // variant only -- they never retry, so a stale line cannot hold them up).
+  template <bool PLAIN>
+  __device__ static __forceinline__ u32x4 rd16(const void* p) {
+    if constexpr (PLAIN) return *(const u32x4*)p;
+    else return ld16(p);
+  }
+  template <bool PLAIN, typename X>
+  __device__ static __forceinline__ X rd(const X* p) {
+    if constexpr (PLAIN) return *p;
+    else return ld(p);
+  }
+
+  // Read of one whole slot in one access.
+  template <bool PLAIN = false>
   __device__ static __forceinline__ void load_slot(const TableDev& tv, uint64_t s, K& k, K& v) {
     if constexpr (sizeof(K) == 8) {
-      u32x4 w = ld16(key_ptr(tv, s));
+      u32x4 w = rd16<PLAIN>(key_ptr(tv, s));
       k = (uint64_t)w.x | ((uint64_t)w.y << 32);
       v = (uint64_t)w.z | ((uint64_t)w.w << 32);
     } else {
-      uint64_t w = ld((const uint64_t*)key_ptr(tv, s));
+      uint64_t w = rd<PLAIN>((const uint64_t*)key_ptr(tv, s));
       k = (uint32_t)w;
       v = (uint32_t)(w >> 32);
     }
@@ -129,7 +148,7 @@ struct Ops {
   // Slot designs read the bucket one tile-width at a time and stop at a hit;
   // tag designs read the tag bucket once and check each tag match against the
   // full key (tags are lossy, Section 4.3).
-  template <bool FIND>
+  template <bool FIND, bool PLAIN = false>
   __device__ static BucketScan<K> scan(const TableDev& tv, const Tile<T>& tile, uint32_t b, K key,
                                        uint32_t tag) {
     BucketScan<K> r;
@@ -147,9 +166,9 @@ struct Ops {
         const uint64_t first = base + (uint64_t)s * T * SPL + (uint64_t)tile.tl * SPL;
         K k[SPL], v[SPL];
         if constexpr (SPL == 1) {
-          load_slot(tv, first, k[0], v[0]);
+          load_slot<PLAIN>(tv, first, k[0], v[0]);
         } else {
-          u32x4 w = ld16(key_ptr(tv, first));
+          u32x4 w = rd16<PLAIN>(key_ptr(tv, first));
           k[0] = (K)w.x; v[0] = (K)w.y; k[1] = (K)w.z; v[1] = (K)w.w;
         }
         uint32_t m_hit = 0, m_free = 0, m_empty = 0;
@@ -192,19 +211,19 @@ struct Ops {
       uint32_t tw[(TPL + 1) / 2];
       const uint32_t* tp = tv.tagw + (base + (uint64_t)tile.tl * TPL) / 2;
       if constexpr (TPL == 16) {
-        u32x4 a = ld16(tp), c = ld16(tp + 4);
+        u32x4 a = rd16<PLAIN>(tp), c = rd16<PLAIN>(tp + 4);
         tw[0] = a.x; tw[1] = a.y; tw[2] = a.z; tw[3] = a.w;
         tw[4] = c.x; tw[5] = c.y; tw[6] = c.z; tw[7] = c.w;
       } else if constexpr (TPL == 8) {
-        u32x4 a = ld16(tp);
+        u32x4 a = rd16<PLAIN>(tp);
         tw[0] = a.x; tw[1] = a.y; tw[2] = a.z; tw[3] = a.w;
       } else if constexpr (TPL == 4) {
-        uint64_t a = ld((const uint64_t*)tp);
+        uint64_t a = rd<PLAIN>((const uint64_t*)tp);
         tw[0] = (uint32_t)a; tw[1] = (uint32_t)(a >> 32);
       } else if constexpr (TPL == 2) {
-        tw[0] = ld(tp);
+        tw[0] = rd<PLAIN>(tp);
       } else {
-        tw[0] = ld((const uint16_t*)tv.tagw + base + tile.tl);
+        tw[0] = rd<PLAIN>((const uint16_t*)tv.tagw + base + tile.tl);
       }
       uint32_t m_hit = 0, m_free = 0, m_empty = 0;
 #pragma unroll
@@ -224,7 +243,7 @@ struct Ops {
             int j = __ffs(mm) - 1;
             mm &= mm - 1;
             K k, v;
-            load_slot(tv, base + src * TPL + j, k, v);
+            load_slot<PLAIN>(tv, base + src * TPL + j, k, v);
             if (k == key) {
               r.hit = src * TPL + j;
               r.val = v;
@@ -408,15 +427,15 @@ struct Ops {
   __device__ static int64_t find(const TableDev& tv, const Tile<T>& tile, const Home& h, K key,
                                  uint32_t tag, K* val) {
     if constexpr (C::ICEBERG) {
-      BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
+      BucketScan<K> r = scan<true, C::BSP>(tv, tile, h.b1, key, tag);
       if (r.hit >= 0) { *val = r.val; return (int64_t)h.b1 * B + r.hit; }
       // The flag is read after the front bucket: a free slot seen there that an
       // erase made is seen together with the flag the erase set first.
       if (r.free >= 0 && !erased(tv, tile)) return -1;
-      r = scan<true>(tv, tile, h.h2, key, tag);
+      r = scan<true, C::BSP>(tv, tile, h.h2, key, tag);
       if (r.hit >= 0) { *val = r.val; return (int64_t)h.h2 * B + r.hit; }
       if (h.b3 != h.h2) {
-        r = scan<true>(tv, tile, h.b3, key, tag);
+        r = scan<true, C::BSP>(tv, tile, h.b3, key, tag);
         if (r.hit >= 0) { *val = r.val; return (int64_t)h.b3 * B + r.hit; }
       }
       return -1;
@@ -424,17 +443,17 @@ struct Ops {
       const uint32_t step = step_of(tv, h);
       uint32_t b = h.b1;
       for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
-        BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
+        BucketScan<K> r = scan<true, C::BSP>(tv, tile, b, key, tag);
         if (r.hit >= 0) { *val = r.val; return (int64_t)b * B + r.hit; }
         if (r.has_empty) break;
       }
       return -1;
     } else {
-      BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
+      BucketScan<K> r = scan<true, C::BSP>(tv, tile, h.b1, key, tag);
       if (r.hit >= 0) { *val = r.val; return (int64_t)h.b1 * B + r.hit; }
       const uint32_t b2 = h.h2 & tv.bucket_mask;
       if (b2 != h.b1) {
-        r = scan<true>(tv, tile, b2, key, tag);
+        r = scan<true, C::BSP>(tv, tile, b2, key, tag);
         if (r.hit >= 0) { *val = r.val; return (int64_t)b2 * B + r.hit; }
       }
       return -1;
@@ -464,6 +483,14 @@ struct Ops {
     // The critical section runs inside the retry loop: a tile that wins the
     // lock finishes and releases it in the same iteration, so tiles of one wave
     // waiting on each other cannot deadlock (lanes of a wave run in lockstep).
+    if constexpr (C::BSP) {
+      if constexpr (C::ICEBERG)
+        return upsert_iceberg_locked(tv, tile, h, key, val, tag, combine);
+      else if constexpr (C::DOUBLE)
+        return upsert_double_locked(tv, tile, h, key, val, tag, combine);
+      else
+        return upsert_p2_locked(tv, tile, h, key, val, tag, combine);
+    }
     while (pending) {
       bo.pause();
       if (tv.no_erase) {
@@ -571,10 +598,11 @@ struct Ops {
       combine_at(tv, tile, (uint64_t)h.b1 * B + rf.hit, val, combine);
       return ST_EXISTED;
     }
-    // Front-yard slots are claimed only under this lock: plain stores suffice.
+    // Front-yard slots are claimed only under this lock: plain stores suffice
+    // (not in the phased variant, which takes no lock).
     if (rf.free >= 0 && !erased(tv, tile)) {
-      claim_in_bucket(tv, tile, h.b1, rf, key, val, tag, true);
-      return ST_DONE;
+      if (claim_in_bucket(tv, tile, h.b1, rf, key, val, tag, !C::BSP) >= 0) return ST_DONE;
+      rf = scan<false>(tv, tile, h.b1, key, tag);  // phased variant: lost the slot to another key
     }
     BucketScan<K> r1 = scan<true>(tv, tile, h.h2, key, tag);
     if (r1.hit >= 0) {
@@ -589,10 +617,7 @@ struct Ops {
         return ST_EXISTED;
       }
     }
-    if (rf.free >= 0) {
-      claim_in_bucket(tv, tile, h.b1, rf, key, val, tag, true);
-      return ST_DONE;
-    }
+    if (rf.free >= 0 && claim_in_bucket(tv, tile, h.b1, rf, key, val, tag, !C::BSP) >= 0) return ST_DONE;
     const bool second_first = h.b3 != h.h2 && r2.fill < r1.fill;
     if (claim_in_bucket(tv, tile, second_first ? h.b3 : h.h2, second_first ? r2 : r1, key, val, tag) >= 0)
       return ST_DONE;
@@ -611,7 +636,8 @@ struct Ops {
     return find(tv, tile, h, key, tag, out) >= 0 ? ST_DONE : ST_MISS;
   }
 
-  // Erase under the primary lock.  ST_DONE if removed, ST_MISS if absent.
+  // Erase under the primary lock (none in the phased variant).  ST_DONE if
+  // removed, ST_MISS if absent.
   __device__ static uint8_t erase(const TableDev& tv, const Tile<T>& tile, K key) {
     if (key >= Keys<K>::FIRST_INVALID || tv.no_erase) return ST_INVALID;
     const Home h = home_of(tv, key);
@@ -622,6 +648,7 @@ struct Ops {
         wait_mem();
       }
     }
+    if constexpr (C::BSP) return erase_locked(tv, tile, h, key, tag);
     uint8_t status = ST_MISS;
     bool pending = true;
     Backoff bo;
@@ -631,46 +658,7 @@ struct Ops {
       const bool go = (attempt & 255) == 0 || lock_looks_free(tv.locks, h.b1, tile);
       ++attempt;
       if (go && try_lock(tv.locks, h.b1, tile)) {
-        if constexpr (C::ICEBERG) {
-          const uint32_t cand[3] = {h.b1, h.h2, h.b3};
-#pragma unroll 1
-          for (int i = 0; i < 3; ++i) {
-            if (i == 2 && h.b3 == h.h2) break;
-            BucketScan<K> r = scan<true>(tv, tile, cand[i], key, tag);
-            if (r.hit >= 0) {
-              remove(tv, tile, (uint64_t)cand[i] * B + r.hit, tag);
-              status = ST_DONE;
-              break;
-            }
-          }
-        } else if constexpr (C::DOUBLE) {
-          const uint32_t step = step_of(tv, h);
-          uint32_t b = h.b1;
-          for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
-            BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
-            if (r.hit >= 0) {
-              remove(tv, tile, (uint64_t)b * B + r.hit, tag);
-              status = ST_DONE;
-              break;
-            }
-            if (r.has_empty) break;
-          }
-        } else {
-          BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
-          if (r.hit >= 0) {
-            remove(tv, tile, (uint64_t)h.b1 * B + r.hit, tag);
-            status = ST_DONE;
-          } else {
-            const uint32_t b2 = h.h2 & tv.bucket_mask;
-            if (b2 != h.b1) {
-              r = scan<true>(tv, tile, b2, key, tag);
-              if (r.hit >= 0) {
-                remove(tv, tile, (uint64_t)b2 * B + r.hit, tag);
-                status = ST_DONE;
-              }
-            }
-          }
-        }
+        status = erase_locked(tv, tile, h, key, tag);
         unlock(tv.locks, h.b1, tile);
         pending = false;
       } else {
@@ -678,6 +666,49 @@ struct Ops {
       }
     }
     return status;
+  }
+
+  // Finds and removes `key` among its candidate buckets.
+  __device__ static uint8_t erase_locked(const TableDev& tv, const Tile<T>& tile, const Home& h, K key,
+                                         uint32_t tag) {
+    if constexpr (C::ICEBERG) {
+      const uint32_t cand[3] = {h.b1, h.h2, h.b3};
+#pragma unroll 1
+      for (int i = 0; i < 3; ++i) {
+        if (i == 2 && h.b3 == h.h2) break;
+        BucketScan<K> r = scan<true>(tv, tile, cand[i], key, tag);
+        if (r.hit >= 0) {
+          remove(tv, tile, (uint64_t)cand[i] * B + r.hit, tag);
+          return ST_DONE;
+        }
+      }
+    } else if constexpr (C::DOUBLE) {
+      const uint32_t step = step_of(tv, h);
+      uint32_t b = h.b1;
+      for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
+        BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
+        if (r.hit >= 0) {
+          remove(tv, tile, (uint64_t)b * B + r.hit, tag);
+          return ST_DONE;
+        }
+        if (r.has_empty) break;
+      }
+    } else {
+      BucketScan<K> r = scan<true>(tv, tile, h.b1, key, tag);
+      if (r.hit >= 0) {
+        remove(tv, tile, (uint64_t)h.b1 * B + r.hit, tag);
+        return ST_DONE;
+      }
+      const uint32_t b2 = h.h2 & tv.bucket_mask;
+      if (b2 != h.b1) {
+        r = scan<true>(tv, tile, b2, key, tag);
+        if (r.hit >= 0) {
+          remove(tv, tile, (uint64_t)b2 * B + r.hit, tag);
+          return ST_DONE;
+        }
+      }
+    }
+    return ST_MISS;
   }
 };
 

@@ -476,3 +476,44 @@ def served_requests(n_tables: int, universe: int, n_req: int, rate_per_s: float,
             vals = None
         zpos += n
         yield dict(t=t, table=table, kind=kind, keys=keys, vals=vals)
+
+
+def stream_keys(seed: int, start: int, count: int) -> np.ndarray:
+    """Elements [start, start+count) of a splitmix64 stream used directly as 64-bit
+    keys.  Disjoint position ranges give disjoint keys (the mix is a bijection of the
+    counter).  A stream value equal to one of the three reserved key patterns (odds
+    about 3 in 2^64 per key) raises instead of being dropped, so positions stay
+    exact."""
+    k = splitmix64(seed, start, count)
+    if count and int(k.max()) > U64_MAX - 3:
+        raise ValueError("stream %#x hit a reserved key pattern in [%d, %d)" % (seed, start, start + count))
+    return k
+
+
+def aging_plan(capacity: int, load: float = 0.85, frac: float = 0.01, iters: int = 1000,
+               config_id: int = 6):
+    """The aging (churn) benchmark of Section 6.5.  The table is filled to `load`
+    (n0 = floor(load * capacity) keys, v = 3k+1); then every iteration, in ONE
+    mixed launch, inserts the next s = floor(frac * n0) new keys, erases the oldest
+    s live keys, queries s live keys and s keys never inserted.
+
+    Key j of one stream is inserted by the preload when j < n0, else by iteration
+    (j - n0) // s; iteration i erases keys [i*s, (i+1)*s).  Its positive queries are
+    the s keys starting at pos_start[i], a seeded offset inside the keys that stay
+    live through iteration i; its negative queries are negs[i*s:(i+1)*s], stream
+    positions past every inserted key.  Every output of an iteration is therefore
+    the same under any order of its operations: inserts and erases succeed,
+    positives return 3k+1, negatives miss.
+
+    Returns dict(n0, s, iters, keys, negs, pos_start)."""
+    n0 = int(load * capacity)
+    s = max(1, int(frac * n0))
+    if n0 < 2 * s:
+        raise ValueError("the fill must hold at least two slices")
+    total = n0 + iters * s
+    seed = stream_seed(config_id, 1)
+    keys = stream_keys(seed, 0, total)
+    negs = stream_keys(seed, total, iters * s)
+    off = uniform_below(stream_seed(config_id, 2), 0, iters, n0 - 2 * s + 1)
+    pos_start = (np.arange(iters, dtype=np.int64) + 1) * s + off.astype(np.int64)
+    return dict(n0=n0, s=s, iters=iters, keys=keys, negs=negs, pos_start=pos_start)

@@ -1,0 +1,53 @@
+"""Aging (churn) benchmark shape on the GPU (Section 6.5), every iteration against
+the oracle: fill to 0.85, then iterations that each insert a new 1% slice, erase the
+oldest 1%, and query 1% live and 1% never-inserted keys, all in one mixed launch.
+Double hashing runs with a cap of 80 buckets per probe sequence (the paper's aged
+double-hashing negative queries average exactly 80 probes, Table 1)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_16407_amd as hw
+from paper_2509_16407_amd import workloads as w
+from gpu_util import dev, host, image, u8
+
+pytestmark = pytest.mark.gpu
+
+ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M,
+           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M}
+OPQ, OPI, OPE = 0, 1, 3
+
+
+@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M"])
+def test_aging_against_oracle(design):
+    cap = 1 << 16
+    plan = w.aging_plan(cap, iters=150, config_id=6)
+    n0, s = plan["n0"], plan["s"]
+    keys, negs = plan["keys"], plan["negs"]
+    t = hw.Table(cap, design, probe_cap=80 if design.startswith("DOUBLE") else 0)
+    om = oracle.OracleMap()
+    st = u8(t.insert(dev(keys[:n0]), dev(w.value_of(keys[:n0]))))
+    assert np.array_equal(st, om.insert(keys[:n0], w.value_of(keys[:n0])))
+    ops = np.concatenate([np.full(s, OPI), np.full(s, OPE), np.full(2 * s, OPQ)]).astype(np.uint8)
+    ops_d = torch.from_numpy(ops).cuda()
+    for i in range(plan["iters"]):
+        ps = int(plan["pos_start"][i])
+        bk = np.concatenate([keys[n0 + i * s: n0 + (i + 1) * s], keys[i * s: (i + 1) * s],
+                             keys[ps: ps + s], negs[i * s: (i + 1) * s]])
+        bv = w.value_of(bk)
+        got_st, got_v = t.mixed(ops_d, dev(bk), dev(bv))
+        ost, ov = om.apply(bk, bv, ops=ops)
+        assert np.array_equal(u8(got_st), ost), i
+        assert np.array_equal(host(got_v), ov), i
+        assert (ost[: 3 * s] == oracle.DONE).all() and (ost[3 * s:] == oracle.MISS).all()
+    k, v = t.export()
+    k, v = host(k), host(v)
+    o = np.argsort(k)
+    ok, ov = om.dump()
+    assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov)
+    slots, tags, locks = image(t)
+    nv, rep = oracle.layout_check(ODESIGN[design], 64, t.num_buckets, t.bucket_slots, slots, tags, locks)
+    assert nv == 0, rep
+    if design.startswith("DOUBLE"):
+        assert rep["max_seq_index"] < 80

@@ -345,3 +345,43 @@ def test_no_erase_table_rejects_erase(design):
     assert t.size() == 100
     f, v = t.query(dev(k))
     assert (u8(f) == hw.ST_DONE).all() and np.array_equal(host(v), k)
+
+
+# ------------------------------------------------------------------ phased variant
+
+@pytest.mark.parametrize("design", ALL)
+def test_phased_variant_against_oracle(design):
+    """The phased (bulk-synchronous) variant, used in phased fashion: distinct-key
+    insert batches, then queries, then an erase batch and a refill, then queries --
+    every output, the dump and the layout against the oracle."""
+    cap = 1 << 16
+    t = hw.Table(cap, design, flags=hw.F_BSP)
+    om = oracle.OracleMap()
+    seed = w.stream_seed(110, ODESIGN[design])
+    pool = w.distinct_keys(seed, int(0.95 * cap))
+    absent = w.distinct_keys(seed, 20000, skip=len(pool))
+    n1 = int(0.8 * cap) + 5
+    for a, b in ((0, n1 // 2), (n1 // 2, n1)):
+        k = pool[a:b]
+        st = u8(t.insert(dev(k), dev(w.value_of(k))))
+        assert np.array_equal(st, om.insert(k, w.value_of(k)))
+    q = np.concatenate([pool, absent])
+    q = q[w.permutation(seed + 1, len(q))]
+    f, v = t.query(dev(q))
+    of, ov = om.query(q)
+    assert np.array_equal(u8(f), of) and np.array_equal(host(v), ov)
+    ke = pool[: n1: 3]
+    assert np.array_equal(u8(t.erase(dev(ke))), om.erase(ke))
+    k = pool[n1: int(0.9 * cap)]
+    assert np.array_equal(u8(t.insert(dev(k), dev(w.value_of(k)))), om.insert(k, w.value_of(k)))
+    f, v = t.query(dev(q))
+    of, ov = om.query(q)
+    assert np.array_equal(u8(f), of) and np.array_equal(host(v), ov)
+    check_dump(t, om)
+    check_layout(t)
+
+
+def test_phased_variant_not_accepted_by_multi():
+    t = hw.Table(1 << 12, "P2_M", flags=hw.F_BSP)
+    with pytest.raises(hw.HashWaveError):
+        hw.Multi([t])

@@ -94,3 +94,16 @@ def test_selection_sample_exact_size_and_uniform():
     assert np.all(np.abs(counts - exp) < 5 * np.sqrt(exp))
     assert len(w.sample_without_replacement(7, 10, 10)) == 10
     assert len(w.sample_without_replacement(7, 10, 0)) == 0
+
+
+def test_aging_plan_slices():
+    """Aging recipe (Section 6.5): every positive slice lies in the keys live through
+    its iteration and misses that iteration's erase slice; negatives were never
+    inserted; all keys are distinct."""
+    p = w.aging_plan(1 << 14, iters=300)
+    n0, s = p["n0"], p["s"]
+    assert n0 == int(0.85 * (1 << 14)) and s == int(0.01 * n0)
+    assert len(p["keys"]) == n0 + 300 * s and len(p["negs"]) == 300 * s
+    assert len(np.unique(np.concatenate([p["keys"], p["negs"]]))) == len(p["keys"]) + len(p["negs"])
+    for i, ps in enumerate(p["pos_start"].tolist()):
+        assert (i + 1) * s <= ps and ps + s <= n0 + i * s
