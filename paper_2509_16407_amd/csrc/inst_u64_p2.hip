@@ -6,7 +6,7 @@ const KernelSet* sets_u64_p2(size_t* n) {
   static const KernelSet s[] = {
       make_set<Cfg<uint64_t, D_P2, 16, 8>>(),   make_set<Cfg<uint64_t, D_P2, 32, 4>>(),
       make_set<Cfg<uint64_t, D_P2, 32, 8>>(),   make_set<Cfg<uint64_t, D_P2, 32, 16>>(),
-      make_set<Cfg<uint64_t, D_P2, 32, 32>>(),  make_set<Cfg<uint64_t, D_P2_M, 16, 4>>(),
+      make_set<Cfg<uint64_t, D_P2, 32, 32>>(),  make_set<Cfg<uint64_t, D_P2_M, 16, 4>>(),   make_set<Cfg<uint64_t, D_P2_M, 32, 2>>(),
       make_set<Cfg<uint64_t, D_P2_M, 32, 4>>(), make_set<Cfg<uint64_t, D_P2_M, 32, 8>>(),
       make_set<Cfg<uint64_t, D_P2_M, 32, 16>>(), make_set<Cfg<uint64_t, D_P2_M, 64, 8>>(),
   };
