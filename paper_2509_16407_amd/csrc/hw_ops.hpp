@@ -564,11 +564,12 @@ struct Ops {
       combine_at(tv, tile, (uint64_t)b1 * B + r1.hit, val, combine);
       return ST_EXISTED;
     }
-    if (tv.shortcut && 4 * r1.fill < 3 * (uint32_t)B) {
-      uint32_t erased = tile.leader() ? ld(tv.ctrl) : 0u;
-      if (tile.bcast(erased, 0) == 0) {
-        if (claim_in_bucket(tv, tile, b1, r1, key, val, tag) >= 0) return ST_DONE;
-        r1 = scan<false>(tv, tile, b1, key, tag);  // filled up meanwhile: full path
+    if (tv.shortcut && 4 * r1.fill < 3 * (uint32_t)B && !erased(tv, tile)) {
+      // After a lost race the shortcut is judged again on the bucket as it now
+      // is: concurrent claims may have taken it past 3/4.
+      while (4 * r1.fill < 3 * (uint32_t)B && r1.free >= 0) {
+        if (claim(tv, tile, (uint64_t)b1 * B + r1.free, r1.free_word, key, val, tag)) return ST_DONE;
+        r1 = scan<false>(tv, tile, b1, key, tag);
       }
     }
     if (b2 == b1) {
@@ -579,12 +580,31 @@ struct Ops {
       combine_at(tv, tile, (uint64_t)b2 * B + r2.hit, val, combine);
       return ST_EXISTED;
     }
-    const bool alt_first = r2.fill < r1.fill;
-    if (claim_in_bucket(tv, tile, alt_first ? b2 : b1, alt_first ? r2 : r1, key, val, tag) >= 0)
-      return ST_DONE;
-    if (claim_in_bucket(tv, tile, alt_first ? b1 : b2, alt_first ? r1 : r2, key, val, tag) >= 0)
-      return ST_DONE;
-    return ST_FULL;
+    return claim_less_loaded(tv, tile, b1, r1, b2, r2, key, val, tag);
+  }
+
+  // Claims a slot in the less loaded of buckets ba and bb (ties to ba), judging
+  // the choice again after every lost race, so that operations deciding at the
+  // same moment on the same pair do not all pile into one bucket.  ST_FULL when
+  // both are full.
+  __device__ static uint8_t claim_less_loaded(const TableDev& tv, const Tile<T>& tile, uint32_t ba,
+                                              BucketScan<K> ra, uint32_t bb, BucketScan<K> rb, K key,
+                                              K val, uint32_t tag) {
+    for (;;) {
+      const bool second = rb.fill < ra.fill;
+      BucketScan<K>& rp = second ? rb : ra;
+      BucketScan<K>& ro = second ? ra : rb;
+      const uint32_t bp = second ? bb : ba, bo = second ? ba : bb;
+      if (rp.free >= 0) {
+        if (claim(tv, tile, (uint64_t)bp * B + rp.free, rp.free_word, key, val, tag)) return ST_DONE;
+        rp = scan<false>(tv, tile, bp, key, tag);
+      } else if (ro.free >= 0) {
+        if (claim(tv, tile, (uint64_t)bo * B + ro.free, ro.free_word, key, val, tag)) return ST_DONE;
+        ro = scan<false>(tv, tile, bo, key, tag);
+      } else {
+        return ST_FULL;
+      }
+    }
   }
 
   // Iceberg insert under the front bucket's lock: the front bucket if it has a
@@ -618,13 +638,8 @@ struct Ops {
       }
     }
     if (rf.free >= 0 && claim_in_bucket(tv, tile, h.b1, rf, key, val, tag, !C::BSP) >= 0) return ST_DONE;
-    const bool second_first = h.b3 != h.h2 && r2.fill < r1.fill;
-    if (claim_in_bucket(tv, tile, second_first ? h.b3 : h.h2, second_first ? r2 : r1, key, val, tag) >= 0)
-      return ST_DONE;
-    if (h.b3 != h.h2 &&
-        claim_in_bucket(tv, tile, second_first ? h.h2 : h.b3, second_first ? r1 : r2, key, val, tag) >= 0)
-      return ST_DONE;
-    return ST_FULL;
+    if (h.b3 == h.h2) return claim_in_bucket(tv, tile, h.h2, r1, key, val, tag) >= 0 ? ST_DONE : ST_FULL;
+    return claim_less_loaded(tv, tile, h.h2, r1, h.b3, r2, key, val, tag);
   }
 
   // Lock-free query (Section 4.2).  Returns ST_DONE/ST_MISS/ST_INVALID, value in *out.
