@@ -425,7 +425,7 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
 
 
 def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):
-    """The served form (SURVEY config 5): n_tables resident P2HT(M) tables of 2^log2cap
+    """The served form (SURVEY config 5): n_tables resident, erase-free P2HT(M) tables of 2^log2cap
     slots, preloaded with half of a Zipf universe of floor(0.85 * capacity) keys;
     n_req requests arriving as a Poisson process at `rate`/s (query / upsert /
     insert 50/30/20, sizes 2^U, U ~ U[8, 20], Zipf 0.99 keys).  The same stream is
@@ -453,7 +453,9 @@ def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):
     offs = [r["t"] for r in reqs]
 
     def run(mode):
-        tabs = [hw.Table(cap, "P2_M") for _ in range(n_tables)]
+        # the served kinds never erase: the tables are declared erase-free, so
+        # present keys (Zipf-hot ones above all) are combined without the lock
+        tabs = [hw.Table(cap, "P2_M", flags=hw.F_NO_ERASE) for _ in range(n_tables)]
         pre_n = universe // 2
         for t in range(n_tables):
             pre = w.splitmix64(w.stream_seed(5, 100 + t), 0, pre_n)

@@ -69,8 +69,9 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
   int n_menu = 0;
   const MenuEntry* menu = kv_bits == 64 ? menu_entries(MenuU64{}, &n_menu) : menu_entries(MenuU32{}, &n_menu);
   if (reps == 0) reps = 3;
-  // enough tables of this class to give the launch at least ~4M slots of work
-  uint64_t n_tab64 = (4ull << 20) / capacity;
+  // enough tables of this class to give each timed launch ~32M slots of work
+  // (tens of milliseconds), so that launch and tail effects do not decide
+  uint64_t n_tab64 = (32ull << 20) / capacity;
   if (n_tab64 < 1) n_tab64 = 1;
   if (n_tab64 > 8192) n_tab64 = 8192;
   const uint32_t n_tab = (uint32_t)n_tab64;
