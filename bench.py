@@ -353,7 +353,9 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
     log("batched: %d tables, %d ops generated in %.1f s" % (n_tables, n_ops, time.time() - t0))
     t0 = time.time()
     classes = sorted(set(int(e) for e in exps))
-    tuned = {e: hw.autotune(32, 1 << e, load=load, reps=tune_reps)[0] for e in classes}
+    tuned, rejected = {}, {}
+    for e in classes:
+        tuned[e], rejected[e] = hw.autotune(32, 1 << e, load=load, reps=tune_reps)
     log("batched: autotuned %d classes in %.1f s" % (len(classes), time.time() - t0))
     kd = torch.from_numpy(keys.view(np.int32)).cuda()
     vd = torch.from_numpy(vals.view(np.int32)).cuda()
@@ -421,7 +423,9 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
             "default_cfg_batched_ms": round(ms_default, 3), "default_cfg_batched_gops": gops(ms_default),
             "speedup_vs_plain": round(ms_plain / ms_batched, 3),
             "tuning": {str(e): "%s/b%d/t%d %.2f" % (v["design"], v["bucket"], v["tile"], v["gops"])
-                       for e, v in tuned.items()}}
+                       for e, v in tuned.items()},
+            "rejected_full": {str(e): ["%s/b%d/t%d" % (a["design"], a["bucket"], a["tile"])
+                                       for a in rej if a["full_ops"]] for e, rej in rejected.items()}}
 
 
 def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):

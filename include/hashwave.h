@@ -253,7 +253,9 @@ int hwave_multi_upsert(hwave_multi* m, const uint64_t* h_offsets, const void* d_
  * over enough tables of that class to fill the GPU and run through the
  * persistent multi-table kernel.  `flags` are the tables' HWAVE_F_* flags.
  * Writes up to results_cap timings to `results` (their count to *n_results) and
- * the fastest to *best.  Allocates and frees its own device memory; blocks.
+ * the fastest to *best.  A configuration that cannot hold the load -- any
+ * operation of its batch ended FULL -- is reported with its FULL count and is
+ * never chosen.  Allocates and frees its own device memory; blocks.
  */
 typedef struct {
   uint32_t design;       /* hwave_design                        */
@@ -261,6 +263,7 @@ typedef struct {
   uint32_t tile;
   uint32_t kv_bits;
   double gops;           /* measured upserts per ns (G ops/s)   */
+  uint64_t full_ops;     /* operations that ended FULL (0 = holds the load) */
 } hwave_tune_result;
 
 int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, double load, uint32_t reps,

@@ -44,7 +44,7 @@ class _Item(ctypes.Structure):
 
 class _Tune(ctypes.Structure):
     _fields_ = [("design", ctypes.c_uint32), ("bucket_slots", ctypes.c_uint32), ("tile", ctypes.c_uint32),
-                ("kv_bits", ctypes.c_uint32), ("gops", ctypes.c_double)]
+                ("kv_bits", ctypes.c_uint32), ("gops", ctypes.c_double), ("full_ops", ctypes.c_uint64)]
 
 
 class _Request(ctypes.Structure):
@@ -428,7 +428,7 @@ def autotune(kv_bits: int, capacity: int, designs=("DOUBLE", "DOUBLE_M", "P2", "
 
     def as_dict(r):
         return {"design": names[r.design], "bucket": r.bucket_slots, "tile": r.tile,
-                "kv_bits": r.kv_bits, "gops": r.gops}
+                "kv_bits": r.kv_bits, "gops": r.gops, "full_ops": r.full_ops}
     return as_dict(best), [as_dict(res[i]) for i in range(min(n.value, 64))]
 
 

@@ -55,6 +55,18 @@ __global__ void k_gen_groupby(K* keys, K* vals, uint32_t n_tab, uint64_t D, uint
   }
 }
 
+__global__ void k_zero_count(unsigned long long* c) { *c = 0; }
+
+// Adds the number of status bytes equal to `code` to *count.
+__global__ void k_count_status(const uint8_t* __restrict__ st, uint64_t n, uint8_t code,
+                               unsigned long long* __restrict__ count) {
+  unsigned long long c = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    c += st[i] == code;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
 }  // namespace
 
 extern "C" {
@@ -75,6 +87,7 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
   if (n_tab64 < 1) n_tab64 = 1;
   if (n_tab64 > 8192) n_tab64 = 8192;
   const uint32_t n_tab = (uint32_t)n_tab64;
+  memset(best, 0, sizeof *best);
   best->gops = -1.0;
   uint32_t nres = 0;
   const size_t kb = kv_bits / 8;
@@ -101,13 +114,19 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
     const uint64_t n_ops = (uint64_t)n_tab * 2 * D;
     uint8_t* region = nullptr;
     void *keys = nullptr, *vals = nullptr;
+    uint8_t* status = nullptr;
+    unsigned long long* n_full = nullptr;
     hipError_t e = hipMalloc(&region, tb * n_tab);
     if (e == hipSuccess) e = hipMalloc(&keys, n_ops * kb);
     if (e == hipSuccess) e = hipMalloc(&vals, n_ops * kb);
+    if (e == hipSuccess) e = hipMalloc(&status, n_ops);
+    if (e == hipSuccess) e = hipMalloc(&n_full, sizeof(unsigned long long));
     if (e != hipSuccess) {
       if (region) (void)hipFree(region);
       if (keys) (void)hipFree(keys);
       if (vals) (void)hipFree(vals);
+      if (status) (void)hipFree(status);
+      if (n_full) (void)hipFree(n_full);
       return HWAVE_ENOMEM;
     }
     std::vector<hwave_table*> tabs(n_tab, nullptr);
@@ -132,7 +151,7 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
         rc = hwave_multi_clear(m, stream);
         if (rc) break;
         (void)hipEventRecord(a, s);
-        rc = hwave_multi_upsert(m, offs.data(), keys, vals, HWAVE_SUM, nullptr, stream);
+        rc = hwave_multi_upsert(m, offs.data(), keys, vals, HWAVE_SUM, status, stream);
         (void)hipEventRecord(b, s);
         if (hipEventSynchronize(b) != hipSuccess) rc = HWAVE_EDEVICE;
         float ms = 0.f;
@@ -142,12 +161,23 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
       (void)hipEventDestroy(a);
       (void)hipEventDestroy(b);
     }
+    unsigned long long full = 0;
+    if (rc == HWAVE_OK) {  // FULL statuses of the last run
+      hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, n_full);
+      hipLaunchKernelGGL(k_count_status, dim3(1024), dim3(256), 0, s, (const uint8_t*)status, n_ops,
+                         (uint8_t)HWAVE_ST_FULL, n_full);
+      if (hipMemcpyAsync(&full, n_full, sizeof full, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        rc = HWAVE_EDEVICE;
+    }
     if (m) hwave_multi_destroy(m);
     for (auto* t : tabs)
       if (t) hwave_destroy(t);
     (void)hipFree(region);
     (void)hipFree(keys);
     (void)hipFree(vals);
+    (void)hipFree(status);
+    (void)hipFree(n_full);
     if (rc) return rc;
     hwave_tune_result res;
     res.design = (uint32_t)d;
@@ -155,9 +185,10 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
     res.tile = cfg.tile;
     res.kv_bits = kv_bits;
     res.gops = (double)n_ops * reps / ((double)total_ms * 1e6);
+    res.full_ops = full;
     if (results && nres < results_cap) results[nres] = res;
     nres++;
-    if (res.gops > best->gops) *best = res;
+    if (full == 0 && res.gops > best->gops) *best = res;
   }
   if (n_results) *n_results = nres;
   return best->gops > 0 ? HWAVE_OK : HWAVE_EUNSUPPORTED;
