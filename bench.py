@@ -192,13 +192,17 @@ def verify_step(step: Step, d) -> None:
 def bench_phased(step: Step, d, design: str, conc_rates: dict, reps=3):
     """Cost of concurrency (Section 6.4): the load phases and the query sets on the
     phased variant of `design` (no locks, plain cacheable loads in queries), against
-    the same phases of the concurrent table.  Outputs are checked by closed form."""
+    the same phases of the concurrent table.  Outputs of the first repetition are
+    checked by closed form.  Without locks, inserts deciding at once on the same
+    bucket pair can crowd it, so a two-choice key may end FULL; such keys are
+    counted and excluded from the positive-query check."""
     import torch
     import paper_2509_16407_amd as hw
     from paper_2509_16407_amd import workloads as w
     t = hw.Table(d["cap"], design, flags=hw.F_BSP)
     b0, b1, b2 = step.bounds
     nq = step.qpos.numel()
+    st_all = torch.empty(b2, dtype=torch.uint8, device="cuda")
     ms = {}
 
     def timed(name, fn):
@@ -209,29 +213,35 @@ def bench_phased(step: Step, d, design: str, conc_rates: dict, reps=3):
         b.record()
         ms.setdefault(name, []).append((a, b))
 
+    n_full = 0
     for r in range(reps + 1):
         t.clear()
-        timed("insert_0.5", lambda: t.insert(step.keys[:b0], step.vals[:b0], status=step.st[:b0]))
-        timed("insert_0.75", lambda: t.insert(step.keys[b0:b1], step.vals[b0:b1], status=step.st[:b1 - b0]))
-        timed("insert_0.9", lambda: t.insert(step.keys[b1:b2], step.vals[b1:b2], status=step.st[:b2 - b1]))
+        timed("insert_0.5", lambda: t.insert(step.keys[:b0], step.vals[:b0], status=st_all[:b0]))
+        timed("insert_0.75", lambda: t.insert(step.keys[b0:b1], step.vals[b0:b1], status=st_all[b0:b1]))
+        timed("insert_0.9", lambda: t.insert(step.keys[b1:b2], step.vals[b1:b2], status=st_all[b1:b2]))
         if r == 0:
-            assert t.size() == b2, "phased %s: size after the load phases" % design
+            full = st_all == 3
+            n_full = int(full.sum().item())
+            assert bool(((st_all == 1) | full).all()), "phased %s: insert statuses" % design
+            assert t.size() == b2 - n_full, "phased %s: size after the load phases" % design
+            kept = ~full[torch.from_numpy(d["pos_idx"]).cuda()]
         timed("query_pos", lambda: t.query(step.qpos, out=step.out, found=step.st[:nq]))
         if r == 0:
             exp = to_dev(w.value_of(d["qpos"]))
-            assert bool((step.st[:nq] == 1).all()) and bool((step.out == exp).all()), "phased positives"
-            del exp
+            assert bool(((step.st[:nq] == 1) == kept).all()), "phased %s: positive flags" % design
+            assert bool(torch.where(kept, step.out == exp, step.out == 0).all()), "phased %s: values" % design
+            del exp, kept
         timed("query_neg", lambda: t.query(step.qneg, out=step.out, found=step.st[:nq]))
         if r == 0:
-            assert bool((step.st[:nq] == 0).all()), "phased negatives"
+            assert bool((step.st[:nq] == 0).all()), "phased %s: negatives" % design
     torch.cuda.synchronize()
-    res = {}
+    res = {"full_inserts": n_full}
     for name, ev in ms.items():
         m = float(np.mean([a.elapsed_time(b) for a, b in ev[1:]]))
         g = step.ops[name] / m / 1e6
         res[name] = {"gops": round(g, 3), "concurrent_gops": conc_rates[name],
                      "overhead_pct": round(100.0 * (g - conc_rates[name]) / g, 2)}
-    del t
+    del t, st_all
     torch.cuda.empty_cache()
     return res
 
