@@ -577,6 +577,28 @@ def load_traffic():
     return phases
 
 
+def load_requests():
+    """Fabric requests (L2 -> memory) per launch, per phase, and the copy kernel's
+    request rate, from the committed counter summary -- current sources only."""
+    path = os.path.join(ROOT, "profiles", "fabric_requests_p2m_2p28.txt")
+    if not os.path.exists(path):
+        return None
+    rec, phases = {}, {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("phase "):
+                parts = line.split()
+                kv = dict(x.split("=", 1) for x in parts[3:])
+                phases.setdefault(parts[1], float(kv["rd_req"]) + float(kv["wr_req"]))
+            elif "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                rec[k] = v
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return phases, float(rec["reference_greq_s"])
+
+
 def roofline(phase_ms: dict, per_step_ops: dict, steps: int, traffic_by_phase):
     """Roofline object of the dominant kernel (largest total time per step):
     algorithmic bytes of all its launches in a step / their total time, against the
@@ -604,6 +626,16 @@ def roofline(phase_ms: dict, per_step_ops: dict, steps: int, traffic_by_phase):
     if traffic is not None:
         roof["traffic_GBps"] = round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
         roof["traffic_frac"] = round(roof["traffic_GBps"] / HBM_PEAK_GBS, 4)
+    req = load_requests()
+    if req is not None:
+        # random single-line accesses: the request rate, not the byte rate, is the ceiling
+        by_phase, ref = req
+        n_req = sum(by_phase[ph] * (len(lst) // steps) for ph, lst in phase_ms.items()
+                    if KERNEL_OF[ph] == dom and ph in by_phase)
+        per_launch = n_req / kern_launch[dom]
+        g = per_launch / (avg_launch_ms * 1e-3) / 1e9
+        roof["fabric_requests"] = {"per_launch": round(per_launch), "achieved_Greq_s": round(g, 2),
+                                   "copy_kernel_Greq_s": ref, "frac_of_copy": round(g / ref, 4)}
     return roof
 
 
