@@ -95,7 +95,15 @@ enum {
                               call overlaps another that writes the keys it
                               touches.  64-bit tables at the default bucket and
                               tile of each design; not accepted by
-                              hwave_multi_create                               */
+                              hwave_multi_create                               */,
+  HWAVE_F_AGGREGATE = 8    /* merge duplicate keys of insert and upsert calls
+                              (SUM, KEEP, MIN, MAX; not REPLACE) within windows
+                              of 128 operations before they reach the table:
+                              one table operation per distinct key, the first
+                              of a window's duplicates reports the table's
+                              status and the others EXISTED (or its FULL).
+                              For skewed batches, whose hot keys would
+                              otherwise serialise on one lock or value word   */
 };
 
 /* Table configuration.  Zero fields take the design's defaults (the

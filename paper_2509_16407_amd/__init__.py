@@ -25,6 +25,7 @@ ST_MISS, ST_DONE, ST_EXISTED, ST_FULL, ST_INVALID = 0, 1, 2, 3, 4
 F_NO_SHORTCUT = 1
 F_NO_ERASE = 2
 F_BSP = 4
+F_AGGREGATE = 8
 
 
 class HashWaveError(RuntimeError):

@@ -217,6 +217,7 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   tv.probe_cap = (uint32_t)(cap > 0xFFFFFFFFull ? 0xFFFFFFFFull : cap);
   tv.shortcut = (c.flags & HWAVE_F_NO_SHORTCUT) ? 0u : 1u;
   tv.no_erase = (c.flags & HWAVE_F_NO_ERASE) ? 1u : 0u;
+  tv.aggregate = (c.flags & HWAVE_F_AGGREGATE) ? 1u : 0u;
   t->la.max_blocks = max_blocks_for(dev);
   return hwave_clear(t, stream);
 }

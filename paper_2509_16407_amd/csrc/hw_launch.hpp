@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "hw_agg.hpp"
 #include "hw_ops.hpp"
 
 namespace hw {
@@ -26,6 +27,21 @@ k_upsert(TableDev tv, const typename C::K* __restrict__ keys, const typename C::
     const K val = vals[i];
     const uint8_t st = Ops<C>::upsert(tv, tile, key, val, combine);
     if (status && tile.leader()) status[i] = st;
+  }
+}
+
+// Upsert with duplicate keys merged per wave window first (hw_agg.hpp).
+template <class C>
+__global__ void __launch_bounds__(BLOCK)
+k_upsert_agg(TableDev tv, const typename C::K* __restrict__ keys, const typename C::K* __restrict__ vals,
+             uint64_t n, int combine, uint8_t* __restrict__ status) {
+  __shared__ AggLds<typename C::K> lds[BLOCK / 64];
+  AggLds<typename C::K>& L = lds[threadIdx.x / 64];
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / 64;
+  const uint64_t n_waves = (uint64_t)gridDim.x * (BLOCK / 64);
+  for (uint64_t i0 = wave * AGG_WIN; i0 < n; i0 += n_waves * AGG_WIN) {
+    const uint64_t left = n - i0;
+    agg_window<C>(tv, L, keys, vals, i0, (uint32_t)(left < AGG_WIN ? left : AGG_WIN), combine, status);
   }
 }
 
@@ -123,8 +139,14 @@ struct Launch {
   using K = typename C::K;
   static hipError_t upsert(const LaunchArgs& a, const void* keys, const void* vals, uint64_t n,
                            int combine, uint8_t* status, hipStream_t s) {
-    hipLaunchKernelGGL((k_upsert<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
-                       (const K*)keys, (const K*)vals, n, combine, status);
+    if (a.tv.aggregate && combine != C_REPLACE) {
+      // one wave per window of AGG_WIN operations
+      hipLaunchKernelGGL((k_upsert_agg<C>), dim3(grid_for((n + AGG_WIN - 1) / AGG_WIN, 64, a.max_blocks)),
+                         dim3(BLOCK), 0, s, a.tv, (const K*)keys, (const K*)vals, n, combine, status);
+    } else {
+      hipLaunchKernelGGL((k_upsert<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
+                         (const K*)keys, (const K*)vals, n, combine, status);
+    }
     return hipGetLastError();
   }
   static hipError_t query(const LaunchArgs& a, const void* keys, uint64_t n, void* out, uint8_t* found,

@@ -44,21 +44,32 @@ struct MultiQueues {
   uint32_t end[NQ];
 };
 
-template <class... Cs>
+template <bool AGG, class C0, class... Cs>
 struct Menu {
-  static constexpr int N = sizeof...(Cs);
+  static constexpr int N = 1 + sizeof...(Cs);
+  static constexpr bool AGGREGATE = AGG;  // compiled with the merging path (hw_agg.hpp)
+  using K = typename C0::K;               // one key width per menu
 };
 
 // Runs ops [m.begin, m.end) of one table with configuration C on this wave.
-template <class C>
+template <class C, bool AGG>
 __device__ __forceinline__ void run_item(const TableDev& tv, const MultiItem& m, const typename C::K* __restrict__ keys,
                          const typename C::K* __restrict__ vals, typename C::K* __restrict__ out,
-                         uint8_t* __restrict__ status) {
+                         uint8_t* __restrict__ status, AggLds<typename C::K>& agg) {
   using K = typename C::K;
   const Tile<C::T> tile;
   const uint32_t lane = __lane_id();
   const int op = (int)(m.op & 0xFF);
   const int combine = op == OP_INSERT ? C_KEEP : (int)((m.op >> 8) & 0xFF);
+  if constexpr (AGG) {
+    if ((op == OP_INSERT || op == OP_UPSERT) && tv.aggregate && agg_merges(combine)) {
+      for (uint64_t i0 = m.begin; i0 < m.end; i0 += AGG_WIN) {
+        const uint64_t left = m.end - i0;
+        agg_window<C>(tv, agg, keys, vals, i0, (uint32_t)(left < AGG_WIN ? left : AGG_WIN), combine, status);
+      }
+      return;
+    }
+  }
   for (uint64_t i = m.begin + lane / C::T; i < m.end; i += 64 / C::T) {
     const K key = keys[i];
     uint8_t st;
@@ -75,13 +86,13 @@ __device__ __forceinline__ void run_item(const TableDev& tv, const MultiItem& m,
   }
 }
 
-template <class... Cs>
+template <bool AGG, class... Cs>
 __device__ __forceinline__ void dispatch(uint32_t cls, const TableDev& tv, const MultiItem& m,
                                          const void* keys, const void* vals, void* out, uint8_t* status,
-                                         Menu<Cs...>) {
+                                         AggLds<typename Menu<AGG, Cs...>::K>& agg, Menu<AGG, Cs...>) {
   uint32_t i = 0;
-  (void)((cls == i++ ? (run_item<Cs>(tv, m, (const typename Cs::K*)keys, (const typename Cs::K*)vals,
-                                     (typename Cs::K*)out, status),
+  (void)((cls == i++ ? (run_item<Cs, AGG>(tv, m, (const typename Cs::K*)keys, (const typename Cs::K*)vals,
+                                     (typename Cs::K*)out, status, agg),
                         true)
                      : false) ||
          ...);
@@ -91,6 +102,8 @@ template <class M>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HW_MULTI_WAVES, 8)))
 k_multi(const MultiTable* __restrict__ tables, const MultiItem* __restrict__ items, MultiQueues qs,
         uint32_t* heads, const void* keys, const void* vals, void* out, uint8_t* status) {
+  __shared__ AggLds<typename M::K> agg_lds[M::AGGREGATE ? BLOCK / 64 : 1];
+  AggLds<typename M::K>& agg = agg_lds[M::AGGREGATE ? threadIdx.x / 64 : 0];
   const uint32_t lane = __lane_id();
   const uint32_t home = blockIdx.x % NQ;
   for (uint32_t k = 0; k < NQ; ++k) {
@@ -103,18 +116,20 @@ k_multi(const MultiTable* __restrict__ tables, const MultiItem* __restrict__ ite
       if (idx >= qlen) break;
       const MultiItem m = items[qs.start[q] + idx];
       const MultiTable& t = tables[m.table];
-      dispatch(__builtin_amdgcn_readfirstlane(t.cls), t.tv, m, keys, vals, out, status, M{});
+      dispatch(__builtin_amdgcn_readfirstlane(t.cls), t.tv, m, keys, vals, out, status, agg, M{});
     }
   }
 }
 
 // Configuration menus of the multi-table kernel (one per key width).  The
 // autotuner chooses among these.
-using MenuU64 = Menu<Cfg<uint64_t, D_DOUBLE, 8, 8>, Cfg<uint64_t, D_DOUBLE, 16, 8>,
+// The 64-bit menu carries the merging path (hw_agg.hpp) for tables created with
+// HWAVE_F_AGGREGATE; the 32-bit menu does not (its register budget is tighter).
+using MenuU64 = Menu<true, Cfg<uint64_t, D_DOUBLE, 8, 8>, Cfg<uint64_t, D_DOUBLE, 16, 8>,
                      Cfg<uint64_t, D_DOUBLE_M, 32, 4>, Cfg<uint64_t, D_DOUBLE_M, 32, 8>,
                      Cfg<uint64_t, D_P2, 32, 8>, Cfg<uint64_t, D_P2_M, 32, 4>,
                      Cfg<uint64_t, D_P2_M, 32, 8>, Cfg<uint64_t, D_P2_M, 64, 8>>;
-using MenuU32 = Menu<Cfg<uint32_t, D_DOUBLE, 16, 4>, Cfg<uint32_t, D_DOUBLE, 16, 8>,
+using MenuU32 = Menu<false, Cfg<uint32_t, D_DOUBLE, 16, 4>, Cfg<uint32_t, D_DOUBLE, 16, 8>,
                      Cfg<uint32_t, D_DOUBLE, 32, 16>, Cfg<uint32_t, D_DOUBLE, 64, 32>,
                      Cfg<uint32_t, D_DOUBLE, 128, 64>, Cfg<uint32_t, D_DOUBLE_M, 32, 4>,
                      Cfg<uint32_t, D_P2, 32, 8>, Cfg<uint32_t, D_P2_M, 16, 4>,
@@ -124,8 +139,8 @@ struct MenuEntry {
   int design, bucket, tile;
 };
 
-template <class... Cs>
-inline const MenuEntry* menu_entries(Menu<Cs...>, int* n) {
+template <bool AGG, class... Cs>
+inline const MenuEntry* menu_entries(Menu<AGG, Cs...>, int* n) {
   static const MenuEntry e[] = {MenuEntry{Cs::DESIGN, Cs::B, Cs::T}...};
   *n = (int)sizeof...(Cs);
   return e;

@@ -58,6 +58,7 @@ struct TableDev {
   uint32_t probe_cap;    // double hashing: most buckets visited
   uint32_t shortcut;     // power-of-two-choice shortcut enabled
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
+  uint32_t aggregate;    // merge duplicate keys of a write batch first (hw_agg.hpp)
 };
 
 // BSP_: the phased (bulk-synchronous) variant used to measure what concurrency
