@@ -282,13 +282,14 @@ def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
     return out
 
 
-def bench_aging(designs, log2cap=26, iters=1000, probe_cap_double=80):
+def bench_aging(designs, log2cap=26, iters=1000, probe_cap_lines=80):
     """The aging (churn) benchmark (Section 6.5) on each design: fill 2^log2cap slots
     to 0.85, then `iters` iterations, each ONE mixed launch inserting a new 1% slice,
     erasing the oldest 1% and querying 1% live and 1% never-inserted keys.  Every
     output of every iteration is checked on the device against its closed form
     (inserts and erases succeed, positives return 3k+1, negatives miss).  Double
-    hashing runs with a probe cap of 80 buckets."""
+    hashing stops its probe sequences after 80 cache lines of bucket data (80
+    buckets of 8 slots, 20 of 32): the cap Table 1's aged probe counts imply."""
     import torch
     import paper_2509_16407_amd as hw
     from paper_2509_16407_amd import workloads as w
@@ -305,7 +306,10 @@ def bench_aging(designs, log2cap=26, iters=1000, probe_cap_double=80):
     out = torch.empty(4 * s, dtype=torch.int64, device="cuda")
     res = {}
     for des in designs:
-        cap = probe_cap_double if des.startswith("DOUBLE") else 0
+        cap = 0
+        if des.startswith("DOUBLE"):
+            bucket = 8 if des == "DOUBLE" else 32
+            cap = probe_cap_lines * 8 // bucket  # 128-byte lines of 16-byte slots
         t = hw.Table(1 << log2cap, des, probe_cap=cap)
         pre = t.insert(kd[:n0], kd[:n0] * 3 + 1)
         bad = (pre != 1).sum()

@@ -106,6 +106,8 @@ def _bind(lib):
     lib.orc_sim_insert.restype = U64
     lib.orc_sim_insert.argtypes = [ctypes.c_int, ctypes.c_int, U64, U64, P, P, P, P, U64,
                                    ctypes.c_int, ctypes.c_int]
+    lib.orc_sim_aging.restype = ctypes.c_int
+    lib.orc_sim_aging.argtypes = [ctypes.c_int, U64, U64, U64, U64, P, U64, U64, U64, P, P, U64, P]
     return lib
 
 
@@ -249,3 +251,19 @@ def iceberg_buckets(key: int, nb: int):
     out = (ctypes.c_uint64 * 3)()
     load().orc_iceberg_buckets(key, nb, out)
     return int(out[0]), int(out[1]), int(out[2])
+
+
+def sim_aging(design, nb, bucket_slots, plan, tile_bytes=128, probe_cap=0, from_iter=0):
+    """Sequential aging run (Section 6.5) over `plan` (workloads.aging_plan):
+    returns (mean positive probes, mean negative probes, failed inserts), probes
+    counted from iteration `from_iter` on."""
+    lib = load()
+    keys = _u64(plan["keys"])
+    negs = _u64(plan["negs"])
+    ps = np.ascontiguousarray(plan["pos_start"], dtype=np.uint64)
+    out = np.zeros(3, dtype=np.float64)
+    rc = lib.orc_sim_aging(design, nb, bucket_slots, tile_bytes, probe_cap, _ptr(keys), plan["n0"], plan["s"],
+                           plan["iters"], _ptr(ps), _ptr(negs), from_iter, _ptr(out))
+    if rc != 0:
+        raise ValueError("bad aging arguments")
+    return float(out[0]), float(out[1]), int(out[2])

@@ -551,4 +551,168 @@ uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_s
   return failed;
 }
 
+// ---------------------------------------------------------------------------
+// 4. Sequential aging simulator (Section 6.5 workload, Table 1 "aging probes")
+// ---------------------------------------------------------------------------
+//
+// Fills an empty 64-bit image with keys[0, n0), then runs `iters` iterations:
+// insert the next s keys, erase the oldest s keys, and count the probes of s
+// positive queries (keys[pos_start[i], pos_start[i] + s)) and s negative ones
+// (negs[i*s, (i+1)*s)).  Placement follows each design's rules once erases
+// have happened:
+//   double hashing: the first free (empty or tombstone) slot along the probe
+//     sequence; erase leaves a tombstone (key and tag);
+//   power-of-two-choice: no shortcut after an erase, so the less loaded of the
+//     two buckets (ties to the primary); erase empties the slot;
+//   iceberg: the front bucket if it has a free slot, else the less loaded
+//     backyard choice (ties to the first); erase empties the slot.
+// Probes use the model of probe_pos; a negative query reads buckets until the
+// design lets it stop: double hashing at the first bucket holding an empty slot
+// or after `probe_cap` buckets (0 = no cap), power-of-two-choice after both
+// buckets, iceberg after all three (the front-yard exit is off once erased).
+// Probes are counted from iteration `from_iter` on.  out[0] = mean positive
+// probes, out[1] = mean negative probes, out[2] = inserts that found no slot.
+// Returns 0, or -1 on a bad argument.
+
+static bool slot_free(const orc_image& im, uint64_t s) {
+  if (design_has_tags(im.design)) return im.tags[s] >= 0xFFFE;
+  uint64_t k = im.key(s);
+  return k == im.empty_key() || k == im.tomb_key();
+}
+
+static uint64_t bucket_fill(const orc_image& im, uint64_t b) {
+  uint64_t f = 0;
+  for (uint64_t j = 0; j < im.bucket_slots; j++) f += !slot_free(im, b * im.bucket_slots + j);
+  return f;
+}
+
+static int64_t first_free(const orc_image& im, uint64_t b) {
+  for (uint64_t j = 0; j < im.bucket_slots; j++)
+    if (slot_free(im, b * im.bucket_slots + j)) return (int64_t)(b * im.bucket_slots + j);
+  return -1;
+}
+
+int orc_sim_aging(int design, uint64_t nb, uint64_t bucket_slots, uint64_t tile_bytes, uint64_t probe_cap,
+                  const uint64_t* keys, uint64_t n0, uint64_t s, uint64_t iters, const uint64_t* pos_start,
+                  const uint64_t* negs, uint64_t from_iter, double* out) {
+  if (!keys || !out || nb == 0 || bucket_slots == 0 || design < ORC_DOUBLE || design > ORC_ICEBERG_M) return -1;
+  const uint64_t nslots = nb * bucket_slots;
+  std::vector<uint64_t> S(2 * nslots, ~0ull);
+  std::vector<uint16_t> T(design_has_tags(design) ? nslots : 0, 0xFFFF);
+  orc_image im{design, 64, nb, bucket_slots, (const uint8_t*)S.data(), T.empty() ? nullptr : T.data()};
+  const uint64_t cap = probe_cap ? std::min(probe_cap, nb) : nb;
+  bool erased = false;
+  uint64_t failed = 0;
+  auto write = [&](int64_t slot, uint64_t key, uint16_t tag) {
+    S[2 * slot] = key;
+    S[2 * slot + 1] = key * 3 + 1;
+    if (!T.empty()) T[slot] = tag;
+  };
+  auto insert = [&](uint64_t key) {
+    int64_t slot = -1;
+    if (design_is_double(design)) {
+      orc_hash h = orc_hash_key(key, nb);
+      for (uint64_t i = 0; i < cap && slot < 0; i++) slot = first_free(im, orc_double_bucket(h, nb, i));
+    } else if (design_is_iceberg(design)) {
+      orc_iceberg ib = orc_iceberg_of(key, nb);
+      slot = first_free(im, ib.front);
+      if (slot < 0) {
+        uint64_t b = bucket_fill(im, ib.back2) < bucket_fill(im, ib.back1) ? ib.back2 : ib.back1;
+        slot = first_free(im, b);
+        if (slot < 0) slot = first_free(im, b == ib.back1 ? ib.back2 : ib.back1);
+      }
+    } else {
+      orc_hash h = orc_hash_key(key, nb);
+      uint64_t b1 = h.b1, b2 = orc_p2_alt(h, nb);
+      uint64_t f1 = bucket_fill(im, b1);
+      if (!erased && 4 * f1 < 3 * bucket_slots) {
+        slot = first_free(im, b1);
+      } else {
+        uint64_t b = bucket_fill(im, b2) < f1 ? b2 : b1;
+        slot = first_free(im, b);
+        if (slot < 0) slot = first_free(im, b == b1 ? b2 : b1);
+      }
+    }
+    if (slot < 0) { failed++; return; }
+    write(slot, key, orc_tag(key));
+  };
+  // Locates a live key: (position in the design's visiting order, slot), or pos -1.
+  auto locate = [&](uint64_t key, int64_t* slot_out) -> int64_t {
+    auto in = [&](uint64_t b) -> int64_t {
+      for (uint64_t j = 0; j < bucket_slots; j++)
+        if (S[2 * (b * bucket_slots + j)] == key) return (int64_t)(b * bucket_slots + j);
+      return -1;
+    };
+    if (design_is_double(design)) {
+      orc_hash h = orc_hash_key(key, nb);
+      for (uint64_t i = 0; i < cap; i++) {
+        int64_t sl = in(orc_double_bucket(h, nb, i));
+        if (sl >= 0) { *slot_out = sl; return (int64_t)i; }
+      }
+      return -1;
+    }
+    uint64_t cand[3];
+    int nc;
+    if (design_is_iceberg(design)) {
+      orc_iceberg ib = orc_iceberg_of(key, nb);
+      cand[0] = ib.front; cand[1] = ib.back1; cand[2] = ib.back2;
+      nc = ib.back2 == ib.back1 ? 2 : 3;
+    } else {
+      orc_hash h = orc_hash_key(key, nb);
+      cand[0] = h.b1; cand[1] = orc_p2_alt(h, nb);
+      nc = cand[1] == cand[0] ? 1 : 2;
+    }
+    for (int c = 0; c < nc; c++) {
+      int64_t sl = in(cand[c]);
+      if (sl >= 0) { *slot_out = sl; return c; }
+    }
+    return -1;
+  };
+  auto erase = [&](uint64_t key) {
+    int64_t sl = -1;
+    if (locate(key, &sl) < 0) return;
+    const bool dbl = design_is_double(design) && ORC_MUTANT != 15;
+    S[2 * sl] = dbl ? im.tomb_key() : im.empty_key();
+    if (!T.empty()) T[sl] = dbl ? 0xFFFE : 0xFFFF;
+    erased = true;
+  };
+  const uint64_t per_bucket = design_has_tags(design) ? lines_of(2 * bucket_slots) : lines_of(bucket_slots * 16);
+  auto neg_probes = [&](uint64_t key) -> double {
+    if (design_is_double(design)) {
+      orc_hash h = orc_hash_key(key, nb);
+      for (uint64_t i = 0; i < cap; i++)
+        if (bucket_has_empty(im, orc_double_bucket(h, nb, i))) return (double)((i + 1) * per_bucket);
+      return (double)(cap * per_bucket);
+    }
+    if (design_is_iceberg(design)) {
+      orc_iceberg ib = orc_iceberg_of(key, nb);
+      if (!erased && bucket_has_empty(im, ib.front)) return (double)per_bucket;
+      return (double)((ib.back1 == ib.back2 ? 2 : 3) * per_bucket);
+    }
+    orc_hash h = orc_hash_key(key, nb);
+    return (double)((orc_p2_alt(h, nb) == h.b1 ? 1 : 2) * per_bucket);
+  };
+  for (uint64_t i = 0; i < n0; i++) insert(keys[i]);
+  double pos_sum = 0, neg_sum = 0;
+  uint64_t pos_n = 0, neg_n = 0;
+  for (uint64_t it = 0; it < iters; it++) {
+    for (uint64_t i = 0; i < s; i++) insert(keys[n0 + it * s + i]);
+    for (uint64_t i = 0; i < s; i++) erase(keys[it * s + i]);
+    if (it < from_iter) continue;
+    for (uint64_t i = 0; i < s; i++) {
+      int64_t sl = -1;
+      int64_t pos = locate(keys[pos_start[it] + i], &sl);
+      if (pos < 0) continue;
+      pos_sum += probe_pos(im, (uint64_t)pos, (uint64_t)sl % bucket_slots, tile_bytes);
+      pos_n++;
+    }
+    if (negs)
+      for (uint64_t i = 0; i < s; i++) { neg_sum += neg_probes(negs[it * s + i]); neg_n++; }
+  }
+  out[0] = pos_n ? pos_sum / (double)pos_n : 0.0;
+  out[1] = neg_n ? neg_sum / (double)neg_n : 0.0;
+  out[2] = (double)failed;
+  return 0;
+}
+
 }  // extern "C"
