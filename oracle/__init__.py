@@ -38,7 +38,7 @@ LIB = os.path.join(HERE, "libhw_oracle.so")
 QUERY, INSERT, UPSERT, ERASE = 0, 1, 2, 3
 SUM, KEEP, REPLACE, MIN, MAX = 0, 1, 2, 3, 4
 MISS, DONE, EXISTED, FULL, INVALID = 0, 1, 2, 3, 4
-DOUBLE, DOUBLE_M, P2, P2_M, ICEBERG, ICEBERG_M = 0, 1, 2, 3, 4, 5
+DOUBLE, DOUBLE_M, P2, P2_M, ICEBERG, ICEBERG_M, CHAINING = 0, 1, 2, 3, 4, 5, 6
 
 
 def build(force: bool = False, extra_flags=(), out: str | None = None) -> str:
@@ -106,6 +106,12 @@ def _bind(lib):
     lib.orc_sim_insert.restype = U64
     lib.orc_sim_insert.argtypes = [ctypes.c_int, ctypes.c_int, U64, U64, P, P, P, P, U64,
                                    ctypes.c_int, ctypes.c_int]
+    lib.orc_chain_bucket.restype = U64
+    lib.orc_chain_bucket.argtypes = [U64, U64]
+    lib.orc_chain_check.restype = U64
+    lib.orc_chain_check.argtypes = [U64, U64, P, P, U64, P, U64, ctypes.POINTER(_Report)]
+    lib.orc_sim_chain_insert.restype = U64
+    lib.orc_sim_chain_insert.argtypes = [U64, U64, P, P, U64, ctypes.c_int]
     lib.orc_sim_aging.restype = ctypes.c_int
     lib.orc_sim_aging.argtypes = [ctypes.c_int, U64, U64, U64, U64, P, U64, U64, U64, P, P, U64, P]
     return lib
@@ -267,3 +273,32 @@ def sim_aging(design, nb, bucket_slots, plan, tile_bytes=128, probe_cap=0, from_
     if rc != 0:
         raise ValueError("bad aging arguments")
     return float(out[0]), float(out[1]), int(out[2])
+
+
+def chain_bucket(key: int, nb: int) -> int:
+    return int(load().orc_chain_bucket(key, nb))
+
+
+def chain_check(nb, nodes, locks=None, neg_keys=None, lib=None):
+    """Invariants and probes of a chaining image: `nodes` is the raw node array
+    (128 bytes per node, nb bucket nodes first).  Returns (violations, report)."""
+    lib = lib or load()
+    rep = _Report()
+    nodes = np.ascontiguousarray(nodes).view(np.uint64)
+    locks = None if locks is None else np.ascontiguousarray(locks, dtype=np.uint64)
+    neg = _u64(neg_keys)
+    nv = lib.orc_chain_check(nb, len(nodes) // 16, _ptr(nodes), _ptr(locks), 0 if locks is None else len(locks),
+                             _ptr(neg), 0 if neg is None else len(neg), ctypes.byref(rep))
+    return int(nv), {name: getattr(rep, name) for name, _ in _Report._fields_}
+
+
+def sim_chain_insert(nb, n_nodes, keys, nodes=None):
+    """Sequential chaining inserts (first empty slot along the chain, else a new
+    tail node).  Returns (nodes uint64 array, n_failed)."""
+    lib = load()
+    init = nodes is None
+    if nodes is None:
+        nodes = np.empty(n_nodes * 16, dtype=np.uint64)
+    keys = _u64(keys)
+    failed = lib.orc_sim_chain_insert(nb, n_nodes, _ptr(nodes), _ptr(keys), len(keys), int(init))
+    return nodes, int(failed)

@@ -189,7 +189,8 @@ void orc_map_digest(const orc_map* h, uint64_t* sum_out, uint64_t* xor_out) {
 // nf + floor(hi32(h) * (nb-nf) / 2^32) and nf + floor(lo32(g) * (nb-nf) / 2^32),
 // with g = fmix64(key XOR 0xbb67ae8584caa73b).
 
-enum { ORC_DOUBLE = 0, ORC_DOUBLE_M = 1, ORC_P2 = 2, ORC_P2_M = 3, ORC_ICEBERG = 4, ORC_ICEBERG_M = 5 };
+enum { ORC_DOUBLE = 0, ORC_DOUBLE_M = 1, ORC_P2 = 2, ORC_P2_M = 3, ORC_ICEBERG = 4, ORC_ICEBERG_M = 5,
+       ORC_CHAINING = 6 };
 
 static uint64_t orc_fmix64(uint64_t k) {
   k ^= k >> 33;
@@ -713,6 +714,117 @@ int orc_sim_aging(int design, uint64_t nb, uint64_t bucket_slots, uint64_t tile_
   out[1] = neg_n ? neg_sum / (double)neg_n : 0.0;
   out[2] = (double)failed;
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// 5. Chaining (Section 5: each chain node is one 128-byte line holding 7
+//    key-value pairs and the pointer to the next node)
+// ---------------------------------------------------------------------------
+//
+// Reading of the node layout: 8 units of 16 bytes; units 0..6 are (key, value)
+// pairs, unit 7 is the link: its key word holds the empty pattern, its value word
+// the index of the next node (all-ones = none).  Nodes 0 .. nb-1 are the
+// buckets' first nodes; later nodes form the overflow pool.  Bucket of a key =
+// floor(lo32(h) * nb / 2^32), with h the hash of part 2.  Erase empties a slot
+// (a chain has no probe sequence to keep intact); an insert takes the first
+// empty slot along its chain, else appends a node.
+
+static const uint64_t ORC_NIL = ~0ull;
+
+uint64_t orc_chain_bucket(uint64_t key, uint64_t nb) {
+  return orc_scale32(orc_fmix64(key ^ ORC_SALT) & 0xFFFFFFFFull, nb);
+}
+
+// Checks a quiescent chaining image of n_nodes nodes (nb buckets).  Violations:
+// duplicate keys, keys in the wrong bucket's chain, reserved/tombstone patterns,
+// a link unit whose key word is not empty, a cycle or a node on two chains, a
+// live key in a node no chain reaches, held locks.  Probes (Section 5.1 unit):
+// a positive query reads the nodes up to the key's, a negative one the whole chain.
+uint64_t orc_chain_check(uint64_t nb, uint64_t n_nodes, const uint64_t* nodes, const uint64_t* locks,
+                         uint64_t nlock_words, const uint64_t* neg_keys, uint64_t n_neg, orc_layout_report* rep) {
+  orc_layout_report r;
+  memset(&r, 0, sizeof r);
+  std::vector<uint8_t> reached(n_nodes, 0);
+  std::vector<uint64_t> chain_len(nb, 0);
+  std::unordered_set<uint64_t> seen;
+  for (uint64_t b = 0; b < nb; b++) {
+    uint64_t node = b, pos = 0;
+    while (node != ORC_NIL) {
+      if (node >= n_nodes || reached[node]) { r.misplaced++; break; }
+      reached[node] = 1;
+      pos++;
+      const uint64_t* u = nodes + 16 * node;
+      for (int j = 0; j < 7; j++) {
+        const uint64_t k = u[2 * j];
+        if (k == ~0ull) { r.empties++; continue; }
+        if (k == ~0ull - 1 || k == ~0ull - 2) { r.reserved++; continue; }
+        r.live++;
+        if (!seen.insert(k).second && ORC_MUTANT != 11) r.duplicate_keys++;
+        if (orc_chain_bucket(k, nb) != b) r.misplaced++;
+        r.pos_probe_sum += (double)pos;
+        if (pos > 1) r.in_alternate++;
+      }
+      if (u[14] != ~0ull) r.misplaced++;  // link unit key word
+      node = u[15];
+    }
+    chain_len[b] = pos;
+    r.max_seq_index = std::max<uint64_t>(r.max_seq_index, pos);
+  }
+  for (uint64_t n = 0; n < n_nodes; n++) {
+    if (reached[n]) continue;
+    const uint64_t* u = nodes + 16 * n;
+    for (int j = 0; j < 7; j++)
+      if (u[2 * j] != ~0ull) r.misplaced++;
+  }
+  if (locks)
+    for (uint64_t w = 0; w < nlock_words; w++) r.locks_held += (uint64_t)__builtin_popcountll(locks[w]);
+  for (uint64_t i = 0; i < n_neg; i++) {
+    r.neg_probe_sum += (double)chain_len[orc_chain_bucket(neg_keys[i], nb)];
+    r.neg_count++;
+  }
+  *rep = r;
+  return r.duplicate_keys + r.misplaced + r.reserved + r.locks_held;
+}
+
+// Sequential chaining inserts of distinct keys into an image of n_nodes nodes
+// (initialised empty when `init`): the first empty slot along the chain, else a
+// new node from the pool (the lowest unused index) linked at the tail.  Returns
+// the number of keys that found no room (pool exhausted).
+uint64_t orc_sim_chain_insert(uint64_t nb, uint64_t n_nodes, uint64_t* nodes, const uint64_t* keys,
+                              uint64_t n, int init) {
+  if (init) memset(nodes, 0xFF, n_nodes * 128);
+  uint64_t next_free = nb;
+  // pool nodes in use are those some chain reaches
+  {
+    std::vector<uint8_t> reached(n_nodes, 0);
+    for (uint64_t b = 0; b < nb; b++)
+      for (uint64_t node = b; node != ORC_NIL && node < n_nodes; node = nodes[16 * node + 15]) reached[node] = 1;
+    while (next_free < n_nodes && reached[next_free]) next_free++;
+  }
+  uint64_t failed = 0;
+  for (uint64_t i = 0; i < n; i++) {
+    const uint64_t k = keys[i];
+    uint64_t node = orc_chain_bucket(k, nb), last = node;
+    bool placed = false;
+    bool first = true;
+    while (node != ORC_NIL && !placed) {
+      uint64_t* u = nodes + 16 * node;
+      if (first || ORC_MUTANT != 16)
+        for (int j = 0; j < 7; j++)
+          if (u[2 * j] == ~0ull) { u[2 * j] = k; u[2 * j + 1] = k * 3 + 1; placed = true; break; }
+      first = false;
+      last = node;
+      node = u[15];
+    }
+    if (placed) continue;
+    if (next_free >= n_nodes) { failed++; continue; }
+    uint64_t* nu = nodes + 16 * next_free;
+    nu[0] = k;
+    nu[1] = k * 3 + 1;
+    nodes[16 * last + 15] = next_free;
+    next_free++;
+  }
+  return failed;
 }
 
 }  // extern "C"

@@ -459,3 +459,80 @@ def test_table1_aging_negative_probes(row):
         _, got, _ = _aging(name, bucket, tb, cap, 0)
         # a repeated candidate bucket is read once: slightly under the bucket count
         assert abs(got - neg) <= 0.04, (name, got, neg)
+
+
+# ---------------------------------------------------------------- chaining (Section 5)
+
+def _poisson_chain_probes(lam):
+    """Closed form for uniform hashing into buckets of 7-slot nodes: a bucket's key
+    count is Poisson(lam); the key at position i (0-based) of a bucket sits in node
+    i // 7 + 1; a negative query reads max(1, ceil(X / 7)) nodes."""
+    from scipy.stats import poisson
+    x = np.arange(0, 80)
+    p = poisson.pmf(x, lam)
+    pos = sum(p[c] * sum(i // 7 + 1 for i in range(c)) for c in x) / lam
+    neg = float(np.sum(p * np.maximum(1, -(-x // 7))))
+    return pos, neg
+
+
+def test_chaining_probes_match_poisson_and_table1():
+    """Sequential chaining at 7 keys per bucket (chains of length 1 in expectation,
+    Section 5) reproduces the Poisson closed form, and with it Table 1's 1.16."""
+    nb = 1 << 16
+    n = 7 * nb
+    keys = w.distinct_keys(w.stream_seed(43, 7), n)
+    neg = w.distinct_keys(w.stream_seed(43, 7), 200000, skip=n)
+    nodes, failed = oracle.sim_chain_insert(nb, nb + nb // 2 + 1, keys)
+    assert failed == 0
+    nv, rep = oracle.chain_check(nb, nodes, neg_keys=neg)
+    assert nv == 0 and rep["live"] == n
+    pos_cf, neg_cf = _poisson_chain_probes(7.0)
+    assert abs(rep["pos_probe_sum"] / n - pos_cf) < 0.004, (rep["pos_probe_sum"] / n, pos_cf)
+    assert abs(rep["neg_probe_sum"] / rep["neg_count"] - neg_cf) < 0.01
+    table = dict((r[0], float(r[1])) for r in _read_golden("table1_chaining.txt"))
+    assert abs(table["load_query"] - pos_cf) < 0.015
+
+
+def test_chain_checker_detects_planted_violations():
+    nb = 64
+    keys = w.distinct_keys(45, 500)  # ~7.8 per bucket: some chains have two nodes
+    nodes, failed = oracle.sim_chain_insert(nb, nb + 40, keys)
+    assert failed == 0
+    nv, rep = oracle.chain_check(nb, nodes)
+    assert nv == 0 and rep["live"] == 500 and rep["in_alternate"] > 0
+    u = nodes.reshape(-1, 16)
+    # a key moved into another bucket's head node
+    bad = u.copy()
+    k = int(bad[0, 0])
+    other = (oracle.chain_bucket(k, nb) + 1) % nb
+    j = [i for i in range(7) if bad[other, 2 * i] == np.uint64((1 << 64) - 1)]
+    if j:
+        bad[other, 2 * j[0]] = np.uint64(k)
+        bad[0, 0] = np.uint64((1 << 64) - 1)
+        nv, rep = oracle.chain_check(nb, bad.reshape(-1))
+        assert rep["misplaced"] >= 1 and nv >= 1
+    # a duplicate in the same chain
+    b0 = oracle.chain_bucket(int(u[0, 0]), nb)
+    dup = u.copy()
+    free = [i for i in range(7) if dup[b0, 2 * i] == np.uint64((1 << 64) - 1)]
+    if free:
+        dup[b0, 2 * free[0]] = dup[0, 0]
+        nv, rep = oracle.chain_check(nb, dup.reshape(-1))
+        assert rep["duplicate_keys"] == 1
+    # a cycle: the last node of a two-node chain links back to its head
+    cyc = u.copy()
+    heads = [b for b in range(nb) if cyc[b, 15] != np.uint64((1 << 64) - 1)]
+    tail = int(cyc[heads[0], 15])
+    cyc[tail, 15] = np.uint64(heads[0])
+    nv, rep = oracle.chain_check(nb, cyc.reshape(-1))
+    assert nv >= 1
+    # a link unit whose key word is not empty
+    lk = u.copy()
+    lk[3, 14] = np.uint64(5)
+    nv, rep = oracle.chain_check(nb, lk.reshape(-1))
+    assert nv >= 1
+    # a live key in a pool node that no chain reaches
+    orph = u.copy()
+    orph[-1, 0] = np.uint64(12345)
+    nv, rep = oracle.chain_check(nb, orph.reshape(-1))
+    assert nv >= 1
