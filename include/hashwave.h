@@ -50,7 +50,12 @@ typedef enum {
   HWAVE_ICEBERG = 4,  /* iceberg: 83% single-hash front yard, 17% power-of-two-
                          choice backyard (Section 2.2, Section 5); bucket 32,
                          tile 8; at least two buckets                          */
-  HWAVE_ICEBERG_M = 5 /* iceberg with 16-bit tags; bucket 32, tile 4           */
+  HWAVE_ICEBERG_M = 5, /* iceberg with 16-bit tags; bucket 32, tile 4          */
+  HWAVE_CHAINING = 6  /* chaining: per bucket a chain of 128-byte nodes of 7
+                         pairs and a link (Section 5); ceil(capacity/7)
+                         buckets plus an overflow pool of as many nodes
+                         (hwave_capacity counts both); 64-bit keys, tile 8;
+                         insert/upsert return FULL once the pool is spent     */
 } hwave_design;
 
 /* Upsert callbacks (Section 5.1): SUM accumulates with wrap-around modulo
@@ -200,12 +205,15 @@ uint64_t hwave_capacity(const hwave_table* t);
 
 /* Device pointers and geometry of a table, for tests that inspect its raw image. */
 typedef struct {
-  void* slots;          /* capacity slots of (key, value), bucket-major            */
+  void* slots;          /* slots of (key, value), bucket-major; chaining: nodes of
+                           8 16-byte units, unit 7 the link (empty key word,
+                           next node index or all-ones in the value word)     */
   uint16_t* tags;       /* capacity 16-bit tags, or NULL without tags             */
   uint32_t* locks;      /* lock bytes: byte b is bucket b's lock (0 = free)       */
   uint64_t n_lock_words;
   uint64_t num_buckets;
   uint32_t bucket_slots, tile, kv_bits, design;
+  uint64_t slot_bytes;  /* bytes of the slot region (chaining: every node)     */
 } hwave_raw_view;
 int hwave_raw(const hwave_table* t, hwave_raw_view* out);
 

@@ -19,6 +19,7 @@ struct hwave_table {
   hwave_design design;
   hwave_config cfg;
   uint64_t nb, capacity, bytes;
+  uint64_t units;  // (key, value) units in the slot region (chaining: link units too)
   uint64_t n_lock_words;
   void* base;
   bool owns;
@@ -39,13 +40,14 @@ constexpr uint64_t ALIGN = 256;
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  uint64_t nb, capacity;
+  uint64_t nb, capacity, units, pool;
   uint64_t off_tags, off_locks, off_ctrl, total;
   uint64_t n_lock_words;
 };
 
 bool design_tags(int d) { return d == HWAVE_DOUBLE_M || d == HWAVE_P2_M || d == HWAVE_ICEBERG_M; }
 bool design_iceberg(int d) { return d == HWAVE_ICEBERG || d == HWAVE_ICEBERG_M; }
+bool design_chain(int d) { return d == HWAVE_CHAINING; }
 
 // Iceberg front yard: 83% of the buckets (Section 5), at least one bucket in
 // each yard.
@@ -60,7 +62,7 @@ const std::vector<const KernelSet*>& registry() {
   static std::vector<const KernelSet*> all;
   static std::once_flag once;
   std::call_once(once, [] {
-    const KernelSet* (*fns[])(size_t*) = {sets_u64_double, sets_u64_p2, sets_u64_iceberg,
+    const KernelSet* (*fns[])(size_t*) = {sets_u64_double, sets_u64_p2, sets_u64_iceberg, sets_u64_chain,
                                           sets_u32_double, sets_u32_p2, sets_u32_iceberg, sets_u64_bsp};
     for (auto f : fns) {
       size_t n = 0;
@@ -85,12 +87,12 @@ const KernelSet* find_set(const hwave_config& c, int design) {
 void defaults_for(hwave_design design, uint32_t kv_bits, hwave_config* c) {
   memset(c, 0, sizeof *c);
   c->kv_bits = kv_bits;
-  c->bucket_slots = design == HWAVE_DOUBLE ? (kv_bits == 64 ? 8 : 16) : 32;
+  c->bucket_slots = design == HWAVE_DOUBLE ? (kv_bits == 64 ? 8 : 16) : design_chain(design) ? 7 : 32;
   c->tile = design_tags(design) ? 4 : 8;
 }
 
 int resolve_config(hwave_design design, const hwave_config* in, hwave_config* out) {
-  if ((int)design < HWAVE_DOUBLE || (int)design > HWAVE_ICEBERG_M) return HWAVE_EINVAL;
+  if ((int)design < HWAVE_DOUBLE || (int)design > HWAVE_CHAINING) return HWAVE_EINVAL;
   const uint32_t kv = in && in->kv_bits ? in->kv_bits : 64;
   if (kv != 64 && kv != 32) return HWAVE_EINVAL;
   hwave_config c;
@@ -107,6 +109,29 @@ int resolve_config(hwave_design design, const hwave_config* in, hwave_config* ou
 
 int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Layout* L) {
   if (capacity == 0 || c.bucket_slots == 0) return HWAVE_EINVAL;
+  if (design_chain(design)) {
+    // Chaining (Section 5): ceil(capacity / 7) buckets, each a 128-byte first
+    // node (7 pairs and a link), then an overflow pool of as many nodes, which
+    // churn draws on as chains grow (nodes are not returned); ~37 bytes per pair
+    // at 7 pairs per bucket, near the paper's 34.  The capacity reported counts
+    // every slot of buckets and pool.
+    const uint64_t nb = (capacity + 6) / 7;
+    if (nb > (1ull << 30)) return HWAVE_EINVAL;
+    const uint64_t pool = nb;
+    L->nb = nb;
+    L->pool = pool;
+    L->units = (nb + pool) * 8;
+    L->capacity = (nb + pool) * 7;
+    uint64_t off = round_up(L->units * 16, ALIGN);
+    L->off_tags = off;
+    L->off_locks = off;
+    L->n_lock_words = (nb + 3) / 4;
+    off += round_up(L->n_lock_words * 4, ALIGN);
+    L->off_ctrl = off;
+    off += ALIGN;
+    L->total = off;
+    return HWAVE_OK;
+  }
   const uint64_t B = c.bucket_slots;
   uint64_t want = (capacity + B - 1) / B;
   uint64_t nb = design_iceberg(design) ? 2 : 1;  // iceberg: a bucket in each yard
@@ -115,6 +140,8 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
   const uint64_t slot_bytes = c.kv_bits / 4;  // two words
   L->nb = nb;
   L->capacity = nb * B;
+  L->units = L->capacity;
+  L->pool = 0;
   uint64_t off = round_up(L->capacity * slot_bytes, ALIGN);
   L->off_tags = off;
   if (design_tags(design)) off += round_up(L->capacity * 2, ALIGN);
@@ -199,6 +226,7 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   t->cfg = c;
   t->nb = L.nb;
   t->capacity = L.capacity;
+  t->units = L.units;
   t->bytes = bytes;
   t->n_lock_words = L.n_lock_words;
   t->base = base;
@@ -212,6 +240,7 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   tv.bucket_mask = (uint32_t)(L.nb - 1);
   tv.nb_front = design_iceberg(design) ? (uint32_t)iceberg_front(L.nb) : (uint32_t)L.nb;
   tv.nb_back = design_iceberg(design) ? (uint32_t)(L.nb - tv.nb_front) : 0u;
+  tv.pool_nodes = (uint32_t)L.pool;
   uint64_t cap = c.probe_cap ? c.probe_cap : L.nb;
   if (cap > L.nb) cap = L.nb;
   tv.probe_cap = (uint32_t)(cap > 0xFFFFFFFFull ? 0xFFFFFFFFull : cap);
@@ -229,7 +258,7 @@ bool bad_ptr(const void* p) { return p == nullptr; }
 extern "C" {
 
 int hwave_config_default(hwave_design design, hwave_config* out) {
-  if (!out || (int)design < HWAVE_DOUBLE || (int)design > HWAVE_ICEBERG_M) return HWAVE_EINVAL;
+  if (!out || (int)design < HWAVE_DOUBLE || (int)design > HWAVE_CHAINING) return HWAVE_EINVAL;
   defaults_for(design, 64, out);
   return HWAVE_OK;
 }
@@ -377,11 +406,11 @@ int hwave_size(hwave_table* t, uint64_t* d_count, void* stream) {
   if (!t || !d_count) return HWAVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_count);
-  const unsigned g = stream_grid(t->capacity, t->device);
+  const unsigned g = stream_grid(t->units, t->device);
   if (t->cfg.kv_bits == 64)
-    hipLaunchKernelGGL(k_count<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)t->base, t->capacity, d_count);
+    hipLaunchKernelGGL(k_count<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)t->base, t->units, d_count);
   else
-    hipLaunchKernelGGL(k_count<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)t->base, t->capacity, d_count);
+    hipLaunchKernelGGL(k_count<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)t->base, t->units, d_count);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
 }
@@ -390,12 +419,12 @@ int hwave_export(hwave_table* t, void* d_keys, void* d_vals, uint64_t* d_count, 
   if (!t || !d_keys || !d_vals || !d_count) return HWAVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_count);
-  const unsigned g = stream_grid(t->capacity, t->device);
+  const unsigned g = stream_grid(t->units, t->device);
   if (t->cfg.kv_bits == 64)
-    hipLaunchKernelGGL(k_export<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)t->base, t->capacity,
+    hipLaunchKernelGGL(k_export<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)t->base, t->units,
                        (uint64_t*)d_keys, (uint64_t*)d_vals, d_count);
   else
-    hipLaunchKernelGGL(k_export<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)t->base, t->capacity,
+    hipLaunchKernelGGL(k_export<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)t->base, t->units,
                        (uint32_t*)d_keys, (uint32_t*)d_vals, d_count);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
@@ -409,7 +438,7 @@ int hwave_primary_bucket(hwave_table* t, const void* d_keys, uint64_t n, uint64_
   if (n == 0) return HWAVE_OK;
   hipStream_t s = (hipStream_t)stream;
   const unsigned g = stream_grid(n, t->device);
-  const uint32_t nf = design_iceberg(t->design) ? t->la.tv.nb_front : 0u;
+  const uint32_t nf = design_iceberg(t->design) || design_chain(t->design) ? t->la.tv.nb_front : 0u;
   if (t->cfg.kv_bits == 64)
     hipLaunchKernelGGL(k_primary<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)d_keys, n,
                        t->la.tv.bucket_mask, nf, d_out);
@@ -431,6 +460,7 @@ int hwave_raw(const hwave_table* t, hwave_raw_view* out) {
   out->tile = t->cfg.tile;
   out->kv_bits = t->cfg.kv_bits;
   out->design = (uint32_t)t->design;
+  out->slot_bytes = t->units * (t->cfg.kv_bits / 4);
   return HWAVE_OK;
 }
 

@@ -183,5 +183,6 @@ const KernelSet* sets_u32_p2(size_t* n);
 const KernelSet* sets_u64_iceberg(size_t* n);
 const KernelSet* sets_u32_iceberg(size_t* n);
 const KernelSet* sets_u64_bsp(size_t* n);
+const KernelSet* sets_u64_chain(size_t* n);
 
 }  // namespace hw

@@ -44,7 +44,7 @@ namespace hw {
 enum : uint8_t { ST_MISS = 0, ST_DONE = 1, ST_EXISTED = 2, ST_FULL = 3, ST_INVALID = 4 };
 enum : int { C_SUM = 0, C_KEEP = 1, C_REPLACE = 2, C_MIN = 3, C_MAX = 4 };
 enum : int { OP_QUERY = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_ERASE = 3 };
-enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, D_ICEBERG_M = 5 };
+enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, D_ICEBERG_M = 5, D_CHAINING = 6 };
 
 // Device view of one table (passed by value to kernels).
 struct TableDev {
@@ -53,8 +53,9 @@ struct TableDev {
   uint32_t* locks;       // one byte per bucket (viewed as 32-bit words)
   uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice, iceberg)
   uint32_t bucket_mask;  // buckets - 1 (a power of two minus one)
-  uint32_t nb_front;     // iceberg: front-yard buckets [0, nb_front)
+  uint32_t nb_front;     // iceberg: front-yard buckets [0, nb_front); chaining: buckets
   uint32_t nb_back;      // iceberg: backyard buckets [nb_front, nb_front + nb_back)
+  uint32_t pool_nodes;   // chaining: overflow nodes after the buckets' first nodes
   uint32_t probe_cap;    // double hashing: most buckets visited
   uint32_t shortcut;     // power-of-two-choice shortcut enabled
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
@@ -73,13 +74,15 @@ struct Cfg {
   static constexpr bool TAGS = DESIGN == D_DOUBLE_M || DESIGN == D_P2_M || DESIGN == D_ICEBERG_M;
   static constexpr bool DOUBLE = DESIGN == D_DOUBLE || DESIGN == D_DOUBLE_M;
   static constexpr bool ICEBERG = DESIGN == D_ICEBERG || DESIGN == D_ICEBERG_M;
+  static constexpr bool CHAIN = DESIGN == D_CHAINING;  // B = 7 slots per node, T = 8
   static constexpr int B = B_;
   static constexpr int T = T_;
   static constexpr int SLOT_BYTES = 2 * (int)sizeof(K);
   static constexpr int SPL = 16 / SLOT_BYTES;   // slots per lane per 16-byte load
   static constexpr int STEPS = B / (T * SPL);   // slot loads per bucket (no tags)
   static constexpr int TPL = B / T;             // tags per lane (tag designs)
-  static_assert(TAGS || (B % (T * SPL) == 0 && STEPS >= 1), "bucket must be a multiple of the tile's load");
+  static_assert(CHAIN || TAGS || (B % (T * SPL) == 0 && STEPS >= 1), "bucket must be a multiple of the tile's load");
+  static_assert(!CHAIN || (B == 7 && T == 8 && sizeof(K_) == 8), "chain node: 7 slots and a link, one per lane");
   static_assert(!TAGS || TPL == 1 || TPL == 2 || TPL == 4 || TPL == 8 || TPL == 16, "tags per lane");
 };
 
@@ -405,7 +408,9 @@ struct Ops {
   };
 
   __device__ static __forceinline__ Home home_of(const TableDev& tv, K key) {
-    if constexpr (C::ICEBERG) {
+    if constexpr (C::CHAIN) {
+      return Home{front_bucket((uint64_t)key, tv.nb_front), 0u, 0u};
+    } else if constexpr (C::ICEBERG) {
       const Yard y = yard_of((uint64_t)key, tv.nb_front, tv.nb_back);
       return Home{y.front, y.back1, y.back2};
     } else {
@@ -424,10 +429,121 @@ struct Ops {
     return (h.h2 & tv.bucket_mask) | 1u;
   }
 
+  // ---------------------------------------------------------------- chaining
+  //
+  // A chain node is one 128-byte line (Section 5): lanes 0..6 of the 8-lane tile
+  // read one (key, value) slot each, lane 7 the link unit, whose value word holds
+  // the next node's index (all-ones: none).  Nodes 0 .. nb-1 are the buckets'
+  // first nodes; the overflow pool follows.  Every write into a chain happens
+  // under its bucket's lock, so slots are taken with plain stores; a new node is
+  // filled before the link to it is published, so lock-free readers never see a
+  // half-built node.
+  static constexpr uint64_t NIL = ~0ull;
+
+  struct NodeScan {
+    int32_t hit, free;  // slot of the key / first empty slot in this node, or -1
+    uint64_t next;      // next node, or NIL
+    K val;
+  };
+
+  template <bool PLAIN = false>
+  __device__ static __forceinline__ NodeScan scan_node(const TableDev& tv, const Tile<T>& tile, uint64_t node,
+                                                       K key) {
+    const u32x4 w = rd16<PLAIN>((const uint64_t*)tv.slots + 16 * node + 2 * tile.tl);
+    const uint64_t k = (uint64_t)w.x | ((uint64_t)w.y << 32);
+    const uint64_t v = (uint64_t)w.z | ((uint64_t)w.w << 32);
+    const bool slot = tile.tl < 7;
+    const uint64_t mh = tile.ballot(slot && k == (uint64_t)key);
+    const uint64_t mf = tile.ballot(slot && k == (uint64_t)EMPTY);
+    NodeScan r;
+    r.hit = mh ? ffs64(mh) : -1;
+    r.free = mf ? ffs64(mf) : -1;
+    r.next = tile.bcast(v, 7);
+    r.val = r.hit >= 0 ? (K)tile.bcast(v, (uint32_t)r.hit) : (K)0;
+    return r;
+  }
+
+  // Most nodes a chain can have: a walk that reaches this many has found a cycle,
+  // which the table never builds; the bound only keeps a damaged image from
+  // holding a tile forever.
+  __device__ static __forceinline__ uint32_t max_chain(const TableDev& tv) { return tv.pool_nodes + 1; }
+
+  __device__ static int64_t chain_find(const TableDev& tv, const Tile<T>& tile, uint32_t b, K key, K* val) {
+    uint64_t node = b;
+    for (uint32_t i = 0; i < max_chain(tv) && node != NIL; ++i) {
+      const NodeScan r = scan_node<C::BSP>(tv, tile, node, key);
+      if (r.hit >= 0) { *val = r.val; return (int64_t)(node * 8 + r.hit); }
+      node = r.next;
+    }
+    return -1;
+  }
+
+  // Takes a node from the overflow pool: eight partitions, each with its own
+  // counter (control words 8..15), so allocations do not funnel through one
+  // address; a wave starts at the partition of its block.  NIL when all are spent.
+  __device__ static uint64_t alloc_node(const TableDev& tv, const Tile<T>& tile) {
+    uint64_t got = NIL;
+    if (tile.leader()) {
+      const uint32_t psz = (tv.pool_nodes + 7) / 8;
+      const uint32_t home = blockIdx.x & 7;
+      for (uint32_t q = 0; q < 8; ++q) {
+        const uint32_t p = (home + q) & 7;
+        const uint32_t lo = p * psz;
+        const uint32_t hi = lo + psz < tv.pool_nodes ? lo + psz : tv.pool_nodes;
+        if (lo >= hi || ld(tv.ctrl + 8 + p) >= hi - lo) continue;
+        const uint32_t i = __hip_atomic_fetch_add(tv.ctrl + 8 + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (i < hi - lo) { got = (uint64_t)tv.nb_front + lo + i; break; }
+      }
+    }
+    return tile.bcast(got, 0);
+  }
+
+  __device__ static uint8_t upsert_chain_locked(const TableDev& tv, const Tile<T>& tile, const Home& h, K key,
+                                                K val, int combine) {
+    uint64_t node = h.b1, last = h.b1, free_slot = NIL;
+    for (uint32_t i = 0; i < max_chain(tv) && node != NIL; ++i) {
+      const NodeScan r = scan_node(tv, tile, node, key);
+      if (r.hit >= 0) {
+        combine_at(tv, tile, node * 8 + r.hit, val, combine);
+        return ST_EXISTED;
+      }
+      if (free_slot == NIL && r.free >= 0) free_slot = node * 8 + r.free;
+      last = node;
+      node = r.next;
+    }
+    if (free_slot != NIL) {
+      if (tile.leader()) publish(tv, free_slot, key, val);
+      return ST_DONE;
+    }
+    const uint64_t fresh = alloc_node(tv, tile);
+    if (fresh == NIL) return ST_FULL;
+    if (tile.leader()) {
+      publish(tv, fresh * 8, key, val);  // the pool node is empty: slot 0
+      wait_mem();                        // node content before the link to it
+      st((uint64_t*)tv.slots + 16 * last + 15, fresh);
+    }
+    return ST_DONE;
+  }
+
+  __device__ static uint8_t erase_chain_locked(const TableDev& tv, const Tile<T>& tile, const Home& h, K key) {
+    uint64_t node = h.b1;
+    for (uint32_t i = 0; i < max_chain(tv) && node != NIL; ++i) {
+      const NodeScan r = scan_node(tv, tile, node, key);
+      if (r.hit >= 0) {
+        if (tile.leader()) st(key_ptr(tv, node * 8 + r.hit), EMPTY);
+        return ST_DONE;
+      }
+      node = r.next;
+    }
+    return ST_MISS;
+  }
+
   // Lock-free search (Section 4.2): the slot holding `key`, or -1.  Value in *val.
   __device__ static int64_t find(const TableDev& tv, const Tile<T>& tile, const Home& h, K key,
                                  uint32_t tag, K* val) {
-    if constexpr (C::ICEBERG) {
+    if constexpr (C::CHAIN) {
+      return chain_find(tv, tile, h.b1, key, val);
+    } else if constexpr (C::ICEBERG) {
       BucketScan<K> r = scan<true, C::BSP>(tv, tile, h.b1, key, tag);
       if (r.hit >= 0) { *val = r.val; return (int64_t)h.b1 * B + r.hit; }
       // The flag is read after the front bucket: a free slot seen there that an
@@ -485,7 +601,9 @@ struct Ops {
     // lock finishes and releases it in the same iteration, so tiles of one wave
     // waiting on each other cannot deadlock (lanes of a wave run in lockstep).
     if constexpr (C::BSP) {
-      if constexpr (C::ICEBERG)
+      if constexpr (C::CHAIN)
+        return upsert_chain_locked(tv, tile, h, key, val, combine);
+      else if constexpr (C::ICEBERG)
         return upsert_iceberg_locked(tv, tile, h, key, val, tag, combine);
       else if constexpr (C::DOUBLE)
         return upsert_double_locked(tv, tile, h, key, val, tag, combine);
@@ -507,7 +625,9 @@ struct Ops {
       const bool go = (attempt & 255) == 0 || lock_looks_free(tv.locks, h.b1, tile);
       ++attempt;
       if (go && try_lock(tv.locks, h.b1, tile)) {
-        if constexpr (C::ICEBERG)
+        if constexpr (C::CHAIN)
+          status = upsert_chain_locked(tv, tile, h, key, val, combine);
+        else if constexpr (C::ICEBERG)
           status = upsert_iceberg_locked(tv, tile, h, key, val, tag, combine);
         else if constexpr (C::DOUBLE)
           status = upsert_double_locked(tv, tile, h, key, val, tag, combine);
@@ -687,7 +807,9 @@ struct Ops {
   // Finds and removes `key` among its candidate buckets.
   __device__ static uint8_t erase_locked(const TableDev& tv, const Tile<T>& tile, const Home& h, K key,
                                          uint32_t tag) {
-    if constexpr (C::ICEBERG) {
+    if constexpr (C::CHAIN) {
+      return erase_chain_locked(tv, tile, h, key);
+    } else if constexpr (C::ICEBERG) {
       const uint32_t cand[3] = {h.b1, h.h2, h.b3};
 #pragma unroll 1
       for (int i = 0; i < 3; ++i) {

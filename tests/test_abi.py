@@ -46,6 +46,18 @@ def test_space_per_slot_matches_section_6_1(design, per_slot, bucket):
     assert b == slots * per_slot + locks + 256
 
 
+def test_chaining_space():
+    """Chaining: ceil(capacity / 7) bucket nodes and as many pool nodes, 128 bytes
+    each (7 pairs and a link, Section 5), one lock byte per bucket."""
+    rc, b = _bytes(7 * 1000, 6)
+    assert rc == 0
+    nb, pool = 1000, 1000
+    node_bytes = -(-(nb + pool) * 128 // 256) * 256
+    lock_bytes = -(-((nb + 3) // 4 * 4) // 256) * 256
+    assert b == node_bytes + lock_bytes + 256
+    assert _bytes(7 * 1000, 6, kv_bits=32)[0] == -4  # 64-bit keys only
+
+
 def test_capacity_rounds_up_to_power_of_two_buckets():
     rc, b1 = _bytes(1000, 0)
     rc2, b2 = _bytes(1024, 0)
@@ -85,7 +97,7 @@ def test_paper_default_configurations():
     tile 4; power-of-two-choice bucket 32 / tile 8; its metadata variant 32 / 4;
     iceberg bucket 32 / tile 8; its metadata variant 32 / 4."""
     L = hw.lib()
-    expect = {0: (8, 8), 1: (32, 4), 2: (32, 8), 3: (32, 4), 4: (32, 8), 5: (32, 4)}
+    expect = {0: (8, 8), 1: (32, 4), 2: (32, 8), 3: (32, 4), 4: (32, 8), 5: (32, 4), 6: (7, 8)}
     for d, (b, t) in expect.items():
         c = hw._Config()
         assert L.hwave_config_default(d, ctypes.byref(c)) == 0

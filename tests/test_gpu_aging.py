@@ -20,7 +20,7 @@ ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2
 OPQ, OPI, OPE = 0, 1, 3
 
 
-@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M"])
+@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING"])
 def test_aging_against_oracle(design):
     cap = 1 << 16
     plan = w.aging_plan(cap, iters=150, config_id=6)
@@ -49,7 +49,10 @@ def test_aging_against_oracle(design):
     ok, ov = om.dump()
     assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov)
     slots, tags, locks = image(t)
-    nv, rep = oracle.layout_check(ODESIGN[design], 64, t.num_buckets, t.bucket_slots, slots, tags, locks)
+    if design == "CHAINING":
+        nv, rep = oracle.chain_check(t.num_buckets, slots, locks)
+    else:
+        nv, rep = oracle.layout_check(ODESIGN[design], 64, t.num_buckets, t.bucket_slots, slots, tags, locks)
     assert nv == 0, rep
     if pcap:
         assert rep["max_seq_index"] < pcap
