@@ -53,7 +53,7 @@ typedef enum {
   HWAVE_ICEBERG_M = 5, /* iceberg with 16-bit tags; bucket 32, tile 4          */
   HWAVE_CHAINING = 6  /* chaining: per bucket a chain of 128-byte nodes of 7
                          pairs and a link (Section 5); ceil(capacity/7)
-                         buckets plus an overflow pool of as many nodes
+                         buckets plus an overflow pool of twice as many nodes
                          (hwave_capacity counts both); 64-bit keys, tile 8;
                          insert/upsert return FULL once the pool is spent     */
 } hwave_design;

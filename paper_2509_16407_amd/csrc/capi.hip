@@ -41,7 +41,7 @@ uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   uint64_t nb, capacity, units, pool;
-  uint64_t off_tags, off_locks, off_ctrl, total;
+  uint64_t off_tags, off_locks, off_ctrl, off_pool_ctr, total;
   uint64_t n_lock_words;
 };
 
@@ -111,13 +111,14 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
   if (capacity == 0 || c.bucket_slots == 0) return HWAVE_EINVAL;
   if (design_chain(design)) {
     // Chaining (Section 5): ceil(capacity / 7) buckets, each a 128-byte first
-    // node (7 pairs and a link), then an overflow pool of as many nodes, which
-    // churn draws on as chains grow (nodes are not returned); ~37 bytes per pair
-    // at 7 pairs per bucket, near the paper's 34.  The capacity reported counts
-    // every slot of buckets and pool.
+    // node (7 pairs and a link), then an overflow pool of twice as many nodes.
+    // A node stays on its chain once linked (lock-free readers may be walking
+    // it), so under churn a chain keeps the nodes its longest past content
+    // needed; two spare nodes per bucket cover that for long aging runs.  The
+    // capacity reported counts every slot of buckets and pool.
     const uint64_t nb = (capacity + 6) / 7;
     if (nb > (1ull << 30)) return HWAVE_EINVAL;
-    const uint64_t pool = nb;
+    const uint64_t pool = 2 * nb;
     L->nb = nb;
     L->pool = pool;
     L->units = (nb + pool) * 8;
@@ -129,6 +130,8 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
     off += round_up(L->n_lock_words * 4, ALIGN);
     L->off_ctrl = off;
     off += ALIGN;
+    L->off_pool_ctr = off;  // POOL_PARTS allocation counters
+    off += round_up(POOL_PARTS * 4, ALIGN);
     L->total = off;
     return HWAVE_OK;
   }
@@ -241,6 +244,7 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   tv.nb_front = design_iceberg(design) ? (uint32_t)iceberg_front(L.nb) : (uint32_t)L.nb;
   tv.nb_back = design_iceberg(design) ? (uint32_t)(L.nb - tv.nb_front) : 0u;
   tv.pool_nodes = (uint32_t)L.pool;
+  tv.pool_ctr = design_chain(design) ? (uint32_t*)(b + L.off_pool_ctr) : nullptr;
   uint64_t cap = c.probe_cap ? c.probe_cap : L.nb;
   if (cap > L.nb) cap = L.nb;
   tv.probe_cap = (uint32_t)(cap > 0xFFFFFFFFull ? 0xFFFFFFFFull : cap);

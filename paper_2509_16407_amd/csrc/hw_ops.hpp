@@ -44,6 +44,10 @@ namespace hw {
 enum : uint8_t { ST_MISS = 0, ST_DONE = 1, ST_EXISTED = 2, ST_FULL = 3, ST_INVALID = 4 };
 enum : int { C_SUM = 0, C_KEEP = 1, C_REPLACE = 2, C_MIN = 3, C_MAX = 4 };
 enum : int { OP_QUERY = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_ERASE = 3 };
+// Chaining's overflow pool is split into this many partitions, each with its own
+// allocation counter; bucket b draws from partition b mod POOL_PARTS first.
+constexpr uint32_t POOL_PARTS = 1024;
+
 enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, D_ICEBERG_M = 5, D_CHAINING = 6 };
 
 // Device view of one table (passed by value to kernels).
@@ -56,6 +60,7 @@ struct TableDev {
   uint32_t nb_front;     // iceberg: front-yard buckets [0, nb_front); chaining: buckets
   uint32_t nb_back;      // iceberg: backyard buckets [nb_front, nb_front + nb_back)
   uint32_t pool_nodes;   // chaining: overflow nodes after the buckets' first nodes
+  uint32_t* pool_ctr;    // chaining: POOL_PARTS allocation counters
   uint32_t probe_cap;    // double hashing: most buckets visited
   uint32_t shortcut;     // power-of-two-choice shortcut enabled
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
@@ -478,20 +483,23 @@ struct Ops {
     return -1;
   }
 
-  // Takes a node from the overflow pool: eight partitions, each with its own
-  // counter (control words 8..15), so allocations do not funnel through one
-  // address; a wave starts at the partition of its block.  NIL when all are spent.
-  __device__ static uint64_t alloc_node(const TableDev& tv, const Tile<T>& tile) {
+  // Takes a node from the overflow pool for bucket b.  The pool is split into
+  // POOL_PARTS partitions with a counter each, and bucket b draws from partition
+  // b mod POOL_PARTS first: allocations spread over a thousand addresses instead
+  // of funnelling through one (a single address serves tens of millions of
+  // atomics per second).  A spent partition sends the tile on to the next ones;
+  // a counter is read before its atomic, so spent partitions cost no atomics.
+  // NIL when the whole pool is spent.
+  __device__ static uint64_t alloc_node(const TableDev& tv, const Tile<T>& tile, uint32_t b) {
     uint64_t got = NIL;
     if (tile.leader()) {
-      const uint32_t psz = (tv.pool_nodes + 7) / 8;
-      const uint32_t home = blockIdx.x & 7;
-      for (uint32_t q = 0; q < 8; ++q) {
-        const uint32_t p = (home + q) & 7;
+      const uint32_t psz = (tv.pool_nodes + POOL_PARTS - 1) / POOL_PARTS;
+      for (uint32_t q = 0; q < POOL_PARTS; ++q) {
+        const uint32_t p = (b + q) % POOL_PARTS;
         const uint32_t lo = p * psz;
         const uint32_t hi = lo + psz < tv.pool_nodes ? lo + psz : tv.pool_nodes;
-        if (lo >= hi || ld(tv.ctrl + 8 + p) >= hi - lo) continue;
-        const uint32_t i = __hip_atomic_fetch_add(tv.ctrl + 8 + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lo >= hi || ld(tv.pool_ctr + p) >= hi - lo) continue;
+        const uint32_t i = __hip_atomic_fetch_add(tv.pool_ctr + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (i < hi - lo) { got = (uint64_t)tv.nb_front + lo + i; break; }
       }
     }
@@ -515,7 +523,7 @@ struct Ops {
       if (tile.leader()) publish(tv, free_slot, key, val);
       return ST_DONE;
     }
-    const uint64_t fresh = alloc_node(tv, tile);
+    const uint64_t fresh = alloc_node(tv, tile, h.b1);
     if (fresh == NIL) return ST_FULL;
     if (tile.leader()) {
       publish(tv, fresh * 8, key, val);  // the pool node is empty: slot 0

@@ -30,7 +30,7 @@ def test_chaining_geometry():
     t = hw.Table(1 << 16, "CHAINING")
     nb = (65536 + 6) // 7
     assert t.num_buckets == nb and t.bucket_slots == 7 and t.tile == 8
-    assert t.capacity == 2 * nb * 7
+    assert t.capacity == 3 * nb * 7
 
 
 def test_chaining_all_ops_against_oracle():
@@ -100,13 +100,13 @@ def test_chaining_layout_equals_sequential_placement():
 
 
 def test_chaining_pool_exhaustion_reports_full():
-    """One bucket and a one-node pool hold 14 keys; the rest report FULL; an erase
+    """One bucket and a two-node pool hold 21 keys; the rest report FULL; an erase
     makes room for exactly one more."""
     t = hw.Table(7, "CHAINING")
     assert t.num_buckets == 1
-    keys = w.distinct_keys(132, 20)
+    keys = w.distinct_keys(132, 30)
     st = u8(t.insert(dev(keys), dev(w.value_of(keys))))
-    assert (st == hw.ST_DONE).sum() == 14 and (st == hw.ST_FULL).sum() == 6
+    assert (st == hw.ST_DONE).sum() == 21 and (st == hw.ST_FULL).sum() == 9
     done = keys[st == hw.ST_DONE]
     om = oracle.OracleMap()
     om.insert(done, w.value_of(done))
