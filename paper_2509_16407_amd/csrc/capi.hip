@@ -130,8 +130,8 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
     off += round_up(L->n_lock_words * 4, ALIGN);
     L->off_ctrl = off;
     off += ALIGN;
-    L->off_pool_ctr = off;  // POOL_PARTS allocation counters
-    off += round_up(POOL_PARTS * 4, ALIGN);
+    L->off_pool_ctr = off;  // POOL_PARTS allocation counters, one per 128-byte line
+    off += round_up((uint64_t)POOL_PARTS * POOL_CTR_STRIDE * 4, ALIGN);
     L->total = off;
     return HWAVE_OK;
   }

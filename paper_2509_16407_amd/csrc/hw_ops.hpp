@@ -45,8 +45,12 @@ enum : uint8_t { ST_MISS = 0, ST_DONE = 1, ST_EXISTED = 2, ST_FULL = 3, ST_INVAL
 enum : int { C_SUM = 0, C_KEEP = 1, C_REPLACE = 2, C_MIN = 3, C_MAX = 4 };
 enum : int { OP_QUERY = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_ERASE = 3 };
 // Chaining's overflow pool is split into this many partitions, each with its own
-// allocation counter; bucket b draws from partition b mod POOL_PARTS first.
+// allocation counter in a 128-byte line of its own (POOL_CTR_STRIDE 32-bit
+// words apart): atomics to one line are served one after another, so counters
+// sharing lines would serialise the allocations.  Bucket b draws from
+// partition b mod POOL_PARTS first.
 constexpr uint32_t POOL_PARTS = 1024;
+constexpr uint32_t POOL_CTR_STRIDE = 32;
 
 enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, D_ICEBERG_M = 5, D_CHAINING = 6 };
 
@@ -60,7 +64,7 @@ struct TableDev {
   uint32_t nb_front;     // iceberg: front-yard buckets [0, nb_front); chaining: buckets
   uint32_t nb_back;      // iceberg: backyard buckets [nb_front, nb_front + nb_back)
   uint32_t pool_nodes;   // chaining: overflow nodes after the buckets' first nodes
-  uint32_t* pool_ctr;    // chaining: POOL_PARTS allocation counters
+  uint32_t* pool_ctr;    // chaining: POOL_PARTS allocation counters, one per line
   uint32_t probe_cap;    // double hashing: most buckets visited
   uint32_t shortcut;     // power-of-two-choice shortcut enabled
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
@@ -485,9 +489,9 @@ struct Ops {
 
   // Takes a node from the overflow pool for bucket b.  The pool is split into
   // POOL_PARTS partitions with a counter each, and bucket b draws from partition
-  // b mod POOL_PARTS first: allocations spread over a thousand addresses instead
-  // of funnelling through one (a single address serves tens of millions of
-  // atomics per second).  A spent partition sends the tile on to the next ones;
+  // b mod POOL_PARTS first: allocations spread over a thousand lines instead of
+  // funnelling through one (a single line serves tens of millions of atomics
+  // per second).  A spent partition sends the tile on to the next ones;
   // a counter is read before its atomic, so spent partitions cost no atomics.
   // NIL when the whole pool is spent.
   __device__ static uint64_t alloc_node(const TableDev& tv, const Tile<T>& tile, uint32_t b) {
@@ -498,8 +502,9 @@ struct Ops {
         const uint32_t p = (b + q) % POOL_PARTS;
         const uint32_t lo = p * psz;
         const uint32_t hi = lo + psz < tv.pool_nodes ? lo + psz : tv.pool_nodes;
-        if (lo >= hi || ld(tv.pool_ctr + p) >= hi - lo) continue;
-        const uint32_t i = __hip_atomic_fetch_add(tv.pool_ctr + p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t* ctr = tv.pool_ctr + p * POOL_CTR_STRIDE;
+        if (lo >= hi || ld(ctr) >= hi - lo) continue;
+        const uint32_t i = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (i < hi - lo) { got = (uint64_t)tv.nb_front + lo + i; break; }
       }
     }

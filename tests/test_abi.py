@@ -49,13 +49,13 @@ def test_space_per_slot_matches_section_6_1(design, per_slot, bucket):
 def test_chaining_space():
     """Chaining: ceil(capacity / 7) bucket nodes and twice as many pool nodes, 128
     bytes each (7 pairs and a link, Section 5), one lock byte per bucket, and 1024
-    pool-partition counters."""
+    pool-partition counters, one per 128-byte line."""
     rc, b = _bytes(7 * 1000, 6)
     assert rc == 0
     nb, pool = 1000, 2000
     node_bytes = -(-(nb + pool) * 128 // 256) * 256
     lock_bytes = -(-((nb + 3) // 4 * 4) // 256) * 256
-    assert b == node_bytes + lock_bytes + 256 + 4096
+    assert b == node_bytes + lock_bytes + 256 + 1024 * 128
     assert _bytes(7 * 1000, 6, kv_bits=32)[0] == -4  # 64-bit keys only
 
 
