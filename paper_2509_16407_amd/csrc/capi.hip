@@ -567,7 +567,7 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
   m->n_tables = n_tables;
   for (uint32_t i = 0; i < n_tables; i++) m->table_bytes.push_back(tables[i]->bytes);
   hipError_t e = hipMalloc(&m->d_tables, n_tables * sizeof(MultiTable));
-  if (e == hipSuccess) e = hipMalloc(&m->d_heads, 64 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&m->d_heads, NQ * HEAD_STRIDE * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemcpyAsync(m->d_tables, h.data(), n_tables * sizeof(MultiTable),
                                           hipMemcpyHostToDevice, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);

@@ -19,6 +19,9 @@
 namespace hw {
 
 constexpr int NQ = 8;
+// Queue head counters sit one per 128-byte line (HEAD_STRIDE 32-bit words
+// apart): atomics to one line are served one after another.
+constexpr int HEAD_STRIDE = 32;
 
 #ifndef HW_MULTI_WAVES
 #define HW_MULTI_WAVES 6  // occupancy target of the multi-table kernel (waves per SIMD)
@@ -111,7 +114,8 @@ k_multi(const MultiTable* __restrict__ tables, const MultiItem* __restrict__ ite
     const uint32_t qlen = qs.end[q] - qs.start[q];
     while (true) {
       uint32_t idx = 0;
-      if (lane == 0) idx = __hip_atomic_fetch_add(heads + q, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        idx = __hip_atomic_fetch_add(heads + q * HEAD_STRIDE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       idx = __builtin_amdgcn_readfirstlane(idx);
       if (idx >= qlen) break;
       const MultiItem m = items[qs.start[q] + idx];

@@ -4,7 +4,7 @@
 namespace hw {
 
 __global__ void k_zero_heads(uint32_t* heads) {
-  if (threadIdx.x < NQ) heads[threadIdx.x] = 0;
+  if (threadIdx.x < NQ) heads[threadIdx.x * HEAD_STRIDE] = 0;
 }
 
 hipError_t launch_multi(int kv_bits, unsigned grid, const MultiTable* tables, const MultiItem* items,
