@@ -38,7 +38,7 @@ LIB = os.path.join(HERE, "libhw_oracle.so")
 QUERY, INSERT, UPSERT, ERASE = 0, 1, 2, 3
 SUM, KEEP, REPLACE, MIN, MAX = 0, 1, 2, 3, 4
 MISS, DONE, EXISTED, FULL, INVALID = 0, 1, 2, 3, 4
-DOUBLE, DOUBLE_M, P2, P2_M, ICEBERG, ICEBERG_M, CHAINING = 0, 1, 2, 3, 4, 5, 6
+DOUBLE, DOUBLE_M, P2, P2_M, ICEBERG, ICEBERG_M, CHAINING, CUCKOO = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 def build(force: bool = False, extra_flags=(), out: str | None = None) -> str:
@@ -112,6 +112,9 @@ def _bind(lib):
     lib.orc_chain_check.argtypes = [U64, U64, P, P, U64, P, U64, ctypes.POINTER(_Report)]
     lib.orc_sim_chain_insert.restype = U64
     lib.orc_sim_chain_insert.argtypes = [U64, U64, P, P, U64, ctypes.c_int]
+    lib.orc_cuckoo_buckets.argtypes = [U64, U64, ctypes.POINTER(U64)]
+    lib.orc_sim_cuckoo_insert.restype = U64
+    lib.orc_sim_cuckoo_insert.argtypes = [U64, U64, P, P, U64, U64, U64, ctypes.c_int]
     lib.orc_sim_aging.restype = ctypes.c_int
     lib.orc_sim_aging.argtypes = [ctypes.c_int, U64, U64, U64, U64, P, U64, U64, U64, P, P, U64, P]
     return lib
@@ -302,3 +305,22 @@ def sim_chain_insert(nb, n_nodes, keys, nodes=None):
     keys = _u64(keys)
     failed = lib.orc_sim_chain_insert(nb, n_nodes, _ptr(nodes), _ptr(keys), len(keys), int(init))
     return nodes, int(failed)
+
+
+def cuckoo_buckets(key: int, nb: int):
+    """The three candidate buckets of a key in hash order (possibly repeated)."""
+    out = (ctypes.c_uint64 * 3)()
+    load().orc_cuckoo_buckets(key, nb, out)
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def sim_cuckoo_insert(nb, bucket_slots, keys, max_kicks=500, seed=1, slots=None):
+    """Sequential three-way cuckoo inserts; returns (slots uint8 array, n_failed)."""
+    lib = load()
+    init = slots is None
+    if slots is None:
+        slots = np.empty(nb * bucket_slots * 16, dtype=np.uint8)
+    keys = _u64(keys)
+    failed = lib.orc_sim_cuckoo_insert(nb, bucket_slots, _ptr(slots), _ptr(keys), len(keys), max_kicks, seed,
+                                       int(init))
+    return slots, int(failed)

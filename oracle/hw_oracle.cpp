@@ -190,7 +190,7 @@ void orc_map_digest(const orc_map* h, uint64_t* sum_out, uint64_t* xor_out) {
 // with g = fmix64(key XOR 0xbb67ae8584caa73b).
 
 enum { ORC_DOUBLE = 0, ORC_DOUBLE_M = 1, ORC_P2 = 2, ORC_P2_M = 3, ORC_ICEBERG = 4, ORC_ICEBERG_M = 5,
-       ORC_CHAINING = 6 };
+       ORC_CHAINING = 6, ORC_CUCKOO = 7 };
 
 static uint64_t orc_fmix64(uint64_t k) {
   k ^= k >> 33;
@@ -270,6 +270,38 @@ void orc_iceberg_buckets(uint64_t key, uint64_t nb, uint64_t* out3) {
 static bool design_has_tags(int d) { return d == ORC_DOUBLE_M || d == ORC_P2_M || d == ORC_ICEBERG_M; }
 static bool design_is_double(int d) { return d == ORC_DOUBLE || d == ORC_DOUBLE_M; }
 static bool design_is_iceberg(int d) { return d == ORC_ICEBERG || d == ORC_ICEBERG_M; }
+static bool design_is_cuckoo(int d) { return d == ORC_CUCKOO; }
+
+// Three-way cuckoo hashing (Section 2.2, configuration of Section 5): a key may
+// live in any of three buckets.  Reading of the silent hashes: lo32(h) mod nb,
+// hi32(h) mod nb and lo32(g) mod nb, with h of part 2 and g the salted hash of
+// the iceberg backyard.
+struct orc_cuckoo {
+  uint64_t c[3];
+  int n;  // distinct candidates, in that order
+};
+
+static orc_cuckoo orc_cuckoo_of(uint64_t key, uint64_t nb) {
+  const uint64_t h = orc_fmix64(key ^ ORC_SALT);
+  const uint64_t g = orc_fmix64(key ^ ORC_SALT_B);
+  const uint64_t raw[3] = {(h & 0xFFFFFFFFull) % nb, (h >> 32) % nb, (g & 0xFFFFFFFFull) % nb};
+  orc_cuckoo r;
+  r.n = 0;
+  for (int i = 0; i < 3; i++) {
+    bool dup = false;
+    for (int j = 0; j < r.n; j++) dup |= r.c[j] == raw[i];
+    if (!dup) r.c[r.n++] = raw[i];
+  }
+  return r;
+}
+
+void orc_cuckoo_buckets(uint64_t key, uint64_t nb, uint64_t* out3) {
+  const uint64_t h = orc_fmix64(key ^ ORC_SALT);
+  const uint64_t g = orc_fmix64(key ^ ORC_SALT_B);
+  out3[0] = (h & 0xFFFFFFFFull) % nb;
+  out3[1] = (h >> 32) % nb;
+  out3[2] = (g & 0xFFFFFFFFull) % nb;
+}
 
 // A table image in host memory.  Slots are (key, value) pairs of key_bits each,
 // bucket-major: slot s = bucket * bucket_slots + j.
@@ -356,6 +388,7 @@ static double probe_neg(const orc_image& im, uint64_t key) {
     }
     return (double)(im.nb * per_bucket);
   }
+  if (design_is_cuckoo(im.design)) return (double)(orc_cuckoo_of(key, im.nb).n * per_bucket);
   if (design_is_iceberg(im.design)) {
     // A table that has never erased keeps a key out of the backyard while its front
     // bucket has room, so a query stops at a front bucket with an empty slot.
@@ -418,6 +451,15 @@ uint64_t orc_layout_check(int design, int key_bits, uint64_t nb, uint64_t bucket
         if (!ok) { r.misplaced++; continue; }
         r.max_seq_index = std::max(r.max_seq_index, i);
         r.pos_probe_sum += probe_pos(im, i, j, tile_bytes);
+      } else if (design_is_cuckoo(design)) {
+        // Any of the three candidates; a query reads them in order.
+        orc_cuckoo cc = orc_cuckoo_of(k, nb);
+        int at = -1;
+        for (int c = 0; c < cc.n; c++)
+          if (cc.c[c] == b) at = c;
+        if (at < 0) { r.misplaced++; continue; }
+        if (at > 0) r.in_alternate++;
+        r.pos_probe_sum += probe_pos(im, (uint64_t)at, j, tile_bytes);
       } else if (design_is_iceberg(design)) {
         // Front bucket, then the backyard choices in order (a repeated choice once).
         orc_iceberg ib = orc_iceberg_of(k, nb);
@@ -823,6 +865,60 @@ uint64_t orc_sim_chain_insert(uint64_t nb, uint64_t n_nodes, uint64_t* nodes, co
     nu[1] = k * 3 + 1;
     nodes[16 * last + 15] = next_free;
     next_free++;
+  }
+  return failed;
+}
+
+// ---------------------------------------------------------------------------
+// 6. Sequential three-way bucketed cuckoo inserts
+// ---------------------------------------------------------------------------
+//
+// Distinct keys into a 64-bit cuckoo image (initialised empty when `init`): the
+// first candidate bucket (in hash order) with an empty slot, else a random walk
+// (Section 2.2: "the new key replaces a key already in a bucket, and the
+// insertion procedure is restarted for the evicted key"): the key displaces a
+// random slot of a random candidate and the displaced key goes on to one of its
+// other candidates, for at most max_kicks displacements.  The walk's random
+// numbers come from a splitmix64 stream seeded with `seed`.  A walk that runs out
+// leaves its last homeless key counted as failed (the table already lost it,
+// which only a sequential model may do).  Returns the number of failed keys.
+
+static uint64_t orc_splitmix_next(uint64_t* st) {
+  uint64_t z = (*st += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t orc_sim_cuckoo_insert(uint64_t nb, uint64_t bucket_slots, uint64_t* slots, const uint64_t* keys,
+                               uint64_t n, uint64_t max_kicks, uint64_t seed, int init) {
+  const uint64_t nslots = nb * bucket_slots;
+  if (init) memset(slots, 0xFF, nslots * 16);
+  uint64_t rng = seed, failed = 0;
+  auto free_in = [&](uint64_t b) -> int64_t {
+    for (uint64_t j = 0; j < bucket_slots; j++)
+      if (slots[2 * (b * bucket_slots + j)] == ~0ull) return (int64_t)(b * bucket_slots + j);
+    return -1;
+  };
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t k = keys[i], v = k * 3 + 1;
+    bool placed = false;
+    for (uint64_t kick = 0; kick <= max_kicks && !placed; kick++) {
+      orc_cuckoo cc = orc_cuckoo_of(k, nb);
+      for (int c = 0; c < cc.n && !placed; c++) {
+        int64_t s = free_in(cc.c[ORC_MUTANT == 17 ? 0 : c]);
+        if (s >= 0) { slots[2 * s] = k; slots[2 * s + 1] = v; placed = true; }
+      }
+      if (placed || kick == max_kicks) break;
+      const uint64_t b = cc.c[orc_splitmix_next(&rng) % (uint64_t)cc.n];
+      const uint64_t s = b * bucket_slots + orc_splitmix_next(&rng) % bucket_slots;
+      const uint64_t ek = slots[2 * s], ev = slots[2 * s + 1];
+      slots[2 * s] = k;
+      slots[2 * s + 1] = v;
+      k = ek;
+      v = ev;
+    }
+    if (!placed) failed++;
   }
   return failed;
 }

@@ -252,6 +252,10 @@ def test_tag_bucket_is_half_line():
 # ---------------------------------------------------------------- layout checker
 
 def _image(design, nb, bucket, keys, shortcut=True):
+    if design == oracle.CUCKOO:
+        slots, failed = oracle.sim_cuckoo_insert(nb, bucket, keys)
+        assert failed == 0
+        return slots, None
     slots, tags, failed = oracle.sim_insert(design, 64, nb, bucket, keys, keys, shortcut=shortcut)
     assert failed == 0
     return slots, tags
@@ -261,14 +265,16 @@ def _candidates(design, key, nb):
     """Every bucket a search for `key` may visit (before any early stop)."""
     if design in ICEBERGS:
         return set(oracle.iceberg_buckets(key, nb))
+    if design == oracle.CUCKOO:
+        return set(oracle.cuckoo_buckets(key, nb))
     if design in (oracle.P2, oracle.P2_M):
         return {oracle.primary_bucket(key, nb), oracle.p2_alternate(key, nb)}
     return {oracle.double_probe(key, nb, i) for i in range(nb)}
 
 
-@pytest.mark.parametrize("design", sorted(DESIGNS.values()))
+@pytest.mark.parametrize("design", sorted(DESIGNS.values()) + [oracle.CUCKOO])
 def test_layout_checker_detects_planted_violations(design):
-    nb, bucket = 64, 8 if design == oracle.DOUBLE else 32
+    nb, bucket = 64, 8 if design in (oracle.DOUBLE, oracle.CUCKOO) else 32
     keys = w.distinct_keys(17, int(0.8 * nb * bucket))
     slots, tags = _image(design, nb, bucket, keys)
     nv, rep = oracle.layout_check(design, 64, nb, bucket, slots, tags)
@@ -536,3 +542,41 @@ def test_chain_checker_detects_planted_violations():
     orph[-1, 0] = np.uint64(12345)
     nv, rep = oracle.chain_check(nb, orph.reshape(-1))
     assert nv >= 1
+
+
+# ---------------------------------------------------------------- cuckoo (Sections 2.2 and 5)
+
+def test_cuckoo_takes_first_candidate_with_room():
+    """Section 2.2's rule: a key goes to a candidate bucket with room before any
+    key is displaced.  Fill a key's first candidate with other keys whose own
+    first candidate it is, then insert the key: it lands in its next candidate
+    with room and nothing moves."""
+    nb, bucket = 1 << 10, 8
+    pool = w.distinct_keys(48, 200000)
+    target = int(pool[0])
+    c0, c1, c2 = oracle.cuckoo_buckets(target, nb)
+    assert c1 != c0
+    fillers = [int(k) for k in pool[1:] if oracle.cuckoo_buckets(int(k), nb)[0] == c0][:bucket]
+    assert len(fillers) == bucket
+    slots, failed = oracle.sim_cuckoo_insert(nb, bucket, np.array(fillers, np.uint64))
+    assert failed == 0
+    before = slots.copy()
+    slots, failed = oracle.sim_cuckoo_insert(nb, bucket, np.array([target], np.uint64), slots=slots)
+    assert failed == 0
+    s64, b64 = slots.view(np.uint64), before.view(np.uint64)
+    changed = np.nonzero(s64[0::2] != b64[0::2])[0]
+    assert len(changed) == 1 and changed[0] // bucket == c1 and int(s64[2 * changed[0]]) == target
+
+
+@pytest.mark.parametrize("load", [0.9, 0.95])
+def test_cuckoo_holds_high_load(load):
+    """Three-way cuckoo hashing with buckets of 8 holds loads far above 0.95
+    (its load threshold is above 0.99); the sequential model places every key, and
+    the image passes the layout checker."""
+    nb, bucket = 1 << 14, 8
+    n = int(load * nb * bucket)
+    keys = w.distinct_keys(w.stream_seed(47, int(load * 100)), n)
+    slots, failed = oracle.sim_cuckoo_insert(nb, bucket, keys)
+    assert failed == 0
+    nv, rep = oracle.layout_check(oracle.CUCKOO, 64, nb, bucket, slots, None, tile_bytes=128)
+    assert nv == 0 and rep["live"] == n
