@@ -55,7 +55,11 @@ typedef enum {
                          pairs and a link (Section 5); ceil(capacity/7)
                          buckets plus an overflow pool of twice as many nodes
                          (hwave_capacity counts both); 64-bit keys, tile 8;
-                         insert/upsert return FULL once the pool is spent     */
+                         insert/upsert return FULL once the pool is spent     */,
+  HWAVE_CUCKOO = 7    /* three-way bucketed cuckoo hashing (Section 5): bucket
+                         8, tile 4, 64-bit keys; keys move between their three
+                         buckets, so every operation, queries included, locks
+                         all three; FULL when no room can be made            */
 } hwave_design;
 
 /* Upsert callbacks (Section 5.1): SUM accumulates with wrap-around modulo

@@ -18,7 +18,7 @@ __all__ = ["Table", "Multi", "Server", "lib", "autotune", "DESIGNS", "COMBINES",
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhashwave.so")
 
-DESIGNS = {"DOUBLE": 0, "DOUBLE_M": 1, "P2": 2, "P2_M": 3, "ICEBERG": 4, "ICEBERG_M": 5, "CHAINING": 6}
+DESIGNS = {"DOUBLE": 0, "DOUBLE_M": 1, "P2": 2, "P2_M": 3, "ICEBERG": 4, "ICEBERG_M": 5, "CHAINING": 6, "CUCKOO": 7}
 COMBINES = {"sum": 0, "keep": 1, "replace": 2, "min": 3, "max": 4}
 OPS = {"query": 0, "insert": 1, "upsert": 2, "erase": 3}
 ST_MISS, ST_DONE, ST_EXISTED, ST_FULL, ST_INVALID = 0, 1, 2, 3, 4
@@ -155,7 +155,7 @@ def _stream(stream):
 class Table:
     """One hash table in device memory.
 
-    design: "DOUBLE" | "DOUBLE_M" | "P2" | "P2_M" | "ICEBERG" | "ICEBERG_M" | "CHAINING"; kv_bits 64 or 32; bucket/tile 0 =
+    design: "DOUBLE" | "DOUBLE_M" | "P2" | "P2_M" | "ICEBERG" | "ICEBERG_M" | "CHAINING" | "CUCKOO"; kv_bits 64 or 32; bucket/tile 0 =
     the design default (Section 5 configurations).  Keys/values are int64 tensors
     (kv_bits=64) or int32 tensors (kv_bits=32) on the table's device.
     """

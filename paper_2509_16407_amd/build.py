@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhashwave.so")
 OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["capi.hip", "inst_u64_double.hip", "inst_u64_p2.hip", "inst_u64_iceberg.hip", "inst_u64_chain.hip", "inst_u32_double.hip",
+SOURCES = ["capi.hip", "inst_u64_double.hip", "inst_u64_p2.hip", "inst_u64_iceberg.hip", "inst_u64_chain.hip", "inst_u64_cuckoo.hip", "inst_u32_double.hip",
            "inst_u32_p2.hip", "inst_u32_iceberg.hip", "inst_u64_bsp.hip", "inst_multi.hip", "autotune.hip",
            "server.hip"]
 HEADERS = ["hw_device.hpp", "hw_ops.hpp", "hw_launch.hpp", "hw_multi.hpp"]

@@ -62,7 +62,7 @@ const std::vector<const KernelSet*>& registry() {
   static std::vector<const KernelSet*> all;
   static std::once_flag once;
   std::call_once(once, [] {
-    const KernelSet* (*fns[])(size_t*) = {sets_u64_double, sets_u64_p2, sets_u64_iceberg, sets_u64_chain,
+    const KernelSet* (*fns[])(size_t*) = {sets_u64_double, sets_u64_p2, sets_u64_iceberg, sets_u64_chain, sets_u64_cuckoo,
                                           sets_u32_double, sets_u32_p2, sets_u32_iceberg, sets_u64_bsp};
     for (auto f : fns) {
       size_t n = 0;
@@ -87,12 +87,15 @@ const KernelSet* find_set(const hwave_config& c, int design) {
 void defaults_for(hwave_design design, uint32_t kv_bits, hwave_config* c) {
   memset(c, 0, sizeof *c);
   c->kv_bits = kv_bits;
-  c->bucket_slots = design == HWAVE_DOUBLE ? (kv_bits == 64 ? 8 : 16) : design_chain(design) ? 7 : 32;
-  c->tile = design_tags(design) ? 4 : 8;
+  c->bucket_slots = design == HWAVE_DOUBLE ? (kv_bits == 64 ? 8 : 16)
+                    : design_chain(design)   ? 7
+                    : design == HWAVE_CUCKOO ? 8
+                                             : 32;
+  c->tile = design_tags(design) || design == HWAVE_CUCKOO ? 4 : 8;
 }
 
 int resolve_config(hwave_design design, const hwave_config* in, hwave_config* out) {
-  if ((int)design < HWAVE_DOUBLE || (int)design > HWAVE_CHAINING) return HWAVE_EINVAL;
+  if ((int)design < HWAVE_DOUBLE || (int)design > HWAVE_CUCKOO) return HWAVE_EINVAL;
   const uint32_t kv = in && in->kv_bits ? in->kv_bits : 64;
   if (kv != 64 && kv != 32) return HWAVE_EINVAL;
   hwave_config c;
@@ -262,7 +265,7 @@ bool bad_ptr(const void* p) { return p == nullptr; }
 extern "C" {
 
 int hwave_config_default(hwave_design design, hwave_config* out) {
-  if (!out || (int)design < HWAVE_DOUBLE || (int)design > HWAVE_CHAINING) return HWAVE_EINVAL;
+  if (!out || (int)design < HWAVE_DOUBLE || (int)design > HWAVE_CUCKOO) return HWAVE_EINVAL;
   defaults_for(design, 64, out);
   return HWAVE_OK;
 }

@@ -184,5 +184,6 @@ const KernelSet* sets_u64_iceberg(size_t* n);
 const KernelSet* sets_u32_iceberg(size_t* n);
 const KernelSet* sets_u64_bsp(size_t* n);
 const KernelSet* sets_u64_chain(size_t* n);
+const KernelSet* sets_u64_cuckoo(size_t* n);
 
 }  // namespace hw

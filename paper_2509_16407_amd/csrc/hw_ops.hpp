@@ -52,7 +52,8 @@ enum : int { OP_QUERY = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_ERASE = 3 };
 constexpr uint32_t POOL_PARTS = 1024;
 constexpr uint32_t POOL_CTR_STRIDE = 32;
 
-enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, D_ICEBERG_M = 5, D_CHAINING = 6 };
+enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, D_ICEBERG_M = 5, D_CHAINING = 6,
+             D_CUCKOO = 7 };
 
 // Device view of one table (passed by value to kernels).
 struct TableDev {
@@ -84,6 +85,7 @@ struct Cfg {
   static constexpr bool DOUBLE = DESIGN == D_DOUBLE || DESIGN == D_DOUBLE_M;
   static constexpr bool ICEBERG = DESIGN == D_ICEBERG || DESIGN == D_ICEBERG_M;
   static constexpr bool CHAIN = DESIGN == D_CHAINING;  // B = 7 slots per node, T = 8
+  static constexpr bool CUCKOO = DESIGN == D_CUCKOO;   // three candidate buckets
   static constexpr int B = B_;
   static constexpr int T = T_;
   static constexpr int SLOT_BYTES = 2 * (int)sizeof(K);
@@ -419,6 +421,10 @@ struct Ops {
   __device__ static __forceinline__ Home home_of(const TableDev& tv, K key) {
     if constexpr (C::CHAIN) {
       return Home{front_bucket((uint64_t)key, tv.nb_front), 0u, 0u};
+    } else if constexpr (C::CUCKOO) {
+      const Hashed h = hash_key((uint64_t)key, tv.bucket_mask);
+      const uint32_t g = (uint32_t)fmix64((uint64_t)key ^ HASH_SALT_B);
+      return Home{h.b1, h.h2 & tv.bucket_mask, g & tv.bucket_mask};
     } else if constexpr (C::ICEBERG) {
       const Yard y = yard_of((uint64_t)key, tv.nb_front, tv.nb_back);
       return Home{y.front, y.back1, y.back2};
@@ -436,6 +442,218 @@ struct Ops {
 
   __device__ static __forceinline__ uint32_t step_of(const TableDev& tv, const Home& h) {
     return (h.h2 & tv.bucket_mask) | 1u;
+  }
+
+  // ---------------------------------------------------------------- cuckoo
+  //
+  // Three-way bucketed cuckoo hashing (Sections 2.2 and 5; concurrent insertion
+  // after libcuckoo): a key lives in one of three buckets, and keys move between
+  // their buckets to make room, so the table is not stable and every operation,
+  // queries included, holds the locks of all its key's buckets (Section 6.4
+  // notes CuckooHT's locked queries).  Locks are taken in ascending bucket order
+  // with try-locks only: a tile that misses one releases what it holds and backs
+  // off, so no tile waits while holding a lock (no deadlock, and no waiting on
+  // a tile of its own wave).  Every write to a bucket happens under its lock,
+  // so slots are written with plain stores.
+  //
+  // Making room: with the locks released, a random walk looks for a path of
+  // displacements ending in a bucket with an empty slot (reads only); the path
+  // is then carried out backwards, each move under the locks of its two buckets
+  // after checking that nothing changed: the key is copied into the empty slot,
+  // the copy completes, then the old slot is emptied.  Any failed check drops the
+  // path and the insert starts over; after CUCKOO_MAX_ROUNDS fruitless rounds it
+  // reports FULL.
+  static constexpr int CUCKOO_MAX_PATH = 6;
+  static constexpr uint32_t CUCKOO_MAX_ROUNDS = 64;
+
+  struct Cands {
+    uint32_t c[3];  // distinct candidate buckets, in hash order
+    uint32_t s[3];  // the same, ascending (lock order)
+    uint32_t n;
+  };
+
+  __device__ static Cands cuckoo_cands(const Home& h) {
+    Cands r;
+    r.c[0] = h.b1;
+    r.n = 1;
+    if (h.h2 != h.b1) r.c[r.n++] = h.h2;
+    if (h.b3 != h.b1 && h.b3 != h.h2) r.c[r.n++] = h.b3;
+    r.s[0] = r.c[0];
+    r.s[1] = r.c[1];
+    r.s[2] = r.c[2];
+    for (uint32_t i = 1; i < r.n; ++i)
+      for (uint32_t j = i; j > 0 && r.s[j - 1] > r.s[j]; --j) {
+        const uint32_t t = r.s[j];
+        r.s[j] = r.s[j - 1];
+        r.s[j - 1] = t;
+      }
+    return r;
+  }
+
+  __device__ static __forceinline__ void release(const TableDev& tv, uint32_t b, const Tile<T>& tile) {
+    if (tile.leader()) st((uint8_t*)tv.locks + b, (uint8_t)0);
+  }
+
+  __device__ static bool try_lock_all(const TableDev& tv, const Tile<T>& tile, const Cands& c) {
+    for (uint32_t i = 0; i < c.n; ++i) {
+      if (!try_lock(tv.locks, c.s[i], tile)) {
+        for (uint32_t j = 0; j < i; ++j) release(tv, c.s[j], tile);
+        return false;
+      }
+    }
+    return true;
+  }
+
+  __device__ static bool all_look_free(const TableDev& tv, const Tile<T>& tile, const Cands& c) {
+    bool f = true;
+    for (uint32_t i = 0; i < c.n; ++i) f &= lock_looks_free(tv.locks, c.s[i], tile);
+    return f;
+  }
+
+  // Releases all of c's locks; after writes, once those have completed.
+  __device__ static void unlock_all(const TableDev& tv, const Tile<T>& tile, const Cands& c, bool wrote) {
+    if (wrote) wait_mem();
+    for (uint32_t i = 0; i < c.n; ++i) release(tv, c.s[i], tile);
+  }
+
+  __device__ static __forceinline__ uint64_t next_rand(uint64_t& st) {
+    uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+
+  // Moves key x from slot j of bucket `from` to an empty slot of bucket `to`
+  // (two of x's buckets) under both locks; false if a lock was busy or the
+  // buckets changed since the path was found.
+  __device__ static bool cuckoo_move(const TableDev& tv, const Tile<T>& tile, uint32_t from, uint32_t j, K x,
+                                     uint32_t to) {
+    const uint32_t lo = from < to ? from : to, hi = from < to ? to : from;
+    if (!try_lock(tv.locks, lo, tile)) return false;
+    if (!try_lock(tv.locks, hi, tile)) {
+      release(tv, lo, tile);
+      return false;
+    }
+    K k, v;
+    load_slot(tv, (uint64_t)from * B + j, k, v);
+    const BucketScan<K> r = scan<false>(tv, tile, to, x, 0u);
+    const bool ok = k == x && r.free >= 0;
+    if (ok && tile.leader()) {
+      publish(tv, (uint64_t)to * B + r.free, x, v);
+      wait_mem();  // the copy is complete before the original goes
+      st(key_ptr(tv, (uint64_t)from * B + j), EMPTY);
+    }
+    if (ok) wait_mem();
+    release(tv, hi, tile);
+    release(tv, lo, tile);
+    return ok;
+  }
+
+  // One attempt at freeing a slot in one of c's buckets (see above).
+  __device__ static void cuckoo_make_room(const TableDev& tv, const Tile<T>& tile, const Cands& c, uint64_t& rng) {
+    uint32_t pb[CUCKOO_MAX_PATH + 1], pj[CUCKOO_MAX_PATH];
+    K px[CUCKOO_MAX_PATH];
+    uint32_t b = c.c[next_rand(rng) % c.n];
+    int len = -1;
+    for (int d = 0; d < CUCKOO_MAX_PATH; ++d) {
+      pb[d] = b;
+      const uint32_t j = (uint32_t)(next_rand(rng) % B);
+      K x, v;
+      load_slot(tv, (uint64_t)b * B + j, x, v);
+      if (x >= Keys<K>::FIRST_INVALID) return;  // a free (or changing) slot: retry the insert
+      const Cands cx = cuckoo_cands(home_of(tv, x));
+      if (cx.n < 2) return;
+      uint32_t alt = cx.c[next_rand(rng) % cx.n];
+      if (alt == b) alt = cx.c[(alt == cx.c[0]) ? 1 : 0];
+      pj[d] = j;
+      px[d] = x;
+      const BucketScan<K> r = scan<false>(tv, tile, alt, x, 0u);
+      if (r.free >= 0) {
+        pb[d + 1] = alt;
+        len = d + 1;
+        break;
+      }
+      b = alt;
+    }
+    for (int i = len - 1; i >= 0; --i)
+      if (!cuckoo_move(tv, tile, pb[i], pj[i], px[i], pb[i + 1])) return;
+  }
+
+  __device__ static uint8_t cuckoo_upsert(const TableDev& tv, const Tile<T>& tile, K key, K val, int combine) {
+    const Cands c = cuckoo_cands(home_of(tv, key));
+    uint64_t rng = (uint64_t)key ^ 0x2545F4914F6CDD1Dull;
+    uint8_t status = ST_FULL;
+    bool done = false;
+    uint32_t rounds = 0, attempt = 0;
+    Backoff bo;
+    while (!done) {
+      bo.pause();
+      const bool go = (attempt & 255) == 0 || all_look_free(tv, tile, c);
+      ++attempt;
+      int outcome = 0;  // 0: locks busy, 1: finished, 2: all buckets full
+      if (go && try_lock_all(tv, tile, c)) {
+        int64_t free_slot = -1;
+        bool wrote = false;
+        for (uint32_t i = 0; i < c.n && outcome == 0; ++i) {
+          const BucketScan<K> r = scan<true>(tv, tile, c.c[i], key, 0u);
+          if (r.hit >= 0) {
+            combine_at(tv, tile, (uint64_t)c.c[i] * B + r.hit, val, combine);
+            wrote = combine != C_KEEP;
+            status = ST_EXISTED;
+            outcome = 1;
+          } else if (free_slot < 0 && r.free >= 0) {
+            free_slot = (int64_t)c.c[i] * B + r.free;
+          }
+        }
+        if (outcome == 0) {
+          if (free_slot >= 0) {
+            if (tile.leader()) publish(tv, (uint64_t)free_slot, key, val);
+            wrote = true;
+            status = ST_DONE;
+            outcome = 1;
+          } else {
+            outcome = 2;
+          }
+        }
+        unlock_all(tv, tile, c, wrote);
+      }
+      if (outcome == 1) {
+        done = true;
+      } else if (outcome == 2) {
+        if (++rounds > CUCKOO_MAX_ROUNDS) done = true;  // status stays FULL
+        else cuckoo_make_room(tv, tile, c, rng);
+      } else {
+        bo.grow();
+      }
+    }
+    return status;
+  }
+
+  // Locked search (cuckoo queries and erases): the key's slot or -1.
+  __device__ static uint8_t cuckoo_locked(const TableDev& tv, const Tile<T>& tile, K key, bool erase, K* out) {
+    const Cands c = cuckoo_cands(home_of(tv, key));
+    Backoff bo;
+    uint32_t attempt = 0;
+    while (true) {
+      bo.pause();
+      const bool go = (attempt & 255) == 0 || all_look_free(tv, tile, c);
+      ++attempt;
+      if (go && try_lock_all(tv, tile, c)) {
+        uint8_t st_ = ST_MISS;
+        for (uint32_t i = 0; i < c.n; ++i) {
+          const BucketScan<K> r = scan<true>(tv, tile, c.c[i], key, 0u);
+          if (r.hit >= 0) {
+            if (erase) remove(tv, tile, (uint64_t)c.c[i] * B + r.hit, 0u);
+            else *out = r.val;
+            st_ = ST_DONE;
+            break;
+          }
+        }
+        unlock_all(tv, tile, c, erase && st_ == ST_DONE);
+        return st_;
+      }
+      bo.grow();
+    }
   }
 
   // ---------------------------------------------------------------- chaining
@@ -604,6 +822,7 @@ struct Ops {
   __device__ static uint8_t upsert(const TableDev& tv, const Tile<T>& tile, K key, K val,
                                    int combine) {
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
+    if constexpr (C::CUCKOO) return cuckoo_upsert(tv, tile, key, val, combine);
     const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
     uint8_t status = ST_FULL;
@@ -780,6 +999,7 @@ struct Ops {
   __device__ static uint8_t query(const TableDev& tv, const Tile<T>& tile, K key, K* out) {
     *out = 0;
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
+    if constexpr (C::CUCKOO) return cuckoo_locked(tv, tile, key, false, out);
     const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
     return find(tv, tile, h, key, tag, out) >= 0 ? ST_DONE : ST_MISS;
@@ -789,6 +1009,10 @@ struct Ops {
   // removed, ST_MISS if absent.
   __device__ static uint8_t erase(const TableDev& tv, const Tile<T>& tile, K key) {
     if (key >= Keys<K>::FIRST_INVALID || tv.no_erase) return ST_INVALID;
+    if constexpr (C::CUCKOO) {
+      K unused;
+      return cuckoo_locked(tv, tile, key, true, &unused);
+    }
     const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
     if constexpr (!C::DOUBLE) {

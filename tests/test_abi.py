@@ -79,7 +79,7 @@ def test_iceberg_has_a_bucket_in_each_yard():
 def test_bad_arguments_rejected_on_host():
     L = hw.lib()
     assert _bytes(0, 0)[0] == -1                      # capacity 0
-    assert _bytes(1024, 7)[0] == -1                   # no such design
+    assert _bytes(1024, 8)[0] == -1                   # no such design
     assert _bytes(1024, 0, kv_bits=16)[0] == -1       # key width
     assert _bytes(1024, 0, bucket=8, tile=16)[0] == -4  # no kernel instance
     assert L.hwave_table_bytes(1024, 0, None, None) == -1
@@ -98,7 +98,7 @@ def test_paper_default_configurations():
     tile 4; power-of-two-choice bucket 32 / tile 8; its metadata variant 32 / 4;
     iceberg bucket 32 / tile 8; its metadata variant 32 / 4."""
     L = hw.lib()
-    expect = {0: (8, 8), 1: (32, 4), 2: (32, 8), 3: (32, 4), 4: (32, 8), 5: (32, 4), 6: (7, 8)}
+    expect = {0: (8, 8), 1: (32, 4), 2: (32, 8), 3: (32, 4), 4: (32, 8), 5: (32, 4), 6: (7, 8), 7: (8, 4)}
     for d, (b, t) in expect.items():
         c = hw._Config()
         assert L.hwave_config_default(d, ctypes.byref(c)) == 0

@@ -16,11 +16,12 @@ from gpu_util import dev, host, image, u8
 pytestmark = pytest.mark.gpu
 
 ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M,
-           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M}
+           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M, "CUCKOO": oracle.CUCKOO}
 OPQ, OPI, OPE = 0, 1, 3
 
 
-@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING"])
+@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING",
+                                    "CUCKOO"])
 def test_aging_against_oracle(design):
     cap = 1 << 16
     plan = w.aging_plan(cap, iters=150, config_id=6)

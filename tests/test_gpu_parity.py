@@ -19,7 +19,7 @@ from gpu_util import dev, host, image, per_key_counts, u8
 pytestmark = pytest.mark.gpu
 
 ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M,
-           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M}
+           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M, "CUCKOO": oracle.CUCKOO}
 ALL = ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M"]
 
 
@@ -97,6 +97,7 @@ CASES = [
     ("DOUBLE", 32, 16, 8), ("DOUBLE_M", 32, 32, 4), ("P2", 32, 32, 8), ("P2_M", 32, 32, 4),
     ("P2_M", 32, 32, 32), ("DOUBLE", 32, 64, 32), ("ICEBERG", 32, 32, 8), ("ICEBERG", 32, 32, 4),
     ("ICEBERG_M", 32, 32, 4), ("ICEBERG_M", 32, 32, 8),
+    ("CUCKOO", 64, 8, 4), ("CUCKOO", 64, 8, 8), ("CUCKOO", 64, 16, 8),
 ]
 
 
@@ -174,7 +175,7 @@ def test_all_ops_against_oracle(design, bits, bucket, tile):
 
 # ------------------------------------------------------------------ mixed batches (config 3 shape)
 
-@pytest.mark.parametrize("design", ["DOUBLE_M", "P2_M", "DOUBLE", "P2", "ICEBERG_M", "ICEBERG"])
+@pytest.mark.parametrize("design", ["DOUBLE_M", "P2_M", "DOUBLE", "P2", "ICEBERG_M", "ICEBERG", "CUCKOO"])
 def test_mixed_batches_against_oracle(design):
     """Preload a 2^k-key universe to load 0.5, then mixed batches (50% query, 30% SUM
     upsert, 20% erase, Zipf 0.99 keys; erase and upsert keys disjoint, queries avoid
@@ -385,3 +386,32 @@ def test_phased_variant_not_accepted_by_multi():
     t = hw.Table(1 << 12, "P2_M", flags=hw.F_BSP)
     with pytest.raises(hw.HashWaveError):
         hw.Multi([t])
+
+
+# ------------------------------------------------------------------ cuckoo at high load
+
+@pytest.mark.parametrize("tile", [4, 8])
+def test_cuckoo_high_load_moves_keys(tile):
+    """Three-way cuckoo filled to 0.93 in two batches: the second batch finds most
+    candidate buckets full and has to move keys along displacement paths; every
+    insert still succeeds, every key is found with its value, the layout holds
+    (each key in one of its three buckets), and erase then re-query agree with
+    the oracle."""
+    cap = 1 << 16
+    t = hw.Table(cap, "CUCKOO", tile=tile)
+    om = oracle.OracleMap()
+    keys = w.distinct_keys(w.stream_seed(140, tile), int(0.93 * cap))
+    for part in (keys[: int(0.8 * cap)], keys[int(0.8 * cap):]):
+        st = u8(t.insert(dev(part), dev(w.value_of(part))))
+        assert np.array_equal(st, om.insert(part, w.value_of(part)))
+    rep = check_layout(t)
+    assert rep["in_alternate"] > 0
+    f, v = t.query(dev(keys))
+    assert (u8(f) == hw.ST_DONE).all() and np.array_equal(host(v), w.value_of(keys))
+    ke = keys[::3]
+    assert np.array_equal(u8(t.erase(dev(ke))), om.erase(ke))
+    f, v = t.query(dev(keys))
+    of, ov = om.query(keys)
+    assert np.array_equal(u8(f), of) and np.array_equal(host(v), ov)
+    check_dump(t, om)
+    check_layout(t)
