@@ -9,7 +9,8 @@ One step = one pass of the whole hot path over one synthetic batch set:
   16 mixed batches of 2^20 ops (50% query / 30% SUM upsert / 20% erase, Zipf 0.99
   over the inserted keys).
 The same step is then run, verified and timed on the other designs (double
-hashing, power-of-two-choice and iceberg, with and without tags, and chaining) for comparison,
+hashing, power-of-two-choice and iceberg, with and without tags, chaining and
+cuckoo hashing) for comparison,
 followed by the aging (churn) benchmark of Section 6.5 on every design.
 Inputs are resident in HBM before timing.  `value` = all operations of K steps /
 wall time of K steps.  Per-kernel durations come from HIP events on the stream
@@ -278,7 +279,7 @@ def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
                     "step_gops": round(step.ops_per_step() * steps / wall / 1e9, 4), "phase_gops": rates}
         step.t = None
         torch.cuda.empty_cache()
-        if des != "CHAINING":  # no phased variant: its lock-free reads already take no lock
+        if des not in ("CHAINING", "CUCKOO"):  # phased variants: the other designs only
             out[des]["phased"] = bench_phased(step, d, des, rates)
         log("design %s: %.2f Gops/s per step (insert_0.9 %.2f, query+ %.2f, query- %.2f)"
             % (des, out[des]["step_gops"], rates["insert_0.9"], rates["query_pos"], rates["query_neg"]))
@@ -663,7 +664,7 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the serving section")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-aging", action="store_true", help="skip the aging (churn) section")
-    ap.add_argument("--compare", default="DOUBLE,DOUBLE_M,P2,ICEBERG,ICEBERG_M,CHAINING",
+    ap.add_argument("--compare", default="DOUBLE,DOUBLE_M,P2,ICEBERG,ICEBERG_M,CHAINING,CUCKOO",
                     help="other designs to run the same step on ('' to skip)")
     ap.add_argument("--cpu-log2cap", type=int, default=24)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -755,7 +756,7 @@ def main():
 
     aging = None
     if not args.no_aging:
-        aging = bench_aging(["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING"])
+        aging = bench_aging(["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING", "CUCKOO"])
 
     batched = None
     if not args.no_batched:
