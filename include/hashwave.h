@@ -112,7 +112,17 @@ enum {
                               of a window's duplicates reports the table's
                               status and the others EXISTED (or its FULL).
                               For skewed batches, whose hot keys would
-                              otherwise serialise on one lock or value word   */
+                              otherwise serialise on one lock or value word.
+                              With HWAVE_F_NO_ERASE too (not CUCKOO, not BSP)
+                              the table also holds 64 KiB of hot-key
+                              accumulators: a present key met more than once
+                              in a window is combined into one of 32 striped
+                              accumulators instead of its value word, and a
+                              second kernel on the same stream folds them
+                              into the table before the call's work is
+                              complete.  Calls that write such a table must
+                              then run one at a time (stream-ordered); queries
+                              may overlap them as with any write            */
 };
 
 /* Table configuration.  Zero fields take the design's defaults (the

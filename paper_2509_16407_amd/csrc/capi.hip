@@ -41,9 +41,25 @@ uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   uint64_t nb, capacity, units, pool;
-  uint64_t off_tags, off_locks, off_ctrl, off_pool_ctr, total;
+  uint64_t off_tags, off_locks, off_ctrl, off_pool_ctr, off_hot, total;
   uint64_t n_lock_words;
 };
+
+// Hot-key accumulators (hw_ops.hpp, HOT_ROWS): tables that merge duplicates and
+// never erase, except cuckoo (it moves keys) and the phased variant.
+bool has_hot(hwave_design design, const hwave_config& c) {
+  const uint32_t f = c.flags;
+  return (f & HWAVE_F_AGGREGATE) && (f & HWAVE_F_NO_ERASE) && !(f & HWAVE_F_BSP) && design != HWAVE_CUCKOO;
+}
+
+// Appends the hot-key accumulators (tags, then accumulators) at `off` if the
+// table has them; they lie in the zero-filled part of the table.
+uint64_t place_hot(hwave_design design, const hwave_config& c, uint64_t off, Layout* L) {
+  L->off_hot = 0;
+  if (!has_hot(design, c)) return off;
+  L->off_hot = off;
+  return off + round_up((uint64_t)HOT_N * 16, ALIGN);
+}
 
 bool design_tags(int d) { return d == HWAVE_DOUBLE_M || d == HWAVE_P2_M || d == HWAVE_ICEBERG_M; }
 bool design_iceberg(int d) { return d == HWAVE_ICEBERG || d == HWAVE_ICEBERG_M; }
@@ -135,7 +151,7 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
     off += ALIGN;
     L->off_pool_ctr = off;  // POOL_PARTS allocation counters, one per 128-byte line
     off += round_up((uint64_t)POOL_PARTS * POOL_CTR_STRIDE * 4, ALIGN);
-    L->total = off;
+    L->total = place_hot(design, c, off, L);
     return HWAVE_OK;
   }
   const uint64_t B = c.bucket_slots;
@@ -156,7 +172,7 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
   off += round_up(L->n_lock_words * 4, ALIGN);
   L->off_ctrl = off;
   off += ALIGN;
-  L->total = off;
+  L->total = place_hot(design, c, off, L);
   return HWAVE_OK;
 }
 
@@ -254,6 +270,8 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   tv.shortcut = (c.flags & HWAVE_F_NO_SHORTCUT) ? 0u : 1u;
   tv.no_erase = (c.flags & HWAVE_F_NO_ERASE) ? 1u : 0u;
   tv.aggregate = (c.flags & HWAVE_F_AGGREGATE) ? 1u : 0u;
+  tv.hot_tag = L.off_hot ? (uint64_t*)(b + L.off_hot) : nullptr;
+  tv.hot_acc = L.off_hot ? tv.hot_tag + HOT_N : nullptr;
   t->la.max_blocks = max_blocks_for(dev);
   return hwave_clear(t, stream);
 }
@@ -495,6 +513,8 @@ struct hwave_multi {
   std::vector<uint64_t> table_bytes;  // footprint per table (queue placement)
   MultiTable* d_tables = nullptr;
   uint32_t* d_heads = nullptr;
+  uint32_t* d_hot = nullptr;  // indices of the tables with hot-key accumulators the kernel fills
+  uint32_t n_hot = 0;
   MultiItem* d_items = nullptr;
   size_t items_cap = 0;
   MultiItem* h_stage = nullptr;  // pinned staging of the item list
@@ -569,7 +589,16 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
   m->kv_bits = kv;
   m->n_tables = n_tables;
   for (uint32_t i = 0; i < n_tables; i++) m->table_bytes.push_back(tables[i]->bytes);
+  // only the 64-bit menu carries the merging path that fills the accumulators
+  std::vector<uint32_t> hot;
+  for (uint32_t i = 0; i < n_tables; i++)
+    if (kv == 64 && tables[i]->la.tv.hot_tag) hot.push_back(i);
+  m->n_hot = (uint32_t)hot.size();
   hipError_t e = hipMalloc(&m->d_tables, n_tables * sizeof(MultiTable));
+  if (e == hipSuccess && m->n_hot) e = hipMalloc(&m->d_hot, m->n_hot * sizeof(uint32_t));
+  if (e == hipSuccess && m->n_hot)
+    e = hipMemcpyAsync(m->d_hot, hot.data(), m->n_hot * sizeof(uint32_t), hipMemcpyHostToDevice,
+                       (hipStream_t)stream);
   if (e == hipSuccess) e = hipMalloc(&m->d_heads, NQ * HEAD_STRIDE * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemcpyAsync(m->d_tables, h.data(), n_tables * sizeof(MultiTable),
                                           hipMemcpyHostToDevice, (hipStream_t)stream);
@@ -592,6 +621,7 @@ int hwave_multi_destroy(hwave_multi* m) {
   (void)hipDeviceSynchronize();
   if (m->d_tables) (void)hipFree(m->d_tables);
   if (m->d_heads) (void)hipFree(m->d_heads);
+  if (m->d_hot) (void)hipFree(m->d_hot);
   if (m->d_items) (void)hipFree(m->d_items);
   if (m->h_stage) (void)hipHostFree(m->h_stage);
   if (m->staged) (void)hipEventDestroy(m->staged);
@@ -609,6 +639,7 @@ int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items,
   std::vector<std::vector<MultiItem>> per_q(NQ);
   uint32_t rr = 0;
   uint64_t total_ops = 0;
+  bool merging = false;  // an upsert whose combine merges (it may fill hot-key accumulators)
   for (uint32_t i = 0; i < n_items; i++)
     if (h_items[i].end > h_items[i].begin) total_ops += h_items[i].end - h_items[i].begin;
   const uint64_t waves = (uint64_t)m->grid * (BLOCK / 64);
@@ -621,6 +652,8 @@ int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items,
     const int op = (int)(it.op & 0xFF);
     if (op > HWAVE_OP_ERASE || ((it.op >> 8) & 0xFF) > HWAVE_MAX) return HWAVE_EINVAL;
     if ((op == HWAVE_OP_INSERT || op == HWAVE_OP_UPSERT) && !d_vals) return HWAVE_EINVAL;
+    const int comb = (int)((it.op >> 8) & 0xFF);
+    if (op == HWAVE_OP_UPSERT && (comb == HWAVE_SUM || comb == HWAVE_MIN || comb == HWAVE_MAX)) merging = true;
     const bool small = m->table_bytes[it.table] <= L2_RESIDENT_BYTES;
     for (uint64_t b = it.begin; b < it.end; b += chunk) {
       MultiItem c;
@@ -658,6 +691,7 @@ int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items,
   m->staged_pending = true;
   e = launch_multi(m->kv_bits, m->grid, m->d_tables, m->d_items, qs, m->d_heads, d_keys,
                    d_vals ? d_vals : d_keys, d_vals_out, d_status, s);
+  if (e == hipSuccess && merging) e = launch_multi_hot_flush(m->kv_bits, m->d_tables, m->d_hot, m->n_hot, s);
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
 }
 

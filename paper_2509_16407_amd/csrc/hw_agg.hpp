@@ -10,7 +10,9 @@
 // ONE table operation per distinct key, and gives every operation a status that
 // matches one serialisation of the window: each key's first operation goes
 // first, the others follow it.  Those report EXISTED (or the first one's FULL).
-// REPLACE is never merged: its result depends on the order.
+// REPLACE is never merged: its result depends on the order.  A key met more than
+// once in a window is likely hot; in tables with hot-key accumulators its one
+// operation combines into those (Ops::hot_add), in the row the caller chose.
 //
 // Everything here is per wave: the LDS region belongs to one wave and the
 // phases are separated by wave-level fences only, so waves of a block may run
@@ -31,7 +33,7 @@ struct AggLds {
   K val[AGG_NE];
   uint16_t lead[AGG_NE];  // window index of the entry's first operation
   uint16_t list[AGG_NE];  // compacted indices of the used entries
-  uint8_t stat[AGG_NE];   // table status of the entry's one operation
+  uint8_t stat[AGG_NE];   // 1 if the entry merged several operations; then its table status
 };
 
 __device__ __forceinline__ bool agg_merges(int combine) {
@@ -52,17 +54,19 @@ __device__ __forceinline__ K agg_identity(int combine) {
 
 // Applies ops [i0, i0 + n) of `keys`/`vals` (n <= AGG_WIN, the same combine for
 // all) to the table through the merge table L.  Writes status[i] if non-null.
-// Called by all 64 lanes of the wave together.
+// `row` < HOT_ROWS picks the hot-key accumulator row.  Called by all 64 lanes of
+// the wave together.
 template <class C>
 __device__ void agg_window(const TableDev& tv, AggLds<typename C::K>& L, const typename C::K* __restrict__ keys,
                            const typename C::K* __restrict__ vals, uint64_t i0, uint32_t n, int combine,
-                           uint8_t* __restrict__ status) {
+                           uint8_t* __restrict__ status, uint32_t row) {
   using K = typename C::K;
   const uint32_t lane = __lane_id();
   const K ident = agg_identity<K>(combine);
   for (uint32_t e = lane; e < AGG_NE; e += 64) {
     L.key[e] = Keys<K>::EMPTY;
     L.val[e] = ident;
+    L.stat[e] = 0;
   }
   wave_sync();
   // Phase 1: find or create each operation's entry and merge its value.
@@ -88,7 +92,10 @@ __device__ void agg_window(const TableDev& tv, AggLds<typename C::K>& L, const t
           break;
         }
       }
-      if (cur == k) break;
+      if (cur == k) {
+        L.stat[h] = 1;  // a second operation on the key
+        break;
+      }
       h = (h + 1) & (AGG_NE - 1);
     }
     ent[r] = (int32_t)h;
@@ -109,7 +116,7 @@ __device__ void agg_window(const TableDev& tv, AggLds<typename C::K>& L, const t
   const Tile<C::T> tile;
   for (uint32_t u = lane / C::T; u < n_u; u += 64 / C::T) {
     const uint32_t e = L.list[u];
-    const uint8_t st = Ops<C>::upsert(tv, tile, L.key[e], L.val[e], combine);
+    const uint8_t st = Ops<C>::upsert(tv, tile, L.key[e], L.val[e], combine, L.stat[e] ? (int)row : -1);
     if (tile.leader()) L.stat[e] = st;
   }
   wave_sync();

@@ -41,8 +41,31 @@ k_upsert_agg(TableDev tv, const typename C::K* __restrict__ keys, const typename
   const uint64_t n_waves = (uint64_t)gridDim.x * (BLOCK / 64);
   for (uint64_t i0 = wave * AGG_WIN; i0 < n; i0 += n_waves * AGG_WIN) {
     const uint64_t left = n - i0;
-    agg_window<C>(tv, L, keys, vals, i0, (uint32_t)(left < AGG_WIN ? left : AGG_WIN), combine, status);
+    agg_window<C>(tv, L, keys, vals, i0, (uint32_t)(left < AGG_WIN ? left : AGG_WIN), combine, status,
+                  (uint32_t)(wave % HOT_ROWS));
   }
+}
+
+// Folds hot-key accumulator i into its slot's value word and frees the entry.
+// Runs after the launch that filled the accumulators, in stream order.
+template <typename K>
+__device__ __forceinline__ void hot_flush_entry(const TableDev& tv, uint32_t i) {
+  const uint64_t tagged = ld(tv.hot_tag + i);
+  if (tagged == 0) return;
+  const uint64_t a = ld(tv.hot_acc + i);
+  K* vp = (K*)tv.slots + 2 * ((tagged & ((1ull << 56) - 1)) - 1) + 1;
+  const int combine = (int)(tagged >> 56);
+  if (combine == C_SUM) __hip_atomic_fetch_add(vp, (K)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else if (combine == C_MAX) __hip_atomic_fetch_max(vp, (K)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else __hip_atomic_fetch_min(vp, (K)~(K)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  st(tv.hot_acc + i, (uint64_t)0);
+  st(tv.hot_tag + i, (uint64_t)0);
+}
+
+template <typename K>
+__global__ void __launch_bounds__(BLOCK) k_hot_flush(TableDev tv) {
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i < HOT_N) hot_flush_entry<K>(tv, i);
 }
 
 template <class C>
@@ -143,6 +166,8 @@ struct Launch {
       // one wave per window of AGG_WIN operations
       hipLaunchKernelGGL((k_upsert_agg<C>), dim3(grid_for((n + AGG_WIN - 1) / AGG_WIN, 64, a.max_blocks)),
                          dim3(BLOCK), 0, s, a.tv, (const K*)keys, (const K*)vals, n, combine, status);
+      if (a.tv.hot_tag && combine != C_KEEP)
+        hipLaunchKernelGGL((k_hot_flush<K>), dim3(HOT_N / BLOCK), dim3(BLOCK), 0, s, a.tv);
     } else {
       hipLaunchKernelGGL((k_upsert<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
                          (const K*)keys, (const K*)vals, n, combine, status);

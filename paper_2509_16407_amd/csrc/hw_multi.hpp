@@ -68,7 +68,8 @@ __device__ __forceinline__ void run_item(const TableDev& tv, const MultiItem& m,
     if ((op == OP_INSERT || op == OP_UPSERT) && tv.aggregate && agg_merges(combine)) {
       for (uint64_t i0 = m.begin; i0 < m.end; i0 += AGG_WIN) {
         const uint64_t left = m.end - i0;
-        agg_window<C>(tv, agg, keys, vals, i0, (uint32_t)(left < AGG_WIN ? left : AGG_WIN), combine, status);
+        agg_window<C>(tv, agg, keys, vals, i0, (uint32_t)(left < AGG_WIN ? left : AGG_WIN), combine, status,
+                      (blockIdx.x * (BLOCK / 64) + threadIdx.x / 64) % HOT_ROWS);
       }
       return;
     }
@@ -155,6 +156,10 @@ hipError_t launch_multi_clear(unsigned grid, const MultiTable* tables, uint32_t 
 hipError_t launch_multi(int kv_bits, unsigned grid, const MultiTable* tables, const MultiItem* items,
                         const MultiQueues& qs, uint32_t* heads, const void* keys, const void* vals, void* out,
                         uint8_t* status, hipStream_t s);
+// Folds the hot-key accumulators of the n_hot tables listed in `hot` (device
+// array of table indices); a no-op for n_hot == 0.
+hipError_t launch_multi_hot_flush(int kv_bits, const MultiTable* tables, const uint32_t* hot, uint32_t n_hot,
+                                  hipStream_t s);
 int multi_menu_index(int kv_bits, int design, int bucket, int tile);
 
 }  // namespace hw

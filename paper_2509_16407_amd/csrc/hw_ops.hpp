@@ -52,6 +52,18 @@ enum : int { OP_QUERY = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_ERASE = 3 };
 constexpr uint32_t POOL_PARTS = 1024;
 constexpr uint32_t POOL_CTR_STRIDE = 32;
 
+// Striped accumulators of hot keys (tables that merge duplicates and never
+// erase).  A key that a merge window saw more than once is combined into one
+// of HOT_ROWS rows (chosen by the wave) of HOT_M entries, keyed by the key's
+// slot, instead of into its value word; a flush after the launch folds every
+// entry into the table.  A hot key thus costs one atomic per row and launch at
+// its value word instead of one per window.  Entry: tag word (slot + 1, the
+// combine in bits 56..63; 0 = free) and accumulator word, in two arrays.
+constexpr uint32_t HOT_ROWS = 32;
+constexpr uint32_t HOT_M = 128;
+constexpr uint32_t HOT_N = HOT_ROWS * HOT_M;
+constexpr int HOT_PROBE = 8;
+
 enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, D_ICEBERG_M = 5, D_CHAINING = 6,
              D_CUCKOO = 7 };
 
@@ -70,6 +82,8 @@ struct TableDev {
   uint32_t shortcut;     // power-of-two-choice shortcut enabled
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
   uint32_t aggregate;    // merge duplicate keys of a write batch first (hw_agg.hpp)
+  uint64_t* hot_tag;     // HOT_N entry tags, or null (see HOT_ROWS)
+  uint64_t* hot_acc;     // HOT_N accumulators
 };
 
 // BSP_: the phased (bulk-synchronous) variant used to measure what concurrency
@@ -808,6 +822,35 @@ struct Ops {
     }
   }
 
+  // Combines val into the hot-key accumulator of slot s in row `row` (leader lane
+  // only): the entry whose tag is (s + 1, combine), claimed by a compare-and-swap
+  // if free; after HOT_PROBE taken entries, into the value word directly.  An
+  // accumulator starts at 0, which every combine accepts as its identity: sums
+  // add, maxima keep the largest value, minima keep the largest complement.
+  __device__ static void hot_add(const TableDev& tv, uint64_t s, K val, int combine, uint32_t row) {
+    const uint64_t tagged = (s + 1) | ((uint64_t)combine << 56);
+    uint64_t* trow = tv.hot_tag + (uint64_t)row * HOT_M;
+    uint64_t* arow = tv.hot_acc + (uint64_t)row * HOT_M;
+    uint32_t j = (uint32_t)fmix64(s);
+    for (int p = 0; p < HOT_PROBE; ++p, ++j) {
+      const uint32_t i = j & (HOT_M - 1);
+      uint64_t cur = ld(trow + i);
+      if (cur == 0) cur = cas(trow + i, (uint64_t)0, tagged);  // 0: claimed
+      if (cur != 0 && cur != tagged) continue;
+      if (combine == C_SUM)
+        __hip_atomic_fetch_add(arow + i, (uint64_t)val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else if (combine == C_MAX)
+        __hip_atomic_fetch_max(arow + i, (uint64_t)val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        __hip_atomic_fetch_max(arow + i, (uint64_t)(K)~val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    K* vp = val_ptr(tv, s);
+    if (combine == C_SUM) __hip_atomic_fetch_add(vp, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if (combine == C_MAX) __hip_atomic_fetch_max(vp, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_fetch_min(vp, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
   // Upsert: lock primary, find or insert, unlock.  Status per hwave.h.
   //
   // Waiting for the lock: after a failed attempt a tile backs off, then polls
@@ -818,9 +861,12 @@ struct Ops {
   // key is combined in place without the lock (as the paper does for sparse
   // tensor contraction, Section 6.7), and a waiting tile looks for its key
   // again before each attempt: once another tile has inserted it, the waiter
-  // finishes without the lock.
+  // finishes without the lock.  hot_row >= 0 (a key that a merge window met more
+  // than once): in a table with hot-key accumulators, where a present key's slot
+  // is fixed for good, a SUM/MIN/MAX combine of a present key goes to row hot_row
+  // of the accumulators instead of the value word.
   __device__ static uint8_t upsert(const TableDev& tv, const Tile<T>& tile, K key, K val,
-                                   int combine) {
+                                   int combine, int hot_row = -1) {
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
     if constexpr (C::CUCKOO) return cuckoo_upsert(tv, tile, key, val, combine);
     const Home h = home_of(tv, key);
@@ -848,7 +894,11 @@ struct Ops {
         K cur;
         const int64_t s = find(tv, tile, h, key, tag, &cur);
         if (s >= 0) {
-          combine_at(tv, tile, (uint64_t)s, val, combine);
+          if (hot_row >= 0 && tv.hot_tag && (combine == C_SUM || combine == C_MIN || combine == C_MAX)) {
+            if (tile.leader()) hot_add(tv, (uint64_t)s, val, combine, (uint32_t)hot_row);
+          } else {
+            combine_at(tv, tile, (uint64_t)s, val, combine);
+          }
           status = ST_EXISTED;
           pending = false;
           continue;

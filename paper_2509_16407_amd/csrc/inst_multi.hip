@@ -20,6 +20,24 @@ hipError_t launch_multi(int kv_bits, unsigned grid, const MultiTable* tables, co
   return hipGetLastError();
 }
 
+// Folds the hot-key accumulators of tables hot[0 .. gridDim.y) (hw_launch.hpp).
+template <typename K>
+__global__ void __launch_bounds__(BLOCK)
+k_multi_hot_flush(const MultiTable* __restrict__ tables, const uint32_t* __restrict__ hot) {
+  const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i < HOT_N) hot_flush_entry<K>(tables[hot[blockIdx.y]].tv, i);
+}
+
+hipError_t launch_multi_hot_flush(int kv_bits, const MultiTable* tables, const uint32_t* hot, uint32_t n_hot,
+                                  hipStream_t s) {
+  if (n_hot == 0) return hipSuccess;
+  if (kv_bits == 64)
+    hipLaunchKernelGGL(k_multi_hot_flush<uint64_t>, dim3(HOT_N / BLOCK, n_hot), dim3(BLOCK), 0, s, tables, hot);
+  else
+    hipLaunchKernelGGL(k_multi_hot_flush<uint32_t>, dim3(HOT_N / BLOCK, n_hot), dim3(BLOCK), 0, s, tables, hot);
+  return hipGetLastError();
+}
+
 // Empties every table of a group: one block per table at a time (grid-stride
 // over tables), 16-byte stores.  Slots and tags are contiguous from `slots`, and
 // locks and control are contiguous from `locks` (the table layout).

@@ -14,6 +14,14 @@
 // the table exactly as a one-request-at-a-time replay in submission order would
 // (plain mode below), and within a request the usual batch semantics apply.
 //
+// Copies: a batch moves every request's arrays with ONE gather kernel (host to
+// device) and ONE scatter kernel (device to host) that read and write the
+// requests' pinned host memory directly, driven by a list of (destination,
+// source, bytes) chunks the worker writes into coherent pinned memory.  One
+// runtime copy per array would cost a dispatch each, and a batch of ~30
+// requests has ~90 arrays.  Requests whose arrays are not device-mapped pinned
+// memory fall back to runtime copies.
+//
 // Plain mode serves one request at a time with the single-table kernels and waits
 // for each to finish: the baseline the batched mode is compared against.
 #include <hip/hip_runtime.h>
@@ -40,13 +48,30 @@ double now_s() { return std::chrono::duration<double>(clk::now().time_since_epoc
 
 struct Req {
   hwave_request r;
+  bool mapped = false;  // every array is device-mapped pinned memory
+  const void* g_keys = nullptr;  // device addresses of the host arrays (mapped)
+  const void* g_vals = nullptr;
+  void* g_vals_out = nullptr;
+  uint8_t* g_status = nullptr;
   uint64_t ticket;
   double t_arrive;
   std::atomic<int> done{0};
   double t_done = 0;
 };
 
+// One piece of a copy: `bytes` from src to dst (device addresses; either may be
+// mapped host memory).
+struct CopyChunk {
+  uint64_t dst, src, bytes;
+};
+constexpr uint64_t CHUNK_BYTES = 64 << 10;
+
 struct Slot {
+  CopyChunk* h_in = nullptr;   // gather list (coherent pinned host memory)
+  CopyChunk* h_out = nullptr;  // scatter list
+  const CopyChunk* g_in = nullptr;  // their device addresses
+  const CopyChunk* g_out = nullptr;
+  uint64_t chunk_cap = 0;
   void* d_keys = nullptr;
   void* d_vals = nullptr;
   void* d_out = nullptr;
@@ -61,6 +86,49 @@ bool writes(uint32_t op) {
   const uint32_t k = op & 0xFF;
   return k == HWAVE_OP_INSERT || k == HWAVE_OP_UPSERT || k == HWAVE_OP_ERASE;
 }
+
+// One block per chunk.  Loads and stores are system-scope (they bypass the GPU
+// caches), so a pinned buffer the host has refilled is never read stale and
+// results reach host memory; 8-byte words when both ends allow, bytes otherwise.
+__global__ void __launch_bounds__(256) k_copy_chunks(const CopyChunk* __restrict__ list) {
+  const CopyChunk c = list[blockIdx.x];
+  const uint64_t n8 = ((c.dst | c.src) & 7) == 0 ? c.bytes / 8 : 0;
+  uint64_t* d8 = (uint64_t*)c.dst;
+  const uint64_t* s8 = (const uint64_t*)c.src;
+#pragma unroll 4
+  for (uint64_t i = threadIdx.x; i < n8; i += 256)
+    __hip_atomic_store(d8 + i, __hip_atomic_load(s8 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  uint8_t* d1 = (uint8_t*)c.dst;
+  const uint8_t* s1 = (const uint8_t*)c.src;
+  for (uint64_t i = n8 * 8 + threadIdx.x; i < c.bytes; i += 256)
+    __hip_atomic_store(d1 + i, __hip_atomic_load(s1 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Device address of pinned host memory at p (null stays null); false if p is
+// not device-mapped host memory.
+bool map_host(const void* p, const void** g) {
+  *g = nullptr;
+  if (!p) return true;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // pageable memory: not an error for the caller
+    return false;
+  }
+  if (a.type != hipMemoryTypeHost || !a.devicePointer) return false;
+  *g = a.devicePointer;
+  return true;
+}
+
+// Appends [src, src + bytes) -> dst to a chunk list, CHUNK_BYTES at a time.
+void add_chunks(CopyChunk* list, uint64_t* n, const void* dst, const void* src, uint64_t bytes) {
+  for (uint64_t o = 0; o < bytes; o += CHUNK_BYTES)
+    list[(*n)++] = CopyChunk{(uint64_t)dst + o, (uint64_t)src + o, bytes - o < CHUNK_BYTES ? bytes - o : CHUNK_BYTES};
+}
+
+// Chunks an array of `bytes` may need.
+uint64_t chunks_for(uint64_t bytes) { return (bytes + CHUNK_BYTES - 1) / CHUNK_BYTES; }
 
 }  // namespace
 
@@ -117,12 +185,20 @@ bool launch_batch(hwave_server* s, Slot& sl) {
   std::unordered_set<uint32_t> writers, readers, blocked;
   std::vector<hwave_item> items;
   uint64_t at = 0;
+  uint64_t n_in = 0, n_out = 0;  // chunk-list entries the admitted requests need
   size_t scanned = 0;
+  const uint32_t kb = s->kb;
   for (auto it = s->pending.begin(); it != s->pending.end() && scanned < 4096; ++scanned) {
     Req* q = *it;
     const uint32_t t = q->r.table;
     const bool w = writes(q->r.op);
-    bool ok = !blocked.count(t) && at + req_ops(q) <= sl.cap_ops && items.size() < s->cfg.max_requests;
+    // each request starts 16 operations aligned, so its arrays in the slot are
+    // 16-byte aligned and the copy kernels move whole words
+    const uint64_t start = (at + 15) / 16 * 16;
+    const uint64_t need_in = q->mapped ? 2 * chunks_for(q->r.n * kb) : 0;
+    const uint64_t need_out = q->mapped ? chunks_for(q->r.n * kb) + chunks_for(q->r.n) : 0;
+    bool ok = !blocked.count(t) && start + req_ops(q) <= sl.cap_ops && items.size() < s->cfg.max_requests &&
+              n_in + need_in <= sl.chunk_cap && n_out + need_out <= sl.chunk_cap;
     if (ok && w) ok = !writers.count(t) && !readers.count(t);
     if (ok && !w) ok = !writers.count(t);
     if (!ok) {
@@ -131,21 +207,33 @@ bool launch_batch(hwave_server* s, Slot& sl) {
       continue;
     }
     (w ? writers : readers).insert(t);
-    items.push_back(hwave_item{t, q->r.op, at, at + q->r.n});
+    items.push_back(hwave_item{t, q->r.op, start, start + q->r.n});
     sl.reqs.push_back(q);
-    at += q->r.n;
+    at = start + q->r.n;
+    n_in += need_in;
+    n_out += need_out;
     it = s->pending.erase(it);
   }
   if (items.empty()) return false;
-  const uint32_t kb = s->kb;
-  // host -> device: each request's keys (and values for writers) into the slot
+  // host -> device: each request's keys (and values for writers) into the slot,
+  // one gather kernel for the mapped requests
+  uint64_t n = 0;
   for (size_t i = 0; i < items.size(); i++) {
     const Req* q = sl.reqs[i];
-    (void)hipMemcpyAsync((uint8_t*)sl.d_keys + items[i].begin * kb, q->r.h_keys, q->r.n * kb,
-                         hipMemcpyHostToDevice, s->s_in);
-    if (writes(q->r.op) && q->r.h_vals)
-      (void)hipMemcpyAsync((uint8_t*)sl.d_vals + items[i].begin * kb, q->r.h_vals, q->r.n * kb,
-                           hipMemcpyHostToDevice, s->s_in);
+    uint8_t* dk = (uint8_t*)sl.d_keys + items[i].begin * kb;
+    uint8_t* dv = (uint8_t*)sl.d_vals + items[i].begin * kb;
+    const bool wv = writes(q->r.op) && q->r.h_vals;
+    if (q->mapped) {
+      add_chunks(sl.h_in, &n, dk, q->g_keys, q->r.n * kb);
+      if (wv) add_chunks(sl.h_in, &n, dv, q->g_vals, q->r.n * kb);
+    } else {
+      (void)hipMemcpyAsync(dk, q->r.h_keys, q->r.n * kb, hipMemcpyHostToDevice, s->s_in);
+      if (wv) (void)hipMemcpyAsync(dv, q->r.h_vals, q->r.n * kb, hipMemcpyHostToDevice, s->s_in);
+    }
+  }
+  if (n) {
+    hipLaunchKernelGGL(k_copy_chunks, dim3((unsigned)n), dim3(256), 0, s->s_in, sl.g_in);
+    if (hipGetLastError() != hipSuccess) fail(s, HWAVE_EDEVICE);
   }
   (void)hipEventRecord(sl.h2d, s->s_in);
   (void)hipStreamWaitEvent(s->s_kern, sl.h2d, 0);
@@ -154,13 +242,23 @@ bool launch_batch(hwave_server* s, Slot& sl) {
   if (rc) fail(s, rc);
   (void)hipEventRecord(sl.kern, s->s_kern);
   (void)hipStreamWaitEvent(s->s_out, sl.kern, 0);
+  n = 0;
   for (size_t i = 0; i < items.size(); i++) {
     const Req* q = sl.reqs[i];
-    if (q->r.h_status)
-      (void)hipMemcpyAsync(q->r.h_status, sl.d_status + items[i].begin, q->r.n, hipMemcpyDeviceToHost, s->s_out);
-    if ((q->r.op & 0xFF) == HWAVE_OP_QUERY && q->r.h_vals_out)
-      (void)hipMemcpyAsync(q->r.h_vals_out, (uint8_t*)sl.d_out + items[i].begin * kb, q->r.n * kb,
-                           hipMemcpyDeviceToHost, s->s_out);
+    const uint8_t* ds = sl.d_status + items[i].begin;
+    const uint8_t* dout = (const uint8_t*)sl.d_out + items[i].begin * kb;
+    const bool wo = (q->r.op & 0xFF) == HWAVE_OP_QUERY && q->r.h_vals_out;
+    if (q->mapped) {
+      if (q->r.h_status) add_chunks(sl.h_out, &n, q->g_status, ds, q->r.n);
+      if (wo) add_chunks(sl.h_out, &n, q->g_vals_out, dout, q->r.n * kb);
+    } else {
+      if (q->r.h_status) (void)hipMemcpyAsync(q->r.h_status, ds, q->r.n, hipMemcpyDeviceToHost, s->s_out);
+      if (wo) (void)hipMemcpyAsync(q->r.h_vals_out, dout, q->r.n * kb, hipMemcpyDeviceToHost, s->s_out);
+    }
+  }
+  if (n) {
+    hipLaunchKernelGGL(k_copy_chunks, dim3((unsigned)n), dim3(256), 0, s->s_out, sl.g_out);
+    if (hipGetLastError() != hipSuccess) fail(s, HWAVE_EDEVICE);
   }
   (void)hipEventRecord(sl.d2h, s->s_out);
   sl.busy = true;
@@ -276,7 +374,15 @@ int hwave_server_create(hwave_server** out, hwave_table* const* tables, uint32_t
   s->slots.resize(nslots);
   for (auto& sl : s->slots) {
     sl.cap_ops = cfg->slot_ops;
-    e = hipMalloc(&sl.d_keys, sl.cap_ops * s->kb);
+    // two arrays per direction, each split into CHUNK_BYTES pieces, plus one
+    // partial piece per array and request
+    sl.chunk_cap = 2 * (chunks_for(sl.cap_ops * s->kb) + s->cfg.max_requests) + 16;
+    const size_t lb = sl.chunk_cap * sizeof(CopyChunk);
+    e = hipHostMalloc((void**)&sl.h_in, lb, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl.h_out, lb, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&sl.g_in, sl.h_in, 0);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&sl.g_out, sl.h_out, 0);
+    if (e == hipSuccess) e = hipMalloc(&sl.d_keys, sl.cap_ops * s->kb);
     if (e == hipSuccess) e = hipMalloc(&sl.d_vals, sl.cap_ops * s->kb);
     if (e == hipSuccess) e = hipMalloc(&sl.d_out, sl.cap_ops * s->kb);
     if (e == hipSuccess) e = hipMalloc((void**)&sl.d_status, sl.cap_ops);
@@ -296,6 +402,12 @@ int hwave_server_submit(hwave_server* s, const hwave_request* r, double arrival_
   if (writes(r->op) && (r->op & 0xFF) != HWAVE_OP_ERASE && !r->h_vals) return HWAVE_EINVAL;
   Req* q = new Req;
   q->r = *r;
+  const void* gv_out = nullptr;
+  const void* g_status = nullptr;
+  q->mapped = map_host(r->h_keys, &q->g_keys) && map_host(r->h_vals, &q->g_vals) &&
+              map_host(r->h_vals_out, &gv_out) && map_host(r->h_status, &g_status);
+  q->g_vals_out = (void*)gv_out;
+  q->g_status = (uint8_t*)g_status;
   q->t_arrive = arrival_s > 0 ? arrival_s : now_s();
   {
     std::lock_guard<std::mutex> g(s->mu);
@@ -382,6 +494,8 @@ int hwave_server_destroy(hwave_server* s) {
   }
   (void)hipDeviceSynchronize();
   for (auto& sl : s->slots) {
+    if (sl.h_in) (void)hipHostFree(sl.h_in);
+    if (sl.h_out) (void)hipHostFree(sl.h_out);
     if (sl.d_keys) (void)hipFree(sl.d_keys);
     if (sl.d_vals) (void)hipFree(sl.d_vals);
     if (sl.d_out) (void)hipFree(sl.d_out);

@@ -27,8 +27,8 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0):
-    c = hw._Config(kv_bits, bucket, tile, 0, 0)
+def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0, flags=0):
+    c = hw._Config(kv_bits, bucket, tile, 0, flags)
     b = ctypes.c_uint64()
     rc = hw.lib().hwave_table_bytes(capacity, design, ctypes.byref(c), ctypes.byref(b))
     return rc, b.value
@@ -57,6 +57,22 @@ def test_chaining_space():
     lock_bytes = -(-((nb + 3) // 4 * 4) // 256) * 256
     assert b == node_bytes + lock_bytes + 256 + 1024 * 128
     assert _bytes(7 * 1000, 6, kv_bits=32)[0] == -4  # 64-bit keys only
+
+
+@pytest.mark.parametrize("design", range(8))
+def test_hot_key_accumulators_only_for_merging_erase_free_tables(design):
+    """32 x 128 entries of two 8-byte words (64 KiB) are added exactly when a
+    table merges duplicates and never erases, and not for cuckoo (it moves keys)
+    or the phased variant."""
+    both = hw.F_AGGREGATE | hw.F_NO_ERASE
+    rc0, plain = _bytes(1 << 16, design)
+    assert rc0 == 0
+    for flags in (hw.F_AGGREGATE, hw.F_NO_ERASE):
+        assert _bytes(1 << 16, design, flags=flags) == (0, plain)
+    extra = 0 if design == 7 else 32 * 128 * 16
+    assert _bytes(1 << 16, design, flags=both) == (0, plain + extra)
+    if design != 7 and design != 6:  # the phased variant: default bucket and tile only
+        assert _bytes(1 << 16, design, flags=both | hw.F_BSP) == (0, plain)
 
 
 def test_capacity_rounds_up_to_power_of_two_buckets():

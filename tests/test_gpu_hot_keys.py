@@ -1,0 +1,117 @@
+"""Hot-key accumulators of tables that merge duplicates and never erase
+(HWAVE_F_AGGREGATE | HWAVE_F_NO_ERASE): a present key met more than once in a
+merge window is combined into striped accumulators, folded into the table by a
+second kernel of the same call.  Every value and per-key status must equal the
+oracle's, for every combine that merges, over consecutive calls (each call's
+fold leaves the accumulators empty for the next), when the accumulators run
+out of entries, and in the multi-table kernel."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_16407_amd as hw
+from paper_2509_16407_amd import workloads as w
+from gpu_util import dev, host, image, per_key_counts, u8
+
+pytestmark = pytest.mark.gpu
+
+ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M,
+           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M}
+COMB = {"sum": oracle.SUM, "keep": oracle.KEEP, "min": oracle.MIN, "max": oracle.MAX}
+FLAGS = hw.F_AGGREGATE | hw.F_NO_ERASE
+
+
+def _check(t, om, bits):
+    k, v = t.export()
+    k, v = host(k, bits), host(v, bits)
+    o = np.argsort(k)
+    ok, ov = om.dump()
+    assert np.array_equal(k[o], ok), "key sets differ"
+    assert np.array_equal(v[o], ov), "values differ"
+    if t.design in ODESIGN:
+        slots, tags, locks = image(t)
+        nv, rep = oracle.layout_check(ODESIGN[t.design], bits, t.num_buckets, t.bucket_slots, slots, tags, locks)
+        assert nv == 0, rep
+
+
+def _counts_match(keys, st, ost):
+    for code in (hw.ST_DONE, hw.ST_EXISTED, hw.ST_FULL, hw.ST_INVALID):
+        assert per_key_counts(keys, st, code) == per_key_counts(keys, ost, code), code
+
+
+def _zipf_batch(seed, uni, n, bits):
+    ks = uni[w.Zipf(len(uni), 0.99).ranks(seed, 0, n)]
+    vs = w.splitmix64(seed + 1, 0, n)
+    if bits == 32:
+        vs &= np.uint64(0xFFFFFFFF)
+    return ks, vs
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+@pytest.mark.parametrize("design", ["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING"])
+def test_hot_keys_every_combine_over_consecutive_calls(design, bits):
+    """Zipf(0.99) batches over 2^13 keys, half of them present first: SUM, MAX,
+    MIN, KEEP and SUM again on one table, each call against the oracle."""
+    if design == "CHAINING" and bits == 32:
+        pytest.skip("chaining is built for 64-bit keys")
+    t = hw.Table(1 << 16, design, kv_bits=bits, flags=FLAGS)
+    om = oracle.OracleMap(key_bits=bits)
+    uni = w.distinct_keys(w.stream_seed(130, bits), 1 << 13, key_bits=bits)
+    pre = uni[::2]
+    pv = w.value_of(pre, bits)
+    st = u8(t.upsert(dev(pre, bits), dev(pv, bits), combine="keep"))
+    assert (st == hw.ST_DONE).all()
+    om.upsert(pre, pv, combine=oracle.KEEP)
+    for rnd, comb in enumerate(["sum", "max", "min", "keep", "sum"]):
+        ks, vs = _zipf_batch(w.stream_seed(131, 10 * bits + rnd), uni, 60000 + 777 * rnd, bits)
+        if comb == "keep":  # which duplicate inserts is racy: equal values per key
+            vs = w.value_of(ks, bits)
+        st = u8(t.upsert(dev(ks, bits), dev(vs, bits), combine=comb))
+        ost = om.upsert(ks, vs, combine=COMB[comb])
+        _counts_match(ks, st, ost)
+        _check(t, om, bits)
+
+
+@pytest.mark.parametrize("design", ["P2_M", "ICEBERG_M"])
+def test_hot_keys_more_than_the_accumulators_hold(design):
+    """Every key twice in a row, 2^17 distinct keys per call: each window marks 64
+    keys hot, far more than the 32 x 128 entries, so most take the direct path;
+    two calls, all present keys, values against the oracle."""
+    t = hw.Table(1 << 19, design, flags=FLAGS)
+    om = oracle.OracleMap()
+    uni = w.distinct_keys(w.stream_seed(132, 0), 1 << 17)
+    pv = w.value_of(uni)
+    t.upsert(dev(uni), dev(pv), combine="keep")
+    om.upsert(uni, pv, combine=oracle.KEEP)
+    for rnd in range(2):
+        ks = np.repeat(uni[w.permutation(w.stream_seed(133, rnd), len(uni))], 2)
+        vs = w.splitmix64(w.stream_seed(134, rnd), 0, len(ks))
+        st = u8(t.upsert(dev(ks), dev(vs), combine="sum"))
+        ost = om.upsert(ks, vs)
+        _counts_match(ks, st, ost)
+        _check(t, om, 64)
+
+
+@pytest.mark.parametrize("comb", ["sum", "min", "max"])
+def test_hot_keys_multi_table(comb):
+    """The multi-table kernel on merging erase-free tables of several menu
+    configurations, Zipf batches per table, two calls, against the oracle."""
+    menu = [("DOUBLE", 8, 8), ("DOUBLE_M", 32, 4), ("P2", 32, 8), ("P2_M", 32, 4), ("P2_M", 64, 8)]
+    tabs = [hw.Table(1 << 15, d, bucket=b, tile=tt, flags=FLAGS) for d, b, tt in menu for _ in range(2)]
+    m = hw.Multi(tabs)
+    oms = [oracle.OracleMap() for _ in tabs]
+    unis = [w.distinct_keys(w.stream_seed(135, i), 5000) for i in range(len(tabs))]
+    for rnd in range(2):
+        parts, vparts, offs = [], [], [0]
+        for i in range(len(tabs)):
+            ks, vs = _zipf_batch(w.stream_seed(136, 100 * rnd + i), unis[i], 9000 + 1311 * i, 64)
+            parts.append(ks)
+            vparts.append(vs)
+            offs.append(offs[-1] + len(ks))
+        ks, vs = np.concatenate(parts), np.concatenate(vparts)
+        st = u8(m.upsert(np.array(offs, np.uint64), dev(ks), dev(vs), combine=comb))
+        for i, t in enumerate(tabs):
+            a, b = offs[i], offs[i + 1]
+            ost = oms[i].upsert(ks[a:b], vs[a:b], combine=COMB[comb])
+            _counts_match(ks[a:b], st[a:b], ost)
+            _check(t, oms[i], 64)

@@ -16,15 +16,20 @@ OPI = hw.OPS["insert"]
 OPU = hw.OPS["upsert"] | (hw.COMBINES["sum"] << 8)
 
 
+def _host(a, bits=64, pinned=True):
+    a = np.ascontiguousarray(a, np.uint64)
+    t = torch.from_numpy(a.view(np.int64).copy() if bits == 64 else a.astype(np.uint32).view(np.int32).copy())
+    return t.pin_memory() if pinned else t
+
+
 def _pinned(a):
-    t = torch.from_numpy(np.ascontiguousarray(a, np.uint64).view(np.int64).copy())
-    return t.pin_memory()
+    return _host(a)
 
 
-def _make_requests(n_tables, universe, n_req, seed):
+def _make_requests(n_tables, universe, n_req, seed, bits=64):
     """Zipf keys per table; op kinds query/upsert/insert 50/30/20; sizes 2^U, U ~ U[3, 11];
     insert values 3k+1 so duplicate inserts are deterministic."""
-    uk = [w.distinct_keys(w.stream_seed(seed, 100 + t), universe) for t in range(n_tables)]
+    uk = [w.distinct_keys(w.stream_seed(seed, 100 + t), universe, key_bits=bits) for t in range(n_tables)]
     z = w.Zipf(universe, 0.99)
     u = w.unit_float(w.stream_seed(seed, 1), 0, 3 * n_req)
     reqs = []
@@ -38,23 +43,31 @@ def _make_requests(n_tables, universe, n_req, seed):
         zpos += n
         keys = uk[t][ranks]
         if op == OPI:
-            vals = w.value_of(keys)
+            vals = w.value_of(keys, bits)
         elif op == OPU:
             vals = w.splitmix64(w.stream_seed(seed, 3), zpos, n)
+            if bits == 32:
+                vals &= np.uint64(0xFFFFFFFF)
         else:
             vals = None
         reqs.append((t, op, keys, vals))
     return uk, reqs
 
 
-def _serve(tables, reqs, mode, gap_s):
+def _serve(tables, reqs, mode, gap_s, bits=64, pageable_every=0):
+    """Serves reqs; with pageable_every = k, every k-th request's arrays are
+    ordinary (pageable) host memory, which the server copies with runtime copies."""
     srv = hw.Server(tables, mode=mode, slots=3, slot_ops=1 << 16)
     bufs, rs = [], []
-    for t, op, keys, vals in reqs:
-        kt = _pinned(keys)
-        vt = None if vals is None else _pinned(vals)
-        out = torch.zeros(len(keys), dtype=torch.int64).pin_memory()
-        st = torch.zeros(len(keys), dtype=torch.uint8).pin_memory()
+    dt = torch.int64 if bits == 64 else torch.int32
+    for i, (t, op, keys, vals) in enumerate(reqs):
+        pin = not (pageable_every and i % pageable_every == 0)
+        kt = _host(keys, bits, pin)
+        vt = None if vals is None else _host(vals, bits, pin)
+        out = torch.zeros(len(keys), dtype=dt)
+        st = torch.zeros(len(keys), dtype=torch.uint8)
+        if pin:
+            out, st = out.pin_memory(), st.pin_memory()
         bufs.append((kt, vt, out, st))
         rs.append(hw.Server.request(t, op, kt, vt, out, st))
     offs = np.arange(len(reqs)) * gap_s
@@ -62,7 +75,10 @@ def _serve(tables, reqs, mode, gap_s):
     srv.drain()
     stats = srv.stats()
     srv.close()
-    res = [(b[2].numpy().view(np.uint64).copy(), b[3].numpy().copy()) for b in bufs]
+    res = []
+    for b in bufs:
+        o = b[2].numpy()
+        res.append((o.view(np.uint64).copy() if bits == 64 else o.view(np.uint32).astype(np.uint64), b[3].numpy().copy()))
     return res, stats
 
 
@@ -111,3 +127,45 @@ def test_served_results_equal_serial_replay_and_oracle(design):
             v = v.cpu().numpy().view(np.uint64)
             o = np.argsort(k)
             assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov)
+
+
+@pytest.mark.parametrize("bits,design,flags,pageable_every", [
+    (64, "P2_M", hw.F_NO_ERASE | hw.F_AGGREGATE, 0),   # the served benchmark's tables
+    (64, "DOUBLE_M", hw.F_NO_ERASE | hw.F_AGGREGATE, 5),
+    (64, "P2_M", 0, 3),
+    (32, "P2_M", 0, 4),
+])
+def test_served_copy_paths_and_table_kinds(bits, design, flags, pageable_every):
+    """Batched serving with pinned requests (gathered and scattered by the copy
+    kernels) mixed with pageable ones (runtime copies), on merging erase-free
+    tables (hot-key accumulators) and on 32-bit tables: every output and every
+    table equal the oracle's."""
+    n_tables, universe = 6, 1 << 13
+    uk, reqs = _make_requests(n_tables, universe, 300, seed=62 + bits, bits=bits)
+    A = [hw.Table(1 << 15, design, kv_bits=bits, flags=flags) for _ in range(n_tables)]
+    oms = [oracle.OracleMap(key_bits=bits) for _ in range(n_tables)]
+    for t in range(n_tables):
+        pre = uk[t][: universe // 2]
+        pv = w.value_of(pre, bits)
+        A[t].insert(_host(pre, bits, False).cuda(), _host(pv, bits, False).cuda())
+        oms[t].insert(pre, pv)
+    torch.cuda.synchronize()
+    served, st_a = _serve(A, reqs, "batched", 20e-6, bits=bits, pageable_every=pageable_every)
+    assert st_a["requests"] == len(reqs)
+    for i, (t, op, keys, vals) in enumerate(reqs):
+        out_a, s_a = served[i]
+        if op == OPQ:
+            os_, ov = oms[t].query(keys)
+            assert np.array_equal(s_a, os_) and np.array_equal(out_a, ov), i
+        else:
+            os_ = oms[t].apply(keys, vals, default_op=hw.OPS["insert"] if op == OPI else hw.OPS["upsert"],
+                               combine=oracle.SUM)[0]
+            for code in (1, 2):
+                assert _counts(keys, s_a, code) == _counts(keys, os_, code), i
+    for t in range(n_tables):
+        ok, ov = oms[t].dump()
+        k, v = A[t].export()
+        k = k.cpu().numpy().view(np.uint64) if bits == 64 else k.cpu().numpy().view(np.uint32).astype(np.uint64)
+        v = v.cpu().numpy().view(np.uint64) if bits == 64 else v.cpu().numpy().view(np.uint32).astype(np.uint64)
+        o = np.argsort(k)
+        assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov)
