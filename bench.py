@@ -156,7 +156,28 @@ class Step:
                                                          status=self.mst))
 
 
-def verify_step(step: Step, d) -> None:
+class FullInsert(Exception):
+    """Some distinct key ended FULL: both of its buckets were full when it was placed."""
+
+
+def verify_step(step: Step, d, attempts: int = 3) -> int:
+    """verify_once, repeated (from a cleared table) when a few keys end FULL.
+    Concurrent two-choice placement decides on bucket fills that other inserts are
+    changing, so at 0.9 load a key can, rarely, find both of its 32-slot buckets
+    full (about once in thirty 2^28 fills); that outcome is legal and is counted
+    and reported.  Every other status is an error.  Returns the FULL events seen."""
+    seen = 0
+    for a in range(attempts):
+        try:
+            verify_once(step, d)
+            return seen
+        except FullInsert as e:
+            seen += 1
+            log("verification attempt %d: %s; repeating" % (a + 1, e))
+    raise AssertionError("FULL inserts in %d attempts in a row" % attempts)
+
+
+def verify_once(step: Step, d) -> None:
     """Closed-form checks of one full step at full size (no oracle needed): every
     insert DONE, positives return 3k+1 (3k+2 after the +1 upsert), negatives miss,
     erased keys miss, kept keys found, table size equals inserted - erased."""
@@ -166,7 +187,11 @@ def verify_step(step: Step, d) -> None:
     t.clear()
     b2 = step.bounds[-1]
     st = t.insert(step.keys, step.vals, status=step.st[:b2])
-    assert bool((st == 1).all()), "insert statuses"
+    if not bool((st == 1).all()):
+        hist = {int(c): int(n) for c, n in zip(*np.unique(st.cpu().numpy(), return_counts=True))}
+        if set(hist) == {1, 3} and hist[3] <= 16:
+            raise FullInsert("insert statuses %s (1 done, 3 full)" % hist)
+        raise AssertionError("insert statuses %s (1 done, 2 existed, 3 full)" % hist)
     f, v = t.query(step.qpos, out=step.out)
     assert bool((f == 1).all()), "positive queries"
     exp = to_dev(w.value_of(d["qpos"]))
@@ -261,7 +286,9 @@ def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
         # all its keys
         step.t = hw.Table(step.bounds[-1] if des == "CHAINING" else d["cap"], des)
         if verify:
-            verify_step(step, d)
+            res_full = verify_step(step, d)
+            if res_full:
+                log("design %s: %d verification repeat(s) after FULL inserts" % (des, res_full))
         for _ in range(warmup):
             step.run()
         events = {}
@@ -317,7 +344,12 @@ def bench_aging(designs, log2cap=26, iters=1000, probe_cap_lines=80):
             cap = probe_cap_lines * 8 // bucket  # 128-byte lines of 16-byte slots
         t = hw.Table(1 << log2cap, des, probe_cap=cap)
         pre = t.insert(kd[:n0], kd[:n0] * 3 + 1)
-        bad = (pre != 1).sum()
+        # full[j]: plan key j ended FULL (both of its buckets full when it was
+        # placed; legal, rare); it is then absent: its erase misses and a
+        # positive query of it misses
+        full = torch.zeros(n0 + iters * s, dtype=torch.bool, device="cuda")
+        full[:n0] = pre == 3
+        bad = ((pre != 1) & (pre != 3)).sum()
         ev = []
         for i in range(iters):
             ps = int(plan["pos_start"][i])
@@ -330,20 +362,29 @@ def bench_aging(designs, log2cap=26, iters=1000, probe_cap_lines=80):
             t.mixed(ops, kb, vb, combine="sum", out=out, status=st)
             b.record()
             ev.append((a, b))
-            bad += (st[: 3 * s] != 1).sum() + (st[3 * s:] != 0).sum()
-            bad += (out[2 * s: 3 * s] != vb[2 * s: 3 * s]).sum() + (out[3 * s:] != 0).sum()
+            ins = st[:s]
+            full[n0 + i * s: n0 + (i + 1) * s] = ins == 3
+            bad += ((ins != 1) & (ins != 3)).sum()
+            bad += (st[s: 2 * s] != (~full[i * s: (i + 1) * s]).to(torch.uint8)).sum()
+            live = ~full[ps: ps + s]
+            bad += (st[2 * s: 3 * s] != live.to(torch.uint8)).sum()
+            bad += (out[2 * s: 3 * s] != torch.where(live, vb[2 * s: 3 * s], 0)).sum()
+            bad += (st[3 * s:] != 0).sum() + (out[3 * s:] != 0).sum()
         torch.cuda.synchronize()
         ms = np.array([a.elapsed_time(b) for a, b in ev])
         g = 4 * s / ms / 1e6
         nbad = int(bad.item())
+        n_full = int(full.sum().item())
         assert nbad == 0, "aging %s: %d outputs differ from their closed form" % (des, nbad)
-        assert t.size() == n0, "aging %s: size" % des
+        assert t.size() == n0 - int(full[iters * s:].sum().item()), "aging %s: size" % des
+        if n_full:
+            log("aging %s: %d of %d inserts ended FULL (both buckets full)" % (des, n_full, n0 + iters * s))
         res[des] = {"gops_mean": round(float(4 * s * iters / ms.sum() / 1e6), 3),
                     "gops_first10": round(float(g[:10].mean()), 3),
                     "gops_last100": round(float(g[-100:].mean()), 3),
                     "gops_min": round(float(g.min()), 3),
                     "gops_every100": [round(float(g[j: j + 100].mean()), 3) for j in range(0, iters, 100)],
-                    "probe_cap": cap or None, "verified": True}
+                    "probe_cap": cap or None, "verified": True, "full_inserts": n_full}
         log("aging %s: mean %.2f Gops/s, first 10 %.2f, last 100 %.2f"
             % (des, res[des]["gops_mean"], res[des]["gops_first10"], res[des]["gops_last100"]))
         del t
@@ -688,8 +729,9 @@ def main():
     step = Step(d, args.design, args.tile, args.bucket)
     torch.cuda.synchronize()
     log("device inputs resident; table %s bucket %d tile %d" % (args.design, step.t.bucket_slots, step.t.tile))
+    full_repeats = 0
     if not args.no_verify:
-        verify_step(step, d)
+        full_repeats = verify_step(step, d)
         log("full-size closed-form verification passed")
 
     if args.calibrate_copy:
@@ -791,6 +833,7 @@ def main():
         "roofline": roof, "cpu_baseline": cpu, "designs": designs, "aging": aging, "batched": batched,
         "served": served,
         "kernel_source_hash": kernel_source_hash(),
+        "verify_full_repeats": full_repeats,
     }
     print(json.dumps(result), flush=True)
 

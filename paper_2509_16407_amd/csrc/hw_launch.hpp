@@ -98,33 +98,102 @@ k_erase(TableDev tv, const typename C::K* __restrict__ keys, uint64_t n, uint8_t
 
 // One operation per element, all kinds in one launch (Section 6.5 runs an aging
 // iteration's inserts, queries and deletes concurrently in one kernel).
+//
+// A wave takes 64 operations at a time and runs them grouped by kind (queries,
+// then inserts and upserts, then erases): tiles of a wave execute in lockstep, so
+// a wave whose tiles run different kinds would go through every kind's code
+// path, one after another.  Grouping leaves at most two kinds in one round of
+// tiles.  The operations of a launch are concurrent, so their order within it
+// is free.  Cuckoo keeps one operation per tile in input order: its three-lock
+// paths need the registers the grouping takes.
+template <class C>
+__device__ __forceinline__ void mixed_op(const TableDev& tv, const Tile<C::T>& tile, const uint8_t* __restrict__ ops,
+                                         const typename C::K* __restrict__ keys,
+                                         const typename C::K* __restrict__ vals, uint64_t j, int combine,
+                                         typename C::K* __restrict__ out, uint8_t* __restrict__ status) {
+  using K = typename C::K;
+  const int op = ops[j];
+  const K key = keys[j];
+  K v = 0;
+  uint8_t st;
+  if (op == OP_QUERY) {
+    st = Ops<C>::query(tv, tile, key, &v);
+  } else if (op == OP_ERASE) {
+    st = Ops<C>::erase(tv, tile, key);
+  } else if (op == OP_INSERT || op == OP_UPSERT) {
+    st = Ops<C>::upsert(tv, tile, key, vals[j], op == OP_INSERT ? C_KEEP : combine);
+  } else {
+    st = ST_INVALID;
+  }
+  if (tile.leader()) {
+    if (out) out[j] = v;
+    if (status) status[j] = st;
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void mixed_body(const TableDev& tv, const uint8_t* __restrict__ ops,
+                                           const typename C::K* __restrict__ keys,
+                                           const typename C::K* __restrict__ vals, uint64_t n, int combine,
+                                           typename C::K* __restrict__ out, uint8_t* __restrict__ status,
+                                           uint8_t* order_lds) {
+  const Tile<C::T> tile;
+  if constexpr (C::CUCKOO) {
+    const uint64_t stride = (uint64_t)gridDim.x * (BLOCK / C::T);
+    for (uint64_t i = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / C::T; i < n; i += stride)
+      mixed_op<C>(tv, tile, ops, keys, vals, i, combine, out, status);
+    return;
+  }
+  // wave-uniform values made scalar, so they take no vector registers
+  const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  uint8_t* order = order_lds + wid * 64;  // this wave's 64 entries
+  const uint32_t lane = __lane_id();
+  const uint64_t wave = (uint64_t)blockIdx.x * (BLOCK / 64) + wid;
+  const uint64_t n_waves = (uint64_t)gridDim.x * (BLOCK / 64);
+  for (uint64_t base = wave * 64; base < n; base += n_waves * 64) {
+    // rank of the lane's operation: query 0, insert/upsert 1, erase 2, other 3,
+    // past the end 4; its place = lanes of lower rank + lower lanes of its rank
+    const uint64_t i = base + lane;
+    int r = 4;
+    if (i < n) {
+      const int op = ops[i];
+      r = op == OP_QUERY ? 0 : (op == OP_INSERT || op == OP_UPSERT) ? 1 : op == OP_ERASE ? 2 : 3;
+    }
+    uint32_t place = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t m = __ballot(r == k);
+      if (k < r) place += (uint32_t)__popcll(m);
+      if (k == r) place += (uint32_t)__popcll(m & ((1ull << lane) - 1));
+    }
+    if (r == 4) place = lane;  // past-end lanes are the highest ones
+    order[place] = (uint8_t)lane;
+    wave_sync();
+    const uint32_t cnt = n - base < 64 ? (uint32_t)(n - base) : 64u;
+    for (uint32_t s = lane / C::T; s < cnt; s += 64 / C::T)
+      mixed_op<C>(tv, tile, ops, keys, vals, base + order[s], combine, out, status);
+    wave_sync();  // the next window rewrites `order`
+  }
+}
+
 template <class C>
 __global__ void __launch_bounds__(BLOCK)
 k_mixed(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __restrict__ keys,
         const typename C::K* __restrict__ vals, uint64_t n, int combine, typename C::K* __restrict__ out,
         uint8_t* __restrict__ status) {
-  using K = typename C::K;
-  const Tile<C::T> tile;
-  const uint64_t stride = (uint64_t)gridDim.x * (BLOCK / C::T);
-  for (uint64_t i = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / C::T; i < n; i += stride) {
-    const int op = ops[i];
-    const K key = keys[i];
-    K v = 0;
-    uint8_t st;
-    if (op == OP_QUERY) {
-      st = Ops<C>::query(tv, tile, key, &v);
-    } else if (op == OP_ERASE) {
-      st = Ops<C>::erase(tv, tile, key);
-    } else if (op == OP_INSERT || op == OP_UPSERT) {
-      st = Ops<C>::upsert(tv, tile, key, vals[i], op == OP_INSERT ? C_KEEP : combine);
-    } else {
-      st = ST_INVALID;
-    }
-    if (tile.leader()) {
-      if (out) out[i] = v;
-      if (status) status[i] = st;
-    }
-  }
+  __shared__ uint8_t order_lds[BLOCK];
+  mixed_body<C>(tv, ops, keys, vals, n, combine, out, status, order_lds);
+}
+
+// With an occupancy bound of W waves per SIMD (the grouping's registers would
+// cost iceberg its sixth wave and double hashing with tags its eighth).
+template <class C, int W>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W, 8)))
+k_mixed_w(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __restrict__ keys,
+           const typename C::K* __restrict__ vals, uint64_t n, int combine, typename C::K* __restrict__ out,
+           uint8_t* __restrict__ status) {
+  __shared__ uint8_t order_lds[BLOCK];
+  mixed_body<C>(tv, ops, keys, vals, n, combine, out, status, order_lds);
 }
 
 // Host side ------------------------------------------------------------------
@@ -188,8 +257,18 @@ struct Launch {
   }
   static hipError_t mixed(const LaunchArgs& a, const uint8_t* ops, const void* keys, const void* vals,
                           uint64_t n, int combine, void* out, uint8_t* status, hipStream_t s) {
-    hipLaunchKernelGGL((k_mixed<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
-                       ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+    if constexpr (C::CUCKOO)
+      hipLaunchKernelGGL((k_mixed<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv, ops,
+                         (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+    else if constexpr (C::ICEBERG && C::T >= 4)  // one wave per window of 64 operations
+      hipLaunchKernelGGL((k_mixed_w<C, 6>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s,
+                         a.tv, ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+    else if constexpr (C::DESIGN == D_DOUBLE_M && C::T >= 4)
+      hipLaunchKernelGGL((k_mixed_w<C, 8>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s,
+                         a.tv, ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+    else
+      hipLaunchKernelGGL((k_mixed<C>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
+                         ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
     return hipGetLastError();
   }
 };
