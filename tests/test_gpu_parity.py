@@ -98,6 +98,7 @@ CASES = [
     ("P2_M", 32, 32, 32), ("DOUBLE", 32, 64, 32), ("ICEBERG", 32, 32, 8), ("ICEBERG", 32, 32, 4),
     ("ICEBERG_M", 32, 32, 4), ("ICEBERG_M", 32, 32, 8),
     ("CUCKOO", 64, 8, 4), ("CUCKOO", 64, 8, 8), ("CUCKOO", 64, 16, 8),
+    ("DOUBLE_M", 64, 32, 2), ("P2_M", 64, 32, 2), ("ICEBERG_M", 64, 32, 2),
 ]
 
 
