@@ -413,19 +413,20 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
     log("batched: %d tables, %d ops generated in %.1f s" % (n_tables, n_ops, time.time() - t0))
     t0 = time.time()
     classes = sorted(set(int(e) for e in exps))
-    tuned, rejected = {}, {}
+    tuned, rejected, tuned_ne = {}, {}, {}
     for e in classes:
         tuned[e], rejected[e] = hw.autotune(32, 1 << e, load=load, reps=tune_reps)
-    log("batched: autotuned %d classes in %.1f s" % (len(classes), time.time() - t0))
+        tuned_ne[e], _ = hw.autotune(32, 1 << e, load=load, reps=tune_reps, flags=hw.F_NO_ERASE)
+    log("batched: autotuned %d classes (locking and erase-free tables) in %.1f s" % (len(classes), time.time() - t0))
     kd = torch.from_numpy(keys.view(np.int32)).cuda()
     vd = torch.from_numpy(vals.view(np.int32)).cuda()
     st = torch.empty(n_ops, dtype=torch.uint8, device="cuda")
 
-    def make(cfg_of):
+    def make(cfg_of, flags=0):
         tabs = []
         for e in exps:
             d, b, t = cfg_of(int(e))
-            tabs.append(hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t))
+            tabs.append(hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t, flags=flags))
         return tabs, hw.Multi(tabs)
 
     def timed(fn, clear):
@@ -443,33 +444,46 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
                 ms.append(a.elapsed_time(b))
         return float(np.median(ms))
 
-    tabs, m = make(lambda e: (tuned[e]["design"], tuned[e]["bucket"], tuned[e]["tile"]))
-    ms_batched = timed(lambda: m.upsert(offsets, kd, vd, status=st), m.clear)
-
-    def plain():
-        for i, t in enumerate(tabs):
-            a, b = int(offsets[i]), int(offsets[i + 1])
-            t.upsert(kd[a:b], vd[a:b], status=st[a:b])
-    ms_plain = timed(plain, m.clear)
-    # verification on the last (plain) run's final state: sizes, and a sample vs the oracle
     import oracle
     ds = (offsets[1:] - offsets[:-1]) // 2
-    sizes = [t.size() for t in tabs]
-    assert sizes == [int(x) for x in ds], "table sizes"
     pick = w.sample_without_replacement(w.stream_seed(4, 9), n_tables, min(n_verify, n_tables))
-    for i in pick.tolist():
-        a, b = int(offsets[i]), int(offsets[i + 1])
-        om = oracle.OracleMap(key_bits=32)
-        om.upsert(keys[a:b].astype(np.uint64), vals[a:b].astype(np.uint64))
-        k, v = tabs[i].export()
-        k = k.cpu().numpy().view(np.uint32).astype(np.uint64)
-        v = v.cpu().numpy().view(np.uint32).astype(np.uint64)
-        o = np.argsort(k)
-        ok, ov = om.dump()
-        assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov), "table %d vs oracle" % i
+
+    def verify(tabs):
+        """Sizes of all tables, and a sample against the oracle."""
+        sizes = [t.size() for t in tabs]
+        assert sizes == [int(x) for x in ds], "table sizes"
+        for i in pick.tolist():
+            a, b = int(offsets[i]), int(offsets[i + 1])
+            om = oracle.OracleMap(key_bits=32)
+            om.upsert(keys[a:b].astype(np.uint64), vals[a:b].astype(np.uint64))
+            k, v = tabs[i].export()
+            k = k.cpu().numpy().view(np.uint32).astype(np.uint64)
+            v = v.cpu().numpy().view(np.uint32).astype(np.uint64)
+            o = np.argsort(k)
+            ok, ov = om.dump()
+            assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov), "table %d vs oracle" % i
+
+    def batched_and_plain(cfg, flags):
+        tabs, m = make(lambda e: (cfg[e]["design"], cfg[e]["bucket"], cfg[e]["tile"]), flags)
+        ms_b = timed(lambda: m.upsert(offsets, kd, vd, status=st), m.clear)
+        verify(tabs)  # the batched run's final state
+
+        def plain():
+            for i, t in enumerate(tabs):
+                a, b = int(offsets[i]), int(offsets[i + 1])
+                t.upsert(kd[a:b], vd[a:b], status=st[a:b])
+        ms_p = timed(plain, m.clear)
+        verify(tabs)  # the plain run's
+        del m, tabs
+        torch.cuda.empty_cache()
+        return ms_b, ms_p
+
+    ms_batched, ms_plain = batched_and_plain(tuned, 0)
     log("batched: verified sizes of all tables and %d tables against the oracle" % len(pick))
-    del m, tabs
-    torch.cuda.empty_cache()
+    # group-by tables never erase: declared so, a repeated key is summed without its lock
+    ms_batched_ne, ms_plain_ne = batched_and_plain(tuned_ne, hw.F_NO_ERASE)
+    log("batched: erase-free tables %.2f Gops/s in one launch vs %.2f Gops/s plain (verified)"
+        % (n_ops / ms_batched_ne / 1e6, n_ops / ms_plain_ne / 1e6))
     tabs_d, m_d = make(lambda e: ("P2_M", 32, 4))
     ms_default = timed(lambda: m_d.upsert(offsets, kd, vd, status=st), m_d.clear)
     del m_d, tabs_d, kd, vd, st
@@ -482,6 +496,10 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
             "plain_ms": round(ms_plain, 3), "plain_gops": gops(ms_plain),
             "default_cfg_batched_ms": round(ms_default, 3), "default_cfg_batched_gops": gops(ms_default),
             "speedup_vs_plain": round(ms_plain / ms_batched, 3),
+            "erase_free": {"batched_ms": round(ms_batched_ne, 3), "batched_gops": gops(ms_batched_ne),
+                           "plain_ms": round(ms_plain_ne, 3), "plain_gops": gops(ms_plain_ne),
+                           "tuning": {str(e): "%s/b%d/t%d %.2f" % (v["design"], v["bucket"], v["tile"], v["gops"])
+                                      for e, v in tuned_ne.items()}},
             "tuning": {str(e): "%s/b%d/t%d %.2f" % (v["design"], v["bucket"], v["tile"], v["gops"])
                        for e, v in tuned.items()},
             "rejected_full": {str(e): ["%s/b%d/t%d" % (a["design"], a["bucket"], a["tile"])
