@@ -396,6 +396,81 @@ def bench_aging(designs, log2cap=26, iters=1000, probe_cap_lines=80):
             "ops_per_iteration": 4 * s, "designs": res}
 
 
+def bench_mixed_cfg3(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE_M"):
+    """SURVEY config 3: a 2^log2cap-slot table preloaded with a 2^universe_log2-key
+    universe (load 0.5, v = 3k+1), then `n_batches` shuffled mixed batches of 2^20
+    operations (50% query, 30% SUM upsert, 20% erase; Zipf 0.99 keys; erase and
+    upsert keys disjoint, queries avoid both).  Per-batch kernel latency from events.
+    Every output is checked on the device against a shadow model of the map indexed
+    by universe rank (present flag, value): queries return the batch-start state,
+    erases report presence, and of a key's upserts exactly one inserts (the key was
+    absent) or none (present), the rest report EXISTED; after the last batch the
+    table's size and its sum of values equal the model's."""
+    import torch
+    import paper_2509_16407_amd as hw
+    from paper_2509_16407_amd import workloads as w
+    t0 = time.time()
+    U = 1 << universe_log2
+    uk = w.universe_keys(U, config_id=3)
+    batches = list(w.mixed_batches(U, 1 << 20, n_batches, config_id=3, ukeys=uk))
+    log("config 3: %d batches of 2^20 ops over a 2^%d-key universe generated in %.1f s"
+        % (n_batches, universe_log2, time.time() - t0))
+    t = hw.Table(1 << log2cap, design)
+    ukd = to_dev(uk)
+    pre = t.insert(ukd, ukd * 3 + 1)
+    assert bool((pre == 1).all()), "config 3 preload"
+    present = torch.ones(U, dtype=torch.bool, device="cuda")
+    val = ukd * 3 + 1
+    del ukd
+    n = 1 << 20
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    st = torch.empty(n, dtype=torch.uint8, device="cuda")
+    bad = torch.zeros((), dtype=torch.int64, device="cuda")
+    ev = []
+    for bt in batches:
+        ops = torch.from_numpy(bt["ops"]).cuda()
+        kd, vd = to_dev(bt["keys"]), to_dev(bt["vals"])
+        r = torch.from_numpy(bt["ranks"]).cuda()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        t.mixed(ops, kd, vd, combine="sum", out=out, status=st)
+        b.record()
+        ev.append((a, b))
+        q, u, e = ops == 0, ops == 2, ops == 3
+        rq, ru, re_ = r[q], r[u], r[e]
+        pq = present[rq]
+        bad += (st[q] != pq.to(torch.uint8)).sum()
+        bad += (out[q] != torch.where(pq, val[rq], 0)).sum()
+        bad += (st[e] != present[re_].to(torch.uint8)).sum()
+        su = st[u]
+        bad += ((su != 1) & (su != 2)).sum()
+        done = torch.zeros(U, dtype=torch.int32, device="cuda")
+        done.index_add_(0, ru, (su == 1).to(torch.int32))
+        # a key absent at batch start inserts exactly once; a present one never
+        bad += (done[ru] != (~present[ru]).to(torch.int32)).sum()
+        val[ru] = torch.where(present[ru], val[ru], 0)
+        val.index_add_(0, ru, vd[u])
+        present[ru] = True
+        present[re_] = False
+    torch.cuda.synchronize()
+    nbad = int(bad.item())
+    assert nbad == 0, "config 3: %d outputs differ from the shadow model" % nbad
+    assert t.size() == int(present.sum().item()), "config 3: size"
+    _, tv = t.export()
+    assert int(tv.sum().item()) == int(val[present].sum().item()), "config 3: sum of values"
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    res = {"workload": "%s, 2^%d slots, 2^%d-key universe preloaded (load 0.5), %d shuffled batches of 2^20 ops "
+                       "(50%% query / 30%% SUM upsert / 20%% erase, Zipf 0.99)" % (design, log2cap, universe_log2, n_batches),
+           "p50_batch_ms": round(float(np.percentile(ms, 50)), 4), "p99_batch_ms": round(float(np.percentile(ms, 99)), 4),
+           "mean_gops": round(float(n * len(ms) / ms.sum() / 1e6), 3), "verified": True}
+    log("config 3: p50 %.3f ms, p99 %.3f ms per 2^20-op batch (%.2f Gops/s), all outputs verified"
+        % (res["p50_batch_ms"], res["p99_batch_ms"], res["mean_gops"]))
+    del t, present, val
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_reps=2, n_verify=16):
     """The batched form (SURVEY config 4): n_tables uint32 tables with capacities 2^e,
     e uniform in [e_min, e_max], each receiving a group-by SUM-upsert batch that
@@ -718,6 +793,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--bucket", type=int, default=0)
     ap.add_argument("--mixed-batches", type=int, default=16)
+    ap.add_argument("--cfg3-batches", type=int, default=256,
+                    help="mixed 2^20-op batches of config 3 (DOUBLE_M, 2^27 slots; 0 to skip)")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-table (batched) section")
     ap.add_argument("--no-served", action="store_true", help="skip the serving section")
@@ -814,6 +891,10 @@ def main():
         designs[args.design]["phased"] = bench_phased(step, d, args.design, designs[args.design]["phase_gops"])
         step.t = main_t
 
+    cfg3 = None
+    if args.cfg3_batches:
+        cfg3 = bench_mixed_cfg3(n_batches=args.cfg3_batches)
+
     aging = None
     if not args.no_aging:
         aging = bench_aging(["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING", "CUCKOO"])
@@ -848,7 +929,8 @@ def main():
         "upsert_gops": rates["upsert"]["gops"],
         "p50_batch_ms": None if p50 is None else round(p50, 4),
         "p99_batch_ms": None if p99 is None else round(p99, 4),
-        "roofline": roof, "cpu_baseline": cpu, "designs": designs, "aging": aging, "batched": batched,
+        "roofline": roof, "cpu_baseline": cpu, "designs": designs, "mixed_config3": cfg3, "aging": aging,
+        "batched": batched,
         "served": served,
         "kernel_source_hash": kernel_source_hash(),
         "verify_full_repeats": full_repeats,
