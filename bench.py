@@ -160,6 +160,31 @@ class FullInsert(Exception):
     """Some distinct key ended FULL: both of its buckets were full when it was placed."""
 
 
+def upsert_miss(step: Step, reps: int = 3) -> dict:
+    """The upsert-miss path (not part of the step): fill a cleared table to 0.75,
+    then time the 0.75 -> 0.9 keys as SUM upserts, which all insert.  Median of
+    `reps` runs after one untimed run."""
+    import torch
+    t = step.t
+    _, b1, b2 = step.bounds
+    ms = []
+    for r in range(reps + 1):
+        t.clear()
+        t.insert(step.keys[:b1], step.vals[:b1])
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        st = t.upsert(step.keys[b1:b2], step.vals[b1:b2], combine="sum", status=step.st[: b2 - b1])
+        b.record()
+        b.synchronize()
+        full = int((st == 3).sum().item())
+        assert int((st == 1).sum().item()) + full == b2 - b1 and full <= 16, "upsert-miss statuses"
+        if r:
+            ms.append(a.elapsed_time(b))
+    m = float(np.median(ms))
+    return {"ms": round(m, 4), "gops": round((b2 - b1) / m / 1e6, 3)}
+
+
 def verify_step(step: Step, d, attempts: int = 3) -> int:
     """verify_once, repeated (from a cleared table) when a few keys end FULL.
     Concurrent two-choice placement decides on bucket fills that other inserts are
@@ -661,32 +686,66 @@ def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):
             "identical_results": True}
 
 
-def cpu_baseline(cap_log2: int):
-    """The CPU oracle (single thread) on the same step recipe at a smaller size."""
+def cpu_baseline(cap_log2: int, max_threads: int = 16):
+    """The CPU oracle on the same step recipe at a smaller size: (i) one thread,
+    one map; (ii) T threads, the keys sharded by a hash of their own into T maps
+    (one per thread), the phases in the step's order with a join between phases.
+    The oracle's map calls release the interpreter lock, so the shards run in
+    parallel.  `value` is the sharded rate, `cores` = T."""
+    import concurrent.futures as cf
     import oracle
     from paper_2509_16407_amd import workloads as w
     d = make_inputs(cap_log2, 0, 0)
-    m = oracle.OracleMap()
     keys = d["keys"]
     vals = w.value_of(keys)
     ones = np.ones(len(d["qpos"]), np.uint64)
-    t0 = time.perf_counter()
     b0, b1, b2 = d["bounds"]
-    m.insert(keys[:b0], vals[:b0])
-    m.insert(keys[b0:b1], vals[b0:b1])
-    m.insert(keys[b1:b2], vals[b1:b2])
-    m.query(d["qpos"])
-    m.query(d["qneg"])
-    m.upsert(d["qpos"], ones)
-    m.erase(d["ekeys"])
-    m.query(d["qpos"])
-    m.query(d["qneg"])
-    dt = time.perf_counter() - t0
-    n_ops = b2 + 5 * len(d["qpos"]) + len(d["ekeys"])  # inserts, 4 query sets + upserts, erases
-    return dict(value=n_ops / dt / 1e9, unit="Gops/s", cores=1, kind="oracle",
+    # (kind, keys, values) in the step's order
+    phases = [("insert", keys[:b0], vals[:b0]), ("insert", keys[b0:b1], vals[b0:b1]),
+              ("insert", keys[b1:b2], vals[b1:b2]), ("query", d["qpos"], None), ("query", d["qneg"], None),
+              ("upsert", d["qpos"], ones), ("erase", d["ekeys"], None), ("query", d["qpos"], None),
+              ("query", d["qneg"], None)]
+    n_ops = sum(len(k) for _, k, _ in phases)
+
+    def run(m, kind, k, v):
+        if kind == "insert":
+            m.insert(k, v)
+        elif kind == "upsert":
+            m.upsert(k, v)
+        elif kind == "query":
+            m.query(k)
+        else:
+            m.erase(k)
+
+    m = oracle.OracleMap()
+    t0 = time.perf_counter()
+    for kind, k, v in phases:
+        run(m, kind, k, v)
+    dt1 = time.perf_counter() - t0
+    del m
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    T = max(1, min(max_threads, avail))
+    with np.errstate(over="ignore"):
+        shard_of = lambda k: ((k * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(40)) % np.uint64(T)
+    parts = []
+    for kind, k, v in phases:
+        sh = shard_of(k)
+        parts.append([(kind, k[sh == i], None if v is None else v[sh == i]) for i in range(T)])
+    maps = [oracle.OracleMap() for _ in range(T)]
+    with cf.ThreadPoolExecutor(T) as ex:
+        t0 = time.perf_counter()
+        for ph in parts:
+            list(ex.map(lambda i: run(maps[i], *ph[i]), range(T)))
+        dtT = time.perf_counter() - t0
+    assert sum(mm.size() for mm in maps) == b2 - len(d["ekeys"]), "sharded oracle size"
+    return dict(value=n_ops / dtT / 1e9, unit="Gops/s", cores=T, kind="oracle",
+                single_thread_value=n_ops / dt1 / 1e9,
                 sample="same step recipe (insert to 0.9, 2^%d pos + neg queries, upserts, 50%% erase, "
-                       "re-query) at 2^%d slots, std::unordered_map, 1 thread; %d ops in %.1f s"
-                       % (cap_log2 - 1, cap_log2, n_ops, dt))
+                       "re-query) at 2^%d slots, std::unordered_map; %d ops: %d threads over %d key-hash "
+                       "shards %.2f s, 1 thread %.2f s" % (cap_log2 - 1, cap_log2, n_ops, T, T, dtT, dt1))
 
 
 KERNEL_OF = {"insert_0.5": "k_upsert", "insert_0.75": "k_upsert", "insert_0.9": "k_upsert",
@@ -871,6 +930,8 @@ def main():
     if step.mixed:
         per_step_ops["mixed"] = step.mixed_ops // len(step.mixed)
     roof = roofline(phase_ms, per_step_ops, args.steps, load_traffic())
+    rates["upsert_miss_0.9"] = upsert_miss(step)
+    log("upsert misses 0.75 -> 0.9: %.2f Gops/s" % rates["upsert_miss_0.9"]["gops"])
 
     cfg = {"workload": "load benchmark at 2^%d slots on %s (bucket %d, tile %d): insert to "
                        "0.5/0.75/0.9, 2^%d pos+neg queries, 2^%d SUM upserts, erase 50%%, "
@@ -926,7 +987,7 @@ def main():
         "config": cfg,
         "phases": rates,
         "insert_0.9_gops": rates["insert_0.9"]["gops"], "query_gops": rates["query_pos"]["gops"],
-        "upsert_gops": rates["upsert"]["gops"],
+        "upsert_gops": rates["upsert"]["gops"], "upsert_miss_gops": rates["upsert_miss_0.9"]["gops"],
         "p50_batch_ms": None if p50 is None else round(p50, 4),
         "p99_batch_ms": None if p99 is None else round(p99, 4),
         "roofline": roof, "cpu_baseline": cpu, "designs": designs, "mixed_config3": cfg3, "aging": aging,
