@@ -304,8 +304,11 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
  * Served form: a request loop over resident tables (continuous batching).
  *
  * A request is one operation kind on n keys of one table, with its arrays in
- * host memory (pinned -- hipHostMalloc or torch pin_memory -- for asynchronous
- * copies); they must stay valid until the request completes.  A worker thread
+ * host memory; they must stay valid until the request completes.  In batched
+ * mode, arrays in device-mapped pinned memory (hipHostMalloc, torch
+ * pin_memory) are read and written directly by one gather and one scatter
+ * kernel per batch; a request with any other array is copied with runtime
+ * copies instead (slower, same results).  A worker thread
  * admits pending requests into the next batch while their data fits a device
  * staging slot of `slot_ops` operations (admission by memory), packs them into
  * one persistent multi-table launch, and keeps up to `slots` batches in flight
