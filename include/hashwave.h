@@ -85,7 +85,8 @@ enum {
   HWAVE_EINVAL = -1,      /* bad argument (null pointer, size, unsupported value)  */
   HWAVE_ENOMEM = -2,      /* device allocation failed or buffer too small          */
   HWAVE_EDEVICE = -3,     /* a HIP call failed; see hwave_last_hip_error()         */
-  HWAVE_EUNSUPPORTED = -4 /* no kernel instance for this design/width/bucket/tile  */
+  HWAVE_EUNSUPPORTED = -4, /* no kernel instance for this design/width/bucket/tile */
+  HWAVE_EIO = -5           /* a file could not be opened, read or written, or is malformed */
 };
 
 /* Flags of hwave_config.flags. */
@@ -299,6 +300,18 @@ typedef struct {
 int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, double load, uint32_t reps,
                    uint32_t flags, hwave_tune_result* results, uint32_t results_cap, uint32_t* n_results,
                    hwave_tune_result* best, void* stream);
+
+/* Persisted tuning, one capacity class per entry: class i is log2_capacity[i]
+ * with its chosen configuration best[i].  The file is text: a first line
+ * "hwave-tune 1", then one line per class,
+ * "<log2_capacity> <kv_bits> <design> <bucket_slots> <tile> <gops> <full_ops>".
+ * Save overwrites `path`.  Load reads at most `cap` classes into the caller's
+ * arrays and their count into *n; it rejects (HWAVE_EIO) a file with another
+ * first line, a line it cannot parse, more than `cap` classes, or a design,
+ * key width, bucket or tile that is out of range.  Host-only; no device work. */
+int hwave_tune_save(const char* path, const uint32_t* log2_capacity, const hwave_tune_result* best, uint32_t n);
+int hwave_tune_load(const char* path, uint32_t* log2_capacity, hwave_tune_result* best, uint32_t cap,
+                    uint32_t* n);
 
 /* ------------------------------------------------------------------------
  * Served form: a request loop over resident tables (continuous batching).

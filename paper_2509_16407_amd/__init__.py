@@ -127,6 +127,10 @@ def _bind(L):
         "hwave_autotune": (I, [ctypes.c_uint32, U64, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.POINTER(_Tune), ctypes.c_uint32,
                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_Tune), P]),
+        "hwave_tune_save": (I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_Tune),
+                                ctypes.c_uint32]),
+        "hwave_tune_load": (I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_Tune),
+                                ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -434,20 +438,36 @@ def autotune(kv_bits: int, capacity: int, designs=("DOUBLE", "DOUBLE_M", "P2", "
 
 
 def tune_classes(kv_bits: int, exponents, path=None, **kw):
-    """Autotunes each capacity class 2^e and (optionally) saves {e: best} as JSON."""
-    import json
+    """Autotunes each capacity class 2^e; returns {e: best} and, with `path`,
+    saves it (C-ABI hwave_tune_save)."""
     table = {}
     for e in exponents:
         best, _ = autotune(kv_bits, 1 << e, **kw)
-        table[str(e)] = best
+        table[int(e)] = best
     if path:
-        with open(path, "w") as f:
-            json.dump({"kv_bits": kv_bits, "classes": table}, f, indent=1)
+        save_tuning(path, table)
     return table
 
 
-def load_tuning(path):
-    import json
-    with open(path) as f:
-        rec = json.load(f)
-    return {int(k): v for k, v in rec["classes"].items()}
+def save_tuning(path, table):
+    """Writes {log2 capacity: best-configuration dict} (C-ABI hwave_tune_save)."""
+    es = sorted(table)
+    arr = (_Tune * max(1, len(es)))()
+    caps = (ctypes.c_uint32 * max(1, len(es)))()
+    for i, e in enumerate(es):
+        v = table[e]
+        arr[i] = _Tune(DESIGNS[v["design"]], v["bucket"], v["tile"], v["kv_bits"], v["gops"], v.get("full_ops", 0))
+        caps[i] = int(e)
+    _check(lib().hwave_tune_save(os.fsencode(path), caps, arr, len(es)))
+
+
+def load_tuning(path, cap=64):
+    """Reads what save_tuning wrote (C-ABI hwave_tune_load): {log2 capacity: dict}."""
+    arr = (_Tune * cap)()
+    caps = (ctypes.c_uint32 * cap)()
+    n = ctypes.c_uint32()
+    _check(lib().hwave_tune_load(os.fsencode(path), caps, arr, cap, ctypes.byref(n)))
+    names = {v: k for k, v in DESIGNS.items()}
+    return {int(caps[i]): {"design": names[arr[i].design], "bucket": arr[i].bucket_slots, "tile": arr[i].tile,
+                           "kv_bits": arr[i].kv_bits, "gops": arr[i].gops, "full_ops": arr[i].full_ops}
+            for i in range(n.value)}

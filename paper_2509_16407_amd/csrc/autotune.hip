@@ -7,6 +7,9 @@
 // capacity class, at run time.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstring>
+
 #include <cstring>
 #include <vector>
 
@@ -192,6 +195,56 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
   }
   if (n_results) *n_results = nres;
   return best->gops > 0 ? HWAVE_OK : HWAVE_EUNSUPPORTED;
+}
+
+int hwave_tune_save(const char* path, const uint32_t* log2_capacity, const hwave_tune_result* best, uint32_t n) {
+  if (!path || (n && (!log2_capacity || !best))) return HWAVE_EINVAL;
+  FILE* f = fopen(path, "w");
+  if (!f) return HWAVE_EIO;
+  bool ok = fprintf(f, "hwave-tune 1\n") > 0;
+  for (uint32_t i = 0; ok && i < n; i++) {
+    const hwave_tune_result& r = best[i];
+    ok = fprintf(f, "%u %u %u %u %u %.17g %llu\n", log2_capacity[i], r.kv_bits, r.design, r.bucket_slots, r.tile,
+                 r.gops, (unsigned long long)r.full_ops) > 0;
+  }
+  ok = (fclose(f) == 0) && ok;
+  return ok ? HWAVE_OK : HWAVE_EIO;
+}
+
+int hwave_tune_load(const char* path, uint32_t* log2_capacity, hwave_tune_result* best, uint32_t cap,
+                    uint32_t* n) {
+  if (!path || !n || (cap && (!log2_capacity || !best))) return HWAVE_EINVAL;
+  *n = 0;
+  FILE* f = fopen(path, "r");
+  if (!f) return HWAVE_EIO;
+  char line[256];
+  int rc = HWAVE_OK;
+  if (!fgets(line, sizeof line, f) || strcmp(line, "hwave-tune 1\n") != 0) rc = HWAVE_EIO;
+  uint32_t count = 0;
+  while (rc == HWAVE_OK && fgets(line, sizeof line, f)) {
+    unsigned e, kv, d, b, t;
+    double g;
+    unsigned long long full;
+    char tail;
+    if (sscanf(line, "%u %u %u %u %u %lg %llu %c", &e, &kv, &d, &b, &t, &g, &full, &tail) != 7 || e > 40 ||
+        (kv != 32 && kv != 64) || d > (unsigned)HWAVE_CUCKOO || b == 0 || b > 1024 || t == 0 || t > 64 ||
+        count == cap) {
+      rc = HWAVE_EIO;
+      break;
+    }
+    log2_capacity[count] = e;
+    hwave_tune_result& r = best[count];
+    r.design = d;
+    r.bucket_slots = b;
+    r.tile = t;
+    r.kv_bits = kv;
+    r.gops = g;
+    r.full_ops = full;
+    count++;
+  }
+  fclose(f);
+  if (rc == HWAVE_OK) *n = count;
+  return rc;
 }
 
 }  // extern "C"

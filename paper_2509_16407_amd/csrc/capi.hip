@@ -496,6 +496,7 @@ const char* hwave_strerror(int code) {
     case HWAVE_ENOMEM: return "out of device memory or buffer too small";
     case HWAVE_EDEVICE: return "HIP error (see hwave_last_hip_error)";
     case HWAVE_EUNSUPPORTED: return "no kernel instance for this configuration";
+    case HWAVE_EIO: return "file could not be read or written, or is malformed";
   }
   return "unknown error";
 }
