@@ -160,6 +160,31 @@ class FullInsert(Exception):
     """Some distinct key ended FULL: both of its buckets were full when it was placed."""
 
 
+def probe_counts(step: Step, design: str) -> dict:
+    """Lines per query measured by the GPU (Table 1's probe unit, Section 5.1): an
+    instrumented table of the step's size filled to 0.9, then the step's positive
+    and negative query sets, counted by the kernels themselves
+    (hwave_probe_counters).  Not part of the timed step."""
+    import torch
+    import paper_2509_16407_amd as hw
+    t = hw.Table(step.t.capacity, design, bucket=step.t.bucket_slots, tile=step.t.tile, instrumented=True)
+    b2 = step.bounds[-1]
+    st = t.insert(step.keys[:b2], step.vals[:b2])
+    n_full = int((st == 3).sum().item())
+    t.probe_counters(reset=True)
+    f, _ = t.query(step.qpos, out=step.out, found=step.st[: len(step.qpos)])
+    found = int((f == 1).sum().item())
+    pos = t.probe_counters(reset=True)
+    t.query(step.qneg, out=step.out, found=step.st[: len(step.qneg)])
+    neg = t.probe_counters(reset=True)
+    del t
+    torch.cuda.empty_cache()
+    per = lambda c: round((c["bucket_lines"] + c["slot_lines"]) / max(1, c["queries"]), 4)
+    return {"design": design, "load": 0.9, "positive_lines_per_query": per(pos),
+            "negative_lines_per_query": per(neg), "positive_found": found, "full_inserts": n_full,
+            "counters": {"positive": pos, "negative": neg}}
+
+
 def upsert_miss(step: Step, reps: int = 3) -> dict:
     """The upsert-miss path (not part of the step): fill a cleared table to 0.75,
     then time the 0.75 -> 0.9 keys as SUM upserts, which all insert.  Median of
@@ -855,6 +880,7 @@ def main():
     ap.add_argument("--cfg3-batches", type=int, default=256,
                     help="mixed 2^20-op batches of config 3 (DOUBLE_M, 2^27 slots; 0 to skip)")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-probes", action="store_true", help="skip the GPU-counted probes (instrumented build)")
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-table (batched) section")
     ap.add_argument("--no-served", action="store_true", help="skip the serving section")
     ap.add_argument("--no-cpu", action="store_true")
@@ -932,6 +958,11 @@ def main():
     roof = roofline(phase_ms, per_step_ops, args.steps, load_traffic())
     rates["upsert_miss_0.9"] = upsert_miss(step)
     log("upsert misses 0.75 -> 0.9: %.2f Gops/s" % rates["upsert_miss_0.9"]["gops"])
+    probes = None
+    if not args.no_probes:
+        probes = probe_counts(step, args.design)
+        log("probes at 0.9 (GPU-counted lines per query): positive %.3f, negative %.3f"
+            % (probes["positive_lines_per_query"], probes["negative_lines_per_query"]))
 
     cfg = {"workload": "load benchmark at 2^%d slots on %s (bucket %d, tile %d): insert to "
                        "0.5/0.75/0.9, 2^%d pos+neg queries, 2^%d SUM upserts, erase 50%%, "
@@ -990,7 +1021,8 @@ def main():
         "upsert_gops": rates["upsert"]["gops"], "upsert_miss_gops": rates["upsert_miss_0.9"]["gops"],
         "p50_batch_ms": None if p50 is None else round(p50, 4),
         "p99_batch_ms": None if p99 is None else round(p99, 4),
-        "roofline": roof, "cpu_baseline": cpu, "designs": designs, "mixed_config3": cfg3, "aging": aging,
+        "roofline": roof, "probes": probes, "cpu_baseline": cpu, "designs": designs, "mixed_config3": cfg3,
+        "aging": aging,
         "batched": batched,
         "served": served,
         "kernel_source_hash": kernel_source_hash(),

@@ -380,6 +380,23 @@ int hwave_server_destroy(hwave_server* s);
 /* Seconds on the server's monotonic clock. */
 double hwave_now(void);
 
+/* Query probe counters (the paper's probe unit, Section 5.1: unique 128-byte
+ * lines a query touches), kept by instrumented builds of the library
+ * (libhashwave_instr.so, compiled with -DHW_INSTRUMENT; its queries pay an
+ * atomic per counted line).  Since the table's creation or the last reset:
+ * queries counted, lines of buckets / tag buckets / chain nodes they read
+ * (each bucket's lines counted once; slot designs count the lines of the
+ * tile-width steps read up to a hit), and key/value slots read after a tag
+ * match.  Cuckoo queries are not counted.  Synchronises `stream`; reset != 0
+ * zeroes the counters afterwards (on `stream`).  Other builds return
+ * HWAVE_EUNSUPPORTED with *out zeroed. */
+typedef struct {
+  uint64_t queries;
+  uint64_t bucket_lines;
+  uint64_t slot_lines;
+} hwave_probe_stats;
+int hwave_probe_counters(hwave_table* t, hwave_probe_stats* out, int reset, void* stream);
+
 /* Text of a return code; HIP error code of the last failing HIP call. */
 const char* hwave_strerror(int code);
 int hwave_last_hip_error(void);

@@ -17,6 +17,7 @@ __all__ = ["Table", "Multi", "Server", "lib", "autotune", "DESIGNS", "COMBINES",
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhashwave.so")
+LIB_INSTR_PATH = os.path.join(HERE, "libhashwave_instr.so")
 
 DESIGNS = {"DOUBLE": 0, "DOUBLE_M": 1, "P2": 2, "P2_M": 3, "ICEBERG": 4, "ICEBERG_M": 5, "CHAINING": 6, "CUCKOO": 7}
 COMBINES = {"sum": 0, "keep": 1, "replace": 2, "min": 3, "max": 4}
@@ -48,6 +49,10 @@ class _Tune(ctypes.Structure):
                 ("kv_bits", ctypes.c_uint32), ("gops", ctypes.c_double), ("full_ops", ctypes.c_uint64)]
 
 
+class _Probe(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_uint64), ("bucket_lines", ctypes.c_uint64), ("slot_lines", ctypes.c_uint64)]
+
+
 class _Request(ctypes.Structure):
     _fields_ = [("table", ctypes.c_uint32), ("op", ctypes.c_uint32), ("n", ctypes.c_uint64),
                 ("h_keys", ctypes.c_void_p), ("h_vals", ctypes.c_void_p), ("h_vals_out", ctypes.c_void_p),
@@ -74,17 +79,24 @@ class _Raw(ctypes.Structure):
 
 
 _lib = None
+_lib_instr = None
 
 
-def lib():
-    """The loaded C library (raises if it has not been built)."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(instrumented: bool = False):
+    """The loaded C library (raises if it has not been built); `instrumented`:
+    the build that keeps query probe counters (hwave_probe_counters)."""
+    global _lib, _lib_instr
+    path = LIB_INSTR_PATH if instrumented else LIB_PATH
+    if (_lib_instr if instrumented else _lib) is None:
+        if not os.path.exists(path):
             raise HashWaveError("%s is missing: build it with __graft_entry__.build() "
-                                "(no CPU fallback exists)" % LIB_PATH)
-        _lib = _bind(ctypes.CDLL(LIB_PATH))
-    return _lib
+                                "(no CPU fallback exists)" % path)
+        L = _bind(ctypes.CDLL(path))
+        if instrumented:
+            _lib_instr = L
+        else:
+            _lib = L
+    return _lib_instr if instrumented else _lib
 
 
 def _bind(L):
@@ -127,6 +139,7 @@ def _bind(L):
         "hwave_autotune": (I, [ctypes.c_uint32, U64, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.POINTER(_Tune), ctypes.c_uint32,
                                ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_Tune), P]),
+        "hwave_probe_counters": (I, [P, ctypes.POINTER(_Probe), I, P]),
         "hwave_tune_save": (I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_Tune),
                                 ctypes.c_uint32]),
         "hwave_tune_load": (I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_Tune),
@@ -165,9 +178,11 @@ class Table:
     """
 
     def __init__(self, capacity: int, design: str = "P2_M", kv_bits: int = 64, bucket: int = 0,
-                 tile: int = 0, probe_cap: int = 0, flags: int = 0, device=None, stream=None):
+                 tile: int = 0, probe_cap: int = 0, flags: int = 0, device=None, stream=None,
+                 instrumented: bool = False):
         import torch
-        L = lib()
+        L = lib(instrumented)
+        self._L = L
         self.design = design
         self.design_id = DESIGNS[design]
         self.cfg = _Config(kv_bits, bucket, tile, probe_cap, flags)
@@ -197,7 +212,7 @@ class Table:
     # -- lifetime
     def close(self):
         if getattr(self, "h", None):
-            lib().hwave_destroy(self.h)
+            self._L.hwave_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -222,19 +237,19 @@ class Table:
 
     # -- operations (asynchronous on the current or given stream)
     def clear(self, stream=None):
-        _check(lib().hwave_clear(self.h, _stream(stream)))
+        _check(self._L.hwave_clear(self.h, _stream(stream)))
 
     def insert(self, keys, vals, status=None, stream=None):
         n = keys.numel()
         status = self._u8(n) if status is None else status
-        _check(lib().hwave_insert(self.h, _ptr(self._keys(keys)), _ptr(self._keys(vals)), n,
+        _check(self._L.hwave_insert(self.h, _ptr(self._keys(keys)), _ptr(self._keys(vals)), n,
                                   _ptr(status), _stream(stream)))
         return status
 
     def upsert(self, keys, vals, combine="sum", status=None, stream=None):
         n = keys.numel()
         status = self._u8(n) if status is None else status
-        _check(lib().hwave_upsert(self.h, _ptr(self._keys(keys)), _ptr(self._keys(vals)), n,
+        _check(self._L.hwave_upsert(self.h, _ptr(self._keys(keys)), _ptr(self._keys(vals)), n,
                                   COMBINES[combine], _ptr(status), _stream(stream)))
         return status
 
@@ -242,21 +257,21 @@ class Table:
         n = keys.numel()
         out = self._empty(n) if out is None else out
         found = self._u8(n) if found is None else found
-        _check(lib().hwave_query(self.h, _ptr(self._keys(keys)), n, _ptr(out), _ptr(found),
+        _check(self._L.hwave_query(self.h, _ptr(self._keys(keys)), n, _ptr(out), _ptr(found),
                                  _stream(stream)))
         return found, out
 
     def erase(self, keys, found=None, stream=None):
         n = keys.numel()
         found = self._u8(n) if found is None else found
-        _check(lib().hwave_erase(self.h, _ptr(self._keys(keys)), n, _ptr(found), _stream(stream)))
+        _check(self._L.hwave_erase(self.h, _ptr(self._keys(keys)), n, _ptr(found), _stream(stream)))
         return found
 
     def mixed(self, ops, keys, vals, combine="sum", out=None, status=None, stream=None):
         n = keys.numel()
         out = self._empty(n) if out is None else out
         status = self._u8(n) if status is None else status
-        _check(lib().hwave_mixed(self.h, _ptr(ops), _ptr(self._keys(keys)),
+        _check(self._L.hwave_mixed(self.h, _ptr(ops), _ptr(self._keys(keys)),
                                  None if vals is None else _ptr(self._keys(vals)), n,
                                  COMBINES[combine], _ptr(out), _ptr(status), _stream(stream)))
         return status, out
@@ -264,7 +279,7 @@ class Table:
     def size(self, stream=None) -> int:
         import torch
         c = torch.zeros(1, dtype=torch.int64, device=self.device)
-        _check(lib().hwave_size(self.h, _ptr(c), _stream(stream)))
+        _check(self._L.hwave_size(self.h, _ptr(c), _stream(stream)))
         return int(c.item())
 
     def export(self, stream=None):
@@ -273,16 +288,22 @@ class Table:
         k = self._empty(self.capacity)
         v = self._empty(self.capacity)
         c = torch.zeros(1, dtype=torch.int64, device=self.device)
-        _check(lib().hwave_export(self.h, _ptr(k), _ptr(v), _ptr(c), _stream(stream)))
+        _check(self._L.hwave_export(self.h, _ptr(k), _ptr(v), _ptr(c), _stream(stream)))
         n = int(c.item())
         return k[:n], v[:n]
 
     def primary_bucket(self, keys, stream=None):
         n = keys.numel()
         out = self._empty(n, dtype=__import__("torch").int64)
-        _check(lib().hwave_primary_bucket(self.h, _ptr(self._keys(keys)), n, _ptr(out),
+        _check(self._L.hwave_primary_bucket(self.h, _ptr(self._keys(keys)), n, _ptr(out),
                                           _stream(stream)))
         return out
+
+    def probe_counters(self, reset: bool = False, stream=None) -> dict:
+        """Query probe counters (instrumented tables only, C-ABI hwave_probe_counters)."""
+        c = _Probe()
+        _check(self._L.hwave_probe_counters(self.h, ctypes.byref(c), int(bool(reset)), _stream(stream)))
+        return {"queries": c.queries, "bucket_lines": c.bucket_lines, "slot_lines": c.slot_lines}
 
     def raw(self):
         """Views of the raw device image: dict(slots=uint8, tags=int16 or None, locks=int32)."""

@@ -272,8 +272,25 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   tv.aggregate = (c.flags & HWAVE_F_AGGREGATE) ? 1u : 0u;
   tv.hot_tag = L.off_hot ? (uint64_t*)(b + L.off_hot) : nullptr;
   tv.hot_acc = L.off_hot ? tv.hot_tag + HOT_N : nullptr;
+  tv.probe_ctr = nullptr;
+#ifdef HW_INSTRUMENT
+  {
+    const size_t pb = (size_t)PROBE_STRIPES * 16 * sizeof(unsigned long long);
+    e = hipMalloc((void**)&tv.probe_ctr, pb);
+    if (e != hipSuccess) {
+      tv.probe_ctr = nullptr;
+      return hip_fail(e);
+    }
+    hipLaunchKernelGGL(k_fill16, dim3(1), dim3(256), 0, (hipStream_t)stream, (uint4*)tv.probe_ctr, pb / 16, 0u);
+  }
+#endif
   t->la.max_blocks = max_blocks_for(dev);
-  return hwave_clear(t, stream);
+  const int rc = hwave_clear(t, stream);
+  if (rc && tv.probe_ctr) {
+    (void)hipFree(tv.probe_ctr);
+    tv.probe_ctr = nullptr;
+  }
+  return rc;
 }
 
 bool bad_ptr(const void* p) { return p == nullptr; }
@@ -360,6 +377,7 @@ int hwave_destroy(hwave_table* t) {
   if (!t) return HWAVE_EINVAL;
   hipError_t e = hipDeviceSynchronize();
   int rc = e == hipSuccess ? HWAVE_OK : hip_fail(e);
+  if (t->la.tv.probe_ctr) (void)hipFree(t->la.tv.probe_ctr);
   if (t->owns) {
     e = hipFree(t->base);
     if (e != hipSuccess && rc == HWAVE_OK) rc = hip_fail(e);
@@ -472,6 +490,29 @@ int hwave_primary_bucket(hwave_table* t, const void* d_keys, uint64_t n, uint64_
                        t->la.tv.bucket_mask, nf, d_out);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
+int hwave_probe_counters(hwave_table* t, hwave_probe_stats* out, int reset, void* stream) {
+  if (!t || !out) return HWAVE_EINVAL;
+  memset(out, 0, sizeof *out);
+  unsigned long long* d = t->la.tv.probe_ctr;
+  if (!d) return HWAVE_EUNSUPPORTED;  // not an instrumented build
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<unsigned long long> h((size_t)PROBE_STRIPES * 16);
+  hipError_t e = hipMemcpyAsync(h.data(), d, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e);
+  for (uint32_t i = 0; i < PROBE_STRIPES; i++) {
+    out->bucket_lines += h[i * 16 + PC_BUCKET];
+    out->slot_lines += h[i * 16 + PC_SLOT];
+    out->queries += h[i * 16 + PC_QUERY];
+  }
+  if (reset) {
+    hipLaunchKernelGGL(k_fill16, dim3(1), dim3(256), 0, s, (uint4*)d, h.size() * sizeof(unsigned long long) / 16, 0u);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return HWAVE_OK;
 }
 
 int hwave_raw(const hwave_table* t, hwave_raw_view* out) {

@@ -84,7 +84,27 @@ struct TableDev {
   uint32_t aggregate;    // merge duplicate keys of a write batch first (hw_agg.hpp)
   uint64_t* hot_tag;     // HOT_N entry tags, or null (see HOT_ROWS)
   uint64_t* hot_acc;     // HOT_N accumulators
+  unsigned long long* probe_ctr;  // instrumented builds: PROBE_STRIPES query probe counters; else null
 };
+
+// Query probe counters of instrumented builds (-DHW_INSTRUMENT): PROBE_STRIPES
+// stripes of 16 words, one 128-byte line each, picked by wave; word PC_BUCKET
+// counts the unique 128-byte lines of buckets, tag buckets and chain nodes a
+// query reads, PC_SLOT the key/value slots it reads after a tag match, PC_QUERY
+// the queries.  Other builds compile the counting out.
+constexpr uint32_t PROBE_STRIPES = 64;
+enum : int { PC_BUCKET = 0, PC_SLOT = 1, PC_QUERY = 2 };
+
+__device__ __forceinline__ void probe_add(const TableDev& tv, int word, uint64_t n) {
+#ifdef HW_INSTRUMENT
+  if (!tv.probe_ctr || n == 0) return;
+  const uint32_t stripe = (blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64) % PROBE_STRIPES;
+  __hip_atomic_fetch_add(tv.probe_ctr + stripe * 16 + word, (unsigned long long)n, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+#else
+  (void)tv; (void)word; (void)n;
+#endif
+}
 
 // BSP_: the phased (bulk-synchronous) variant used to measure what concurrency
 // costs (Section 6.4): writes take no lock and queries read with plain cacheable
@@ -164,6 +184,12 @@ struct Ops {
     }
   }
 
+  // Unique 128-byte lines of a slot bucket read in its first `steps` tile-width
+  // steps (buckets start on a line).
+  static constexpr uint32_t lines_after(int steps) {
+    return (uint32_t)(((uint64_t)steps * T * SPL * 2 * sizeof(K) + 127) / 128);
+  }
+
   // Sum over the tile of a per-lane count.
   __device__ static __forceinline__ uint32_t tile_sum(uint32_t x) {
 #pragma unroll
@@ -177,7 +203,8 @@ struct Ops {
   // Slot designs read the bucket one tile-width at a time and stop at a hit;
   // tag designs read the tag bucket once and check each tag match against the
   // full key (tags are lossy, Section 4.3).
-  template <bool FIND, bool PLAIN = false>
+  // COUNT: a query's scan, counted by instrumented builds (probe_add).
+  template <bool FIND, bool PLAIN = false, bool COUNT = false>
   __device__ static BucketScan<K> scan(const TableDev& tv, const Tile<T>& tile, uint32_t b, K key,
                                        uint32_t tag) {
     BucketScan<K> r;
@@ -217,6 +244,9 @@ struct Ops {
             if constexpr (SPL == 2) vv = j ? v[1] : v[0];
             r.val = tile.bcast(vv, src);
             r.hit = s * T * SPL + src * SPL + j;
+            if constexpr (COUNT) {
+              if (tile.leader()) probe_add(tv, PC_BUCKET, lines_after(s + 1));
+            }
             return r;
           }
         }
@@ -236,6 +266,9 @@ struct Ops {
         occ += (uint32_t)__popc(~m_free & ((1u << SPL) - 1));
       }
       r.fill = tile_sum(occ);
+      if constexpr (COUNT) {
+        if (tile.leader()) probe_add(tv, PC_BUCKET, lines_after(C::STEPS));
+      }
     } else {
       uint32_t tw[(TPL + 1) / 2];
       const uint32_t* tp = tv.tagw + (base + (uint64_t)tile.tl * TPL) / 2;
@@ -253,6 +286,9 @@ struct Ops {
         tw[0] = rd<PLAIN>(tp);
       } else {
         tw[0] = rd<PLAIN>((const uint16_t*)tv.tagw + base + tile.tl);
+      }
+      if constexpr (COUNT) {
+        if (tile.leader()) probe_add(tv, PC_BUCKET, (2 * B + 127) / 128);
       }
       uint32_t m_hit = 0, m_free = 0, m_empty = 0;
 #pragma unroll
@@ -273,6 +309,9 @@ struct Ops {
             mm &= mm - 1;
             K k, v;
             load_slot<PLAIN>(tv, base + src * TPL + j, k, v);
+            if constexpr (COUNT) {
+              if (tile.leader()) probe_add(tv, PC_SLOT, 1);
+            }
             if (k == key) {
               r.hit = src * TPL + j;
               r.val = v;
@@ -709,10 +748,14 @@ struct Ops {
   // holding a tile forever.
   __device__ static __forceinline__ uint32_t max_chain(const TableDev& tv) { return tv.pool_nodes + 1; }
 
+  template <bool COUNT = false>
   __device__ static int64_t chain_find(const TableDev& tv, const Tile<T>& tile, uint32_t b, K key, K* val) {
     uint64_t node = b;
     for (uint32_t i = 0; i < max_chain(tv) && node != NIL; ++i) {
       const NodeScan r = scan_node<C::BSP>(tv, tile, node, key);
+      if constexpr (COUNT) {
+        if (tile.leader()) probe_add(tv, PC_BUCKET, 1);
+      }
       if (r.hit >= 0) { *val = r.val; return (int64_t)(node * 8 + r.hit); }
       node = r.next;
     }
@@ -784,20 +827,21 @@ struct Ops {
   }
 
   // Lock-free search (Section 4.2): the slot holding `key`, or -1.  Value in *val.
+  template <bool COUNT = false>
   __device__ static int64_t find(const TableDev& tv, const Tile<T>& tile, const Home& h, K key,
                                  uint32_t tag, K* val) {
     if constexpr (C::CHAIN) {
-      return chain_find(tv, tile, h.b1, key, val);
+      return chain_find<COUNT>(tv, tile, h.b1, key, val);
     } else if constexpr (C::ICEBERG) {
-      BucketScan<K> r = scan<true, C::BSP>(tv, tile, h.b1, key, tag);
+      BucketScan<K> r = scan<true, C::BSP, COUNT>(tv, tile, h.b1, key, tag);
       if (r.hit >= 0) { *val = r.val; return (int64_t)h.b1 * B + r.hit; }
       // The flag is read after the front bucket: a free slot seen there that an
       // erase made is seen together with the flag the erase set first.
       if (r.free >= 0 && !erased(tv, tile)) return -1;
-      r = scan<true, C::BSP>(tv, tile, h.h2, key, tag);
+      r = scan<true, C::BSP, COUNT>(tv, tile, h.h2, key, tag);
       if (r.hit >= 0) { *val = r.val; return (int64_t)h.h2 * B + r.hit; }
       if (h.b3 != h.h2) {
-        r = scan<true, C::BSP>(tv, tile, h.b3, key, tag);
+        r = scan<true, C::BSP, COUNT>(tv, tile, h.b3, key, tag);
         if (r.hit >= 0) { *val = r.val; return (int64_t)h.b3 * B + r.hit; }
       }
       return -1;
@@ -805,17 +849,17 @@ struct Ops {
       const uint32_t step = step_of(tv, h);
       uint32_t b = h.b1;
       for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
-        BucketScan<K> r = scan<true, C::BSP>(tv, tile, b, key, tag);
+        BucketScan<K> r = scan<true, C::BSP, COUNT>(tv, tile, b, key, tag);
         if (r.hit >= 0) { *val = r.val; return (int64_t)b * B + r.hit; }
         if (r.has_empty) break;
       }
       return -1;
     } else {
-      BucketScan<K> r = scan<true, C::BSP>(tv, tile, h.b1, key, tag);
+      BucketScan<K> r = scan<true, C::BSP, COUNT>(tv, tile, h.b1, key, tag);
       if (r.hit >= 0) { *val = r.val; return (int64_t)h.b1 * B + r.hit; }
       const uint32_t b2 = h.h2 & tv.bucket_mask;
       if (b2 != h.b1) {
-        r = scan<true, C::BSP>(tv, tile, b2, key, tag);
+        r = scan<true, C::BSP, COUNT>(tv, tile, b2, key, tag);
         if (r.hit >= 0) { *val = r.val; return (int64_t)b2 * B + r.hit; }
       }
       return -1;
@@ -1052,7 +1096,12 @@ struct Ops {
     if constexpr (C::CUCKOO) return cuckoo_locked(tv, tile, key, false, out);
     const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
+#ifdef HW_INSTRUMENT
+    if (tile.leader()) probe_add(tv, PC_QUERY, 1);
+    return find<true>(tv, tile, h, key, tag, out) >= 0 ? ST_DONE : ST_MISS;
+#else
     return find(tv, tile, h, key, tag, out) >= 0 ? ST_DONE : ST_MISS;
+#endif
   }
 
   // Erase under the primary lock (none in the phased variant).  ST_DONE if

@@ -1,0 +1,77 @@
+"""Probe counts measured on the GPU against the oracle's probe model.
+
+The instrumented build (libhashwave_instr.so) counts, per query, the unique
+128-byte lines of buckets, tag buckets and chain nodes it reads, and the
+key/value slots it reads after a tag match (the paper's probe unit, Section
+5.1).  The oracle's layout checker computes the same quantity from the table
+image with its own restatement of the hash and placement rules.  The two must
+agree exactly on bucket lines; slot reads are one per positive query plus tag
+false positives (a 16-bit tag matches a foreign key with probability 2^-16 per
+compared tag), whose count is bounded."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2509_16407_amd as hw
+from paper_2509_16407_amd import workloads as w
+from gpu_util import dev, image, u8
+
+pytestmark = pytest.mark.gpu
+
+ODESIGN = {"DOUBLE": oracle.DOUBLE, "DOUBLE_M": oracle.DOUBLE_M, "P2": oracle.P2, "P2_M": oracle.P2_M,
+           "ICEBERG": oracle.ICEBERG, "ICEBERG_M": oracle.ICEBERG_M}
+TAGS = {"DOUBLE_M", "P2_M", "ICEBERG_M"}
+
+
+def _reports(t, neg):
+    slots, tags, locks = image(t)
+    if t.design == "CHAINING":
+        nv, rep = oracle.chain_check(t.num_buckets, slots, locks, neg_keys=neg)
+    else:
+        nv, rep = oracle.layout_check(ODESIGN[t.design], t.kv_bits, t.num_buckets, t.bucket_slots, slots, tags,
+                                      locks, neg_keys=neg, tile_bytes=t.tile * 16)
+    assert nv == 0, rep
+    return rep
+
+
+@pytest.mark.parametrize("design,bits,bucket,tile", [
+    ("DOUBLE", 64, 8, 8), ("DOUBLE", 64, 8, 4), ("DOUBLE", 64, 32, 8), ("DOUBLE_M", 64, 32, 4),
+    ("P2", 64, 32, 8), ("P2_M", 64, 32, 4), ("P2_M", 64, 64, 8), ("ICEBERG", 64, 32, 8),
+    ("ICEBERG_M", 64, 32, 4), ("CHAINING", 64, 0, 0), ("DOUBLE", 32, 16, 8), ("P2_M", 32, 32, 4),
+], ids=lambda x: str(x))
+def test_query_probe_counts_equal_the_oracle_model(design, bits, bucket, tile):
+    cap = 1 << 16
+    t = hw.Table(cap, design, kv_bits=bits, bucket=bucket, tile=tile, instrumented=True)
+    seed = w.stream_seed(150, hw.DESIGNS[design] * 1000 + bits * 10 + tile)
+    n = int(0.9 * (cap if design != "CHAINING" else t.num_buckets * 7))
+    pool = w.distinct_keys(seed, n + 30000, key_bits=bits)
+    keys, neg = pool[:n], pool[n:]
+    st = u8(t.insert(dev(keys, bits), dev(w.value_of(keys, bits), bits)))
+    assert (st == hw.ST_DONE).all()
+    rep = _reports(t, neg)
+    t.probe_counters(reset=True)
+    found, _ = t.query(dev(keys, bits))
+    assert (u8(found) == 1).all()
+    pos = t.probe_counters(reset=True)
+    found, _ = t.query(dev(neg, bits))
+    assert (u8(found) == 0).all()
+    negc = t.probe_counters(reset=True)
+    assert pos["queries"] == n and negc["queries"] == len(neg)
+    fp_bound = lambda q: 0.003 * q + 8  # tag false positives
+    if design in TAGS:
+        # the model counts one key/value line per positive query
+        assert pos["bucket_lines"] + n == rep["pos_probe_sum"], (pos, rep["pos_probe_sum"])
+        assert n <= pos["slot_lines"] <= n + fp_bound(n)
+        assert negc["bucket_lines"] == rep["neg_probe_sum"], (negc, rep["neg_probe_sum"])
+        assert negc["slot_lines"] <= fp_bound(len(neg))
+    else:
+        assert pos["bucket_lines"] == rep["pos_probe_sum"], (pos, rep["pos_probe_sum"])
+        assert negc["bucket_lines"] == rep["neg_probe_sum"], (negc, rep["neg_probe_sum"])
+        assert pos["slot_lines"] == 0 and negc["slot_lines"] == 0
+
+
+def test_probe_counters_absent_from_the_plain_build():
+    """The product library keeps no counters: the call reports EUNSUPPORTED."""
+    t = hw.Table(1 << 12, "P2_M")
+    with pytest.raises(hw.HashWaveError):
+        t.probe_counters()
