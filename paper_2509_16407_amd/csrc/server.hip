@@ -87,23 +87,31 @@ bool writes(uint32_t op) {
   return k == HWAVE_OP_INSERT || k == HWAVE_OP_UPSERT || k == HWAVE_OP_ERASE;
 }
 
-// One block per chunk.  Loads and stores are system-scope (they bypass the GPU
-// caches), so a pinned buffer the host has refilled is never read stale and
-// results reach host memory; 8-byte words when both ends allow, bytes otherwise.
-__global__ void __launch_bounds__(256) k_copy_chunks(const CopyChunk* __restrict__ list) {
-  const CopyChunk c = list[blockIdx.x];
-  const uint64_t n8 = ((c.dst | c.src) & 7) == 0 ? c.bytes / 8 : 0;
-  uint64_t* d8 = (uint64_t*)c.dst;
-  const uint64_t* s8 = (const uint64_t*)c.src;
+// Blocks walk the chunk list (block b takes chunks b, b + grid, ...).  Loads and
+// stores are system-scope (they bypass the GPU caches), so a pinned buffer the
+// host has refilled is never read stale and results reach host memory; 8-byte
+// words when both ends allow, bytes otherwise.  The grid is kept small
+// (COPY_BLOCKS): PCIe bandwidth needs only ~100 KiB in flight, and the copies
+// run beside another batch's multi-table kernel, whose persistent grid needs
+// the wave slots.
+constexpr unsigned COPY_BLOCKS = 128;
+
+__global__ void __launch_bounds__(256) k_copy_chunks(const CopyChunk* __restrict__ list, uint32_t n) {
+  for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const CopyChunk c = list[k];
+    const uint64_t n8 = ((c.dst | c.src) & 7) == 0 ? c.bytes / 8 : 0;
+    uint64_t* d8 = (uint64_t*)c.dst;
+    const uint64_t* s8 = (const uint64_t*)c.src;
 #pragma unroll 4
-  for (uint64_t i = threadIdx.x; i < n8; i += 256)
-    __hip_atomic_store(d8 + i, __hip_atomic_load(s8 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  uint8_t* d1 = (uint8_t*)c.dst;
-  const uint8_t* s1 = (const uint8_t*)c.src;
-  for (uint64_t i = n8 * 8 + threadIdx.x; i < c.bytes; i += 256)
-    __hip_atomic_store(d1 + i, __hip_atomic_load(s1 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    for (uint64_t i = threadIdx.x; i < n8; i += 256)
+      __hip_atomic_store(d8 + i, __hip_atomic_load(s8 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    uint8_t* d1 = (uint8_t*)c.dst;
+    const uint8_t* s1 = (const uint8_t*)c.src;
+    for (uint64_t i = n8 * 8 + threadIdx.x; i < c.bytes; i += 256)
+      __hip_atomic_store(d1 + i, __hip_atomic_load(s1 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 // Device address of pinned host memory at p (null stays null); false if p is
@@ -232,7 +240,8 @@ bool launch_batch(hwave_server* s, Slot& sl) {
     }
   }
   if (n) {
-    hipLaunchKernelGGL(k_copy_chunks, dim3((unsigned)n), dim3(256), 0, s->s_in, sl.g_in);
+    hipLaunchKernelGGL(k_copy_chunks, dim3(n < COPY_BLOCKS ? (unsigned)n : COPY_BLOCKS), dim3(256), 0, s->s_in,
+                       sl.g_in, (uint32_t)n);
     if (hipGetLastError() != hipSuccess) fail(s, HWAVE_EDEVICE);
   }
   (void)hipEventRecord(sl.h2d, s->s_in);
@@ -257,7 +266,8 @@ bool launch_batch(hwave_server* s, Slot& sl) {
     }
   }
   if (n) {
-    hipLaunchKernelGGL(k_copy_chunks, dim3((unsigned)n), dim3(256), 0, s->s_out, sl.g_out);
+    hipLaunchKernelGGL(k_copy_chunks, dim3(n < COPY_BLOCKS ? (unsigned)n : COPY_BLOCKS), dim3(256), 0, s->s_out,
+                       sl.g_out, (uint32_t)n);
     if (hipGetLastError() != hipSuccess) fail(s, HWAVE_EDEVICE);
   }
   (void)hipEventRecord(sl.d2h, s->s_out);
