@@ -359,6 +359,8 @@ typedef struct {
   double mean_requests_per_batch;
   double wall_s;                      /* first arrival to last completion     */
   double p50_ms, p99_ms, max_ms, mean_ms; /* completion - arrival             */
+  uint64_t runtime_copied;            /* batched requests moved by runtime
+                                         copies (arrays not device-mapped)    */
 } hwave_serve_stats;
 
 /* The tables (same key width; in the multi-table menu for batched mode) must

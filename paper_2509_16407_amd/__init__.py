@@ -68,7 +68,7 @@ class _ServeStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_uint64), ("ops", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("mean_requests_per_batch", ctypes.c_double), ("wall_s", ctypes.c_double),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
-                ("mean_ms", ctypes.c_double)]
+                ("mean_ms", ctypes.c_double), ("runtime_copied", ctypes.c_uint64)]
 
 
 class _Raw(ctypes.Structure):

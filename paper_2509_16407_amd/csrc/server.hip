@@ -154,7 +154,9 @@ struct hwave_server {
   std::unordered_map<uint64_t, Req*> by_ticket;
   std::vector<double> latencies;
   uint64_t next_ticket = 1;
-  uint64_t n_done = 0, ops_done = 0, batches = 0, batch_reqs = 0;
+  uint64_t n_done = 0, ops_done = 0;
+  // written by the worker outside `mu`, read by hwave_server_stats
+  std::atomic<uint64_t> batches{0}, batch_reqs{0}, runtime_copied{0};
   double t_first = 0, t_last = 0;
   bool stop = false;
   int error = 0;
@@ -235,6 +237,7 @@ bool launch_batch(hwave_server* s, Slot& sl) {
       add_chunks(sl.h_in, &n, dk, q->g_keys, q->r.n * kb);
       if (wv) add_chunks(sl.h_in, &n, dv, q->g_vals, q->r.n * kb);
     } else {
+      s->runtime_copied++;
       (void)hipMemcpyAsync(dk, q->r.h_keys, q->r.n * kb, hipMemcpyHostToDevice, s->s_in);
       if (wv) (void)hipMemcpyAsync(dv, q->r.h_vals, q->r.n * kb, hipMemcpyHostToDevice, s->s_in);
     }
@@ -475,9 +478,11 @@ int hwave_server_stats(hwave_server* s, hwave_serve_stats* out) {
   memset(out, 0, sizeof *out);
   out->requests = s->n_done;
   out->ops = s->ops_done;
-  out->batches = s->batches;
-  out->mean_requests_per_batch = s->batches ? (double)s->batch_reqs / (double)s->batches : 0.0;
+  const uint64_t nb = s->batches.load(), nr = s->batch_reqs.load();
+  out->batches = nb;
+  out->mean_requests_per_batch = nb ? (double)nr / (double)nb : 0.0;
   out->wall_s = s->t_last > s->t_first ? s->t_last - s->t_first : 0.0;
+  out->runtime_copied = s->runtime_copied.load();
   if (!s->latencies.empty()) {
     std::vector<double> v = s->latencies;
     std::sort(v.begin(), v.end());

@@ -152,6 +152,8 @@ def test_served_copy_paths_and_table_kinds(bits, design, flags, pageable_every):
     torch.cuda.synchronize()
     served, st_a = _serve(A, reqs, "batched", 20e-6, bits=bits, pageable_every=pageable_every)
     assert st_a["requests"] == len(reqs)
+    n_pageable = len(range(0, len(reqs), pageable_every)) if pageable_every else 0
+    assert st_a["runtime_copied"] == n_pageable
     for i, (t, op, keys, vals) in enumerate(reqs):
         out_a, s_a = served[i]
         if op == OPQ:
@@ -169,3 +171,57 @@ def test_served_copy_paths_and_table_kinds(bits, design, flags, pageable_every):
         v = v.cpu().numpy().view(np.uint64) if bits == 64 else v.cpu().numpy().view(np.uint32).astype(np.uint64)
         o = np.argsort(k)
         assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov)
+
+
+def test_served_unaligned_pinned_arrays():
+    """Request arrays that are views at odd offsets into pinned buffers (keys 8
+    bytes past a 16-byte boundary, statuses at byte offsets 1..7): the batch copy
+    kernels fall back to word and byte copies, and every output equals the
+    oracle's."""
+    n_tables, universe = 4, 1 << 12
+    uk, reqs = _make_requests(n_tables, universe, 120, seed=71)
+    A = [hw.Table(1 << 14, "P2_M") for _ in range(n_tables)]
+    oms = [oracle.OracleMap() for _ in range(n_tables)]
+    for t in range(n_tables):
+        pre = uk[t][: universe // 2]
+        A[t].insert(_host(pre, 64, False).cuda(), _host(w.value_of(pre), 64, False).cuda())
+        oms[t].insert(pre, w.value_of(pre))
+    torch.cuda.synchronize()
+    total = sum(len(r[2]) for r in reqs)
+    kbuf = torch.zeros(total + 2 * len(reqs), dtype=torch.int64).pin_memory()
+    vbuf = torch.zeros(total + 2 * len(reqs), dtype=torch.int64).pin_memory()
+    obuf = torch.zeros(total + 2 * len(reqs), dtype=torch.int64).pin_memory()
+    sbuf = torch.zeros(total + 8 * len(reqs), dtype=torch.uint8).pin_memory()
+    srv = hw.Server(A, mode="batched", slots=3, slot_ops=1 << 16)
+    rs, views = [], []
+    ka = sa = 0
+    for i, (t, op, keys, vals) in enumerate(reqs):
+        n = len(keys)
+        ka += 1  # 8 bytes past the previous array's end
+        sa += 1 + i % 7
+        k = kbuf[ka: ka + n]
+        k.copy_(torch.from_numpy(keys.view(np.int64)))
+        v = None
+        if vals is not None:
+            v = vbuf[ka: ka + n]
+            v.copy_(torch.from_numpy(vals.view(np.int64)))
+        o = obuf[ka: ka + n]
+        s = sbuf[sa: sa + n]
+        views.append((o, s))
+        rs.append(hw.Server.request(t, op, k, v, o, s))
+        ka += n
+        sa += n
+    srv.replay(rs, np.arange(len(reqs)) * 20e-6)
+    srv.drain()
+    assert srv.stats()["runtime_copied"] == 0  # every request went through the copy kernels
+    srv.close()
+    for i, (t, op, keys, vals) in enumerate(reqs):
+        o, s = views[i][0].numpy().view(np.uint64), views[i][1].numpy()
+        if op == OPQ:
+            os_, ov = oms[t].query(keys)
+            assert np.array_equal(s, os_) and np.array_equal(o, ov), i
+        else:
+            os_ = oms[t].apply(keys, vals, default_op=hw.OPS["insert"] if op == OPI else hw.OPS["upsert"],
+                               combine=oracle.SUM)[0]
+            for code in (1, 2):
+                assert _counts(keys, s, code) == _counts(keys, os_, code), i
