@@ -75,3 +75,67 @@ def test_probe_counters_absent_from_the_plain_build():
     t = hw.Table(1 << 12, "P2_M")
     with pytest.raises(hw.HashWaveError):
         t.probe_counters()
+
+
+def _tag_matches(design, key, nb, tags, slots_keys=None):
+    """Slots a query of `key` reads after a tag match, from the image, following
+    the documented scan order (candidate buckets in order, slots ascending within
+    a bucket, stop at the key).  Returns (slot reads, occupied tags compared)."""
+    B = tags.shape[1]
+    tg = oracle.tag_of(int(key))
+    if design == "P2_M":
+        b1 = oracle.primary_bucket(int(key), nb)
+        b2 = oracle.p2_alternate(int(key), nb)
+        seq = [b1] if b2 == b1 else [b1, b2]
+    elif design == "DOUBLE_M":
+        seq = []
+        for i in range(nb):
+            b = oracle.double_probe(int(key), nb, i)
+            seq.append(b)
+            if (tags[b] == 0xFFFF).any():
+                break
+    else:  # ICEBERG_M, never erased: a front bucket with room ends the search
+        f, b1, b2 = oracle.iceberg_buckets(int(key), nb)
+        seq = [f] if (tags[f] == 0xFFFF).any() else ([f, b1] if b1 == b2 else [f, b1, b2])
+    reads = compared = 0
+    for b in seq:
+        compared += int((tags[b] < 0xFFFE).sum())
+        for j in np.nonzero(tags[b] == tg)[0]:
+            reads += 1
+            if slots_keys is not None and slots_keys[b * B + j] == key:
+                return reads, compared
+    return reads, compared
+
+
+@pytest.mark.parametrize("design", ["P2_M", "DOUBLE_M", "ICEBERG_M"])
+def test_tag_false_positives_exactly_and_at_the_paper_rate(design):
+    """Slot reads after tag matches equal, query by query summed, the matches the
+    image holds along each query's scan; over 2^18 absent keys the match rate per
+    occupied tag compared is the paper's 1/65,536 (Section 4.3), within 5 sigma."""
+    cap = 1 << 18
+    t = hw.Table(cap, design, instrumented=True)
+    seed = w.stream_seed(151, hw.DESIGNS[design])
+    n = int(0.9 * cap)
+    pool = w.distinct_keys(seed, n + (1 << 18))
+    keys, neg = pool[:n], pool[n:]
+    assert (u8(t.insert(dev(keys), dev(w.value_of(keys)))) == hw.ST_DONE).all()
+    slots, tags, _ = image(t)
+    nb = t.num_buckets
+    tags = tags.reshape(nb, t.bucket_slots)
+    sk = slots.view(np.uint64)[0::2]
+    t.probe_counters(reset=True)
+    t.query(dev(neg))
+    c = t.probe_counters(reset=True)
+    exp_reads = compared = 0
+    for k in neg.tolist():
+        r, m = _tag_matches(design, k, nb, tags)
+        exp_reads += r
+        compared += m
+    assert c["slot_lines"] == exp_reads
+    mean = compared / 65534.0  # tags of keys take 65,534 values (two are reserved)
+    assert abs(exp_reads - mean) <= 5 * np.sqrt(mean) + 1, (exp_reads, mean)
+    sample = keys[:20000]
+    t.query(dev(sample))
+    c = t.probe_counters(reset=True)
+    exp_pos = sum(_tag_matches(design, k, nb, tags, slots_keys=sk)[0] for k in sample.tolist())
+    assert c["slot_lines"] == exp_pos
