@@ -267,7 +267,8 @@ def verify_once(step: Step, d) -> None:
 
 def bench_phased(step: Step, d, design: str, conc_rates: dict, reps=3):
     """Cost of concurrency (Section 6.4): the load phases and the query sets on the
-    phased variant of `design` (no locks, plain cacheable loads in queries), against
+    phased variant of `design` (no locks, plain cacheable loads in queries; chaining
+    and cuckoo keep their write locks, so only their queries differ), against
     the same phases of the concurrent table.  Outputs of the first repetition are
     checked by closed form.  Without locks, inserts deciding at once on the same
     bucket pair can crowd it, so a two-choice key may end FULL; such keys are
@@ -275,7 +276,8 @@ def bench_phased(step: Step, d, design: str, conc_rates: dict, reps=3):
     import torch
     import paper_2509_16407_amd as hw
     from paper_2509_16407_amd import workloads as w
-    t = hw.Table(d["cap"], design, flags=hw.F_BSP)
+    # chaining sized as in the concurrent comparison (7 pairs per chain at the end)
+    t = hw.Table(step.bounds[-1] if design == "CHAINING" else d["cap"], design, flags=hw.F_BSP)
     b0, b1, b2 = step.bounds
     nq = step.qpos.numel()
     st_all = torch.empty(b2, dtype=torch.uint8, device="cuda")
@@ -356,8 +358,7 @@ def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
                     "step_gops": round(step.ops_per_step() * steps / wall / 1e9, 4), "phase_gops": rates}
         step.t = None
         torch.cuda.empty_cache()
-        if des not in ("CHAINING", "CUCKOO"):  # phased variants: the other designs only
-            out[des]["phased"] = bench_phased(step, d, des, rates)
+        out[des]["phased"] = bench_phased(step, d, des, rates)
         log("design %s: %.2f Gops/s per step (insert_0.9 %.2f, query+ %.2f, query- %.2f)"
             % (des, out[des]["step_gops"], rates["insert_0.9"], rates["query_pos"], rates["query_neg"]))
     step.t = main_t

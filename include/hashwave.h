@@ -99,8 +99,9 @@ enum {
                               (stable slots are never reused; Section 2.1)    */,
   HWAVE_F_BSP = 4          /* phased (bulk-synchronous) variant, to measure what
                               concurrency costs (Section 6.4): writes take no
-                              lock, queries read with plain cacheable loads.
-                              Results are defined only for phased use: the
+                              lock (chaining and cuckoo keep their write locks),
+                              queries take none and read with plain cacheable
+                              loads.  Results are defined only for phased use: the
                               writes of one call are to distinct keys, and no
                               call overlaps another that writes the keys it
                               touches.  64-bit tables at the default bucket and

@@ -922,10 +922,10 @@ struct Ops {
     // The critical section runs inside the retry loop: a tile that wins the
     // lock finishes and releases it in the same iteration, so tiles of one wave
     // waiting on each other cannot deadlock (lanes of a wave run in lockstep).
-    if constexpr (C::BSP) {
-      if constexpr (C::CHAIN)
-        return upsert_chain_locked(tv, tile, h, key, val, combine);
-      else if constexpr (C::ICEBERG)
+    // Phased chaining keeps its write locks: appending a node is not safe for
+    // two writers of one chain (only its queries differ, Table 1's phased column).
+    if constexpr (C::BSP && !C::CHAIN) {
+      if constexpr (C::ICEBERG)
         return upsert_iceberg_locked(tv, tile, h, key, val, tag, combine);
       else if constexpr (C::DOUBLE)
         return upsert_double_locked(tv, tile, h, key, val, tag, combine);
@@ -1093,7 +1093,22 @@ struct Ops {
   __device__ static uint8_t query(const TableDev& tv, const Tile<T>& tile, K key, K* out) {
     *out = 0;
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
-    if constexpr (C::CUCKOO) return cuckoo_locked(tv, tile, key, false, out);
+    if constexpr (C::CUCKOO) {
+      if constexpr (C::BSP) {
+        // phased: no locks, plain loads over the three buckets (no writer runs)
+        const Cands c = cuckoo_cands(home_of(tv, key));
+        for (uint32_t i = 0; i < c.n; ++i) {
+          const BucketScan<K> r = scan<true, true>(tv, tile, c.c[i], key, 0u);
+          if (r.hit >= 0) {
+            *out = r.val;
+            return ST_DONE;
+          }
+        }
+        return ST_MISS;
+      } else {
+        return cuckoo_locked(tv, tile, key, false, out);
+      }
+    }
     const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
 #ifdef HW_INSTRUMENT
@@ -1120,7 +1135,7 @@ struct Ops {
         wait_mem();
       }
     }
-    if constexpr (C::BSP) return erase_locked(tv, tile, h, key, tag);
+    if constexpr (C::BSP && !C::CHAIN) return erase_locked(tv, tile, h, key, tag);
     uint8_t status = ST_MISS;
     bool pending = true;
     Backoff bo;
