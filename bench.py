@@ -365,6 +365,93 @@ def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
     return out
 
 
+# Table 1's aged positive / negative query probes (A40), for context beside the
+# GPU-counted ones
+PAPER_AGED_PROBES = {"DOUBLE": (1.61, 80.00), "DOUBLE_M": (2.10, 19.39), "P2": (3.96, 8.01),
+                     "P2_M": (2.42, 2.01), "ICEBERG": (3.12, 12.02), "ICEBERG_M": (2.2, 3.02),
+                     "CHAINING": (1.2, 2.06)}
+
+
+# Table 1's load query probes at 0.9 (A40)
+PAPER_LOAD_PROBES = {"DOUBLE": 1.22, "DOUBLE_M": 2.05, "P2": 2.83, "P2_M": 2.13, "ICEBERG": 2.97,
+                     "ICEBERG_M": 2.16, "CHAINING": 1.16}
+
+
+def load_probes(designs, log2cap=22):
+    """Positive-query probes at 0.9 load counted by the GPU (instrumented build):
+    2^log2cap slots (chaining: sized for its keys, 7 pairs per chain), filled with
+    floor(0.9 * 2^log2cap) distinct keys, every key queried once."""
+    import torch
+    import paper_2509_16407_amd as hw
+    from paper_2509_16407_amd import workloads as w
+    n = int(0.9 * (1 << log2cap))
+    keys = to_dev(w.distinct_keys(w.stream_seed(2, 40), n))
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    st = torch.empty(n, dtype=torch.uint8, device="cuda")
+    res = {}
+    for des in designs:
+        t = hw.Table(n if des == "CHAINING" else 1 << log2cap, des, instrumented=True)
+        ins = t.insert(keys, keys * 3 + 1)
+        ok = ins == 1
+        t.probe_counters(reset=True)
+        f, _ = t.query(keys, out=out, found=st)
+        assert bool((f == ok.to(torch.uint8)).all()), "load probes %s: queries" % des
+        c = t.probe_counters(reset=True)
+        res[des] = {"positive": round((c["bucket_lines"] + c["slot_lines"]) / max(1, c["queries"]), 3),
+                    "full_inserts": int((~ok).sum().item()), "paper_a40": PAPER_LOAD_PROBES.get(des)}
+        del t
+        torch.cuda.empty_cache()
+    log("load probes at 0.9 (GPU-counted, 2^%d slots): %s" % (log2cap, ", ".join(
+        "%s %.2f (Table 1: %s)" % (d, r["positive"], r["paper_a40"]) for d, r in res.items())))
+    return res
+
+
+def aging_probes(designs, log2cap=22, iters=1000, probe_cap_lines=80):
+    """Query probes of aged tables counted by the GPU (instrumented build): the
+    aging recipe of bench_aging at 2^log2cap slots, then one more iteration's
+    live and absent query sets, counted separately.  Cuckoo queries are not
+    counted by the instrumented build."""
+    import torch
+    import paper_2509_16407_amd as hw
+    from paper_2509_16407_amd import workloads as w
+    plan = w.aging_plan(1 << log2cap, iters=iters + 1, config_id=6)
+    n0, s = plan["n0"], plan["s"]
+    kd = to_dev(plan["keys"])
+    nd = to_dev(plan["negs"])
+    ops = torch.cat([torch.full((s,), 1, dtype=torch.uint8), torch.full((s,), 3, dtype=torch.uint8),
+                     torch.zeros(2 * s, dtype=torch.uint8)]).cuda()
+    kb = torch.empty(4 * s, dtype=torch.int64, device="cuda")
+    out = torch.empty(4 * s, dtype=torch.int64, device="cuda")
+    st = torch.empty(4 * s, dtype=torch.uint8, device="cuda")
+    res = {}
+    for des in designs:
+        cap = 0
+        if des.startswith("DOUBLE"):
+            cap = probe_cap_lines * 8 // (8 if des == "DOUBLE" else 32)
+        t = hw.Table(1 << log2cap, des, probe_cap=cap, instrumented=True)
+        t.insert(kd[:n0], kd[:n0] * 3 + 1)
+        for i in range(iters):
+            ps = int(plan["pos_start"][i])
+            torch.cat([kd[n0 + i * s: n0 + (i + 1) * s], kd[i * s: (i + 1) * s], kd[ps: ps + s],
+                       nd[i * s: (i + 1) * s]], out=kb)
+            t.mixed(ops, kb, kb * 3 + 1, combine="sum", out=out, status=st)
+        ps = int(plan["pos_start"][iters])
+        t.probe_counters(reset=True)
+        f, _ = t.query(kd[ps: ps + s], out=out[:s], found=st[:s])
+        assert bool((f == 1).all()), "aged %s: live keys" % des
+        pos = t.probe_counters(reset=True)
+        f, _ = t.query(nd[iters * s: (iters + 1) * s], out=out[:s], found=st[:s])
+        assert bool((f == 0).all()), "aged %s: absent keys" % des
+        neg = t.probe_counters(reset=True)
+        per = lambda c: round((c["bucket_lines"] + c["slot_lines"]) / max(1, c["queries"]), 3)
+        res[des] = {"positive": per(pos), "negative": per(neg), "paper_a40": PAPER_AGED_PROBES.get(des)}
+        log("aged probes %s (GPU-counted, 2^%d slots, %d iterations): positive %.2f, negative %.2f (Table 1: %s)"
+            % (des, log2cap, iters, res[des]["positive"], res[des]["negative"], PAPER_AGED_PROBES.get(des)))
+        del t
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_aging(designs, log2cap=26, iters=1000, probe_cap_lines=80):
     """The aging (churn) benchmark (Section 6.5) on each design: fill 2^log2cap slots
     to 0.85, then `iters` iterations, each ONE mixed launch inserting a new 1% slice,
@@ -964,6 +1051,8 @@ def main():
         probes = probe_counts(step, args.design)
         log("probes at 0.9 (GPU-counted lines per query): positive %.3f, negative %.3f"
             % (probes["positive_lines_per_query"], probes["negative_lines_per_query"]))
+        probes["load_probes_all_designs"] = load_probes(["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG",
+                                                         "ICEBERG_M", "CHAINING"])
 
     cfg = {"workload": "load benchmark at 2^%d slots on %s (bucket %d, tile %d): insert to "
                        "0.5/0.75/0.9, 2^%d pos+neg queries, 2^%d SUM upserts, erase 50%%, "
@@ -991,6 +1080,8 @@ def main():
     aging = None
     if not args.no_aging:
         aging = bench_aging(["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING", "CUCKOO"])
+        if not args.no_probes:
+            aging["probes"] = aging_probes(["DOUBLE", "DOUBLE_M", "P2", "P2_M", "ICEBERG", "ICEBERG_M", "CHAINING"])
 
     batched = None
     if not args.no_batched:
