@@ -253,7 +253,13 @@ typedef struct {
   uint64_t end;   /* one past the last                                            */
 } hwave_item;
 
-/* 1 if a table with this (kv_bits, design, bucket, tile) can join a hwave_multi. */
+/* 1 if a table with this (kv_bits, design, bucket, tile) can join a hwave_multi.
+ * Menus: 32-bit keys -- DOUBLE b16 t4/t8, b32 t16, b64 t32, b128 t64; DOUBLE_M
+ * b32 t4; P2 b32 t8; P2_M b16 t4, b32 t4/t8.  64-bit keys -- DOUBLE b8 t8, b16
+ * t8; DOUBLE_M b32 t4/t8; P2 b32 t8; P2_M b32 t4/t8, b64 t8; and, on an
+ * extended kernel that a group runs on when it holds one of them (more
+ * registers, lower occupancy), ICEBERG b32 t8, ICEBERG_M b32 t4, CHAINING
+ * (default), CUCKOO b8 t4. */
 int hwave_multi_supported(uint32_t kv_bits, hwave_design design, uint32_t bucket_slots, uint32_t tile);
 
 /* Creates a group over n_tables existing tables (same device and key width).

@@ -82,7 +82,9 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
   if (n_results) *n_results = 0;
   hipStream_t s = (hipStream_t)stream;
   int n_menu = 0;
-  const MenuEntry* menu = kv_bits == 64 ? menu_entries(MenuU64{}, &n_menu) : menu_entries(MenuU32{}, &n_menu);
+  // 64-bit keys: every configuration of the extended menu (a group of one
+  // configuration runs on the base menu whenever that holds it)
+  const MenuEntry* menu = kv_bits == 64 ? menu_entries(MenuU64X{}, &n_menu) : menu_entries(MenuU32{}, &n_menu);
   if (reps == 0) reps = 3;
   // enough tables of this class to give each timed launch ~32M slots of work
   // (tens of milliseconds), so that launch and tail effects do not decide
@@ -108,7 +110,9 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
     if (rc == HWAVE_EUNSUPPORTED) continue;
     if (rc) return rc;
     const uint64_t real_cap = [&] {
-      uint64_t nb = 1, want = (capacity + cfg.bucket_slots - 1) / cfg.bucket_slots;
+      const uint64_t want = (capacity + cfg.bucket_slots - 1) / cfg.bucket_slots;
+      if (d == HWAVE_CHAINING) return want * cfg.bucket_slots;  // bucket nodes; the pool is spare
+      uint64_t nb = 1;
       while (nb < want) nb <<= 1;
       return nb * cfg.bucket_slots;
     }();

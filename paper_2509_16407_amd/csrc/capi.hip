@@ -551,6 +551,7 @@ int hwave_last_hip_error(void) { return g_last_hip_error; }
 struct hwave_multi {
   int device;
   int kv_bits;
+  int menu;  // MENU_BASE or MENU_EXT
   uint32_t n_tables;
   std::vector<uint64_t> table_bytes;  // footprint per table (queue placement)
   MultiTable* d_tables = nullptr;
@@ -604,7 +605,9 @@ int multi_reserve(hwave_multi* m, size_t n) {
 extern "C" {
 
 int hwave_multi_supported(uint32_t kv_bits, hwave_design design, uint32_t bucket_slots, uint32_t tile) {
-  return multi_menu_index((int)kv_bits, (int)design, (int)bucket_slots, (int)tile) >= 0 ? 1 : 0;
+  for (int menu : {MENU_BASE, MENU_EXT})
+    if (multi_menu_index((int)kv_bits, menu, (int)design, (int)bucket_slots, (int)tile) >= 0) return 1;
+  return 0;
 }
 
 int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n_tables, void* stream) {
@@ -612,12 +615,19 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
   *out = nullptr;
   const int kv = (int)tables[0]->cfg.kv_bits;
   const int dev = tables[0]->device;
-  std::vector<MultiTable> h(n_tables);
+  // the base menu when it holds every table's configuration, else the extended one
+  int menu = MENU_BASE;
   for (uint32_t i = 0; i < n_tables; i++) {
     const hwave_table* t = tables[i];
     if (!t || (int)t->cfg.kv_bits != kv || t->device != dev) return HWAVE_EINVAL;
     if (t->cfg.flags & HWAVE_F_BSP) return HWAVE_EUNSUPPORTED;
-    int cls = multi_menu_index(kv, (int)t->design, (int)t->cfg.bucket_slots, (int)t->cfg.tile);
+    if (multi_menu_index(kv, MENU_BASE, (int)t->design, (int)t->cfg.bucket_slots, (int)t->cfg.tile) < 0)
+      menu = MENU_EXT;
+  }
+  std::vector<MultiTable> h(n_tables);
+  for (uint32_t i = 0; i < n_tables; i++) {
+    const hwave_table* t = tables[i];
+    int cls = multi_menu_index(kv, menu, (int)t->design, (int)t->cfg.bucket_slots, (int)t->cfg.tile);
     if (cls < 0) return HWAVE_EUNSUPPORTED;
     h[i].tv = t->la.tv;
     h[i].cls = (uint32_t)cls;
@@ -629,6 +639,7 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
   hwave_multi* m = new hwave_multi;
   m->device = dev;
   m->kv_bits = kv;
+  m->menu = menu;
   m->n_tables = n_tables;
   for (uint32_t i = 0; i < n_tables; i++) m->table_bytes.push_back(tables[i]->bytes);
   // only the 64-bit menu carries the merging path that fills the accumulators
@@ -653,7 +664,8 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
   // Persistent grid: full occupancy of the multi-table kernel.
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-  m->grid = (unsigned)cus * (4 * HW_MULTI_WAVES * 64 / BLOCK);
+  const int waves = menu == MENU_EXT ? MenuU64X::WAVES : HW_MULTI_WAVES;
+  m->grid = (unsigned)cus * (4 * waves * 64 / BLOCK);
   *out = m;
   return HWAVE_OK;
 }
@@ -731,7 +743,7 @@ int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items,
   if (e == hipSuccess) e = hipEventRecord(m->staged, s);
   if (e != hipSuccess) return hip_fail(e);
   m->staged_pending = true;
-  e = launch_multi(m->kv_bits, m->grid, m->d_tables, m->d_items, qs, m->d_heads, d_keys,
+  e = launch_multi(m->kv_bits, m->menu, m->grid, m->d_tables, m->d_items, qs, m->d_heads, d_keys,
                    d_vals ? d_vals : d_keys, d_vals_out, d_status, s);
   if (e == hipSuccess && merging) e = launch_multi_hot_flush(m->kv_bits, m->d_tables, m->d_hot, m->n_hot, s);
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);

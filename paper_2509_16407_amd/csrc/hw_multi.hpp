@@ -52,6 +52,8 @@ struct Menu {
   static constexpr int N = 1 + sizeof...(Cs);
   static constexpr bool AGGREGATE = AGG;  // compiled with the merging path (hw_agg.hpp)
   using K = typename C0::K;               // one key width per menu
+  // occupancy target: cuckoo's three-lock paths need more registers
+  static constexpr int WAVES = (C0::CUCKOO || ... || Cs::CUCKOO) ? 4 : HW_MULTI_WAVES;
 };
 
 // Runs ops [m.begin, m.end) of one table with configuration C on this wave.
@@ -103,7 +105,7 @@ __device__ __forceinline__ void dispatch(uint32_t cls, const TableDev& tv, const
 }
 
 template <class M>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(HW_MULTI_WAVES, 8)))
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(M::WAVES, 8)))
 k_multi(const MultiTable* __restrict__ tables, const MultiItem* __restrict__ items, MultiQueues qs,
         uint32_t* heads, const void* keys, const void* vals, void* out, uint8_t* status) {
   __shared__ AggLds<typename M::K> agg_lds[M::AGGREGATE ? BLOCK / 64 : 1];
@@ -134,6 +136,15 @@ using MenuU64 = Menu<true, Cfg<uint64_t, D_DOUBLE, 8, 8>, Cfg<uint64_t, D_DOUBLE
                      Cfg<uint64_t, D_DOUBLE_M, 32, 4>, Cfg<uint64_t, D_DOUBLE_M, 32, 8>,
                      Cfg<uint64_t, D_P2, 32, 8>, Cfg<uint64_t, D_P2_M, 32, 4>,
                      Cfg<uint64_t, D_P2_M, 32, 8>, Cfg<uint64_t, D_P2_M, 64, 8>>;
+// Extended 64-bit menu: the base menu plus iceberg, chaining and cuckoo.  A
+// group that holds a table of these designs runs on it; its inlined paths cost
+// registers (and spills), so groups of base designs keep the base menu.
+using MenuU64X = Menu<true, Cfg<uint64_t, D_DOUBLE, 8, 8>, Cfg<uint64_t, D_DOUBLE, 16, 8>,
+                      Cfg<uint64_t, D_DOUBLE_M, 32, 4>, Cfg<uint64_t, D_DOUBLE_M, 32, 8>,
+                      Cfg<uint64_t, D_P2, 32, 8>, Cfg<uint64_t, D_P2_M, 32, 4>,
+                      Cfg<uint64_t, D_P2_M, 32, 8>, Cfg<uint64_t, D_P2_M, 64, 8>,
+                      Cfg<uint64_t, D_ICEBERG, 32, 8>, Cfg<uint64_t, D_ICEBERG_M, 32, 4>,
+                      Cfg<uint64_t, D_CHAINING, 7, 8>, Cfg<uint64_t, D_CUCKOO, 8, 4>>;
 using MenuU32 = Menu<false, Cfg<uint32_t, D_DOUBLE, 16, 4>, Cfg<uint32_t, D_DOUBLE, 16, 8>,
                      Cfg<uint32_t, D_DOUBLE, 32, 16>, Cfg<uint32_t, D_DOUBLE, 64, 32>,
                      Cfg<uint32_t, D_DOUBLE, 128, 64>, Cfg<uint32_t, D_DOUBLE_M, 32, 4>,
@@ -153,13 +164,15 @@ inline const MenuEntry* menu_entries(Menu<AGG, Cs...>, int* n) {
 
 // Host launchers (inst_multi.hip).
 hipError_t launch_multi_clear(unsigned grid, const MultiTable* tables, uint32_t n_tables, hipStream_t s);
-hipError_t launch_multi(int kv_bits, unsigned grid, const MultiTable* tables, const MultiItem* items,
+// menu: MENU_BASE or MENU_EXT (64-bit keys only).
+enum : int { MENU_BASE = 0, MENU_EXT = 1 };
+hipError_t launch_multi(int kv_bits, int menu, unsigned grid, const MultiTable* tables, const MultiItem* items,
                         const MultiQueues& qs, uint32_t* heads, const void* keys, const void* vals, void* out,
                         uint8_t* status, hipStream_t s);
 // Folds the hot-key accumulators of the n_hot tables listed in `hot` (device
 // array of table indices); a no-op for n_hot == 0.
 hipError_t launch_multi_hot_flush(int kv_bits, const MultiTable* tables, const uint32_t* hot, uint32_t n_hot,
                                   hipStream_t s);
-int multi_menu_index(int kv_bits, int design, int bucket, int tile);
+int multi_menu_index(int kv_bits, int menu, int design, int bucket, int tile);
 
 }  // namespace hw

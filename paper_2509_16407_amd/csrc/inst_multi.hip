@@ -7,11 +7,14 @@ __global__ void k_zero_heads(uint32_t* heads) {
   if (threadIdx.x < NQ) heads[threadIdx.x * HEAD_STRIDE] = 0;
 }
 
-hipError_t launch_multi(int kv_bits, unsigned grid, const MultiTable* tables, const MultiItem* items,
+hipError_t launch_multi(int kv_bits, int menu, unsigned grid, const MultiTable* tables, const MultiItem* items,
                         const MultiQueues& qs, uint32_t* heads, const void* keys, const void* vals, void* out,
                         uint8_t* status, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_heads, dim3(1), dim3(64), 0, s, heads);
-  if (kv_bits == 64)
+  if (kv_bits == 64 && menu == MENU_EXT)
+    hipLaunchKernelGGL((k_multi<MenuU64X>), dim3(grid), dim3(BLOCK), 0, s, tables, items, qs, heads, keys, vals,
+                       out, status);
+  else if (kv_bits == 64)
     hipLaunchKernelGGL((k_multi<MenuU64>), dim3(grid), dim3(BLOCK), 0, s, tables, items, qs, heads, keys, vals,
                        out, status);
   else
@@ -58,9 +61,12 @@ hipError_t launch_multi_clear(unsigned grid, const MultiTable* tables, uint32_t 
   return hipGetLastError();
 }
 
-int multi_menu_index(int kv_bits, int design, int bucket, int tile) {
+int multi_menu_index(int kv_bits, int menu, int design, int bucket, int tile) {
   int n = 0;
-  const MenuEntry* e = kv_bits == 64 ? menu_entries(MenuU64{}, &n) : menu_entries(MenuU32{}, &n);
+  if (kv_bits != 64 && menu != MENU_BASE) return -1;
+  const MenuEntry* e = kv_bits != 64        ? menu_entries(MenuU32{}, &n)
+                       : menu == MENU_EXT ? menu_entries(MenuU64X{}, &n)
+                                          : menu_entries(MenuU64{}, &n);
   for (int i = 0; i < n; i++)
     if (e[i].design == design && e[i].bucket == bucket && e[i].tile == tile) return i;
   return -1;

@@ -92,11 +92,15 @@ def test_hot_keys_more_than_the_accumulators_hold(design):
         _check(t, om, 64)
 
 
+@pytest.mark.parametrize("ext", [False, True], ids=["base", "extended"])
 @pytest.mark.parametrize("comb", ["sum", "min", "max"])
-def test_hot_keys_multi_table(comb):
+def test_hot_keys_multi_table(comb, ext):
     """The multi-table kernel on merging erase-free tables of several menu
-    configurations, Zipf batches per table, two calls, against the oracle."""
+    configurations (the extended menu adds iceberg and chaining), Zipf batches
+    per table, two calls, against the oracle."""
     menu = [("DOUBLE", 8, 8), ("DOUBLE_M", 32, 4), ("P2", 32, 8), ("P2_M", 32, 4), ("P2_M", 64, 8)]
+    if ext:
+        menu += [("ICEBERG", 32, 8), ("ICEBERG_M", 32, 4), ("CHAINING", 7, 8)]
     tabs = [hw.Table(1 << 15, d, bucket=b, tile=tt, flags=FLAGS) for d, b, tt in menu for _ in range(2)]
     m = hw.Multi(tabs)
     oms = [oracle.OracleMap() for _ in tabs]

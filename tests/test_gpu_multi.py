@@ -17,6 +17,8 @@ MENU32 = [("DOUBLE", 16, 4), ("DOUBLE", 16, 8), ("DOUBLE", 32, 16), ("DOUBLE", 6
           ("P2_M", 32, 8)]
 MENU64 = [("DOUBLE", 8, 8), ("DOUBLE", 16, 8), ("DOUBLE_M", 32, 4), ("DOUBLE_M", 32, 8), ("P2", 32, 8),
           ("P2_M", 32, 4), ("P2_M", 32, 8), ("P2_M", 64, 8)]
+# the extended 64-bit menu adds these (a group holding one runs on it)
+MENU64X = MENU64 + [("ICEBERG", 32, 8), ("ICEBERG_M", 32, 4), ("CHAINING", 7, 8), ("CUCKOO", 8, 4)]
 
 
 def _dump(t):
@@ -29,9 +31,10 @@ def _dump(t):
 def test_menus_match_library():
     for d, b, t in MENU32:
         assert hw.multi_supported(32, d, b, t)
-    for d, b, t in MENU64:
+    for d, b, t in MENU64X:
         assert hw.multi_supported(64, d, b, t)
     assert not hw.multi_supported(32, "P2", 64, 32)
+    assert not hw.multi_supported(32, "CUCKOO", 8, 4)
 
 
 @pytest.mark.parametrize("flags", [0, hw.F_NO_ERASE], ids=["locked", "noerase"])
@@ -67,10 +70,13 @@ def test_multi_groupby_equals_plain_and_oracle(flags):
     assert all(t.size() == 0 for t in A)
 
 
-def test_multi_mixed_items_u64():
-    """Items of every kind across tables of every u64 menu configuration; at most
-    one writing item per table per launch, so every output is deterministic."""
-    tabs = [hw.Table(1 << 14, d, bucket=b, tile=t) for d, b, t in MENU64]
+@pytest.mark.parametrize("menu", ["base", "extended"])
+def test_multi_mixed_items_u64(menu):
+    """Items of every kind across tables of every configuration of the u64 menu
+    (base, or extended with iceberg, chaining and cuckoo); at most one writing
+    item per table per launch, so every output is deterministic; a third launch
+    erases."""
+    tabs = [hw.Table(1 << 14, d, bucket=b, tile=t) for d, b, t in (MENU64 if menu == "base" else MENU64X)]
     oms = [oracle.OracleMap() for _ in tabs]
     m = hw.Multi(tabs)
     pool = [w.distinct_keys(w.stream_seed(42, i), 20000) for i in range(len(tabs))]
@@ -105,6 +111,18 @@ def test_multi_mixed_items_u64():
         else:
             os_ = oms[i].upsert(keys[a:b], vals[a:b])
             assert np.array_equal(st[a:b], os_)
+    # launch 3: erase items (present and absent keys) on every table
+    segs, items, pos = [], [], 0
+    for i in range(len(tabs)):
+        k = np.concatenate([pool[i][:3000:2], pool[i][19000:19500]])
+        segs.append(k)
+        items.append((i, hw.OPS["erase"], pos, pos + len(k)))
+        pos += len(k)
+    keys = np.concatenate(segs)
+    st, _ = m.run(items, dev(keys), None)
+    st = u8(st)
+    for i, (t, op, a, b) in enumerate(items):
+        assert np.array_equal(st[a:b], oms[i].erase(keys[a:b]))
     for i, t in enumerate(tabs):
         ok, ov = oms[i].dump()
         k, v = _dump(t)
