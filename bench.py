@@ -1117,6 +1117,14 @@ def main():
         "aging": aging,
         "batched": batched,
         "served": served,
+        # the paper's own numbers on an NVIDIA A40 (Section 6.3, Table 1), beside
+        # this run's matching figures: context, not a baseline of this workload
+        "paper_a40_context": {
+            "p2m_query_at_0.9_gops": {"paper": 2.605, "here": rates["query_pos"]["gops"]},
+            "p2m_query_concurrent_phased_mops": {"paper": [2903, 2909]},
+            "p2_insert_peak_gops": {"paper": 2.037},
+            "metadata_tables_delete_gops": {"paper": 1.17, "here_p2m_erase": rates["erase"]["gops"]},
+        },
         "kernel_source_hash": kernel_source_hash(),
         "verify_full_repeats": full_repeats,
     }
