@@ -128,11 +128,23 @@ enum {
 };
 
 /* Table configuration.  Zero fields take the design's defaults (the
- * configurations of Section 5).  Supported (kv_bits, design, bucket, tile):
- *   64-bit keys/values: DOUBLE bucket 8/16/32, tile 4/8 (tile <= bucket);
- *                       DOUBLE_M, P2_M bucket 32, tile 4/8;
- *                       P2 bucket 32, tile 4/8/16.
- *   32-bit keys/values: every design, bucket 16/32, tile 4/8/16 (tile <= bucket).
+ * configurations of Section 5).  Supported (kv_bits, design, bucket/tile);
+ * others return HWAVE_EUNSUPPORTED:
+ *   64-bit keys/values:
+ *     DOUBLE    b8/t4 b8/t8 b16/t4 b16/t8 b16/t16 b32/t8 b32/t16 b32/t32
+ *     DOUBLE_M  b16/t4 b32/t2 b32/t4 b32/t8 b32/t16 b64/t8
+ *     P2        b16/t8 b32/t4 b32/t8 b32/t16 b32/t32
+ *     P2_M      b16/t4 b32/t2 b32/t4 b32/t8 b32/t16 b64/t8
+ *     ICEBERG   b32/t4 b32/t8 b32/t16;  ICEBERG_M b32/t2 b32/t4 b32/t8 b64/t8
+ *     CHAINING  7 pairs per node, tile 8 (the defaults)
+ *     CUCKOO    b8/t4 b8/t8 b16/t8
+ *     HWAVE_F_BSP: each design's default configuration only.
+ *   32-bit keys/values:
+ *     DOUBLE    b8/t4 b16/t4 b16/t8 b32/t8 b32/t16 b64/t32 b128/t64
+ *     DOUBLE_M  b16/t4 b32/t4 b32/t8 b32/t16 b64/t8
+ *     P2        b16/t4 b16/t8 b32/t4 b32/t8 b32/t16 b64/t32
+ *     P2_M      b16/t4 b32/t4 b32/t8 b32/t16 b32/t32 b64/t8
+ *     ICEBERG, ICEBERG_M  b32/t4 b32/t8  (no chaining or cuckoo)
  * Reserved key patterns (rejected with HWAVE_ST_INVALID): 64-bit keys
  * 0xFFFFFFFFFFFFFFFF (empty), ...FE (tombstone), ...FD (reservation marker);
  * 32-bit keys 0xFFFFFFFF and 0xFFFFFFFE. */

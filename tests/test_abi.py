@@ -164,3 +164,26 @@ def test_tuning_file_errors(tmp_path):
     assert n.value == 0
     assert L.hwave_tune_save(None, None, None, 0) == -1
     assert L.hwave_strerror(-5).startswith(b"file")
+
+
+def test_documented_configurations_have_instances():
+    """Every (kv_bits, design, bucket, tile) the header lists sizes a table (an
+    instance exists); a few unlisted ones report EUNSUPPORTED."""
+    import re
+    text = open(os.path.join(os.path.dirname(hw.LIB_PATH), "..", "include", "hashwave.h")).read()
+    block = text[text.index("Supported (kv_bits, design, bucket/tile)"): text.index("Reserved key patterns")]
+    bits = None
+    seen = 0
+    for line in block.splitlines():
+        if "64-bit keys/values" in line:
+            bits = 64
+        elif "32-bit keys/values" in line:
+            bits = 32
+        for name, cfgs in re.findall(r"\b(DOUBLE_M|DOUBLE|P2_M|P2|ICEBERG_M|ICEBERG)\s+((?:b\d+/t\d+\s*)+)", line):
+            for b, t in re.findall(r"b(\d+)/t(\d+)", cfgs):
+                rc, _ = _bytes(1 << 12, hw.DESIGNS[name], kv_bits=bits, bucket=int(b), tile=int(t))
+                assert rc == 0, (bits, name, b, t)
+                seen += 1
+    assert seen >= 40
+    assert _bytes(1 << 12, hw.DESIGNS["P2_M"], bucket=32, tile=64)[0] == -4
+    assert _bytes(1 << 12, hw.DESIGNS["CUCKOO"], kv_bits=32)[0] == -4
