@@ -59,7 +59,8 @@ typedef enum {
   HWAVE_CUCKOO = 7    /* three-way bucketed cuckoo hashing (Section 5): bucket
                          8, tile 4, 64-bit keys; keys move between their three
                          buckets, so every operation, queries included, locks
-                         all three; FULL when no room can be made            */
+                         all three (the phased variant's queries excepted);
+                         FULL when no room can be made                        */
 } hwave_design;
 
 /* Upsert callbacks (Section 5.1): SUM accumulates with wrap-around modulo
@@ -209,7 +210,9 @@ int hwave_erase(hwave_table* t, const void* d_keys, uint64_t n, uint8_t* d_found
  * operations of an aging iteration concurrently in one kernel, Section 6.5).
  * d_ops[i] is a hwave_op; upserts use `combine`; d_vals is read for inserts and
  * upserts (nullable when there are none); d_vals_out (nullable) receives query
- * results (0 for other ops); d_status (nullable) the per-op status. */
+ * results (0 for other ops); d_status (nullable) the per-op status.  The
+ * operations of one call are concurrent: the kernel runs each group of 64 in
+ * order of kind (queries, inserts/upserts, erases), not in array order. */
 int hwave_mixed(hwave_table* t, const uint8_t* d_ops, const void* d_keys, const void* d_vals,
                 uint64_t n, hwave_combine combine, void* d_vals_out, uint8_t* d_status,
                 void* stream);
