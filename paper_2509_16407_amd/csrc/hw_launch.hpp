@@ -185,8 +185,11 @@ k_mixed(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __res
   mixed_body<C>(tv, ops, keys, vals, n, combine, out, status, order_lds);
 }
 
-// With an occupancy bound of W waves per SIMD (the grouping's registers would
-// cost iceberg its sixth wave and double hashing with tags its eighth).
+// With an occupancy bound of W waves per SIMD: the grouping's registers would
+// cost iceberg its sixth wave and the double-hashing and two-choice designs
+// their eighth.  A 2^20-operation launch is 16384 windows: at 8 waves/SIMD the
+// chip holds 8192 waves and runs them in two rounds, at 7 it needs three.  The
+// bound costs the two-choice designs 12-24 bytes of spill per lane.
 template <class C, int W>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W, 8)))
 k_mixed_w(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __restrict__ keys,
@@ -263,7 +266,7 @@ struct Launch {
     else if constexpr (C::ICEBERG && C::T >= 4)  // one wave per window of 64 operations
       hipLaunchKernelGGL((k_mixed_w<C, 6>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s,
                          a.tv, ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
-    else if constexpr (C::DESIGN == D_DOUBLE_M && C::T >= 4)
+    else if constexpr (!C::ICEBERG && !C::CHAIN && C::T >= 4)  // double hashing, two-choice
       hipLaunchKernelGGL((k_mixed_w<C, 8>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s,
                          a.tv, ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
     else
