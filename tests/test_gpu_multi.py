@@ -140,3 +140,16 @@ def test_autotune_small_class(logcap):
     ok = [a for a in alls if a["full_ops"] == 0]
     assert best["full_ops"] == 0 and best["gops"] == max(a["gops"] for a in ok) and best["gops"] > 0
     assert all(a["full_ops"] == 0 for a in alls if a["design"].startswith("DOUBLE"))
+
+
+def test_tune_classes_round_trip_and_extended_menu(tmp_path):
+    """tune_classes on two classes, saved and loaded through the C-ABI tuning
+    file, equals what it returned; the 64-bit tuner also times the extended
+    menu's designs when asked, and every choice can build a table."""
+    path = str(tmp_path / "tune.txt")
+    table = hw.tune_classes(32, [10, 13], path=path, reps=1)
+    assert hw.load_tuning(path) == table
+    best, alls = hw.autotune(64, 1 << 12, designs=("P2_M", "ICEBERG_M", "CHAINING", "CUCKOO"), reps=1)
+    assert {a["design"] for a in alls} == {"P2_M", "ICEBERG_M", "CHAINING", "CUCKOO"}
+    assert best["full_ops"] == 0 and best["gops"] > 0
+    hw.Table(1 << 12, best["design"], bucket=best["bucket"], tile=best["tile"])
