@@ -159,14 +159,20 @@ struct hwave_server {
   std::atomic<uint64_t> batches{0}, batch_reqs{0}, runtime_copied{0};
   double t_first = 0, t_last = 0;
   bool stop = false;
-  int error = 0;
+  std::atomic<int> error{0};  // first error; set by the worker, read by callers
   std::thread worker;
 };
 
 namespace {
 
+// Records the first error and wakes callers waiting in hwave_server_drain.
 int fail(hwave_server* s, int code) {
-  if (!s->error) s->error = code;
+  int none = 0;
+  s->error.compare_exchange_strong(none, code);
+  {
+    std::lock_guard<std::mutex> g(s->mu);  // a waiter checks `error` under mu
+  }
+  s->cv.notify_all();
   return code;
 }
 
@@ -334,10 +340,14 @@ void worker_main(hwave_server* s) {
     }
     bool progressed = false;
     for (auto& sl : s->slots) {  // retire finished batches
-      if (sl.busy && hipEventQuery(sl.d2h) == hipSuccess) {
-        retire(s, sl);
-        progressed = true;
-      }
+      if (!sl.busy) continue;
+      const hipError_t e = hipEventQuery(sl.d2h);
+      if (e == hipErrorNotReady) continue;
+      // a device error retires the batch too (its requests report the error),
+      // so drain and destroy never wait on an event that cannot complete
+      if (e != hipSuccess) fail(s, HWAVE_EDEVICE);
+      retire(s, sl);
+      progressed = true;
     }
     for (auto& sl : s->slots) {  // fill free slots
       if (sl.busy) continue;
