@@ -94,8 +94,9 @@ enum {
 enum {
   HWAVE_F_NO_SHORTCUT = 1, /* power-of-two-choice: never take the 75% shortcut    */
   HWAVE_F_NO_ERASE = 2     /* the table never erases: hwave_erase returns
-                              HWAVE_EINVAL, erase ops of hwave_mixed get
-                              HWAVE_ST_INVALID, and upserts of present keys are
+                              HWAVE_EINVAL, erase ops of hwave_mixed and erase
+                              items of hwave_multi_run get HWAVE_ST_INVALID,
+                              and upserts of present keys are
                               combined in place without taking the bucket lock
                               (stable slots are never reused; Section 2.1)    */,
   HWAVE_F_BSP = 4          /* phased (bulk-synchronous) variant, to measure what

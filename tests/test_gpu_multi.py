@@ -153,3 +153,23 @@ def test_tune_classes_round_trip_and_extended_menu(tmp_path):
     assert {a["design"] for a in alls} == {"P2_M", "ICEBERG_M", "CHAINING", "CUCKOO"}
     assert best["full_ops"] == 0 and best["gops"] > 0
     hw.Table(1 << 12, best["design"], bucket=best["bucket"], tile=best["tile"])
+
+
+def test_multi_erase_items_on_erase_free_tables_are_invalid():
+    """An erase item on a table built with HWAVE_F_NO_ERASE reports INVALID for
+    every key and leaves the table as it was; an erase item on an ordinary table
+    of the same launch erases."""
+    a = hw.Table(1 << 13, "P2_M", flags=hw.F_NO_ERASE)
+    b = hw.Table(1 << 13, "P2_M")
+    m = hw.Multi([a, b])
+    keys = w.distinct_keys(w.stream_seed(44, 0), 4000)
+    vals = w.value_of(keys)
+    for t in (a, b):
+        assert (u8(t.insert(dev(keys), dev(vals))) == hw.ST_DONE).all()
+    items = [(0, hw.OPS["erase"], 0, 2000), (1, hw.OPS["erase"], 2000, 4000)]
+    st, _ = m.run(items, dev(keys), None)
+    st = u8(st)
+    assert (st[:2000] == hw.ST_INVALID).all() and (st[2000:] == hw.ST_DONE).all()
+    assert a.size() == 4000 and b.size() == 2000
+    found, v = a.query(dev(keys))
+    assert (u8(found) == hw.ST_DONE).all() and np.array_equal(host(v), vals)
