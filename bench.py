@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per operation (64-byte sectors of tag and slot data, plus the
 # op's own input/output bytes) for the tagged power-of-two-choice table at 0.9
-# load; derivation in the design doc.
+# load: probed lines from Table 1's probe counts, in 64-byte sectors, plus key,
+# value and status bytes of the op batch.
 ALGO_BYTES = {
     "insert": 273.0, "query_pos": 153.0, "query_neg": 137.0, "upsert": 222.0,
     "erase": 278.0, "requery_pos": 145.0, "requery_neg": 137.0, "mixed": 180.0,
@@ -535,7 +536,7 @@ def bench_aging(designs, log2cap=26, iters=1000, probe_cap_lines=80):
 
 
 def bench_mixed_cfg3(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE_M"):
-    """SURVEY config 3: a 2^log2cap-slot table preloaded with a 2^universe_log2-key
+    """The mixed concurrent workload: a 2^log2cap-slot table preloaded with a 2^universe_log2-key
     universe (load 0.5, v = 3k+1), then `n_batches` shuffled mixed batches of 2^20
     operations (50% query, 30% SUM upsert, 20% erase; Zipf 0.99 keys; erase and
     upsert keys disjoint, queries avoid both).  Per-batch kernel latency from events.
@@ -610,7 +611,7 @@ def bench_mixed_cfg3(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE
 
 
 def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_reps=2, n_verify=16):
-    """The batched form (SURVEY config 4): n_tables uint32 tables with capacities 2^e,
+    """The batched form: n_tables uint32 tables with capacities 2^e,
     e uniform in [e_min, e_max], each receiving a group-by SUM-upsert batch that
     fills it to `load`.  Times one persistent multi-table launch (configuration
     autotuned per capacity class) against one plain launch per table (same
@@ -720,7 +721,7 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
 
 
 def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):
-    """The served form (SURVEY config 5): n_tables resident, erase-free P2HT(M) tables of 2^log2cap
+    """The served form: n_tables resident, erase-free P2HT(M) tables of 2^log2cap
     slots, preloaded with half of a Zipf universe of floor(0.85 * capacity) keys;
     n_req requests arriving as a Poisson process at `rate`/s (query / upsert /
     insert 50/30/20, sizes 2^U, U ~ U[8, 20], Zipf 0.99 keys).  The same stream is
