@@ -318,6 +318,9 @@ typedef struct {
   uint32_t kv_bits;
   double gops;           /* measured upserts per ns (G ops/s)   */
   uint64_t full_ops;     /* operations that ended FULL (0 = holds the load) */
+  double load;           /* the load factor it was timed at      */
+  uint32_t flags;        /* the tables' HWAVE_F_* flags it was timed with */
+  uint32_t reserved;     /* zero                                 */
 } hwave_tune_result;
 
 int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, double load, uint32_t reps,
@@ -325,13 +328,16 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
                    hwave_tune_result* best, void* stream);
 
 /* Persisted tuning, one capacity class per entry: class i is log2_capacity[i]
- * with its chosen configuration best[i].  The file is text: a first line
- * "hwave-tune 1", then one line per class,
- * "<log2_capacity> <kv_bits> <design> <bucket_slots> <tile> <gops> <full_ops>".
- * Save overwrites `path`.  Load reads at most `cap` classes into the caller's
- * arrays and their count into *n; it rejects (HWAVE_EIO) a file with another
- * first line, a line it cannot parse, more than `cap` classes, or a design,
- * key width, bucket or tile that is out of range.  Host-only; no device work. */
+ * with its chosen configuration best[i], which also records the load factor
+ * and table flags it was tuned for (one file may hold classes tuned at several
+ * loads or flags).  The file is text: a first line "hwave-tune 2", then one
+ * line per class, "<log2_capacity> <load> <flags> <kv_bits> <design>
+ * <bucket_slots> <tile> <gops> <full_ops>".  Save overwrites `path`.  Load
+ * reads at most `cap` classes into the caller's arrays and their count into
+ * *n; it rejects (HWAVE_EIO) a file with another first line, a line it cannot
+ * parse, more than `cap` classes, or a load outside (0, 1], unknown flags, or a
+ * design, key width, bucket or tile that is out of range.  Host-only; no device
+ * work. */
 int hwave_tune_save(const char* path, const uint32_t* log2_capacity, const hwave_tune_result* best, uint32_t n);
 int hwave_tune_load(const char* path, uint32_t* log2_capacity, hwave_tune_result* best, uint32_t cap,
                     uint32_t* n);

@@ -46,7 +46,8 @@ class _Item(ctypes.Structure):
 
 class _Tune(ctypes.Structure):
     _fields_ = [("design", ctypes.c_uint32), ("bucket_slots", ctypes.c_uint32), ("tile", ctypes.c_uint32),
-                ("kv_bits", ctypes.c_uint32), ("gops", ctypes.c_double), ("full_ops", ctypes.c_uint64)]
+                ("kv_bits", ctypes.c_uint32), ("gops", ctypes.c_double), ("full_ops", ctypes.c_uint64),
+                ("load", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class _Probe(ctypes.Structure):
@@ -450,17 +451,19 @@ def autotune(kv_bits: int, capacity: int, designs=("DOUBLE", "DOUBLE_M", "P2", "
     best = _Tune()
     _check(lib().hwave_autotune(kv_bits, capacity, mask, load, reps, flags, res, 64, ctypes.byref(n),
                                 ctypes.byref(best), _stream(stream)))
-    names = {v: k for k, v in DESIGNS.items()}
+    return _tune_dict(best), [_tune_dict(res[i]) for i in range(min(n.value, 64))]
 
-    def as_dict(r):
-        return {"design": names[r.design], "bucket": r.bucket_slots, "tile": r.tile,
-                "kv_bits": r.kv_bits, "gops": r.gops, "full_ops": r.full_ops}
-    return as_dict(best), [as_dict(res[i]) for i in range(min(n.value, 64))]
+
+def _tune_dict(r):
+    names = {v: k for k, v in DESIGNS.items()}
+    return {"design": names[r.design], "bucket": r.bucket_slots, "tile": r.tile, "kv_bits": r.kv_bits,
+            "gops": r.gops, "full_ops": r.full_ops, "load": r.load, "flags": r.flags}
 
 
 def tune_classes(kv_bits: int, exponents, path=None, **kw):
-    """Autotunes each capacity class 2^e; returns {e: best} and, with `path`,
-    saves it (C-ABI hwave_tune_save)."""
+    """Autotunes each capacity class 2^e at one load and set of flags (keyword
+    arguments of `autotune`); returns {e: best} and, with `path`, saves it (C-ABI
+    hwave_tune_save).  Each entry records the load and flags it was tuned for."""
     table = {}
     for e in exponents:
         best, _ = autotune(kv_bits, 1 << e, **kw)
@@ -477,7 +480,8 @@ def save_tuning(path, table):
     caps = (ctypes.c_uint32 * max(1, len(es)))()
     for i, e in enumerate(es):
         v = table[e]
-        arr[i] = _Tune(DESIGNS[v["design"]], v["bucket"], v["tile"], v["kv_bits"], v["gops"], v.get("full_ops", 0))
+        arr[i] = _Tune(DESIGNS[v["design"]], v["bucket"], v["tile"], v["kv_bits"], v["gops"], v.get("full_ops", 0),
+                       v["load"], v.get("flags", 0), 0)
         caps[i] = int(e)
     _check(lib().hwave_tune_save(os.fsencode(path), caps, arr, len(es)))
 
@@ -488,7 +492,4 @@ def load_tuning(path, cap=64):
     caps = (ctypes.c_uint32 * cap)()
     n = ctypes.c_uint32()
     _check(lib().hwave_tune_load(os.fsencode(path), caps, arr, cap, ctypes.byref(n)))
-    names = {v: k for k, v in DESIGNS.items()}
-    return {int(caps[i]): {"design": names[arr[i].design], "bucket": arr[i].bucket_slots, "tile": arr[i].tile,
-                           "kv_bits": arr[i].kv_bits, "gops": arr[i].gops, "full_ops": arr[i].full_ops}
-            for i in range(n.value)}
+    return {int(caps[i]): _tune_dict(arr[i]) for i in range(n.value)}

@@ -94,6 +94,8 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
   const uint32_t n_tab = (uint32_t)n_tab64;
   memset(best, 0, sizeof *best);
   best->gops = -1.0;
+  best->load = load;
+  best->flags = flags;
   uint32_t nres = 0;
   const size_t kb = kv_bits / 8;
   for (int c = 0; c < n_menu; c++) {
@@ -193,6 +195,9 @@ int hwave_autotune(uint32_t kv_bits, uint64_t capacity, uint32_t design_mask, do
     res.kv_bits = kv_bits;
     res.gops = (double)n_ops * reps / ((double)total_ms * 1e6);
     res.full_ops = full;
+    res.load = load;
+    res.flags = flags;
+    res.reserved = 0;
     if (results && nres < results_cap) results[nres] = res;
     nres++;
     if (full == 0 && res.gops > best->gops) *best = res;
@@ -205,11 +210,11 @@ int hwave_tune_save(const char* path, const uint32_t* log2_capacity, const hwave
   if (!path || (n && (!log2_capacity || !best))) return HWAVE_EINVAL;
   FILE* f = fopen(path, "w");
   if (!f) return HWAVE_EIO;
-  bool ok = fprintf(f, "hwave-tune 1\n") > 0;
+  bool ok = fprintf(f, "hwave-tune 2\n") > 0;
   for (uint32_t i = 0; ok && i < n; i++) {
     const hwave_tune_result& r = best[i];
-    ok = fprintf(f, "%u %u %u %u %u %.17g %llu\n", log2_capacity[i], r.kv_bits, r.design, r.bucket_slots, r.tile,
-                 r.gops, (unsigned long long)r.full_ops) > 0;
+    ok = fprintf(f, "%u %.17g %u %u %u %u %u %.17g %llu\n", log2_capacity[i], r.load, r.flags, r.kv_bits, r.design,
+                 r.bucket_slots, r.tile, r.gops, (unsigned long long)r.full_ops) > 0;
   }
   ok = (fclose(f) == 0) && ok;
   return ok ? HWAVE_OK : HWAVE_EIO;
@@ -223,16 +228,17 @@ int hwave_tune_load(const char* path, uint32_t* log2_capacity, hwave_tune_result
   if (!f) return HWAVE_EIO;
   char line[256];
   int rc = HWAVE_OK;
-  if (!fgets(line, sizeof line, f) || strcmp(line, "hwave-tune 1\n") != 0) rc = HWAVE_EIO;
+  if (!fgets(line, sizeof line, f) || strcmp(line, "hwave-tune 2\n") != 0) rc = HWAVE_EIO;
   uint32_t count = 0;
+  const unsigned known_flags = HWAVE_F_NO_SHORTCUT | HWAVE_F_NO_ERASE | HWAVE_F_BSP | HWAVE_F_AGGREGATE;
   while (rc == HWAVE_OK && fgets(line, sizeof line, f)) {
-    unsigned e, kv, d, b, t;
-    double g;
+    unsigned e, fl, kv, d, b, t;
+    double ld, g;
     unsigned long long full;
     char tail;
-    if (sscanf(line, "%u %u %u %u %u %lg %llu %c", &e, &kv, &d, &b, &t, &g, &full, &tail) != 7 || e > 40 ||
-        (kv != 32 && kv != 64) || d > (unsigned)HWAVE_CUCKOO || b == 0 || b > 1024 || t == 0 || t > 64 ||
-        count == cap) {
+    if (sscanf(line, "%u %lg %u %u %u %u %u %lg %llu %c", &e, &ld, &fl, &kv, &d, &b, &t, &g, &full, &tail) != 9 ||
+        e > 40 || !(ld > 0.0 && ld <= 1.0) || (fl & ~known_flags) || (kv != 32 && kv != 64) ||
+        d > (unsigned)HWAVE_CUCKOO || b == 0 || b > 1024 || t == 0 || t > 64 || count == cap) {
       rc = HWAVE_EIO;
       break;
     }
@@ -244,6 +250,9 @@ int hwave_tune_load(const char* path, uint32_t* log2_capacity, hwave_tune_result
     r.kv_bits = kv;
     r.gops = g;
     r.full_ops = full;
+    r.load = ld;
+    r.flags = fl;
+    r.reserved = 0;
     count++;
   }
   fclose(f);

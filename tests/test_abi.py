@@ -124,26 +124,32 @@ def test_paper_default_configurations():
 def test_tuning_file_round_trip(tmp_path):
     """hwave_tune_save / hwave_tune_load: every field survives, the text format is
     the documented one, and classes come back in the saved order."""
-    table = {10: {"design": "DOUBLE", "bucket": 16, "tile": 4, "kv_bits": 32, "gops": 7.25, "full_ops": 0},
-             22: {"design": "DOUBLE_M", "bucket": 32, "tile": 4, "kv_bits": 32, "gops": 6.125, "full_ops": 3},
-             14: {"design": "P2_M", "bucket": 64, "tile": 8, "kv_bits": 64, "gops": 1e-3, "full_ops": 0}}
+    table = {10: {"design": "DOUBLE", "bucket": 16, "tile": 4, "kv_bits": 32, "gops": 7.25, "full_ops": 0,
+                  "load": 0.85, "flags": 0},
+             22: {"design": "DOUBLE_M", "bucket": 32, "tile": 4, "kv_bits": 32, "gops": 6.125, "full_ops": 3,
+                  "load": 0.9, "flags": hw.F_NO_ERASE},
+             14: {"design": "P2_M", "bucket": 64, "tile": 8, "kv_bits": 64, "gops": 1e-3, "full_ops": 0,
+                  "load": 0.5, "flags": hw.F_AGGREGATE | hw.F_NO_ERASE}}
     path = tmp_path / "tune.txt"
     hw.save_tuning(str(path), table)
     lines = path.read_text().splitlines()
-    assert lines[0] == "hwave-tune 1"
-    assert lines[1].split()[:5] == ["10", "32", str(hw.DESIGNS["DOUBLE"]), "16", "4"]
+    assert lines[0] == "hwave-tune 2"
+    assert lines[1].split()[:7] == ["10", "0.84999999999999998", "0", "32", str(hw.DESIGNS["DOUBLE"]), "16", "4"]
     back = hw.load_tuning(str(path))
     assert back == table
     assert list(back) == [10, 14, 22]
 
 
 @pytest.mark.parametrize("body", [
-    "hwave-tune 2\n",                                   # another format version
-    "hwave-tune 1\n10 32 0 16 4 7.0\n",                  # a field missing
-    "hwave-tune 1\n10 32 0 16 4 7.0 0 extra\n",          # trailing text
-    "hwave-tune 1\n10 48 0 16 4 7.0 0\n",                # key width
-    "hwave-tune 1\n10 32 9 16 4 7.0 0\n",                # design
-    "hwave-tune 1\n10 32 0 16 0 7.0 0\n",                # tile
+    "hwave-tune 1\n10 32 0 16 4 7.0 0\n",                # the earlier format, without load and flags
+    "hwave-tune 2\n10 0.85 0 32 0 16 4 7.0\n",           # a field missing
+    "hwave-tune 2\n10 0.85 0 32 0 16 4 7.0 0 extra\n",   # trailing text
+    "hwave-tune 2\n10 0.85 0 48 0 16 4 7.0 0\n",         # key width
+    "hwave-tune 2\n10 0.85 0 32 9 16 4 7.0 0\n",         # design
+    "hwave-tune 2\n10 0.85 0 32 0 16 0 7.0 0\n",         # tile
+    "hwave-tune 2\n10 0 0 32 0 16 4 7.0 0\n",            # load 0
+    "hwave-tune 2\n10 1.5 0 32 0 16 4 7.0 0\n",          # load above 1
+    "hwave-tune 2\n10 0.85 16 32 0 16 4 7.0 0\n",        # unknown flag
 ])
 def test_tuning_file_rejects_malformed(tmp_path, body):
     path = tmp_path / "bad.txt"
@@ -157,7 +163,7 @@ def test_tuning_file_errors(tmp_path):
     n = ctypes.c_uint32()
     assert L.hwave_tune_load(str(tmp_path / "missing.txt").encode(), None, None, 0, ctypes.byref(n)) == -5
     path = tmp_path / "two.txt"
-    path.write_text("hwave-tune 1\n10 32 0 16 4 7.0 0\n11 32 0 16 4 7.0 0\n")
+    path.write_text("hwave-tune 2\n10 0.85 0 32 0 16 4 7.0 0\n11 0.85 0 32 0 16 4 7.0 0\n")
     caps = (ctypes.c_uint32 * 1)()
     arr = (hw._Tune * 1)()
     assert L.hwave_tune_load(str(path).encode(), caps, arr, 1, ctypes.byref(n)) == -5  # more classes than room

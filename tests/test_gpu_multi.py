@@ -147,8 +147,9 @@ def test_tune_classes_round_trip_and_extended_menu(tmp_path):
     file, equals what it returned; the 64-bit tuner also times the extended
     menu's designs when asked, and every choice can build a table."""
     path = str(tmp_path / "tune.txt")
-    table = hw.tune_classes(32, [10, 13], path=path, reps=1)
+    table = hw.tune_classes(32, [10, 13], path=path, reps=1, load=0.8, flags=hw.F_NO_ERASE)
     assert hw.load_tuning(path) == table
+    assert all(v["load"] == 0.8 and v["flags"] == hw.F_NO_ERASE for v in table.values())
     best, alls = hw.autotune(64, 1 << 12, designs=("P2_M", "ICEBERG_M", "CHAINING", "CUCKOO"), reps=1)
     assert {a["design"] for a in alls} == {"P2_M", "ICEBERG_M", "CHAINING", "CUCKOO"}
     assert best["full_ops"] == 0 and best["gops"] > 0
