@@ -1,0 +1,72 @@
+"""The bench's on-device check of the mixed concurrent workload (cfg3_check),
+run on the CPU with the oracle standing in for the table: it must accept the
+oracle's outputs batch after batch, keep the model's size and value sum equal to
+the oracle's, and reject each kind of planted mistake."""
+import numpy as np
+import pytest
+import torch
+
+import bench
+import oracle
+from paper_2509_16407_amd import workloads as w
+
+U = 1 << 12
+
+
+def _setup(n_batches=4, batch=1 << 10):
+    uk = w.universe_keys(U, config_id=3)
+    om = oracle.OracleMap()
+    om.insert(uk, 3 * uk + 1)
+    present = torch.ones(U, dtype=torch.bool)
+    val = torch.from_numpy((3 * uk + 1).view(np.int64).copy())
+    done = torch.zeros(U, dtype=torch.int32)
+    return uk, om, present, val, done, list(w.mixed_batches(U, batch, n_batches, config_id=3, ukeys=uk))
+
+
+def _run(om, bt):
+    st, out = om.apply(bt["keys"], bt["vals"], ops=bt["ops"])
+    return torch.from_numpy(st.copy()), torch.from_numpy(out.view(np.int64).copy())
+
+
+def _args(bt):
+    return (torch.from_numpy(bt["ops"].copy()), torch.from_numpy(bt["ranks"].astype(np.int64)),
+            torch.from_numpy(bt["vals"].view(np.int64).copy()))
+
+
+def test_cfg3_check_accepts_the_oracle_batch_after_batch():
+    uk, om, present, val, done, batches = _setup()
+    for bt in batches:
+        st, out = _run(om, bt)
+        ops, r, vd = _args(bt)
+        assert int(bench.cfg3_check(present, val, done, ops, r, vd, st, out)) == 0
+    assert int(present.sum()) == om.size()
+    _, ov = om.dump()
+    assert int(val[present].sum()) == int(ov.view(np.int64).sum())
+
+
+@pytest.mark.parametrize("mistake", ["query_status", "query_value", "erase_status", "upsert_twice",
+                                     "upsert_status"])
+def test_cfg3_check_rejects_planted_mistakes(mistake):
+    uk, om, present, val, done, batches = _setup(n_batches=2)
+    bt = batches[0]
+    st, out = _run(om, bt)
+    ops, r, vd = _args(bt)
+    q = np.nonzero(bt["ops"] == 0)[0]
+    e = np.nonzero(bt["ops"] == 3)[0]
+    u = np.nonzero(bt["ops"] == 2)[0]
+    if mistake == "query_status":
+        st[q[0]] ^= 1
+    elif mistake == "query_value":
+        out[q[np.nonzero(st.numpy()[q] == 1)[0][0]]] += 1
+    elif mistake == "erase_status":
+        st[e[0]] ^= 1
+    elif mistake == "upsert_twice":
+        # a key upserted more than once whose first upsert inserted: a second DONE
+        ranks = bt["ranks"][u]
+        vals, counts = np.unique(ranks, return_counts=True)
+        multi = set(vals[counts > 1].tolist())
+        cand = [i for i in u if bt["ranks"][i] in multi and st[i] == 2]
+        st[cand[0]] = 1
+    else:
+        st[u[0]] = 3  # FULL is never a valid outcome here
+    assert int(bench.cfg3_check(present, val, done, ops, r, vd, st, out)) > 0
