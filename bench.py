@@ -64,7 +64,7 @@ def log(*a):
 def make_inputs(cap_log2: int, n_mixed: int, mixed_batch: int):
     from paper_2509_16407_amd import workloads as w
     cap = 1 << cap_log2
-    keys, bounds = w.load_phases(cap, (0.5, 0.75, 0.9), config_id=2)
+    keys, bounds = w.load_phases(cap, (0.5, 0.75, 0.9), workload_id=2)
     n = bounds[-1]
     nq = min(1 << (cap_log2 - 1), n)  # 2^27 positive and 2^27 negative queries at 2^28
     pos_idx = w.sample_without_replacement(w.stream_seed(2, 3), n, nq)
@@ -74,7 +74,7 @@ def make_inputs(cap_log2: int, n_mixed: int, mixed_batch: int):
     ekeys = keys[er_idx]
     mixed = []
     if n_mixed:
-        for b in w.mixed_batches(n, mixed_batch, n_mixed, config_id=2, ukeys=keys):
+        for b in w.mixed_batches(n, mixed_batch, n_mixed, workload_id=2, ukeys=keys):
             mixed.append(b)
     return dict(cap=cap, keys=keys, bounds=bounds, qpos=qpos, qneg=qneg, ekeys=ekeys,
                 pos_idx=pos_idx, er_idx=er_idx, mixed=mixed)
@@ -415,7 +415,7 @@ def aging_probes(designs, log2cap=22, iters=1000, probe_cap_lines=80):
     import torch
     import paper_2509_16407_amd as hw
     from paper_2509_16407_amd import workloads as w
-    plan = w.aging_plan(1 << log2cap, iters=iters + 1, config_id=6)
+    plan = w.aging_plan(1 << log2cap, iters=iters + 1, workload_id=6)
     n0, s = plan["n0"], plan["s"]
     kd = to_dev(plan["keys"])
     nd = to_dev(plan["negs"])
@@ -465,7 +465,7 @@ def bench_aging(designs, log2cap=26, iters=1000, probe_cap_lines=80):
     import paper_2509_16407_amd as hw
     from paper_2509_16407_amd import workloads as w
     t0 = time.time()
-    plan = w.aging_plan(1 << log2cap, iters=iters, config_id=6)
+    plan = w.aging_plan(1 << log2cap, iters=iters, workload_id=6)
     n0, s = plan["n0"], plan["s"]
     kd = to_dev(plan["keys"])
     nd = to_dev(plan["negs"])
@@ -535,7 +535,7 @@ def bench_aging(designs, log2cap=26, iters=1000, probe_cap_lines=80):
             "ops_per_iteration": 4 * s, "designs": res}
 
 
-def cfg3_check(present, val, done, ops, r, vd, st, out):
+def mixed_zipf_check(present, val, done, ops, r, vd, st, out):
     """Checks one mixed batch's outputs against the shadow model of the map (a
     present flag and a value per universe rank) and advances the model to the
     batch's end.  Queries must return the batch-start state, erases report
@@ -562,7 +562,7 @@ def cfg3_check(present, val, done, ops, r, vd, st, out):
     return bad
 
 
-def bench_mixed_cfg3(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE_M"):
+def bench_mixed_zipf(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE_M"):
     """The mixed concurrent workload: a 2^log2cap-slot table preloaded with a 2^universe_log2-key
     universe (load 0.5, v = 3k+1), then `n_batches` shuffled mixed batches of 2^20
     operations (50% query, 30% SUM upsert, 20% erase; Zipf 0.99 keys; erase and
@@ -577,14 +577,14 @@ def bench_mixed_cfg3(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE
     from paper_2509_16407_amd import workloads as w
     t0 = time.time()
     U = 1 << universe_log2
-    uk = w.universe_keys(U, config_id=3)
-    batches = list(w.mixed_batches(U, 1 << 20, n_batches, config_id=3, ukeys=uk))
-    log("config 3: %d batches of 2^20 ops over a 2^%d-key universe generated in %.1f s"
+    uk = w.universe_keys(U, workload_id=3)
+    batches = list(w.mixed_batches(U, 1 << 20, n_batches, workload_id=3, ukeys=uk))
+    log("mixed Zipf workload: %d batches of 2^20 ops over a 2^%d-key universe generated in %.1f s"
         % (n_batches, universe_log2, time.time() - t0))
     t = hw.Table(1 << log2cap, design)
     ukd = to_dev(uk)
     pre = t.insert(ukd, ukd * 3 + 1)
-    assert bool((pre == 1).all()), "config 3 preload"
+    assert bool((pre == 1).all()), "mixed Zipf workload: preload"
     present = torch.ones(U, dtype=torch.bool, device="cuda")
     val = ukd * 3 + 1
     del ukd
@@ -607,19 +607,19 @@ def bench_mixed_cfg3(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE
         t.mixed(ops, kd, vd, combine="sum", out=out, status=st)
         b.record()
         ev.append((a, b))
-        bad += cfg3_check(present, val, done, ops, r, vd, st, out)
+        bad += mixed_zipf_check(present, val, done, ops, r, vd, st, out)
     torch.cuda.synchronize()
     nbad = int(bad.item())
-    assert nbad == 0, "config 3: %d outputs differ from the shadow model" % nbad
-    assert t.size() == int(present.sum().item()), "config 3: size"
+    assert nbad == 0, "mixed Zipf workload: %d outputs differ from the shadow model" % nbad
+    assert t.size() == int(present.sum().item()), "mixed Zipf workload: size"
     _, tv = t.export()
-    assert int(tv.sum().item()) == int(val[present].sum().item()), "config 3: sum of values"
+    assert int(tv.sum().item()) == int(val[present].sum().item()), "mixed Zipf workload: sum of values"
     ms = np.array([a.elapsed_time(b) for a, b in ev])
     res = {"workload": "%s, 2^%d slots, 2^%d-key universe preloaded (load 0.5), %d shuffled batches of 2^20 ops "
                        "(50%% query / 30%% SUM upsert / 20%% erase, Zipf 0.99)" % (design, log2cap, universe_log2, n_batches),
            "p50_batch_ms": round(float(np.percentile(ms, 50)), 4), "p99_batch_ms": round(float(np.percentile(ms, 99)), 4),
            "mean_gops": round(float(n * len(ms) / ms.sum() / 1e6), 3), "verified": True}
-    log("config 3: p50 %.3f ms, p99 %.3f ms per 2^20-op batch (%.2f Gops/s), all outputs verified"
+    log("mixed Zipf workload: p50 %.3f ms, p99 %.3f ms per 2^20-op batch (%.2f Gops/s), all outputs verified"
         % (res["p50_batch_ms"], res["p99_batch_ms"], res["mean_gops"]))
     del t, present, val, staged, done
     torch.cuda.empty_cache()
@@ -637,8 +637,8 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
     import paper_2509_16407_amd as hw
     from paper_2509_16407_amd import workloads as w
     t0 = time.time()
-    exps = w.table_exponents(n_tables, e_min, e_max, config_id=4)
-    offsets, keys, vals = w.groupby_tables(exps, load, config_id=4)
+    exps = w.table_exponents(n_tables, e_min, e_max, workload_id=4)
+    offsets, keys, vals = w.groupby_tables(exps, load, workload_id=4)
     n_ops = int(offsets[-1])
     log("batched: %d tables, %d ops generated in %.1f s" % (n_tables, n_ops, time.time() - t0))
     t0 = time.time()
@@ -749,7 +749,7 @@ def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):
     cap = 1 << log2cap
     universe = int(0.85 * cap)
     t0 = time.time()
-    reqs = list(w.served_requests(n_tables, universe, n_req, rate, config_id=5))
+    reqs = list(w.served_requests(n_tables, universe, n_req, rate, workload_id=5))
     n_ops = sum(len(r["keys"]) for r in reqs)
     log("served: %d requests, %d ops generated in %.1f s" % (n_req, n_ops, time.time() - t0))
     OP = {"query": hw.OPS["query"], "insert": hw.OPS["insert"],
@@ -982,8 +982,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--bucket", type=int, default=0)
     ap.add_argument("--mixed-batches", type=int, default=16)
-    ap.add_argument("--cfg3-batches", type=int, default=256,
-                    help="mixed 2^20-op batches of config 3 (DOUBLE_M, 2^27 slots; 0 to skip)")
+    ap.add_argument("--zipf-batches", type=int, default=256,
+                    help="2^20-op batches of the mixed Zipf workload (DOUBLE_M, 2^27 slots; 0 to skip)")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-probes", action="store_true", help="skip the GPU-counted probes (instrumented build)")
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-table (batched) section")
@@ -1090,9 +1090,9 @@ def main():
         designs[args.design]["phased"] = bench_phased(step, d, args.design, designs[args.design]["phase_gops"])
         step.t = main_t
 
-    cfg3 = None
-    if args.cfg3_batches:
-        cfg3 = bench_mixed_cfg3(n_batches=args.cfg3_batches)
+    zipf = None
+    if args.zipf_batches:
+        zipf = bench_mixed_zipf(n_batches=args.zipf_batches)
 
     aging = None
     if not args.no_aging:
@@ -1130,7 +1130,7 @@ def main():
         "upsert_gops": rates["upsert"]["gops"], "upsert_miss_gops": rates["upsert_miss_0.9"]["gops"],
         "p50_batch_ms": None if p50 is None else round(p50, 4),
         "p99_batch_ms": None if p99 is None else round(p99, 4),
-        "roofline": roof, "probes": probes, "cpu_baseline": cpu, "designs": designs, "mixed_config3": cfg3,
+        "roofline": roof, "probes": probes, "cpu_baseline": cpu, "designs": designs, "mixed_zipf": zipf,
         "aging": aging,
         "batched": batched,
         "served": served,

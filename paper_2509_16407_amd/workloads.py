@@ -302,7 +302,7 @@ def value_of(keys: np.ndarray, key_bits: int = 64) -> np.ndarray:
     return v
 
 
-def load_then_query(capacity: int, load: float, config_id: int = 1):
+def load_then_query(capacity: int, load: float, workload_id: int = 1):
     """Insert floor(load*capacity) distinct keys (v = 3k+1), then query them plus the
     same number of absent keys (continuation of the key stream), shuffled.
 
@@ -310,29 +310,29 @@ def load_then_query(capacity: int, load: float, config_id: int = 1):
     positive queries.  Absent keys are guaranteed distinct from inserted ones.
     """
     n = int(load * capacity)
-    s_keys = stream_seed(config_id, 1)
+    s_keys = stream_seed(workload_id, 1)
     keys = distinct_keys(s_keys, n)
     absent = distinct_keys(s_keys, n, skip=n)
     q = np.concatenate([keys, absent])
-    perm = permutation(stream_seed(config_id, 2), len(q))
+    perm = permutation(stream_seed(workload_id, 2), len(q))
     qkeys = q[perm]
     expect_found = perm < n
     return dict(keys=keys, vals=value_of(keys), qkeys=qkeys, expect_found=expect_found)
 
 
-def load_phases(capacity: int, fractions=(0.5, 0.75, 0.9), config_id: int = 2):
+def load_phases(capacity: int, fractions=(0.5, 0.75, 0.9), workload_id: int = 2):
     """Distinct-key insert phases filling a table to each fraction of `capacity`.
 
     Phase p inserts keys [floor(f_{p-1} * cap), floor(f_p * cap)) of one stream.
     Returns (all_keys, bounds) with bounds[p] = cumulative count after phase p.
     """
     bounds = [int(f * capacity) for f in fractions]
-    keys = distinct_keys(stream_seed(config_id, 1), bounds[-1])
+    keys = distinct_keys(stream_seed(workload_id, 1), bounds[-1])
     return keys, bounds
 
 
 def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99,
-                  frac_upsert: float = 0.3, frac_erase: float = 0.2, config_id: int = 3,
+                  frac_upsert: float = 0.3, frac_erase: float = 0.2, workload_id: int = 3,
                   ukeys: np.ndarray | None = None):
     """Generator of deterministic mixed batches over a Zipf-distributed key universe.
 
@@ -348,13 +348,13 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
     Yields dict(ops, keys, vals) with ops coded 0 query, 2 upsert, 3 erase.
     """
     if ukeys is None:
-        ukeys = distinct_keys(stream_seed(config_id, 1), universe)
+        ukeys = distinct_keys(stream_seed(workload_id, 1), universe)
     assert len(ukeys) == universe
     z = Zipf(universe, theta)
     n_up = int(frac_upsert * batch)
     n_er = int(frac_erase * batch)
     n_q = batch - n_up - n_er
-    zs = stream_seed(config_id, 3)
+    zs = stream_seed(workload_id, 3)
     zpos = 0
     for b in range(n_batches):
         def draw(count):
@@ -386,8 +386,8 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
                               np.full(n_er, 3, np.uint8)])
         ranks = np.concatenate([qr, up, er])
         vals = np.zeros(batch, dtype=np.uint64)
-        vals[n_q:n_q + n_up] = splitmix64(stream_seed(config_id, 4), b * batch, n_up)
-        perm = permutation(stream_seed(config_id, 1000 + b), batch)
+        vals[n_q:n_q + n_up] = splitmix64(stream_seed(workload_id, 4), b * batch, n_up)
+        perm = permutation(stream_seed(workload_id, 1000 + b), batch)
         yield dict(ops=ops[perm], keys=ukeys[ranks[perm]], vals=vals[perm], ranks=ranks[perm])
 
 
@@ -405,12 +405,12 @@ def sample_without_replacement(seed: int, n: int, k: int) -> np.ndarray:
     return out
 
 
-def universe_keys(universe: int, config_id: int = 3) -> np.ndarray:
+def universe_keys(universe: int, workload_id: int = 3) -> np.ndarray:
     """The key universe used by `mixed_batches` (same stream)."""
-    return distinct_keys(stream_seed(config_id, 1), universe)
+    return distinct_keys(stream_seed(workload_id, 1), universe)
 
 
-def groupby_tables(exponents, load: float = 0.85, config_id: int = 4):
+def groupby_tables(exponents, load: float = 0.85, workload_id: int = 4):
     """Group-by aggregation batches for tables of capacity 2^e (e in `exponents`):
     table t gets D_t = floor(load * 2^e) distinct uint32 keys, each followed by a
     uniform repeat of one of them, with uint32 values.  Returns (offsets, keys,
@@ -424,7 +424,7 @@ def groupby_tables(exponents, load: float = 0.85, config_id: int = 4):
 
     def fill(t):
         a, d = int(offsets[t]), ds[t]
-        h.groupby_fill(_c_u64(stream_seed(config_id, 1 << 20 | t)), _c_u64(d),
+        h.groupby_fill(_c_u64(stream_seed(workload_id, 1 << 20 | t)), _c_u64(d),
                        _cptr(keys[a: a + 2 * d]), _cptr(vals[a: a + 2 * d]))
 
     import concurrent.futures as cf
@@ -434,9 +434,9 @@ def groupby_tables(exponents, load: float = 0.85, config_id: int = 4):
     return offsets, keys, vals
 
 
-def table_exponents(n_tables: int, e_min: int, e_max: int, config_id: int = 4) -> np.ndarray:
+def table_exponents(n_tables: int, e_min: int, e_max: int, workload_id: int = 4) -> np.ndarray:
     """Capacity exponents uniform in [e_min, e_max] (log-uniform capacities)."""
-    return uniform_below(stream_seed(config_id, 2), 0, n_tables, e_max - e_min + 1) + e_min
+    return uniform_below(stream_seed(workload_id, 2), 0, n_tables, e_max - e_min + 1) + e_min
 
 
 def splitmix64_at(seed: int, idx: np.ndarray) -> np.ndarray:
@@ -449,14 +449,14 @@ def splitmix64_at(seed: int, idx: np.ndarray) -> np.ndarray:
 
 
 def served_requests(n_tables: int, universe: int, n_req: int, rate_per_s: float, log2_min: float = 8,
-                    log2_max: float = 20, theta: float = 0.99, mix=(0.5, 0.3, 0.2), config_id: int = 5):
+                    log2_max: float = 20, theta: float = 0.99, mix=(0.5, 0.3, 0.2), workload_id: int = 5):
     """Request stream of the served form: Poisson arrivals at `rate_per_s` (exponential
     gaps), table uniform over n_tables, kind query / upsert / insert with
     probabilities `mix`, size floor(2^U) with U uniform in [log2_min, log2_max], keys
     Zipf(theta) ranks over a per-table universe whose rank-r key is element r of
     stream (config, 100 + table).  Yields dicts (t_offset, table, kind, keys, vals);
     insert values are 3k+1, upsert values a separate stream."""
-    u = unit_float(stream_seed(config_id, 1), 0, 4 * n_req)
+    u = unit_float(stream_seed(workload_id, 1), 0, 4 * n_req)
     z = Zipf(universe, theta)
     t = 0.0
     zpos = 0
@@ -466,12 +466,12 @@ def served_requests(n_tables: int, universe: int, n_req: int, rate_per_s: float,
         r = u[4 * i + 2]
         kind = "query" if r < mix[0] else ("upsert" if r < mix[0] + mix[1] else "insert")
         n = int(2.0 ** (log2_min + (log2_max - log2_min) * u[4 * i + 3]))
-        ranks = z.ranks(stream_seed(config_id, 2), zpos, n)
-        keys = splitmix64_at(stream_seed(config_id, 100 + table), ranks)
+        ranks = z.ranks(stream_seed(workload_id, 2), zpos, n)
+        keys = splitmix64_at(stream_seed(workload_id, 100 + table), ranks)
         if kind == "insert":
             vals = value_of(keys)
         elif kind == "upsert":
-            vals = splitmix64(stream_seed(config_id, 3), zpos, n)
+            vals = splitmix64(stream_seed(workload_id, 3), zpos, n)
         else:
             vals = None
         zpos += n
@@ -491,7 +491,7 @@ def stream_keys(seed: int, start: int, count: int) -> np.ndarray:
 
 
 def aging_plan(capacity: int, load: float = 0.85, frac: float = 0.01, iters: int = 1000,
-               config_id: int = 6):
+               workload_id: int = 6):
     """The aging (churn) benchmark of Section 6.5.  The table is filled to `load`
     (n0 = floor(load * capacity) keys, v = 3k+1); then every iteration, in ONE
     mixed launch, inserts the next s = floor(frac * n0) new keys, erases the oldest
@@ -511,9 +511,9 @@ def aging_plan(capacity: int, load: float = 0.85, frac: float = 0.01, iters: int
     if n0 < 2 * s:
         raise ValueError("the fill must hold at least two slices")
     total = n0 + iters * s
-    seed = stream_seed(config_id, 1)
+    seed = stream_seed(workload_id, 1)
     keys = stream_keys(seed, 0, total)
     negs = stream_keys(seed, total, iters * s)
-    off = uniform_below(stream_seed(config_id, 2), 0, iters, n0 - 2 * s + 1)
+    off = uniform_below(stream_seed(workload_id, 2), 0, iters, n0 - 2 * s + 1)
     pos_start = (np.arange(iters, dtype=np.int64) + 1) * s + off.astype(np.int64)
     return dict(n0=n0, s=s, iters=iters, keys=keys, negs=negs, pos_start=pos_start)

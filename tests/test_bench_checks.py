@@ -1,4 +1,4 @@
-"""The bench's on-device check of the mixed concurrent workload (cfg3_check),
+"""The bench's on-device check of the mixed concurrent workload (mixed_zipf_check),
 run on the CPU with the oracle standing in for the table: it must accept the
 oracle's outputs batch after batch, keep the model's size and value sum equal to
 the oracle's, and reject each kind of planted mistake."""
@@ -14,13 +14,13 @@ U = 1 << 12
 
 
 def _setup(n_batches=4, batch=1 << 10):
-    uk = w.universe_keys(U, config_id=3)
+    uk = w.universe_keys(U, workload_id=3)
     om = oracle.OracleMap()
     om.insert(uk, 3 * uk + 1)
     present = torch.ones(U, dtype=torch.bool)
     val = torch.from_numpy((3 * uk + 1).view(np.int64).copy())
     done = torch.zeros(U, dtype=torch.int32)
-    return uk, om, present, val, done, list(w.mixed_batches(U, batch, n_batches, config_id=3, ukeys=uk))
+    return uk, om, present, val, done, list(w.mixed_batches(U, batch, n_batches, workload_id=3, ukeys=uk))
 
 
 def _run(om, bt):
@@ -33,12 +33,12 @@ def _args(bt):
             torch.from_numpy(bt["vals"].view(np.int64).copy()))
 
 
-def test_cfg3_check_accepts_the_oracle_batch_after_batch():
+def test_mixed_zipf_check_accepts_the_oracle_batch_after_batch():
     uk, om, present, val, done, batches = _setup()
     for bt in batches:
         st, out = _run(om, bt)
         ops, r, vd = _args(bt)
-        assert int(bench.cfg3_check(present, val, done, ops, r, vd, st, out)) == 0
+        assert int(bench.mixed_zipf_check(present, val, done, ops, r, vd, st, out)) == 0
     assert int(present.sum()) == om.size()
     _, ov = om.dump()
     assert int(val[present].sum()) == int(ov.view(np.int64).sum())
@@ -46,7 +46,7 @@ def test_cfg3_check_accepts_the_oracle_batch_after_batch():
 
 @pytest.mark.parametrize("mistake", ["query_status", "query_value", "erase_status", "upsert_twice",
                                      "upsert_status"])
-def test_cfg3_check_rejects_planted_mistakes(mistake):
+def test_mixed_zipf_check_rejects_planted_mistakes(mistake):
     uk, om, present, val, done, batches = _setup(n_batches=2)
     bt = batches[0]
     st, out = _run(om, bt)
@@ -69,4 +69,4 @@ def test_cfg3_check_rejects_planted_mistakes(mistake):
         st[cand[0]] = 1
     else:
         st[u[0]] = 3  # FULL is never a valid outcome here
-    assert int(bench.cfg3_check(present, val, done, ops, r, vd, st, out)) > 0
+    assert int(bench.mixed_zipf_check(present, val, done, ops, r, vd, st, out)) > 0

@@ -24,7 +24,7 @@ OPQ, OPI, OPE = 0, 1, 3
                                     "CUCKOO"])
 def test_aging_against_oracle(design):
     cap = 1 << 16
-    plan = w.aging_plan(cap, iters=150, config_id=6)
+    plan = w.aging_plan(cap, iters=150, workload_id=6)
     n0, s = plan["n0"], plan["s"]
     keys, negs = plan["keys"], plan["negs"]
     pcap = {"DOUBLE": 80, "DOUBLE_M": 20}.get(design, 0)

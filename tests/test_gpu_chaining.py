@@ -118,14 +118,14 @@ def test_chaining_pool_exhaustion_reports_full():
 
 
 def test_chaining_mixed_and_litmus():
-    """Mixed batches (config 3 shape) and concurrent inserts with queries of the
+    """Mixed Zipf batches with disjoint erase, upsert and query keys and concurrent inserts with queries of the
     same fresh keys: a reported key always carries its own value."""
     cap = 1 << 18
     t = hw.Table(cap, "CHAINING")
     om = oracle.OracleMap()
-    uk = w.universe_keys(cap // 2, config_id=3)
+    uk = w.universe_keys(cap // 2, workload_id=3)
     assert np.array_equal(u8(t.insert(dev(uk), dev(w.value_of(uk)))), om.insert(uk, w.value_of(uk)))
-    for b in w.mixed_batches(cap // 2, 1 << 15, 3, config_id=3):
+    for b in w.mixed_batches(cap // 2, 1 << 15, 3, workload_id=3):
         ops = b["ops"]
         s, v = t.mixed(torch.from_numpy(ops).cuda(), dev(b["keys"]), dev(b["vals"]), combine="sum")
         s, v = u8(s), host(v)

@@ -40,10 +40,10 @@ def test_menus_match_library():
 @pytest.mark.parametrize("flags", [0, hw.F_NO_ERASE], ids=["locked", "noerase"])
 def test_multi_groupby_equals_plain_and_oracle(flags):
     n = 2 * len(MENU32) * 3
-    exps = w.table_exponents(n, 9, 14, config_id=41)
+    exps = w.table_exponents(n, 9, 14, workload_id=41)
     cfgs = [MENU32[i % len(MENU32)] for i in range(n)]
     # power-of-two-choice tables get a lower fill so no key finds both buckets full
-    offsets, keys, vals = w.groupby_tables(exps, 0.65, config_id=41)
+    offsets, keys, vals = w.groupby_tables(exps, 0.65, workload_id=41)
     A = [hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t, flags=flags) for e, (d, b, t) in zip(exps, cfgs)]
     B = [hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t, flags=flags) for e, (d, b, t) in zip(exps, cfgs)]
     m = hw.Multi(A)

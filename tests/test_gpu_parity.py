@@ -63,12 +63,12 @@ def check_dump(t, om):
     assert t.size() == len(ok)
 
 
-# ------------------------------------------------------------------ load benchmark (config 1)
+# ------------------------------------------------------------------ load benchmark, double hashing at 2^20 slots
 
-def test_config1_double_hashing_2p20():
+def test_load_double_hashing_2p20():
     """2^20-slot double hashing, bucket 8: insert 943,718 keys (v = 3k+1), query them
     and 943,718 absent keys; all outputs, the dump and the layout against the oracle."""
-    d = w.load_then_query(1 << 20, 0.9, config_id=1)
+    d = w.load_then_query(1 << 20, 0.9, workload_id=1)
     t = hw.Table(1 << 20, "DOUBLE")
     assert t.capacity == 1 << 20 and t.num_buckets == 1 << 17
     om = oracle.OracleMap()
@@ -174,7 +174,7 @@ def test_all_ops_against_oracle(design, bits, bucket, tile):
     check_layout(t)
 
 
-# ------------------------------------------------------------------ mixed batches (config 3 shape)
+# ------------------------------------------------------------------ mixed batches (Zipf 0.99, disjoint erase / upsert / query keys)
 
 @pytest.mark.parametrize("design", ["DOUBLE_M", "P2_M", "DOUBLE", "P2", "ICEBERG_M", "ICEBERG", "CUCKOO"])
 def test_mixed_batches_against_oracle(design):
@@ -186,10 +186,10 @@ def test_mixed_batches_against_oracle(design):
     universe = cap // 2
     t = hw.Table(cap, design)
     om = oracle.OracleMap()
-    uk = w.universe_keys(universe, config_id=3)
+    uk = w.universe_keys(universe, workload_id=3)
     st = u8(t.insert(dev(uk), dev(w.value_of(uk))))
     assert np.array_equal(st, om.insert(uk, w.value_of(uk)))
-    for b in w.mixed_batches(universe, 1 << 15, 4, config_id=3):
+    for b in w.mixed_batches(universe, 1 << 15, 4, workload_id=3):
         ops = b["ops"]
         import torch
         s, v = t.mixed(torch.from_numpy(ops).cuda(), dev(b["keys"]), dev(b["vals"]), combine="sum")
@@ -205,7 +205,7 @@ def test_mixed_batches_against_oracle(design):
     check_layout(t)
 
 
-# ------------------------------------------------------------------ 32-bit group-by (config 4 shape)
+# ------------------------------------------------------------------ 32-bit group-by over many tables
 
 @pytest.mark.parametrize("flags", [0, hw.F_NO_ERASE], ids=["locked", "noerase"])
 @pytest.mark.parametrize("design", ALL)
@@ -315,7 +315,7 @@ def test_iceberg_load_2p20(design, paper):
     those keys plus as many absent ones: every output, the dump and the layout
     against the oracle; no backyard key has room in its front bucket (the table
     never erased); positive-query probes near Table 1's load-phase figure."""
-    d = w.load_then_query(1 << 20, 0.9, config_id=1)
+    d = w.load_then_query(1 << 20, 0.9, workload_id=1)
     t = hw.Table(1 << 20, design)
     om = oracle.OracleMap()
     st = u8(t.insert(dev(d["keys"]), dev(d["vals"])))

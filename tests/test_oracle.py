@@ -65,7 +65,7 @@ def test_map_matches_brute_force(key_bits, seed):
 def test_load_benchmark_closed_form():
     """Insert 0.9 * 2^20 distinct keys with v = 3k+1, query them and as many absent
     keys: every insert reports INSERTED, positives return 3k+1, negatives miss."""
-    d = w.load_then_query(1 << 20, 0.9, config_id=1)
+    d = w.load_then_query(1 << 20, 0.9, workload_id=1)
     assert len(d["keys"]) == 943718
     m = oracle.OracleMap()
     st = m.insert(d["keys"], d["vals"])
@@ -430,7 +430,7 @@ _AGING = {}
 def _aging(name, bucket, tile_bytes, cap_buckets, from_iter):
     key = (name, from_iter)
     if key not in _AGING:
-        plan = w.aging_plan(1 << 16, iters=1000, config_id=6)
+        plan = w.aging_plan(1 << 16, iters=1000, workload_id=6)
         _AGING[key] = oracle.sim_aging(DESIGNS[name], (1 << 16) // bucket, bucket, plan,
                                        tile_bytes=tile_bytes, probe_cap=cap_buckets, from_iter=from_iter)
     return _AGING[key]

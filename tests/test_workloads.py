@@ -68,7 +68,7 @@ def test_zipf_rank_frequencies():
 
 
 def test_mixed_batches_are_deterministic_and_disjoint():
-    gen = w.mixed_batches(1 << 14, 1 << 12, 2, config_id=3)
+    gen = w.mixed_batches(1 << 14, 1 << 12, 2, workload_id=3)
     for b in gen:
         ops, keys = b["ops"], b["keys"]
         er = keys[ops == 3]
@@ -78,8 +78,8 @@ def test_mixed_batches_are_deterministic_and_disjoint():
         assert len(up) == int(0.3 * 4096)
         assert len(np.intersect1d(er, up)) == 0
         assert len(np.intersect1d(q, np.concatenate([er, up]))) == 0
-    g1 = next(w.mixed_batches(1 << 14, 1 << 12, 1, config_id=3))
-    g2 = next(w.mixed_batches(1 << 14, 1 << 12, 1, config_id=3))
+    g1 = next(w.mixed_batches(1 << 14, 1 << 12, 1, workload_id=3))
+    g2 = next(w.mixed_batches(1 << 14, 1 << 12, 1, workload_id=3))
     assert all(np.array_equal(g1[k], g2[k]) for k in g1)
 
 
