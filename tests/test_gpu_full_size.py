@@ -93,3 +93,39 @@ def test_full_size_mixed_zipf_batches_against_oracle():
     of, ov = om.query(touched)
     assert np.array_equal(u8(f), of) and np.array_equal(host(v), ov), "state of the touched keys"
     assert t.size() == U - erased_total + inserted_total
+
+
+def test_full_size_batched_groupby_against_oracle():
+    """The batched form at full size: 4096 uint32 tables with capacities 2^e (e
+    uniform in 10..22, ~2.7e9 slots in all), each receiving a group-by SUM-upsert
+    batch that fills it to 0.85, in one persistent multi-table launch (double
+    hashing, bucket 16, tile 4: the tuner's choice for most classes).  Per table,
+    exactly its distinct keys insert and its size equals their count; twelve
+    sampled tables and the first of the largest class equal the oracle's
+    group-by, key by key."""
+    import torch
+    exps = w.table_exponents(4096, 10, 22, workload_id=4)
+    offsets, keys, vals = w.groupby_tables(exps, 0.85, workload_id=4)
+    ds = (offsets[1:] - offsets[:-1]) // 2
+    tabs = [hw.Table(1 << int(e), "DOUBLE", kv_bits=32, bucket=16, tile=4) for e in exps]
+    m = hw.Multi(tabs)
+    kd = torch.from_numpy(keys.view(np.int32)).cuda()
+    vd = torch.from_numpy(vals.view(np.int32)).cuda()
+    st = m.upsert(offsets, kd, vd, combine="sum")
+    del kd, vd
+    assert int((st == hw.ST_DONE).sum()) == int(ds.sum())
+    assert int((st == hw.ST_EXISTED).sum()) == int(ds.sum())
+    del st
+    assert [t.size() for t in tabs] == [int(x) for x in ds]
+    pick = w.sample_without_replacement(w.stream_seed(4, 10), len(tabs), 12).tolist()
+    pick.append(int(np.argmax(exps)))
+    for i in pick:
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        om = oracle.OracleMap(key_bits=32)
+        om.upsert(keys[a:b].astype(np.uint64), vals[a:b].astype(np.uint64))
+        k, v = tabs[i].export()
+        k = k.cpu().numpy().view(np.uint32).astype(np.uint64)
+        v = v.cpu().numpy().view(np.uint32).astype(np.uint64)
+        o = np.argsort(k)
+        ok, ov = om.dump()
+        assert np.array_equal(k[o], ok) and np.array_equal(v[o], ov), i
