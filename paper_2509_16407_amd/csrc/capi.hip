@@ -4,6 +4,7 @@
 // (initialisation, counting, export, primary-bucket lookup).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -220,14 +221,20 @@ __global__ void k_primary(const K* __restrict__ keys, uint64_t n, uint32_t mask,
     out[i] = nf ? front_bucket((uint64_t)keys[i], nf) : hash_key((uint64_t)keys[i], mask).b1;
 }
 
+// Grid cap for grid-stride kernels, cached per device (tables may be created
+// from several host threads, e.g. beside a serving loop's worker).
 unsigned max_blocks_for(int device) {
-  static unsigned cache[64] = {0};
-  if (device >= 0 && device < 64 && cache[device]) return cache[device];
+  static std::atomic<unsigned> cache[64];
+  const bool cached = device >= 0 && device < 64;
+  if (cached) {
+    const unsigned c = cache[device].load(std::memory_order_relaxed);
+    if (c) return c;
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
     cus = 256;
-  unsigned v = (unsigned)cus * 32;
-  if (device >= 0 && device < 64) cache[device] = v;
+  const unsigned v = (unsigned)cus * 32;
+  if (cached) cache[device].store(v, std::memory_order_relaxed);
   return v;
 }
 
