@@ -150,6 +150,7 @@ def test_tuning_file_round_trip(tmp_path):
     "hwave-tune 2\n10 0 0 32 0 16 4 7.0 0\n",            # load 0
     "hwave-tune 2\n10 1.5 0 32 0 16 4 7.0 0\n",          # load above 1
     "hwave-tune 2\n10 0.85 16 32 0 16 4 7.0 0\n",        # unknown flag
+    "hwave-tune 2\n10 nan 0 32 0 16 4 7.0 0\n",           # load not a number
 ])
 def test_tuning_file_rejects_malformed(tmp_path, body):
     path = tmp_path / "bad.txt"
