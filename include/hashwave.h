@@ -77,7 +77,14 @@ enum {
   HWAVE_ST_DONE = 1,     /* insert/upsert: inserted; query: found; erase: erased   */
   HWAVE_ST_EXISTED = 2,  /* insert/upsert: key present, combine applied           */
   HWAVE_ST_FULL = 3,     /* insert/upsert: no free slot among the key's buckets   */
-  HWAVE_ST_INVALID = 4   /* key equals a reserved pattern; the op had no effect   */
+  HWAVE_ST_INVALID = 4,  /* key equals a reserved pattern; the op had no effect   */
+  HWAVE_ST_TIMEOUT = 5   /* insert/upsert/erase: waited longer than the table's
+                            lock_timeout_us for the key's bucket lock, or saw
+                            that another operation of the table had; the op
+                            had no effect.  A failure report, not a result: the
+                            abandoned ticket leaves that bucket's lock unusable,
+                            so later writers of the bucket time out as well,
+                            until hwave_clear empties the table               */
 };
 
 /* Return codes. */
@@ -126,7 +133,23 @@ enum {
                               into the table before the call's work is
                               complete.  Calls that write such a table must
                               then run one at a time (stream-ordered); queries
-                              may overlap them as with any write            */
+                              may overlap them as with any write            */,
+  HWAVE_F_MERGE_MIXED = 16 /* hwave_mixed merges the upserts of each call by key
+                              before they reach the table (SUM, KEEP, MIN,
+                              MAX; not REPLACE, and not inserts): every key's
+                              upserts become ONE table upsert of their combined
+                              value, run by the one with the smallest index,
+                              which reports the table's status; the others
+                              report EXISTED (or its FULL / INVALID / TIMEOUT).
+                              That is the serialisation "each key's upserts
+                              back to back" (Section 4.1 serialises a key's
+                              writers on one lock anyway), and it spares a
+                              skewed batch's hot keys thousands of locked
+                              operations in one lock queue.  Costs two more
+                              launches per 2^20 operations and 52 MiB of
+                              workspace in the table; calls that write the
+                              table must then run one at a time
+                              (stream-ordered)                              */
 };
 
 /* Table configuration.  Zero fields take the design's defaults (the
@@ -156,12 +179,20 @@ typedef struct {
   uint32_t tile;         /* lanes cooperating on one operation                */
   uint32_t probe_cap;    /* double hashing: max buckets visited (0 = all)      */
   uint32_t flags;        /* HWAVE_F_*                                         */
+  uint32_t lock_timeout_us; /* longest wait of one operation for its bucket's
+                           lock, in microseconds (0 = 10 s; at most 40 s, else
+                           HWAVE_EINVAL).  Bucket locks are FIFO ticket locks
+                           (Section 4.1 serialises a key's writers on its
+                           primary bucket's lock), so a wait is bounded by the
+                           operations queued ahead times one critical section;
+                           an operation still waiting at the limit gives up
+                           with HWAVE_ST_TIMEOUT (see there)                   */
 } hwave_config;
 
 /* Fills *out with the design's defaults.  Returns HWAVE_OK or HWAVE_EINVAL. */
 int hwave_config_default(hwave_design design, hwave_config* out);
 
-/* Device bytes a table needs (slots + tags + lock bytes + control word) for a
+/* Device bytes a table needs (slots + tags + lock words + control word) for a
  * capacity rounded up to bucket_slots * 2^k slots.  Host-only arithmetic. */
 int hwave_table_bytes(uint64_t capacity_slots, hwave_design design, const hwave_config* cfg,
                       uint64_t* bytes);
@@ -183,7 +214,8 @@ int hwave_create_in(hwave_table** out, void* d_buffer, uint64_t buffer_bytes,
 /* Synchronises the device, then frees the table (and its memory if owned). */
 int hwave_destroy(hwave_table* t);
 
-/* Empties the table (every slot empty, tags empty, locks clear) on `stream`. */
+/* Empties the table (every slot empty, tags empty, locks free, the lock
+ * failure flag of HWAVE_ST_TIMEOUT cleared) on `stream`. */
 int hwave_clear(hwave_table* t, void* stream);
 
 /* Insert = Upsert with KEEP (Section 5.1).  d_vals may not be NULL.  d_status
@@ -232,6 +264,18 @@ uint64_t hwave_num_buckets(const hwave_table* t);
 int hwave_primary_bucket(hwave_table* t, const void* d_keys, uint64_t n, uint64_t* d_out,
                          void* stream);
 
+/* The buckets each key may occupy, three entries per key in d_out (3n
+ * uint64_t; unused entries all-ones): power-of-two-choice -- primary and
+ * alternate bucket (Section 2.2); iceberg -- front-yard bucket and the two
+ * backyard choices; cuckoo -- its three buckets; double hashing -- the primary
+ * bucket and the probe step (the sequence is primary + i * step modulo the
+ * bucket count); chaining -- the bucket.  With a raw image (hwave_raw) this
+ * lets a caller check that a FULL status was legal: every candidate bucket
+ * full (Section 2.2: a power-of-two-choice insert fails only when both of
+ * its buckets are full). */
+int hwave_candidate_buckets(hwave_table* t, const void* d_keys, uint64_t n, uint64_t* d_out,
+                            void* stream);
+
 /* Slot capacity after rounding. */
 uint64_t hwave_capacity(const hwave_table* t);
 
@@ -241,8 +285,9 @@ typedef struct {
                            8 16-byte units, unit 7 the link (empty key word,
                            next node index or all-ones in the value word)     */
   uint16_t* tags;       /* capacity 16-bit tags, or NULL without tags             */
-  uint32_t* locks;      /* lock bytes: byte b is bucket b's lock (0 = free)       */
-  uint64_t n_lock_words;
+  uint32_t* locks;      /* bucket b's lock: 32-bit words 2b (ticket being served)
+                           and 2b + 1 (next ticket); free when equal           */
+  uint64_t n_lock_words; /* 32-bit words: 2 per bucket                           */
   uint64_t num_buckets;
   uint32_t bucket_slots, tile, kv_bits, design;
   uint64_t slot_bytes;  /* bytes of the slot region (chaining: every node)     */

@@ -22,11 +22,12 @@ LIB_INSTR_PATH = os.path.join(HERE, "libhashwave_instr.so")
 DESIGNS = {"DOUBLE": 0, "DOUBLE_M": 1, "P2": 2, "P2_M": 3, "ICEBERG": 4, "ICEBERG_M": 5, "CHAINING": 6, "CUCKOO": 7}
 COMBINES = {"sum": 0, "keep": 1, "replace": 2, "min": 3, "max": 4}
 OPS = {"query": 0, "insert": 1, "upsert": 2, "erase": 3}
-ST_MISS, ST_DONE, ST_EXISTED, ST_FULL, ST_INVALID = 0, 1, 2, 3, 4
+ST_MISS, ST_DONE, ST_EXISTED, ST_FULL, ST_INVALID, ST_TIMEOUT = 0, 1, 2, 3, 4, 5
 F_NO_SHORTCUT = 1
 F_NO_ERASE = 2
 F_BSP = 4
 F_AGGREGATE = 8
+F_MERGE_MIXED = 16
 
 
 class HashWaveError(RuntimeError):
@@ -36,7 +37,7 @@ class HashWaveError(RuntimeError):
 class _Config(ctypes.Structure):
     _fields_ = [("kv_bits", ctypes.c_uint32), ("bucket_slots", ctypes.c_uint32),
                 ("tile", ctypes.c_uint32), ("probe_cap", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("lock_timeout_us", ctypes.c_uint32)]
 
 
 class _Item(ctypes.Structure):
@@ -119,6 +120,7 @@ def _bind(L):
         "hwave_num_buckets": (U64, [P]),
         "hwave_capacity": (U64, [P]),
         "hwave_primary_bucket": (I, [P, P, U64, P, P]),
+        "hwave_candidate_buckets": (I, [P, P, U64, P, P]),
         "hwave_raw": (I, [P, ctypes.POINTER(_Raw)]),
         "hwave_strerror": (ctypes.c_char_p, [I]),
         "hwave_last_hip_error": (I, []),
@@ -180,13 +182,13 @@ class Table:
 
     def __init__(self, capacity: int, design: str = "P2_M", kv_bits: int = 64, bucket: int = 0,
                  tile: int = 0, probe_cap: int = 0, flags: int = 0, device=None, stream=None,
-                 instrumented: bool = False):
+                 instrumented: bool = False, lock_timeout_us: int = 0):
         import torch
         L = lib(instrumented)
         self._L = L
         self.design = design
         self.design_id = DESIGNS[design]
-        self.cfg = _Config(kv_bits, bucket, tile, probe_cap, flags)
+        self.cfg = _Config(kv_bits, bucket, tile, probe_cap, flags, lock_timeout_us)
         nbytes = ctypes.c_uint64()
         _check(L.hwave_table_bytes(capacity, self.design_id, ctypes.byref(self.cfg),
                                    ctypes.byref(nbytes)))
@@ -299,6 +301,15 @@ class Table:
         _check(self._L.hwave_primary_bucket(self.h, _ptr(self._keys(keys)), n, _ptr(out),
                                           _stream(stream)))
         return out
+
+    def candidate_buckets(self, keys, stream=None):
+        """(n, 3) int64 tensor: the buckets each key may occupy (C-ABI
+        hwave_candidate_buckets; unused entries -1)."""
+        n = keys.numel()
+        out = self._empty(3 * n, dtype=__import__("torch").int64)
+        _check(self._L.hwave_candidate_buckets(self.h, _ptr(self._keys(keys)), n, _ptr(out),
+                                             _stream(stream)))
+        return out.view(n, 3)
 
     def probe_counters(self, reset: bool = False, stream=None) -> dict:
         """Query probe counters (instrumented tables only, C-ABI hwave_probe_counters)."""

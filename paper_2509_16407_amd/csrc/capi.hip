@@ -26,6 +26,8 @@ struct hwave_table {
   bool owns;
   const KernelSet* ks;
   LaunchArgs la;
+  bool has_merge;  // HWAVE_F_MERGE_MIXED: workspace for merging mixed calls' upserts
+  MergeWs ws;
 };
 
 namespace {
@@ -38,11 +40,15 @@ int hip_fail(hipError_t e) {
 }
 
 constexpr uint64_t ALIGN = 256;
+// A waiter's limit for its bucket lock (hwave_config.lock_timeout_us), converted
+// to ticks of the 100 MHz wall clock, which must fit 32 bits.
+constexpr uint32_t DEFAULT_LOCK_TIMEOUT_US = 10000000;
+constexpr uint32_t MAX_LOCK_TIMEOUT_US = 40000000;
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   uint64_t nb, capacity, units, pool;
-  uint64_t off_tags, off_locks, off_ctrl, off_pool_ctr, off_hot, total;
+  uint64_t off_tags, off_locks, off_ctrl, off_pool_ctr, off_hot, off_merge, total;
   uint64_t n_lock_words;
 };
 
@@ -54,12 +60,25 @@ bool has_hot(hwave_design design, const hwave_config& c) {
 }
 
 // Appends the hot-key accumulators (tags, then accumulators) at `off` if the
-// table has them; they lie in the zero-filled part of the table.
+// table has them; they lie in the zero-filled part of the table.  Then the
+// merge workspace of HWAVE_F_MERGE_MIXED tables (hw_merge.hpp: 2 * MERGE_CHUNK
+// entries of a key word and 16 bytes, and a word per operation of a chunk), also
+// all zero when empty.
+constexpr uint64_t MERGE_ENTRIES = 2ull * MERGE_CHUNK;
+uint64_t merge_bytes() { return MERGE_ENTRIES * (8 + sizeof(MergeEntry)) + (uint64_t)MERGE_CHUNK * 4; }
+
 uint64_t place_hot(hwave_design design, const hwave_config& c, uint64_t off, Layout* L) {
   L->off_hot = 0;
-  if (!has_hot(design, c)) return off;
-  L->off_hot = off;
-  return off + round_up((uint64_t)HOT_N * 16, ALIGN);
+  L->off_merge = 0;
+  if (has_hot(design, c)) {
+    L->off_hot = off;
+    off += round_up((uint64_t)HOT_N * 16, ALIGN);
+  }
+  if (c.flags & HWAVE_F_MERGE_MIXED) {
+    L->off_merge = off;
+    off += round_up(merge_bytes(), ALIGN);
+  }
+  return off;
 }
 
 bool design_tags(int d) { return d == HWAVE_DOUBLE_M || d == HWAVE_P2_M || d == HWAVE_ICEBERG_M; }
@@ -122,7 +141,9 @@ int resolve_config(hwave_design design, const hwave_config* in, hwave_config* ou
     if (in->tile) c.tile = in->tile;
     c.probe_cap = in->probe_cap;
     c.flags = in->flags;
+    c.lock_timeout_us = in->lock_timeout_us;
   }
+  if (c.lock_timeout_us > MAX_LOCK_TIMEOUT_US) return HWAVE_EINVAL;
   *out = c;
   return HWAVE_OK;
 }
@@ -146,7 +167,7 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
     uint64_t off = round_up(L->units * 16, ALIGN);
     L->off_tags = off;
     L->off_locks = off;
-    L->n_lock_words = (nb + 3) / 4;
+    L->n_lock_words = 2 * nb;  // one 64-bit ticket-lock word per bucket
     off += round_up(L->n_lock_words * 4, ALIGN);
     L->off_ctrl = off;
     off += ALIGN;
@@ -169,7 +190,7 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
   L->off_tags = off;
   if (design_tags(design)) off += round_up(L->capacity * 2, ALIGN);
   L->off_locks = off;
-  L->n_lock_words = (nb + 3) / 4;  // one lock byte per bucket
+  L->n_lock_words = 2 * nb;  // one 64-bit ticket-lock word per bucket
   off += round_up(L->n_lock_words * 4, ALIGN);
   L->off_ctrl = off;
   off += ALIGN;
@@ -221,6 +242,38 @@ __global__ void k_primary(const K* __restrict__ keys, uint64_t n, uint32_t mask,
     out[i] = nf ? front_bucket((uint64_t)keys[i], nf) : hash_key((uint64_t)keys[i], mask).b1;
 }
 
+// Every bucket a key may occupy (hwave_candidate_buckets): three per key,
+// unused entries all-ones.
+template <typename K>
+__global__ void k_candidates(const K* __restrict__ keys, uint64_t n, int design, uint32_t mask, uint32_t nf,
+                             uint32_t nback, uint64_t* __restrict__ out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = (uint64_t)keys[i];
+    uint64_t c0 = ~0ull, c1 = ~0ull, c2 = ~0ull;
+    if (design == HWAVE_CHAINING) {
+      c0 = front_bucket(k, nf);
+    } else if (design == HWAVE_ICEBERG || design == HWAVE_ICEBERG_M) {
+      const Yard y = yard_of(k, nf, nback);
+      c0 = y.front;
+      c1 = y.back1;
+      c2 = y.back2;
+    } else {
+      const Hashed h = hash_key(k, mask);
+      c0 = h.b1;
+      if (design == HWAVE_DOUBLE || design == HWAVE_DOUBLE_M) {
+        c1 = (h.h2 & mask) | 1u;  // the probe step
+      } else {
+        c1 = h.h2 & mask;
+        if (design == HWAVE_CUCKOO) c2 = (uint32_t)fmix64(k ^ HASH_SALT_B) & mask;
+      }
+    }
+    out[3 * i] = c0;
+    out[3 * i + 1] = c1;
+    out[3 * i + 2] = c2;
+  }
+}
+
 // Grid cap for grid-stride kernels, cached per device (tables may be created
 // from several host threads, e.g. beside a serving loop's worker).
 unsigned max_blocks_for(int device) {
@@ -264,7 +317,7 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   TableDev& tv = t->la.tv;
   tv.slots = b;
   tv.tagw = design_tags(design) ? (uint32_t*)(b + L.off_tags) : nullptr;
-  tv.locks = (uint32_t*)(b + L.off_locks);
+  tv.locks = (uint64_t*)(b + L.off_locks);
   tv.ctrl = (uint32_t*)(b + L.off_ctrl);
   tv.bucket_mask = (uint32_t)(L.nb - 1);
   tv.nb_front = design_iceberg(design) ? (uint32_t)iceberg_front(L.nb) : (uint32_t)L.nb;
@@ -277,8 +330,19 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   tv.shortcut = (c.flags & HWAVE_F_NO_SHORTCUT) ? 0u : 1u;
   tv.no_erase = (c.flags & HWAVE_F_NO_ERASE) ? 1u : 0u;
   tv.aggregate = (c.flags & HWAVE_F_AGGREGATE) ? 1u : 0u;
+  tv.lock_limit = (uint32_t)((c.lock_timeout_us ? c.lock_timeout_us : DEFAULT_LOCK_TIMEOUT_US) * 100ull);
   tv.hot_tag = L.off_hot ? (uint64_t*)(b + L.off_hot) : nullptr;
   tv.hot_acc = L.off_hot ? tv.hot_tag + HOT_N : nullptr;
+  t->has_merge = L.off_merge != 0;
+  t->ws = MergeWs{};
+  if (t->has_merge) {
+    uint8_t* m = b + L.off_merge;
+    t->ws.key = (uint64_t*)m;
+    t->ws.ent = (MergeEntry*)(m + MERGE_ENTRIES * 8);
+    t->ws.op_ent = (uint32_t*)(m + MERGE_ENTRIES * (8 + sizeof(MergeEntry)));
+    t->ws.ne_mask = (uint32_t)(MERGE_ENTRIES - 1);
+    t->ws.chunk = MERGE_CHUNK;
+  }
   tv.probe_ctr = nullptr;
 #ifdef HW_INSTRUMENT
   {
@@ -448,7 +512,7 @@ int hwave_mixed(hwave_table* t, const uint8_t* d_ops, const void* d_keys, const 
   // in which case the keys array stands in (never dereferenced for other ops).
   const void* vals = d_vals ? d_vals : d_keys;
   hipError_t e = t->ks->mixed(t->la, d_ops, d_keys, vals, n, (int)combine, d_vals_out, d_status,
-                              (hipStream_t)stream);
+                              t->has_merge ? &t->ws : nullptr, (hipStream_t)stream);
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
 }
 
@@ -499,6 +563,22 @@ int hwave_primary_bucket(hwave_table* t, const void* d_keys, uint64_t n, uint64_
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
 }
 
+int hwave_candidate_buckets(hwave_table* t, const void* d_keys, uint64_t n, uint64_t* d_out, void* stream) {
+  if (!t || (n && (!d_keys || !d_out))) return HWAVE_EINVAL;
+  if (n == 0) return HWAVE_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned g = stream_grid(n, t->device);
+  const TableDev& tv = t->la.tv;
+  if (t->cfg.kv_bits == 64)
+    hipLaunchKernelGGL(k_candidates<uint64_t>, dim3(g), dim3(256), 0, s, (const uint64_t*)d_keys, n,
+                       (int)t->design, tv.bucket_mask, tv.nb_front, tv.nb_back, d_out);
+  else
+    hipLaunchKernelGGL(k_candidates<uint32_t>, dim3(g), dim3(256), 0, s, (const uint32_t*)d_keys, n,
+                       (int)t->design, tv.bucket_mask, tv.nb_front, tv.nb_back, d_out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
 int hwave_probe_counters(hwave_table* t, hwave_probe_stats* out, int reset, void* stream) {
   if (!t || !out) return HWAVE_EINVAL;
   memset(out, 0, sizeof *out);
@@ -526,7 +606,7 @@ int hwave_raw(const hwave_table* t, hwave_raw_view* out) {
   if (!t || !out) return HWAVE_EINVAL;
   out->slots = t->la.tv.slots;
   out->tags = (uint16_t*)t->la.tv.tagw;
-  out->locks = t->la.tv.locks;
+  out->locks = (uint32_t*)t->la.tv.locks;
   out->n_lock_words = t->n_lock_words;
   out->num_buckets = t->nb;
   out->bucket_slots = t->cfg.bucket_slots;

@@ -19,8 +19,8 @@
 //    second, instead of the full-L2 write-back / invalidate that a C++ release /
 //    acquire fence costs on this chip (measured 3x slower for publishes).
 //    Building with -DHW_STRICT_ORDER adds those fences back (for comparison);
-//  * the lock bit of a bucket (Section 5.1: one bit per bucket in an external
-//    array), taken by the tile's leader lane with an atomic OR.
+//  * the lock of a bucket (Section 5.1: one lock per bucket in an external
+//    array), a ticket lock taken by the tile's leader lane.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -175,36 +175,124 @@ __device__ __forceinline__ X cas(X* p, X expected, X desired) {
 
 // ------------------------------------------------------------------ locks
 //
-// One lock byte per bucket (the paper keeps one lock bit per bucket in an
-// external array, Section 5.1).  Taking the lock is an atomic OR of the bucket's
-// bit 0 on the 32-bit word holding four buckets' bytes; releasing it is a plain
-// agent-coherent store of the byte, which cannot disturb the neighbours' bytes.
-// A byte per bucket thus saves the atomic AND a bit-packed release needs: on this
-// chip the atomic unit, not HBM bandwidth, bounds the write operations.
+// One lock per bucket (the paper keeps one lock bit per bucket in an external
+// array, Section 5.1), here a ticket lock with proportional back-off
+// (Mellor-Crummey and Scott, ACM TOCS 9(1), 1991) in one 64-bit word per bucket:
+// the high half is the next ticket, the low half the ticket being served, and
+// the lock is free when the two are equal.
+//
+//  * Taking the lock is one 64-bit atomic add of 2^32: it returns the word as it
+//    was, so an uncontended acquire costs one atomic, as a test-and-set would.
+//    Carries out of the high half fall off the word; they never reach the low one.
+//  * Releasing it is a 32-bit store of (own ticket + 1) into the low half, after
+//    every write of the critical section has completed.  Only the holder writes
+//    the low half.
+//  * A waiter d tickets behind the one being served reads the low half again
+//    after about d - 1 critical sections, so the waiters' reads stay spread out.
+//
+// Why not test-and-set: one address of MI355X memory serves ~80 M requests per
+// second.  With test-and-set every waiter keeps an atomic (or, polling, a load)
+// queued at the lock word, and each release waits behind all of them: with 2^16
+// tiles on one bucket a hand-off costs ~0.8 ms.  Ticket waiters issue no
+// read-modify-write and poll rarely, so a hand-off costs one critical section
+// plus a short poll delay, and service is first come first served.
+//
+// A ticket cannot be given back, so a waiter never leaves the queue -- except
+// when its wait exceeds the table's time limit, a failure that the lock protocol
+// itself never produces (FIFO service bounds every wait by the waiters ahead of
+// it times one critical section).  Such an operation reports ST_TIMEOUT and sets
+// the table's failure flag; every waiter that sees the flag gives up too, so the
+// kernel still ends.  The table's lock state is then undefined.
 
-__device__ __forceinline__ uint32_t lock_bit(uint32_t b) { return 1u << ((b & 3) * 8); }
+// Wall clock of the chip: 100 MHz (s_memrealtime).
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
-// Leader lane sets bucket b's lock; every lane of the tile learns whether the
-// lock was free.  On success the caller owns the bucket until unlock().
+constexpr uint32_t LOCK_UNIT_TICKS = 100;  // 1 us: assumed critical section per ticket ahead
+constexpr uint32_t LOCK_FIRST_TICKS = 25;  // 0.25 us: next in line polls this often
+constexpr uint32_t LOCK_FLAG_WORD = 32;    // ctrl word of the failure flag (its own 128-byte line)
+
+__device__ __forceinline__ uint32_t* serving_of(uint64_t* locks, uint32_t b) { return (uint32_t*)(locks + b); }
+
+// Leader lane takes a ticket for bucket b; every lane of the tile gets the
+// word as it was (high half: our ticket; low half: the ticket being served).
 template <int T>
-__device__ __forceinline__ bool try_lock(uint32_t* locks, uint32_t b, const Tile<T>& tile) {
-  const uint32_t bit = lock_bit(b);
-  uint32_t old = 0;
+__device__ __forceinline__ uint64_t take_ticket(uint64_t* locks, uint32_t b, const Tile<T>& tile) {
+  uint64_t old = 0;
   if (tile.leader()) {
 #ifdef HW_STRICT_ORDER
-    old = __hip_atomic_fetch_or(locks + (b >> 2), bit, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    old = __hip_atomic_fetch_add(locks + b, (uint64_t)1 << 32, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 #else
-    old = __hip_atomic_fetch_or(locks + (b >> 2), bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    old = __hip_atomic_fetch_add(locks + b, (uint64_t)1 << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #endif
   }
-  old = tile.bcast(old, 0);
-  return (old & bit) == 0;
+  return tile.bcast(old, 0);
 }
 
-// Backoff between failed lock attempts: a pause that doubles from 128 cycles up
-// to ~3.4 us (64 x 128 cycles), about one critical section.  Waiters poll the
-// lock with loads between attempts, so short pauses cost no atomics; long pauses
-// would leave a released lock idle while its waiters sleep.
+// The ticket bucket b is serving now (a coherent load; no atomic).
+template <int T>
+__device__ __forceinline__ uint32_t read_serving(uint64_t* locks, uint32_t b, const Tile<T>& tile) {
+  uint32_t s = 0;
+  if (tile.leader()) {
+#ifdef HW_STRICT_ORDER
+    s = __hip_atomic_load(serving_of(locks, b), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+#else
+    s = ld(serving_of(locks, b));
+#endif
+  }
+  return tile.bcast(s, 0);
+}
+
+// When a waiter d tickets behind should look again: after d - 1 assumed
+// critical sections, but at least every LOCK_MAX_GAP_TICKS, so that the time
+// limit is checked even far back in a long queue.
+constexpr uint64_t LOCK_MAX_GAP_TICKS = 1u << 20;  // ~10 ms
+__device__ __forceinline__ uint64_t next_look(uint64_t now, uint32_t d) {
+  const uint64_t gap = (uint64_t)(d - 1) * LOCK_UNIT_TICKS;
+  return now + (gap < LOCK_MAX_GAP_TICKS ? gap : LOCK_MAX_GAP_TICKS) + LOCK_FIRST_TICKS;
+}
+
+// Releases bucket b, held with ticket `mine`, after every write of the critical
+// section has completed.
+template <int T>
+__device__ __forceinline__ void unlock(uint64_t* locks, uint32_t b, uint32_t mine, const Tile<T>& tile) {
+#ifdef HW_STRICT_ORDER
+  if (tile.leader())
+    __hip_atomic_store(serving_of(locks, b), mine + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+#else
+  wait_mem();
+  if (tile.leader()) st(serving_of(locks, b), mine + 1);
+#endif
+}
+
+// Cuckoo operations hold all three of their buckets' locks at once and take
+// them with try-locks (test-and-set on the low half of the lock word: bit 0 set
+// = held; the high half stays 0), so a tile that misses one releases the others
+// and never waits while holding a lock.  A waiting tile reads the word first and
+// tries the atomic only when it reads free (or on every 256th attempt).
+
+// Leader lane sets bucket b's lock bit; every lane learns whether it was free.
+template <int T>
+__device__ __forceinline__ bool try_lock(uint64_t* locks, uint32_t b, const Tile<T>& tile) {
+  uint32_t old = 0;
+  if (tile.leader())
+    old = __hip_atomic_fetch_or(serving_of(locks, b), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (tile.bcast(old, 0) & 1u) == 0;
+}
+
+// Whether bucket b's try-lock currently reads free (a coherent load; no atomic).
+template <int T>
+__device__ __forceinline__ bool lock_looks_free(uint64_t* locks, uint32_t b, const Tile<T>& tile) {
+  uint32_t w = 0;
+  if (tile.leader()) w = ld(serving_of(locks, b));
+  return tile.bcast(w, 0) == 0;
+}
+
+// Releases a try-lock (leader lane), after the caller has waited for the
+// critical section's writes.
+__device__ __forceinline__ void release_try_lock(uint64_t* locks, uint32_t b) { st(serving_of(locks, b), 0u); }
+
+// Back-off between failed try-lock attempts: a pause that doubles from 128
+// cycles up to ~3.4 us (64 x 128 cycles).
 struct Backoff {
   uint32_t n = 0;
   __device__ __forceinline__ void pause() {
@@ -212,28 +300,5 @@ struct Backoff {
   }
   __device__ __forceinline__ void grow() { n = n ? (n < 64 ? 2 * n : 64) : 1; }
 };
-
-// Whether bucket b's lock currently reads clear (a coherent load; no atomic).
-// Waiting tiles poll with this and only try the atomic when it looks clear, so
-// the lock word's atomic unit -- which serves one address at ~80 M operations/s
-// on MI355X -- is left to the holders.
-template <int T>
-__device__ __forceinline__ bool lock_looks_free(const uint32_t* locks, uint32_t b, const Tile<T>& tile) {
-  uint32_t w = 0;
-  if (tile.leader()) w = ld((const uint8_t*)locks + b);
-  return tile.bcast(w, 0) == 0;
-}
-
-// Releases bucket b after every write of the critical section has completed.
-template <int T>
-__device__ __forceinline__ void unlock(uint32_t* locks, uint32_t b, const Tile<T>& tile) {
-#ifdef HW_STRICT_ORDER
-  if (tile.leader())
-    __hip_atomic_fetch_and(locks + (b >> 2), ~lock_bit(b), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-#else
-  wait_mem();
-  if (tile.leader()) st((uint8_t*)locks + b, (uint8_t)0);
-#endif
-}
 
 }  // namespace hw

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hw_agg.hpp"
+#include "hw_merge.hpp"
 #include "hw_ops.hpp"
 
 namespace hw {
@@ -106,42 +107,59 @@ k_erase(TableDev tv, const typename C::K* __restrict__ keys, uint64_t n, uint8_t
 // tiles.  The operations of a launch are concurrent, so their order within it
 // is free.  Cuckoo keeps one operation per tile in input order: its three-lock
 // paths need the registers the grouping takes.
-template <class C>
+//
+// MERGED: the call's upserts were merged by key (hw_merge.hpp); only each key's
+// leader runs its table upsert, and a follower's status is written later.
+template <class C, bool MERGED = false>
 __device__ __forceinline__ void mixed_op(const TableDev& tv, const Tile<C::T>& tile, const uint8_t* __restrict__ ops,
                                          const typename C::K* __restrict__ keys,
                                          const typename C::K* __restrict__ vals, uint64_t j, int combine,
-                                         typename C::K* __restrict__ out, uint8_t* __restrict__ status) {
+                                         typename C::K* __restrict__ out, uint8_t* __restrict__ status,
+                                         const MergeWs& ws) {
   using K = typename C::K;
   const int op = ops[j];
   const K key = keys[j];
   K v = 0;
   uint8_t st;
+  bool report = true;
   if (op == OP_QUERY) {
     st = Ops<C>::query(tv, tile, key, &v);
   } else if (op == OP_ERASE) {
     st = Ops<C>::erase(tv, tile, key);
   } else if (op == OP_INSERT || op == OP_UPSERT) {
-    st = Ops<C>::upsert(tv, tile, key, vals[j], op == OP_INSERT ? C_KEEP : combine);
+    K val = vals[j];
+    const int cmb = op == OP_INSERT ? C_KEEP : combine;
+    uint32_t e = MERGE_NONE;
+    if constexpr (MERGED) {
+      if (op == OP_UPSERT) report = merge_take<K>(ws, tile, j, cmb, &val, &e);
+    }
+    st = ST_EXISTED;
+    if (report) {
+      st = Ops<C>::upsert(tv, tile, key, val, cmb);
+      if constexpr (MERGED) {
+        if (e != MERGE_NONE && tile.leader()) ws.ent[e].stat = st;
+      }
+    }
   } else {
     st = ST_INVALID;
   }
   if (tile.leader()) {
     if (out) out[j] = v;
-    if (status) status[j] = st;
+    if (status && report) status[j] = st;
   }
 }
 
-template <class C>
+template <class C, bool MERGED>
 __device__ __forceinline__ void mixed_body(const TableDev& tv, const uint8_t* __restrict__ ops,
                                            const typename C::K* __restrict__ keys,
                                            const typename C::K* __restrict__ vals, uint64_t n, int combine,
                                            typename C::K* __restrict__ out, uint8_t* __restrict__ status,
-                                           uint8_t* order_lds) {
+                                           uint8_t* order_lds, const MergeWs& ws) {
   const Tile<C::T> tile;
   if constexpr (C::CUCKOO) {
     const uint64_t stride = (uint64_t)gridDim.x * (BLOCK / C::T);
     for (uint64_t i = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / C::T; i < n; i += stride)
-      mixed_op<C>(tv, tile, ops, keys, vals, i, combine, out, status);
+      mixed_op<C, MERGED>(tv, tile, ops, keys, vals, i, combine, out, status, ws);
     return;
   }
   // wave-uniform values made scalar, so they take no vector registers
@@ -171,18 +189,18 @@ __device__ __forceinline__ void mixed_body(const TableDev& tv, const uint8_t* __
     wave_sync();
     const uint32_t cnt = n - base < 64 ? (uint32_t)(n - base) : 64u;
     for (uint32_t s = lane / C::T; s < cnt; s += 64 / C::T)
-      mixed_op<C>(tv, tile, ops, keys, vals, base + order[s], combine, out, status);
+      mixed_op<C, MERGED>(tv, tile, ops, keys, vals, base + order[s], combine, out, status, ws);
     wave_sync();  // the next window rewrites `order`
   }
 }
 
-template <class C>
+template <class C, bool MERGED = false>
 __global__ void __launch_bounds__(BLOCK)
 k_mixed(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __restrict__ keys,
         const typename C::K* __restrict__ vals, uint64_t n, int combine, typename C::K* __restrict__ out,
-        uint8_t* __restrict__ status) {
+        uint8_t* __restrict__ status, MergeWs ws) {
   __shared__ uint8_t order_lds[BLOCK];
-  mixed_body<C>(tv, ops, keys, vals, n, combine, out, status, order_lds);
+  mixed_body<C, MERGED>(tv, ops, keys, vals, n, combine, out, status, order_lds, ws);
 }
 
 // With an occupancy bound of W waves per SIMD: the grouping's registers would
@@ -190,13 +208,13 @@ k_mixed(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __res
 // their eighth.  A 2^20-operation launch is 16384 windows: at 8 waves/SIMD the
 // chip holds 8192 waves and runs them in two rounds, at 7 it needs three.  The
 // bound costs the two-choice designs 12-24 bytes of spill per lane.
-template <class C, int W>
+template <class C, int W, bool MERGED = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(W, 8)))
 k_mixed_w(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __restrict__ keys,
            const typename C::K* __restrict__ vals, uint64_t n, int combine, typename C::K* __restrict__ out,
-           uint8_t* __restrict__ status) {
+           uint8_t* __restrict__ status, MergeWs ws) {
   __shared__ uint8_t order_lds[BLOCK];
-  mixed_body<C>(tv, ops, keys, vals, n, combine, out, status, order_lds);
+  mixed_body<C, MERGED>(tv, ops, keys, vals, n, combine, out, status, order_lds, ws);
 }
 
 // Host side ------------------------------------------------------------------
@@ -218,7 +236,7 @@ typedef hipError_t (*upsert_fn)(const LaunchArgs&, const void*, const void*, uin
 typedef hipError_t (*query_fn)(const LaunchArgs&, const void*, uint64_t, void*, uint8_t*, hipStream_t);
 typedef hipError_t (*erase_fn)(const LaunchArgs&, const void*, uint64_t, uint8_t*, hipStream_t);
 typedef hipError_t (*mixed_fn)(const LaunchArgs&, const uint8_t*, const void*, const void*, uint64_t,
-                               int, void*, uint8_t*, hipStream_t);
+                               int, void*, uint8_t*, const MergeWs*, hipStream_t);
 
 struct KernelSet {
   int kv_bits, design, bucket, tile;
@@ -258,20 +276,48 @@ struct Launch {
                        (const K*)keys, n, found);
     return hipGetLastError();
   }
-  static hipError_t mixed(const LaunchArgs& a, const uint8_t* ops, const void* keys, const void* vals,
-                          uint64_t n, int combine, void* out, uint8_t* status, hipStream_t s) {
+  // One kernel launch of the mixed kernel over ops [0, n).
+  template <bool MERGED>
+  static void mixed_launch(const LaunchArgs& a, const uint8_t* ops, const K* keys, const K* vals, uint64_t n,
+                           int combine, K* out, uint8_t* status, const MergeWs& ws, hipStream_t s) {
     if constexpr (C::CUCKOO)
-      hipLaunchKernelGGL((k_mixed<C>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv, ops,
-                         (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+      hipLaunchKernelGGL((k_mixed<C, MERGED>), dim3(grid_for(n, C::T, a.max_blocks)), dim3(BLOCK), 0, s, a.tv, ops,
+                         keys, vals, n, combine, out, status, ws);
     else if constexpr (C::ICEBERG && C::T >= 4)  // one wave per window of 64 operations
-      hipLaunchKernelGGL((k_mixed_w<C, 6>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s,
-                         a.tv, ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+      hipLaunchKernelGGL((k_mixed_w<C, 6, MERGED>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK),
+                         0, s, a.tv, ops, keys, vals, n, combine, out, status, ws);
     else if constexpr (!C::ICEBERG && !C::CHAIN && C::T >= 4)  // double hashing, two-choice
-      hipLaunchKernelGGL((k_mixed_w<C, 8>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s,
-                         a.tv, ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+      hipLaunchKernelGGL((k_mixed_w<C, 8, MERGED>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK),
+                         0, s, a.tv, ops, keys, vals, n, combine, out, status, ws);
     else
-      hipLaunchKernelGGL((k_mixed<C>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s, a.tv,
-                         ops, (const K*)keys, (const K*)vals, n, combine, (K*)out, status);
+      hipLaunchKernelGGL((k_mixed<C, MERGED>), dim3(grid_for((n + 63) / 64, 64, a.max_blocks)), dim3(BLOCK), 0, s,
+                         a.tv, ops, keys, vals, n, combine, out, status, ws);
+  }
+
+  // ws non-null (and a mergeable combine): the call's upserts are merged by key,
+  // chunk by chunk of at most ws->chunk operations (hw_merge.hpp).  Chunks run
+  // one after another, which is one serialisation of the call.
+  static hipError_t mixed(const LaunchArgs& a, const uint8_t* ops, const void* keys, const void* vals,
+                          uint64_t n, int combine, void* out, uint8_t* status, const MergeWs* ws, hipStream_t s) {
+    const K* k = (const K*)keys;
+    const K* v = (const K*)vals;
+    K* o = (K*)out;
+    if (!ws || combine == C_REPLACE || !vals) {
+      mixed_launch<false>(a, ops, k, v, n, combine, o, status, MergeWs{}, s);
+      return hipGetLastError();
+    }
+    for (uint64_t off = 0; off < n; off += ws->chunk) {
+      const uint64_t m = n - off < ws->chunk ? n - off : ws->chunk;
+      const unsigned gb = (unsigned)((m + MERGE_BLOCK_OPS - 1) / MERGE_BLOCK_OPS);
+      hipLaunchKernelGGL((k_merge_build<K>), dim3(gb < a.max_blocks ? gb : a.max_blocks), dim3(256), 0, s, *ws,
+                         ops + off, k + off, v + off, m, combine);
+      mixed_launch<true>(a, ops + off, k + off, v + off, m, combine, o ? o + off : nullptr,
+                         status ? status + off : nullptr, *ws, s);
+      hipLaunchKernelGGL((k_merge_finish<K>), dim3(grid_for(m, 1, a.max_blocks)), dim3(256), 0, s, *ws, ops + off, m,
+                         status ? status + off : nullptr);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
   }
 };

@@ -41,7 +41,7 @@
 
 namespace hw {
 
-enum : uint8_t { ST_MISS = 0, ST_DONE = 1, ST_EXISTED = 2, ST_FULL = 3, ST_INVALID = 4 };
+enum : uint8_t { ST_MISS = 0, ST_DONE = 1, ST_EXISTED = 2, ST_FULL = 3, ST_INVALID = 4, ST_TIMEOUT = 5 };
 enum : int { C_SUM = 0, C_KEEP = 1, C_REPLACE = 2, C_MIN = 3, C_MAX = 4 };
 enum : int { OP_QUERY = 0, OP_INSERT = 1, OP_UPSERT = 2, OP_ERASE = 3 };
 // Chaining's overflow pool is split into this many partitions, each with its own
@@ -71,8 +71,9 @@ enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, 
 struct TableDev {
   void* slots;           // (key, value) pairs, bucket-major
   uint32_t* tagw;        // 16-bit tags viewed as 32-bit words; null without tags
-  uint32_t* locks;       // one byte per bucket (viewed as 32-bit words)
-  uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice, iceberg)
+  uint64_t* locks;       // one ticket-lock word per bucket (hw_device.hpp)
+  uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice, iceberg);
+                         // ctrl[LOCK_FLAG_WORD]: a lock wait timed out
   uint32_t bucket_mask;  // buckets - 1 (a power of two minus one)
   uint32_t nb_front;     // iceberg: front-yard buckets [0, nb_front); chaining: buckets
   uint32_t nb_back;      // iceberg: backyard buckets [nb_front, nb_front + nb_back)
@@ -82,6 +83,7 @@ struct TableDev {
   uint32_t shortcut;     // power-of-two-choice shortcut enabled
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
   uint32_t aggregate;    // merge duplicate keys of a write batch first (hw_agg.hpp)
+  uint32_t lock_limit;   // longest wait for a bucket lock, in 100 MHz ticks
   uint64_t* hot_tag;     // HOT_N entry tags, or null (see HOT_ROWS)
   uint64_t* hot_acc;     // HOT_N accumulators
   unsigned long long* probe_ctr;  // instrumented builds: PROBE_STRIPES query probe counters; else null
@@ -544,7 +546,7 @@ struct Ops {
   }
 
   __device__ static __forceinline__ void release(const TableDev& tv, uint32_t b, const Tile<T>& tile) {
-    if (tile.leader()) st((uint8_t*)tv.locks + b, (uint8_t)0);
+    if (tile.leader()) release_try_lock(tv.locks, b);
   }
 
   __device__ static bool try_lock_all(const TableDev& tv, const Tile<T>& tile, const Cands& c) {
@@ -895,33 +897,79 @@ struct Ops {
     else __hip_atomic_fetch_min(vp, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
+  // Runs cs() under bucket b's lock (hw_device.hpp) and returns its status, or
+  // ST_TIMEOUT when the wait outlasted the table's limit or another waiter of
+  // the table reported such a failure (checked on every 16th look).
+  //
+  // The tile takes a ticket, then looks at the serving counter at times spaced
+  // by its place in the queue.  The critical section runs inside the waiting
+  // loop, in the iteration whose look found the tile's turn, so tiles of one
+  // wave that wait on each other cannot deadlock: lanes of a wave run in
+  // lockstep, and a tile whose turn has come finishes and releases in the same
+  // iteration as the others go on waiting.
+  template <class F>
+  __device__ static uint8_t locked(const TableDev& tv, const Tile<T>& tile, uint32_t b, F&& cs) {
+    const uint64_t w = take_ticket(tv.locks, b, tile);
+    const uint32_t mine = (uint32_t)(w >> 32);
+    uint32_t served = (uint32_t)w;
+    uint64_t since = 0, look = 0;
+    if (served != mine) {
+      since = now_ticks();
+      look = next_look(since, mine - served);
+    }
+    uint32_t looks = 0;
+    uint8_t status = ST_TIMEOUT;
+    bool pending = true;
+    while (pending) {
+      bool go = served == mine;
+      if (!go) {
+        const uint64_t now = now_ticks();
+        if (now >= look) {
+          served = read_serving(tv.locks, b, tile);
+          go = served == mine;
+          if (!go) {
+            if (now - since > tv.lock_limit || ((++looks & 15) == 0 && lock_failed(tv, tile))) {
+              if (tile.leader()) st(tv.ctrl + LOCK_FLAG_WORD, 1u);
+              pending = false;  // status stays ST_TIMEOUT
+            }
+            look = next_look(now, mine - served);
+          }
+        } else {
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      if (go) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // critical-section accesses after the lock's
+        status = cs();
+        unlock(tv.locks, b, mine, tile);
+        pending = false;
+      }
+    }
+    return status;
+  }
+
+  // Whether a lock wait of this table has timed out (leader reads, broadcast).
+  __device__ static __forceinline__ bool lock_failed(const TableDev& tv, const Tile<T>& tile) {
+    const uint32_t f = tile.leader() ? ld(tv.ctrl + LOCK_FLAG_WORD) : 0u;
+    return tile.bcast(f, 0) != 0;
+  }
+
   // Upsert: lock primary, find or insert, unlock.  Status per hwave.h.
   //
-  // Waiting for the lock: after a failed attempt a tile backs off, then polls
-  // the lock word with a load and tries the atomic only when the bit reads
-  // clear -- or on every 256th attempt regardless, so progress never depends on
-  // how soon a load observes the release.  In a table that never erases, a slot
-  // once filled keeps its key for good (stability, Section 2.1), so a present
-  // key is combined in place without the lock (as the paper does for sparse
-  // tensor contraction, Section 6.7), and a waiting tile looks for its key
-  // again before each attempt: once another tile has inserted it, the waiter
-  // finishes without the lock.  hot_row >= 0 (a key that a merge window met more
-  // than once): in a table with hot-key accumulators, where a present key's slot
-  // is fixed for good, a SUM/MIN/MAX combine of a present key goes to row hot_row
-  // of the accumulators instead of the value word.
+  // In a table that never erases, a slot once filled keeps its key for good
+  // (stability, Section 2.1), so a present key is combined in place without the
+  // lock (as the paper does for sparse tensor contraction, Section 6.7); only an
+  // absent key queues for the lock, whose holder then finds or inserts it.
+  // hot_row >= 0 (a key that a merge window met more than once): in a table with
+  // hot-key accumulators, where a present key's slot is fixed for good, a
+  // SUM/MIN/MAX combine of a present key goes to row hot_row of the accumulators
+  // instead of the value word.
   __device__ static uint8_t upsert(const TableDev& tv, const Tile<T>& tile, K key, K val,
                                    int combine, int hot_row = -1) {
     if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
     if constexpr (C::CUCKOO) return cuckoo_upsert(tv, tile, key, val, combine);
     const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
-    uint8_t status = ST_FULL;
-    bool pending = true;
-    Backoff bo;
-    uint32_t attempt = 0;
-    // The critical section runs inside the retry loop: a tile that wins the
-    // lock finishes and releases it in the same iteration, so tiles of one wave
-    // waiting on each other cannot deadlock (lanes of a wave run in lockstep).
     // Phased chaining keeps its write locks: appending a node is not safe for
     // two writers of one chain (only its queries differ, Table 1's phased column).
     if constexpr (C::BSP && !C::CHAIN) {
@@ -932,40 +980,28 @@ struct Ops {
       else
         return upsert_p2_locked(tv, tile, h, key, val, tag, combine);
     }
-    while (pending) {
-      bo.pause();
-      if (tv.no_erase) {
-        K cur;
-        const int64_t s = find(tv, tile, h, key, tag, &cur);
-        if (s >= 0) {
-          if (hot_row >= 0 && tv.hot_tag && (combine == C_SUM || combine == C_MIN || combine == C_MAX)) {
-            if (tile.leader()) hot_add(tv, (uint64_t)s, val, combine, (uint32_t)hot_row);
-          } else {
-            combine_at(tv, tile, (uint64_t)s, val, combine);
-          }
-          status = ST_EXISTED;
-          pending = false;
-          continue;
+    if (tv.no_erase) {
+      K cur;
+      const int64_t s = find(tv, tile, h, key, tag, &cur);
+      if (s >= 0) {
+        if (hot_row >= 0 && tv.hot_tag && (combine == C_SUM || combine == C_MIN || combine == C_MAX)) {
+          if (tile.leader()) hot_add(tv, (uint64_t)s, val, combine, (uint32_t)hot_row);
+        } else {
+          combine_at(tv, tile, (uint64_t)s, val, combine);
         }
-      }
-      const bool go = (attempt & 255) == 0 || lock_looks_free(tv.locks, h.b1, tile);
-      ++attempt;
-      if (go && try_lock(tv.locks, h.b1, tile)) {
-        if constexpr (C::CHAIN)
-          status = upsert_chain_locked(tv, tile, h, key, val, combine);
-        else if constexpr (C::ICEBERG)
-          status = upsert_iceberg_locked(tv, tile, h, key, val, tag, combine);
-        else if constexpr (C::DOUBLE)
-          status = upsert_double_locked(tv, tile, h, key, val, tag, combine);
-        else
-          status = upsert_p2_locked(tv, tile, h, key, val, tag, combine);
-        unlock(tv.locks, h.b1, tile);
-        pending = false;
-      } else {
-        bo.grow();
+        return ST_EXISTED;
       }
     }
-    return status;
+    return locked(tv, tile, h.b1, [&]() -> uint8_t {
+      if constexpr (C::CHAIN)
+        return upsert_chain_locked(tv, tile, h, key, val, combine);
+      else if constexpr (C::ICEBERG)
+        return upsert_iceberg_locked(tv, tile, h, key, val, tag, combine);
+      else if constexpr (C::DOUBLE)
+        return upsert_double_locked(tv, tile, h, key, val, tag, combine);
+      else
+        return upsert_p2_locked(tv, tile, h, key, val, tag, combine);
+    });
   }
 
   __device__ static uint8_t upsert_double_locked(const TableDev& tv, const Tile<T>& tile,
@@ -1136,23 +1172,7 @@ struct Ops {
       }
     }
     if constexpr (C::BSP && !C::CHAIN) return erase_locked(tv, tile, h, key, tag);
-    uint8_t status = ST_MISS;
-    bool pending = true;
-    Backoff bo;
-    uint32_t attempt = 0;
-    while (pending) {
-      bo.pause();
-      const bool go = (attempt & 255) == 0 || lock_looks_free(tv.locks, h.b1, tile);
-      ++attempt;
-      if (go && try_lock(tv.locks, h.b1, tile)) {
-        status = erase_locked(tv, tile, h, key, tag);
-        unlock(tv.locks, h.b1, tile);
-        pending = false;
-      } else {
-        bo.grow();
-      }
-    }
-    return status;
+    return locked(tv, tile, h.b1, [&]() -> uint8_t { return erase_locked(tv, tile, h, key, tag); });
   }
 
   // Finds and removes `key` among its candidate buckets.

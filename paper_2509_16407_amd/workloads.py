@@ -337,15 +337,19 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
     """Generator of deterministic mixed batches over a Zipf-distributed key universe.
 
     The universe is `universe` distinct keys (stream (config,1), or the given `ukeys`);
-    Zipf ranks index it.
-    Per batch of `batch` ops:
-      * erase keys: Zipf draws, repeats rejected, until floor(frac_erase*batch) distinct;
-      * upsert keys: Zipf draws with erase keys rejected (repeats allowed);
-      * query keys: Zipf draws with erase and upsert keys rejected;
-      * upsert values: a splitmix64 stream; op order shuffled.
+    Zipf ranks index it.  Per batch of `batch` ops (n_up = floor(frac_upsert*batch)
+    upserts, n_er = floor(frac_erase*batch) erases, the rest queries), draws are
+    interleaved: a stream of candidates, each a kind (query / upsert / erase in
+    those proportions) and a Zipf rank, is read in order; the first candidate that
+    names a rank makes that kind the rank's owner for the batch, and a candidate is
+    kept only if its kind owns its rank (erases: only the first, so erase keys are
+    distinct), until every kind has its count.  So every kind draws from the whole
+    distribution -- a hot rank is as likely to become an upsert key (repeated many
+    times) as its kind's share -- and the three key sets stay disjoint.
+    Upsert values: a splitmix64 stream; op order shuffled.
     Because erase and upsert keys are disjoint and queries avoid both, every output is
     the same under any serialisation of the batch.
-    Yields dict(ops, keys, vals) with ops coded 0 query, 2 upsert, 3 erase.
+    Yields dict(ops, keys, vals, ranks) with ops coded 0 query, 2 upsert, 3 erase.
     """
     if ukeys is None:
         ukeys = distinct_keys(stream_seed(workload_id, 1), universe)
@@ -354,34 +358,55 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
     n_up = int(frac_upsert * batch)
     n_er = int(frac_erase * batch)
     n_q = batch - n_up - n_er
+    want = np.array([n_q, n_up, n_er], dtype=np.int64)
+    cum = np.cumsum(want / batch)
     zs = stream_seed(workload_id, 3)
+    ks = stream_seed(workload_id, 5)
     zpos = 0
+    owner = np.full(universe, -1, dtype=np.int8)   # rank -> owning kind this batch
+    etaken = np.zeros(universe, dtype=bool)        # rank already erased this batch
     for b in range(n_batches):
-        def draw(count):
-            nonlocal zpos
-            r = z.ranks(zs, zpos, count)
-            zpos += count
-            return r
-        # erase: distinct ranks
-        er = np.empty(0, dtype=np.int64)
-        while len(er) < n_er:
-            r = draw(2 * (n_er - len(er)) + 1024)
-            allr = np.concatenate([er, r])
-            _, first = np.unique(allr, return_index=True)
-            first.sort()
-            er = allr[first][:n_er]
-        er_sorted = np.sort(er)
-        up = np.empty(0, dtype=np.int64)
-        while len(up) < n_up:
-            r = draw(n_up - len(up) + 1024)
-            r = r[~np.isin(r, er_sorted, assume_unique=False)]
-            up = np.concatenate([up, r])[:n_up]
-        bad = np.union1d(er_sorted, up)
-        qr = np.empty(0, dtype=np.int64)
-        while len(qr) < n_q:
-            r = draw(n_q - len(qr) + 1024)
-            r = r[~np.isin(r, bad)]
-            qr = np.concatenate([qr, r])[:n_q]
+        got = [[], [], []]
+        have = np.zeros(3, dtype=np.int64)
+        touched = []
+        rate = np.ones(3)  # kept / drawn per kind in the last chunk
+        drawn = 0
+        while (have < want).any():
+            if drawn > 64 * batch:
+                raise ValueError("mixed_batches: a %d-key universe is too small for %d distinct erase keys "
+                                 "per batch" % (universe, n_er))
+            # enough candidates for the slowest kind at its last acceptance rate
+            need = (want - have) / (want / batch) / np.maximum(rate, 0.02)
+            m = int(1.1 * need.max()) + 4096
+            r = z.ranks(zs, zpos, m)
+            kind = np.searchsorted(cum, unit_float(ks, zpos, m), side="right").clip(0, 2).astype(np.int8)
+            zpos += m
+            drawn += m
+            # a rank's owner is the kind of its first candidate (earlier chunks first)
+            uniq, first = np.unique(r, return_index=True)
+            fresh = owner[uniq] < 0
+            owner[uniq[fresh]] = kind[first[fresh]]
+            touched.append(uniq[fresh])
+            ok = owner[r] == kind
+            # erases: the first candidate of each rank only, across chunks too
+            idx = np.flatnonzero(ok & (kind == 2))
+            if len(idx):
+                _, fi = np.unique(r[idx], return_index=True)
+                keep = np.zeros(len(idx), dtype=bool)
+                keep[fi] = ~etaken[r[idx[fi]]]
+                etaken[r[idx[keep]]] = True
+                ok[idx[~keep]] = False
+            for k in range(3):
+                offered = kind == k
+                kept = r[ok & offered]
+                rate[k] = len(kept) / max(1, int(offered.sum()))
+                sel = kept[: int(want[k] - have[k])]
+                got[k].append(sel)
+                have[k] += len(sel)
+        for u in touched:
+            owner[u] = -1
+            etaken[u] = False
+        qr, up, er = (np.concatenate(g) for g in got)
         ops = np.concatenate([np.zeros(n_q, np.uint8), np.full(n_up, 2, np.uint8),
                               np.full(n_er, 3, np.uint8)])
         ranks = np.concatenate([qr, up, er])
@@ -389,6 +414,15 @@ def mixed_batches(universe: int, batch: int, n_batches: int, theta: float = 0.99
         vals[n_q:n_q + n_up] = splitmix64(stream_seed(workload_id, 4), b * batch, n_up)
         perm = permutation(stream_seed(workload_id, 1000 + b), batch)
         yield dict(ops=ops[perm], keys=ukeys[ranks[perm]], vals=vals[perm], ranks=ranks[perm])
+
+
+def hottest_upsert_share(batch: dict) -> float:
+    """Share of a mixed batch's upserts that go to its most frequent upsert key."""
+    u = batch["ops"] == 2
+    if not u.any():
+        return 0.0
+    _, c = np.unique(batch["ranks"][u], return_counts=True)
+    return float(c.max()) / float(u.sum())
 
 
 def sample_without_replacement(seed: int, n: int, k: int) -> np.ndarray:
@@ -476,6 +510,17 @@ def served_requests(n_tables: int, universe: int, n_req: int, rate_per_s: float,
             vals = None
         zpos += n
         yield dict(t=t, table=table, kind=kind, keys=keys, vals=vals)
+
+
+def poisson_arrivals(seed: int, rate_per_s: float, seconds: float) -> np.ndarray:
+    """Arrival times (s) of a Poisson process at `rate_per_s` over [0, seconds):
+    exponential gaps -ln(1 - u) / rate from a splitmix64 stream."""
+    n = int(rate_per_s * seconds * 1.2) + 64
+    while True:
+        t = np.cumsum(-np.log1p(-unit_float(seed, 0, n)) / rate_per_s)
+        if t[-1] >= seconds:
+            return t[t < seconds]
+        n *= 2
 
 
 def stream_keys(seed: int, start: int, count: int) -> np.ndarray:

@@ -23,16 +23,24 @@ def u8(t):
     return t.detach().cpu().numpy().astype(np.uint8)
 
 
+def held_lock_bitmap(lock_words32):
+    """Ticket-lock words (per bucket: the ticket being served, then the next
+    ticket) -> the layout checker's bitmap of held locks (bit b % 64 of 64-bit
+    word b // 64 set when bucket b's lock is held, i.e. the two differ)."""
+    w = np.ascontiguousarray(lock_words32, dtype=np.uint32).reshape(-1, 2)
+    held = w[:, 0] != w[:, 1]
+    packed = np.packbits(held, bitorder="little")
+    packed = np.concatenate([packed, np.zeros(-len(packed) % 8, np.uint8)])
+    return packed.view(np.uint64)
+
+
 def image(table):
-    """Raw table image copied to the host: (slots uint8, tags uint16 or None, locks uint64 words)."""
+    """Raw table image copied to the host: (slots uint8, tags uint16 or None,
+    bitmap of held bucket locks as uint64 words)."""
     r = table.raw()
     slots = r["slots"].cpu().numpy()
     tags = None if r["tags"] is None else r["tags"].cpu().numpy().view(np.uint16)
-    locks32 = r["locks"].cpu().numpy().view(np.uint32)
-    # the checker reads 64-bit lock words; pad to an even count
-    if len(locks32) % 2:
-        locks32 = np.concatenate([locks32, np.zeros(1, np.uint32)])
-    return slots, tags, locks32.view(np.uint64)
+    return slots, tags, held_lock_bitmap(r["locks"].cpu().numpy().view(np.uint32))
 
 
 def per_key_counts(keys, status, code):
@@ -40,3 +48,25 @@ def per_key_counts(keys, status, code):
     k = keys[status == code]
     u, c = np.unique(k, return_counts=True)
     return dict(zip(u.tolist(), c.tolist()))
+
+
+def full_is_genuine(t, full_keys):
+    """A two-choice table reports FULL only when both candidate buckets are full,
+    iceberg only when its front bucket and both backyard choices are: checked on
+    the final image of an insert-only table, with the oracle's own placement
+    rules for the candidate buckets."""
+    import oracle
+    slots, tags, _ = image(t)
+    if t.kv_bits == 64:
+        kw = slots.view(np.uint64)[0::2]
+        free = kw >= np.uint64((1 << 64) - 2)
+    else:
+        kw = slots.view(np.uint32)[0::2]
+        free = kw >= np.uint32(0xFFFFFFFE)
+    occ = (~free).reshape(t.num_buckets, t.bucket_slots).sum(axis=1)
+    for k in np.unique(full_keys).tolist():
+        if t.design.startswith("ICEBERG"):
+            cand = oracle.iceberg_buckets(k, t.num_buckets)
+        else:
+            cand = (oracle.primary_bucket(k, t.num_buckets), oracle.p2_alternate(k, t.num_buckets))
+        assert all(occ[b] == t.bucket_slots for b in cand), (k, [occ[b] for b in cand])

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0, flags=0):
-    c = hw._Config(kv_bits, bucket, tile, 0, flags)
+    c = hw._Config(kv_bits, bucket, tile, 0, flags, 0)
     b = ctypes.c_uint64()
     rc = hw.lib().hwave_table_bytes(capacity, design, ctypes.byref(c), ctypes.byref(b))
     return rc, b.value
@@ -38,25 +38,37 @@ def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0, flags=0):
                                                     (4, 16, 32), (5, 18, 32)])
 def test_space_per_slot_matches_section_6_1(design, per_slot, bucket):
     """16 bytes per key-value slot, plus 2 bytes of tag in the metadata designs
-    (Section 6.1); on top, one lock byte per bucket and a 256-byte control word."""
+    (Section 6.1); on top, one 8-byte ticket-lock word per bucket and a 256-byte
+    control word."""
     slots = 1 << 28
     rc, b = _bytes(slots, design)
     assert rc == 0
-    locks = slots // bucket
+    locks = 8 * (slots // bucket)
     assert b == slots * per_slot + locks + 256
 
 
 def test_chaining_space():
     """Chaining: ceil(capacity / 7) bucket nodes and twice as many pool nodes, 128
-    bytes each (7 pairs and a link, Section 5), one lock byte per bucket, and 1024
-    pool-partition counters, one per 128-byte line."""
+    bytes each (7 pairs and a link, Section 5), one 8-byte ticket-lock word per
+    bucket, and 1024 pool-partition counters, one per 128-byte line."""
     rc, b = _bytes(7 * 1000, 6)
     assert rc == 0
     nb, pool = 1000, 2000
     node_bytes = -(-(nb + pool) * 128 // 256) * 256
-    lock_bytes = -(-((nb + 3) // 4 * 4) // 256) * 256
+    lock_bytes = -(-(8 * nb) // 256) * 256
     assert b == node_bytes + lock_bytes + 256 + 1024 * 128
     assert _bytes(7 * 1000, 6, kv_bits=32)[0] == -4  # 64-bit keys only
+
+
+@pytest.mark.parametrize("design", range(8))
+def test_merge_workspace_size(design):
+    """HWAVE_F_MERGE_MIXED adds the merge workspace: 2 * 2^20 entries of an 8-byte
+    key word and 16 bytes, and a 4-byte word per operation of a 2^20-operation
+    chunk (rounded to 256 bytes)."""
+    rc0, plain = _bytes(1 << 16, design)
+    rc1, merged = _bytes(1 << 16, design, flags=hw.F_MERGE_MIXED)
+    assert rc0 == rc1 == 0
+    assert merged - plain == (2 << 20) * 24 + (1 << 20) * 4
 
 
 @pytest.mark.parametrize("design", range(8))
@@ -98,6 +110,10 @@ def test_bad_arguments_rejected_on_host():
     assert _bytes(1024, 8)[0] == -1                   # no such design
     assert _bytes(1024, 0, kv_bits=16)[0] == -1       # key width
     assert _bytes(1024, 0, bucket=8, tile=16)[0] == -4  # no kernel instance
+    b = ctypes.c_uint64()
+    for limit, rc in ((40000000, 0), (40000001, -1)):    # lock time limit, microseconds
+        c = hw._Config(64, 0, 0, 0, 0, limit)
+        assert L.hwave_table_bytes(1024, 0, ctypes.byref(c), ctypes.byref(b)) == rc
     assert L.hwave_table_bytes(1024, 0, None, None) == -1
     c = hw._Config()
     assert L.hwave_config_default(9, ctypes.byref(c)) == -1

@@ -25,7 +25,10 @@ def test_full_size_step_and_mixed_batch_against_oracle():
     d = bench.make_inputs(28, 1, 1 << 20)
     step = bench.Step(d, "P2_M", 0, 0)  # the benchmark's defaults: bucket 32, tile 4
     assert (step.t.bucket_slots, step.t.tile, step.t.capacity) == (32, 4, 1 << 28)
-    bench.verify_step(step, d)  # raises on any output that breaks its closed form
+    # raises on any output that breaks its closed form, or on a FULL insert with a
+    # free slot in one of its key's buckets
+    n_full = bench.verify_step(step, d)
+    print("full-size step verified; %d insert(s) ended FULL, each with both buckets full" % n_full)
 
     keys = d["keys"]
     n = len(keys)

@@ -14,7 +14,7 @@ import pytest
 import oracle
 import paper_2509_16407_amd as hw
 from paper_2509_16407_amd import workloads as w
-from gpu_util import dev, host, image, per_key_counts, u8
+from gpu_util import dev, full_is_genuine, host, image, per_key_counts, u8
 
 pytestmark = pytest.mark.gpu
 
@@ -30,26 +30,6 @@ def check_layout(t, neg_keys=None, tile_bytes=None):
                                   slots, tags, locks, neg_keys=neg_keys, tile_bytes=tb)
     assert nv == 0, rep
     return rep
-
-
-def p2_full_is_genuine(t, full_keys):
-    """Power-of-two-choice reports FULL only when both candidate buckets are full,
-    iceberg only when its front bucket and both backyard choices are (checked on
-    the final image of an insert-only table)."""
-    slots, tags, _ = image(t)
-    if t.kv_bits == 64:
-        kw = slots.view(np.uint64)[0::2]
-        free = kw >= np.uint64((1 << 64) - 2)
-    else:
-        kw = slots.view(np.uint32)[0::2]
-        free = kw >= np.uint32(0xFFFFFFFE)
-    occ = (~free).reshape(t.num_buckets, t.bucket_slots).sum(axis=1)
-    for k in np.unique(full_keys).tolist():
-        if t.design.startswith("ICEBERG"):
-            cand = oracle.iceberg_buckets(k, t.num_buckets)
-        else:
-            cand = (oracle.primary_bucket(k, t.num_buckets), oracle.p2_alternate(k, t.num_buckets))
-        assert all(occ[b] == t.bucket_slots for b in cand), (k, [occ[b] for b in cand])
 
 
 def check_dump(t, om):
@@ -229,7 +209,7 @@ def test_u32_groupby_sum(design, logcap, flags):
     full = st == hw.ST_FULL
     if full.any():
         assert not design.startswith("DOUBLE"), "double hashing reported FULL below capacity"
-        p2_full_is_genuine(t, ops_k[full])
+        full_is_genuine(t, ops_k[full])
         # a key that never got in is absent from the table: drop all its ops
         lost = np.setdiff1d(ops_k[full], ops_k[st == hw.ST_DONE])
         keep = ~np.isin(ops_k, lost)
@@ -305,6 +285,29 @@ def test_primary_bucket_hook_matches_oracle():
     exp = np.array([oracle.iceberg_buckets(int(k), t.num_buckets)[0] for k in keys[:2000]])
     assert np.array_equal(got[:2000], exp)
     assert got.max() < oracle.iceberg_front_buckets(t.num_buckets)
+
+
+def test_candidate_bucket_hook_matches_oracle():
+    """hwave_candidate_buckets (used to check that a FULL status was legal) agrees
+    with the oracle's independent restatement of each design's placement rule:
+    two-choice primary and alternate, iceberg front and backyard choices, cuckoo's
+    three buckets, double hashing's primary bucket and probe step."""
+    keys = w.distinct_keys(6, 3000)
+    for design in ("P2_M", "P2", "ICEBERG_M", "CUCKOO", "DOUBLE_M", "DOUBLE"):
+        t = hw.Table(1 << 20, design)
+        nb = t.num_buckets
+        got = t.candidate_buckets(dev(keys)).cpu().numpy().view(np.uint64)
+        for i, k in enumerate(keys.tolist()):
+            if design.startswith("P2"):
+                exp = (oracle.primary_bucket(k, nb), oracle.p2_alternate(k, nb), (1 << 64) - 1)
+            elif design.startswith("ICEBERG"):
+                exp = oracle.iceberg_buckets(k, nb)
+            elif design == "CUCKOO":
+                exp = oracle.cuckoo_buckets(k, nb)
+            else:
+                b0 = oracle.double_probe(k, nb, 0)
+                exp = (b0, (oracle.double_probe(k, nb, 1) - b0) % nb, (1 << 64) - 1)
+            assert tuple(int(x) for x in got[i]) == tuple(exp), (design, k)
 
 
 # ------------------------------------------------------------------ iceberg load

@@ -14,7 +14,7 @@ import pytest
 import oracle
 import paper_2509_16407_amd as hw
 from paper_2509_16407_amd import workloads as w
-from gpu_util import dev, image, u8
+from gpu_util import dev, full_is_genuine, image, u8
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +47,15 @@ def test_query_probe_counts_equal_the_oracle_model(design, bits, bucket, tile):
     pool = w.distinct_keys(seed, n + 30000, key_bits=bits)
     keys, neg = pool[:n], pool[n:]
     st = u8(t.insert(dev(keys, bits), dev(w.value_of(keys, bits), bits)))
-    assert (st == hw.ST_DONE).all()
+    # concurrent two-choice placement can, rarely, leave a key FULL at 0.9 load;
+    # legal only with both of its buckets full, and the key is then absent
+    full = st == hw.ST_FULL
+    assert ((st == hw.ST_DONE) | full).all()
+    if full.any():
+        assert design in ("P2", "P2_M", "ICEBERG", "ICEBERG_M"), design
+        full_is_genuine(t, keys[full])
+        keys = keys[~full]
+        n = len(keys)
     rep = _reports(t, neg)
     t.probe_counters(reset=True)
     found, _ = t.query(dev(keys, bits))

@@ -83,6 +83,24 @@ def test_mixed_batches_are_deterministic_and_disjoint():
     assert all(np.array_equal(g1[k], g2[k]) for k in g1)
 
 
+def test_mixed_batches_give_hot_ranks_to_every_kind():
+    """Draws are interleaved: a rank belongs, for one batch, to the kind of its
+    first candidate, so the hottest ranks fall to queries, upserts and erases in
+    proportion to their shares instead of all going to erases.  Over 40 batches
+    the hottest rank (p ~ 4.9% of Zipf 0.99 draws over 2^16 ranks) is an upsert
+    key in some batch and a query key in another, and in a batch where it is
+    an upsert key it takes a large share of the upserts."""
+    kinds, shares = set(), []
+    for b in w.mixed_batches(1 << 16, 1 << 12, 40, workload_id=11):
+        r0 = b["ranks"] == 0
+        if r0.any():
+            kinds.add(int(b["ops"][r0][0]))
+            if b["ops"][r0][0] == 2:
+                shares.append(w.hottest_upsert_share(b))
+    assert {0, 2} <= kinds
+    assert max(shares) > 0.05
+
+
 def test_selection_sample_exact_size_and_uniform():
     """Algorithm S returns exactly k distinct increasing indices; every index is
     taken with probability k/n (checked on per-decile counts)."""
