@@ -92,7 +92,9 @@ class Step:
         import torch
         import paper_2509_16407_amd as hw
         from paper_2509_16407_amd import workloads as w
-        self.t = hw.Table(d["cap"], design, bucket=bucket, tile=tile)
+        # the step's mixed batches put Zipf-hot keys among their upserts: merged by key
+        # (HWAVE_F_MERGE_MIXED; bulk calls are unaffected by the flag)
+        self.t = hw.Table(d["cap"], design, bucket=bucket, tile=tile, flags=hw.F_MERGE_MIXED)
         self.keys = to_dev(d["keys"])
         self.vals = to_dev(w.value_of(d["keys"]))
         self.bounds = d["bounds"]
@@ -157,10 +159,6 @@ class Step:
                                                          status=self.mst))
 
 
-class FullInsert(Exception):
-    """Some distinct key ended FULL: both of its buckets were full when it was placed."""
-
-
 def probe_counts(step: Step, design: str) -> dict:
     """Lines per query measured by the GPU (Table 1's probe unit, Section 5.1): an
     instrumented table of the step's size filled to 0.9, then the step's positive
@@ -203,67 +201,93 @@ def upsert_miss(step: Step, reps: int = 3) -> dict:
         st = t.upsert(step.keys[b1:b2], step.vals[b1:b2], combine="sum", status=step.st[: b2 - b1])
         b.record()
         b.synchronize()
-        full = int((st == 3).sum().item())
-        assert int((st == 1).sum().item()) + full == b2 - b1 and full <= 16, "upsert-miss statuses"
+        full = full_inserts_legal(t, step.keys[b1:b2], st)
+        assert int((st == 1).sum().item()) + full == b2 - b1, "upsert-miss statuses"
         if r:
             ms.append(a.elapsed_time(b))
     m = float(np.median(ms))
     return {"ms": round(m, 4), "gops": round((b2 - b1) / m / 1e6, 3)}
 
 
-def verify_step(step: Step, d, attempts: int = 3) -> int:
-    """verify_once, repeated (from a cleared table) when a few keys end FULL.
-    Concurrent two-choice placement decides on bucket fills that other inserts are
-    changing, so at 0.9 load a key can, rarely, find both of its 32-slot buckets
-    full (about once in thirty 2^28 fills); that outcome is legal and is counted
-    and reported.  Every other status is an error.  Returns the FULL events seen."""
-    seen = 0
-    for a in range(attempts):
-        try:
-            verify_once(step, d)
-            return seen
-        except FullInsert as e:
-            seen += 1
-            log("verification attempt %d: %s; repeating" % (a + 1, e))
-    raise AssertionError("FULL inserts in %d attempts in a row" % attempts)
+def full_inserts_legal(t, keys, st) -> int:
+    """Checks every FULL status of an insert-only batch against the table image:
+    a key may end FULL only when every bucket it may occupy is full (Section
+    2.2: a two-choice insert fails only when both of its buckets are full; for
+    iceberg, its front bucket and both backyard choices; for double hashing and
+    chaining, when no slot is left).  Inserts only add keys, so a bucket full
+    when the key was refused is still full in the final image.  The buckets come
+    from the library's hwave_candidate_buckets hook, the image from hwave_raw.
+    Returns the number of FULL keys; raises AssertionError on an illegal one."""
+    import torch
+    full = (st == 3).nonzero().flatten()
+    nf = int(full.numel())
+    if nf == 0:
+        return 0
+    if t.design in ("DOUBLE", "DOUBLE_M", "CHAINING"):
+        assert t.size() == t.capacity, "FULL while the table has free slots"
+        return nf
+    cand = t.candidate_buckets(keys[full])
+    ncand = 3 if t.design.startswith("ICEBERG") or t.design == "CUCKOO" else 2
+    b = cand[:, :ncand].reshape(-1)
+    B = t.bucket_slots
+    raw = t.raw()["slots"]
+    kw = raw.view(torch.int64 if t.kv_bits == 64 else torch.int32).view(-1, 2)[:, 0]
+    idx = (b[:, None] * B + torch.arange(B, device=b.device)[None, :]).reshape(-1)
+    k = kw[idx]
+    # the empty, tombstone and reservation patterns are -1, -2, -3 as signed words
+    live = (k < -3) | (k >= 0)
+    ok = live.view(-1, B).all(dim=1)
+    assert bool(ok.all()), "a FULL key has a candidate bucket with a free slot"
+    return nf
 
 
-def verify_once(step: Step, d) -> None:
-    """Closed-form checks of one full step at full size (no oracle needed): every
-    insert DONE, positives return 3k+1 (3k+2 after the +1 upsert), negatives miss,
-    erased keys miss, kept keys found, table size equals inserted - erased."""
+def verify_step(step: Step, d) -> int:
+    """Closed-form checks of one full step at full size (no oracle needed):
+    every insert DONE, or FULL when full_inserts_legal() confirms that all of the
+    key's buckets are full (concurrent two-choice placement decides on bucket
+    fills that other inserts are changing, so at 0.9 load a key can, rarely,
+    find both of its 32-slot buckets full); positives return 3k+1 (3k+2 after
+    the +1 upsert), negatives miss, erased keys miss, kept keys found, table size
+    equals inserted - erased.  A FULL key counts as never inserted throughout:
+    its queries miss, its upsert is FULL again (no erase has freed a slot), its
+    erase misses.  Returns the number of FULL keys."""
     import torch
     from paper_2509_16407_amd import workloads as w
     t = step.t
     t.clear()
     b2 = step.bounds[-1]
     st = t.insert(step.keys, step.vals, status=step.st[:b2])
-    if not bool((st == 1).all()):
+    if not bool(((st == 1) | (st == 3)).all()):
         hist = {int(c): int(n) for c, n in zip(*np.unique(st.cpu().numpy(), return_counts=True))}
-        if set(hist) == {1, 3} and hist[3] <= 16:
-            raise FullInsert("insert statuses %s (1 done, 3 full)" % hist)
-        raise AssertionError("insert statuses %s (1 done, 2 existed, 3 full)" % hist)
-    f, v = t.query(step.qpos, out=step.out)
-    assert bool((f == 1).all()), "positive queries"
+        raise AssertionError("insert statuses %s (1 done, 2 existed, 3 full, 5 timeout)" % hist)
+    n_full = full_inserts_legal(t, step.keys, st)
+    isfull = st == 3
+    pos_full = isfull[torch.from_numpy(d["pos_idx"]).cuda()]
+    er_full = isfull[torch.from_numpy(d["er_idx"]).cuda()]
+    n_er_full = int(er_full.sum().item())
     exp = to_dev(w.value_of(d["qpos"]))
-    assert bool((v == exp).all()), "positive values"
+    zero = torch.zeros_like(exp)
+    f, v = t.query(step.qpos, out=step.out)
+    assert bool((f == torch.where(pos_full, 0, 1).to(f.dtype)).all()), "positive queries"
+    assert bool((v == torch.where(pos_full, zero, exp)).all()), "positive values"
     f, v = t.query(step.qneg, out=step.out)
     assert bool((f == 0).all()) and bool((v == 0).all()), "negative queries"
     st = t.upsert(step.qpos, step.ones, combine="sum")
-    assert bool((st == 2).all()), "upsert statuses"
+    assert bool((st == torch.where(pos_full, 3, 2).to(st.dtype)).all()), "upsert statuses"
     f, v = t.query(step.qpos, out=step.out)
-    assert bool((v == exp + 1).all()), "upserted values"
+    assert bool((v == torch.where(pos_full, zero, exp + 1)).all()), "upserted values"
     st = t.erase(step.ekeys)
-    assert bool((st == 1).all()), "erase statuses"
-    assert t.size() == b2 - len(d["ekeys"]), "size after erase"
+    assert bool((st == torch.where(er_full, 0, 1).to(st.dtype)).all()), "erase statuses"
+    assert t.size() == b2 - n_full - (len(d["ekeys"]) - n_er_full), "size after erase"
     erased = np.zeros(b2, dtype=bool)
     erased[d["er_idx"]] = True
-    kept_mask = torch.from_numpy(~erased[d["pos_idx"]]).cuda()
+    kept_mask = torch.from_numpy(~erased[d["pos_idx"]]).cuda() & ~pos_full
     f, v = t.query(step.qpos, out=step.out)
     assert bool(((f == 1) == kept_mask).all()), "re-query membership"
     assert bool(torch.where(kept_mask, v == exp + 1, v == 0).all()), "re-query values"
     torch.cuda.synchronize()
-    del exp
+    del exp, zero
+    return n_full
 
 
 def bench_phased(step: Step, d, design: str, conc_rates: dict, reps=3):
@@ -300,7 +324,7 @@ def bench_phased(step: Step, d, design: str, conc_rates: dict, reps=3):
         timed("insert_0.9", lambda: t.insert(step.keys[b1:b2], step.vals[b1:b2], status=st_all[b1:b2]))
         if r == 0:
             full = st_all == 3
-            n_full = int(full.sum().item())
+            n_full = full_inserts_legal(t, step.keys, st_all)
             assert bool(((st_all == 1) | full).all()), "phased %s: insert statuses" % design
             assert t.size() == b2 - n_full, "phased %s: size after the load phases" % design
             kept = ~full[torch.from_numpy(d["pos_idx"]).cuda()]
@@ -337,11 +361,11 @@ def bench_designs(step: Step, d, designs, steps=2, warmup=1, verify=True):
         # chaining is sized, as in the paper's evaluation (Section 5), so that its
         # chains hold 7 pairs (length 1) in expectation once the step has loaded
         # all its keys
-        step.t = hw.Table(step.bounds[-1] if des == "CHAINING" else d["cap"], des)
+        step.t = hw.Table(step.bounds[-1] if des == "CHAINING" else d["cap"], des, flags=hw.F_MERGE_MIXED)
         if verify:
             res_full = verify_step(step, d)
             if res_full:
-                log("design %s: %d verification repeat(s) after FULL inserts" % (des, res_full))
+                log("design %s: %d insert(s) ended FULL, each with all of its buckets full" % (des, res_full))
         for _ in range(warmup):
             step.run()
         events = {}
@@ -562,16 +586,21 @@ def mixed_zipf_check(present, val, done, ops, r, vd, st, out):
     return bad
 
 
-def bench_mixed_zipf(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE_M"):
+def bench_mixed_zipf(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE_M", n_unmerged=8):
     """The mixed concurrent workload: a 2^log2cap-slot table preloaded with a 2^universe_log2-key
     universe (load 0.5, v = 3k+1), then `n_batches` shuffled mixed batches of 2^20
-    operations (50% query, 30% SUM upsert, 20% erase; Zipf 0.99 keys; erase and
-    upsert keys disjoint, queries avoid both).  Per-batch kernel latency from events.
-    Every output is checked on the device against a shadow model of the map indexed
-    by universe rank (present flag, value): queries return the batch-start state,
-    erases report presence, and of a key's upserts exactly one inserts (the key was
-    absent) or none (present), the rest report EXISTED; after the last batch the
-    table's size and its sum of values equal the model's."""
+    operations (50% query, 30% SUM upsert, 20% erase; Zipf 0.99 keys drawn
+    interleaved, so hot keys fall to every kind; erase and upsert keys disjoint,
+    queries avoid both).  The table merges each call's upserts by key
+    (HWAVE_F_MERGE_MIXED).  Per-batch latency from events around the call.
+    Every output is checked on the device against a shadow model of the map
+    indexed by universe rank (present flag, value): queries return the
+    batch-start state, erases report presence, and of a key's upserts exactly one
+    inserts (the key was absent) or none (present), the rest report EXISTED;
+    after the last batch the table's size and its sum of values equal the
+    model's.  Then the first `n_unmerged` batches again on a table without
+    merging (same preload, same checks): every upsert of a hot key waits in its
+    bucket's lock queue."""
     import torch
     import paper_2509_16407_amd as hw
     from paper_2509_16407_amd import workloads as w
@@ -579,49 +608,68 @@ def bench_mixed_zipf(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE
     U = 1 << universe_log2
     uk = w.universe_keys(U, workload_id=3)
     batches = list(w.mixed_batches(U, 1 << 20, n_batches, workload_id=3, ukeys=uk))
-    log("mixed Zipf workload: %d batches of 2^20 ops over a 2^%d-key universe generated in %.1f s"
-        % (n_batches, universe_log2, time.time() - t0))
-    t = hw.Table(1 << log2cap, design)
-    ukd = to_dev(uk)
-    pre = t.insert(ukd, ukd * 3 + 1)
-    assert bool((pre == 1).all()), "mixed Zipf workload: preload"
-    present = torch.ones(U, dtype=torch.bool, device="cuda")
-    val = ukd * 3 + 1
-    del ukd
+    shares = np.array([w.hottest_upsert_share(bt) for bt in batches])
+    log("mixed Zipf workload: %d batches of 2^20 ops over a 2^%d-key universe generated in %.1f s; "
+        "hottest upsert key: median %.3f, max %.3f of a batch's upserts"
+        % (n_batches, universe_log2, time.time() - t0, float(np.median(shares)), float(shares.max())))
     n = 1 << 20
     out = torch.empty(n, dtype=torch.int64, device="cuda")
     st = torch.empty(n, dtype=torch.uint8, device="cuda")
-    bad = torch.zeros((), dtype=torch.int64, device="cuda")
-    done = torch.zeros(U, dtype=torch.int32, device="cuda")
     # every batch is resident in HBM before the first launch (~26 MB each), so no
     # host copy sits between two batches' kernels
     staged = [(torch.from_numpy(bt["ops"]).cuda(), to_dev(bt["keys"]), to_dev(bt["vals"]),
                torch.from_numpy(bt["ranks"]).cuda()) for bt in batches]
     del batches
-    torch.cuda.synchronize()
-    ev = []
-    for ops, kd, vd, r in staged:
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        t.mixed(ops, kd, vd, combine="sum", out=out, status=st)
-        b.record()
-        ev.append((a, b))
-        bad += mixed_zipf_check(present, val, done, ops, r, vd, st, out)
-    torch.cuda.synchronize()
-    nbad = int(bad.item())
-    assert nbad == 0, "mixed Zipf workload: %d outputs differ from the shadow model" % nbad
-    assert t.size() == int(present.sum().item()), "mixed Zipf workload: size"
-    _, tv = t.export()
-    assert int(tv.sum().item()) == int(val[present].sum().item()), "mixed Zipf workload: sum of values"
-    ms = np.array([a.elapsed_time(b) for a, b in ev])
+
+    def run(flags, count):
+        t = hw.Table(1 << log2cap, design, flags=flags)
+        ukd = to_dev(uk)
+        pre = t.insert(ukd, ukd * 3 + 1)
+        assert bool((pre == 1).all()), "mixed Zipf workload: preload"
+        present = torch.ones(U, dtype=torch.bool, device="cuda")
+        val = ukd * 3 + 1
+        del ukd
+        bad = torch.zeros((), dtype=torch.int64, device="cuda")
+        done = torch.zeros(U, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        ev = []
+        for ops, kd, vd, r in staged[:count]:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            t.mixed(ops, kd, vd, combine="sum", out=out, status=st)
+            b.record()
+            ev.append((a, b))
+            bad += mixed_zipf_check(present, val, done, ops, r, vd, st, out)
+        torch.cuda.synchronize()
+        nbad = int(bad.item())
+        assert nbad == 0, "mixed Zipf workload: %d outputs differ from the shadow model" % nbad
+        assert t.size() == int(present.sum().item()), "mixed Zipf workload: size"
+        _, tv = t.export()
+        assert int(tv.sum().item()) == int(val[present].sum().item()), "mixed Zipf workload: sum of values"
+        del t, present, val, done, tv
+        torch.cuda.empty_cache()
+        return np.array([a.elapsed_time(b) for a, b in ev])
+
+    ms = run(hw.F_MERGE_MIXED, len(staged))
+    ms_plain = run(0, min(n_unmerged, len(staged))) if n_unmerged else None
     res = {"workload": "%s, 2^%d slots, 2^%d-key universe preloaded (load 0.5), %d shuffled batches of 2^20 ops "
-                       "(50%% query / 30%% SUM upsert / 20%% erase, Zipf 0.99)" % (design, log2cap, universe_log2, n_batches),
+                       "(50%% query / 30%% SUM upsert / 20%% erase, Zipf 0.99, interleaved draws), upserts merged "
+                       "by key per call" % (design, log2cap, universe_log2, n_batches),
            "p50_batch_ms": round(float(np.percentile(ms, 50)), 4), "p99_batch_ms": round(float(np.percentile(ms, 99)), 4),
-           "mean_gops": round(float(n * len(ms) / ms.sum() / 1e6), 3), "verified": True}
-    log("mixed Zipf workload: p50 %.3f ms, p99 %.3f ms per 2^20-op batch (%.2f Gops/s), all outputs verified"
-        % (res["p50_batch_ms"], res["p99_batch_ms"], res["mean_gops"]))
-    del t, present, val, staged, done
+           "mean_gops": round(float(n * len(ms) / ms.sum() / 1e6), 3), "verified": True,
+           "hottest_upsert_key_share": {"median": round(float(np.median(shares)), 4),
+                                        "max": round(float(shares.max()), 4)}}
+    if ms_plain is not None:
+        res["unmerged_first_batches"] = {
+            "batches": len(ms_plain), "p50_batch_ms": round(float(np.percentile(ms_plain, 50)), 4),
+            "max_batch_ms": round(float(ms_plain.max()), 4), "merged_p50_same_batches_ms":
+                round(float(np.percentile(ms[:len(ms_plain)], 50)), 4), "verified": True}
+    log("mixed Zipf workload: p50 %.3f ms, p99 %.3f ms per 2^20-op batch (%.2f Gops/s), all outputs verified%s"
+        % (res["p50_batch_ms"], res["p99_batch_ms"], res["mean_gops"],
+           "" if ms_plain is None else "; unmerged p50 %.3f ms over the first %d" % (
+               res["unmerged_first_batches"]["p50_batch_ms"], len(ms_plain))))
+    del staged
     torch.cuda.empty_cache()
     return res
 
@@ -738,7 +786,8 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
                                        for a in rej if a["full_ops"]] for e, rej in rejected.items()}}
 
 
-def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):
+def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3, sweep_rates=(14000.0, 20000.0, 26000.0),
+                 sweep_s=10.0):
     """The served form: n_tables resident, erase-free P2HT(M) tables of 2^log2cap
     slots, preloaded with half of a Zipf universe of floor(0.85 * capacity) keys;
     n_req requests arriving as a Poisson process at `rate`/s (query / upsert /
@@ -812,72 +861,131 @@ def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3):
                     "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
                     "wall_s": round(st["wall_s"], 4), "requests_per_launch": round(st["mean_requests_per_batch"], 2)}
     offered = n_ops / offs[-1] / 1e9
-    return {"workload": "%d P2HT(M) tables x 2^%d slots, %d Poisson requests at %.0f/s, sizes 2^U (U~U[8,20]), "
-                        "query/upsert/insert 50/30/20, Zipf 0.99" % (n_tables, log2cap, n_req, rate),
-            "ops": n_ops, "offered_gops": round(offered, 3), "batched": f(st_b), "plain": f(st_p),
-            "identical_results": True}
+    out = {"workload": "%d P2HT(M) tables x 2^%d slots, %d Poisson requests at %.0f/s, sizes 2^U (U~U[8,20]), "
+                       "query/upsert/insert 50/30/20, Zipf 0.99" % (n_tables, log2cap, n_req, rate),
+           "ops": n_ops, "offered_gops": round(offered, 3), "batched": f(st_b), "plain": f(st_p),
+           "identical_results": True}
+    if sweep_rates:
+        out["sweep"] = served_sweep(reqs, bufs, n_tables, cap, universe, sweep_rates, sweep_s, slots, OP, f)
+    return out
 
 
-def cpu_baseline(cap_log2: int, max_threads: int = 16):
-    """The CPU oracle on the same step recipe at a smaller size: (i) one thread,
-    one map; (ii) T threads, the keys sharded by a hash of their own into T maps
-    (one per thread), the phases in the step's order with a join between phases.
-    The oracle's map calls release the interpreter lock, so the shards run in
-    parallel.  `value` is the sharded rate, `cores` = T."""
-    import concurrent.futures as cf
-    import oracle
+def served_sweep(reqs, bufs, n_tables, cap, universe, rates, seconds, slots, OP, f):
+    """Long runs of the served form: at each arrival rate, `seconds` of Poisson
+    arrivals whose requests cycle through the verified run's request payloads
+    (table, kind, keys, values; outputs are overwritten and not checked), served
+    batched and then plain on one set of resident tables.  Reports ops/s and
+    p50/p99 latency per rate and mode, and the offered rate."""
+    import torch
+    import paper_2509_16407_amd as hw
     from paper_2509_16407_amd import workloads as w
-    d = make_inputs(cap_log2, 0, 0)
+    tabs = [hw.Table(cap, "P2_M", flags=hw.F_NO_ERASE | hw.F_AGGREGATE) for _ in range(n_tables)]
+    pre_n = universe // 2
+    for t in range(n_tables):
+        pre = w.splitmix64(w.stream_seed(5, 100 + t), 0, pre_n)
+        kk = torch.from_numpy(pre.view(np.int64)).cuda()
+        tabs[t].insert(kk, kk * 3 + 1)
+        del kk
+    torch.cuda.synchronize()
+    mean_ops = float(np.mean([len(r["keys"]) for r in reqs]))
+    rows = []
+    for i, rate in enumerate(rates):
+        offs = w.poisson_arrivals(w.stream_seed(5, 7000 + i), rate, seconds)
+        n = len(offs)
+        row = {"rate_per_s": rate, "requests": n, "offered_gops": round(rate * mean_ops / 1e9, 3)}
+        for mode in ("batched", "plain"):
+            srv = hw.Server(tabs, mode=mode, slots=slots, slot_ops=1 << 22)
+            P = len(reqs)
+            rs = [hw.Server.request(reqs[j % P]["table"], OP[reqs[j % P]["kind"]], *bufs[j % P]) for j in range(n)]
+            srv.replay(rs, list(offs))
+            srv.drain()
+            st = srv.stats()
+            srv.close()
+            row[mode] = f(st)
+            log("served sweep: %.0f req/s (offered %.2f Gops/s), %s: %.2f Gops/s, p50 %.2f ms, p99 %.2f ms"
+                % (rate, row["offered_gops"], mode, row[mode]["gops"], row[mode]["p50_ms"], row[mode]["p99_ms"]))
+        rows.append(row)
+    del tabs
+    torch.cuda.empty_cache()
+    return {"seconds_of_arrivals": seconds, "payloads_cycled": len(reqs), "rates": rows}
+
+
+def _step_phases(d):
+    """(kind, keys, values) of the load benchmark's step, in its order."""
+    from paper_2509_16407_amd import workloads as w
     keys = d["keys"]
     vals = w.value_of(keys)
     ones = np.ones(len(d["qpos"]), np.uint64)
     b0, b1, b2 = d["bounds"]
-    # (kind, keys, values) in the step's order
-    phases = [("insert", keys[:b0], vals[:b0]), ("insert", keys[b0:b1], vals[b0:b1]),
-              ("insert", keys[b1:b2], vals[b1:b2]), ("query", d["qpos"], None), ("query", d["qneg"], None),
-              ("upsert", d["qpos"], ones), ("erase", d["ekeys"], None), ("query", d["qpos"], None),
-              ("query", d["qneg"], None)]
+    return [("insert", keys[:b0], vals[:b0]), ("insert", keys[b0:b1], vals[b0:b1]),
+            ("insert", keys[b1:b2], vals[b1:b2]), ("query", d["qpos"], None), ("query", d["qneg"], None),
+            ("upsert", d["qpos"], ones), ("erase", d["ekeys"], None), ("query", d["qpos"], None),
+            ("query", d["qneg"], None)]
+
+
+def _oracle_run(m, kind, k, v):
+    if kind == "insert":
+        m.insert(k, v)
+    elif kind == "upsert":
+        m.upsert(k, v)
+    elif kind == "query":
+        m.query(k)
+    else:
+        m.erase(k)
+
+
+def cpu_baseline(d, cap_log2: int, single_log2: int = 24, max_threads: int = 16):
+    """The CPU oracle on the benchmark's own step at the metric's size (the same
+    inputs as the GPU step): T threads, the keys sharded by a hash of their own
+    into T maps (one per thread), the phases in the step's order with a join
+    between phases.  The oracle's map calls release the interpreter lock, so the
+    shards run in parallel.  `value` is that rate, `cores` = T.  A one-thread,
+    one-map run of the whole step at this size would take minutes, so
+    `single_thread_value` runs the same recipe at 2^single_log2 slots."""
+    import concurrent.futures as cf
+    import oracle
+    phases = _step_phases(d)
     n_ops = sum(len(k) for _, k, _ in phases)
-
-    def run(m, kind, k, v):
-        if kind == "insert":
-            m.insert(k, v)
-        elif kind == "upsert":
-            m.upsert(k, v)
-        elif kind == "query":
-            m.query(k)
-        else:
-            m.erase(k)
-
-    m = oracle.OracleMap()
-    t0 = time.perf_counter()
-    for kind, k, v in phases:
-        run(m, kind, k, v)
-    dt1 = time.perf_counter() - t0
-    del m
+    b2 = d["bounds"][-1]
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count() or 1
     T = max(1, min(max_threads, avail))
-    with np.errstate(over="ignore"):
-        shard_of = lambda k: ((k * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(40)) % np.uint64(T)
     parts = []
-    for kind, k, v in phases:
-        sh = shard_of(k)
-        parts.append([(kind, k[sh == i], None if v is None else v[sh == i]) for i in range(T)])
+    with np.errstate(over="ignore"):
+        for kind, k, v in phases:
+            sh = (((k * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(40)) % np.uint64(T)).astype(np.uint8)
+            order = np.argsort(sh, kind="stable")
+            cuts = np.cumsum(np.bincount(sh, minlength=T))[:-1]
+            ks = np.split(k[order], cuts)
+            vs = [None] * T if v is None else np.split(v[order], cuts)
+            parts.append([(kind, ks[i], vs[i]) for i in range(T)])
+            del sh, order
     maps = [oracle.OracleMap() for _ in range(T)]
     with cf.ThreadPoolExecutor(T) as ex:
         t0 = time.perf_counter()
         for ph in parts:
-            list(ex.map(lambda i: run(maps[i], *ph[i]), range(T)))
+            list(ex.map(lambda i: _oracle_run(maps[i], *ph[i]), range(T)))
         dtT = time.perf_counter() - t0
     assert sum(mm.size() for mm in maps) == b2 - len(d["ekeys"]), "sharded oracle size"
+    del maps, parts
+    ds = make_inputs(single_log2, 0, 0)
+    sph = _step_phases(ds)
+    n1 = sum(len(k) for _, k, _ in sph)
+    m = oracle.OracleMap()
+    t0 = time.perf_counter()
+    for kind, k, v in sph:
+        _oracle_run(m, kind, k, v)
+    dt1 = time.perf_counter() - t0
+    del m, ds
     return dict(value=n_ops / dtT / 1e9, unit="Gops/s", cores=T, kind="oracle",
-                single_thread_value=n_ops / dt1 / 1e9,
-                sample="same step recipe (insert to 0.9, 2^%d pos + neg queries, upserts, 50%% erase, "
-                       "re-query) at 2^%d slots, std::unordered_map; %d ops: %d threads over %d key-hash "
-                       "shards %.2f s, 1 thread %.2f s" % (cap_log2 - 1, cap_log2, n_ops, T, T, dtT, dt1))
+                single_thread_value=n1 / dt1 / 1e9,
+                sample="the benchmark's step at 2^%d slots (insert to 0.9, 2^%d positive and negative "
+                       "queries, upserts, 50%% erase, re-queries; the GPU step's own inputs), "
+                       "std::unordered_map: %d ops over %d key-hash shards on %d threads in %.2f s; "
+                       "single_thread_value: one thread, one map, the same recipe at 2^%d slots "
+                       "(%d ops in %.2f s)" % (cap_log2, cap_log2 - 1, n_ops, T, T, dtT, single_log2, n1, dt1))
 
 
 KERNEL_OF = {"insert_0.5": "k_upsert", "insert_0.75": "k_upsert", "insert_0.9": "k_upsert",
@@ -990,11 +1098,14 @@ def main():
     ap.add_argument("--no-probes", action="store_true", help="skip the GPU-counted probes (instrumented build)")
     ap.add_argument("--no-batched", action="store_true", help="skip the multi-table (batched) section")
     ap.add_argument("--no-served", action="store_true", help="skip the serving section")
+    ap.add_argument("--served-sweep-s", type=float, default=10.0,
+                    help="seconds of arrivals per rate in the served-form rate sweep (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-aging", action="store_true", help="skip the aging (churn) section")
     ap.add_argument("--compare", default="DOUBLE,DOUBLE_M,P2,ICEBERG,ICEBERG_M,CHAINING,CUCKOO",
                     help="other designs to run the same step on ('' to skip)")
-    ap.add_argument("--cpu-log2cap", type=int, default=24)
+    ap.add_argument("--cpu-single-log2cap", type=int, default=24,
+                    help="table size of the one-thread CPU oracle figure")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB read + 1 GiB write elementwise kernel first "
                          "(reference for HBM byte counters)")
@@ -1016,10 +1127,10 @@ def main():
     step = Step(d, args.design, args.tile, args.bucket)
     torch.cuda.synchronize()
     log("device inputs resident; table %s bucket %d tile %d" % (args.design, step.t.bucket_slots, step.t.tile))
-    full_repeats = 0
+    verify_full = None
     if not args.no_verify:
-        full_repeats = verify_step(step, d)
-        log("full-size closed-form verification passed")
+        verify_full = verify_step(step, d)
+        log("full-size closed-form verification passed (%d FULL inserts, each legal)" % verify_full)
 
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
@@ -1114,12 +1225,13 @@ def main():
         if args.no_batched:
             del step
         torch.cuda.empty_cache()
-        served = bench_served()
+        served = bench_served(sweep_rates=(14000.0, 20000.0, 26000.0) if args.served_sweep_s > 0 else (),
+                              sweep_s=args.served_sweep_s)
 
     cpu = None
     if not args.no_cpu:
-        log("cpu baseline (oracle) at 2^%d" % args.cpu_log2cap)
-        cpu = cpu_baseline(args.cpu_log2cap)
+        log("cpu baseline (oracle) at 2^%d" % args.log2cap)
+        cpu = cpu_baseline(d, args.log2cap, args.cpu_single_log2cap)
 
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gops/s", "n_gpus": 1,
@@ -1145,7 +1257,9 @@ def main():
             "metadata_tables_delete_gops": {"paper": 1.17, "here_p2m_erase": rates["erase"]["gops"]},
         },
         "kernel_source_hash": kernel_source_hash(),
-        "verify_full_repeats": full_repeats,
+        # inserts of the verified fill that ended FULL with every bucket of the
+        # key full (null when verification was skipped)
+        "verify_full_inserts": verify_full,
     }
     print(json.dumps(result), flush=True)
 
