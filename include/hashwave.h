@@ -336,6 +336,19 @@ int hwave_multi_destroy(hwave_multi* m);
 int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items, const void* d_keys,
                     const void* d_vals, void* d_vals_out, uint8_t* d_status, void* stream);
 
+/* The batched group-by upsert over a table list, offsets on the device: tables[i]
+ * receives ops [d_offsets[i], d_offsets[i+1]) of the shared arrays as one upsert
+ * with `combine` (the accumulating upsert of Section 5.1; d_offsets: n_tables + 1
+ * device words, d_offsets[0] = 0, non-decreasing, else HWAVE_EINVAL), all in one
+ * persistent launch.  The library keeps a group (hwave_multi) per
+ * distinct table list, made on the first call and dropped when one of its
+ * tables is destroyed.  Blocks until the offsets have been copied to the host
+ * (the stream's earlier work has completed), then enqueues like
+ * hwave_multi_upsert. */
+int hwave_multi_upsert_tables(hwave_table* const* tables, uint32_t n_tables, const uint64_t* d_offsets,
+                              const void* d_keys, const void* d_vals, hwave_combine combine, uint8_t* d_status,
+                              void* stream);
+
 /* Empties every table of the group in one launch on `stream`. */
 int hwave_multi_clear(hwave_multi* m, void* stream);
 

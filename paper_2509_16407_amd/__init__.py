@@ -13,7 +13,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Table", "Multi", "Server", "lib", "autotune", "DESIGNS", "COMBINES", "OPS", "HashWaveError"]
+__all__ = ["Table", "Multi", "Server", "lib", "autotune", "multi_upsert_tables", "DESIGNS", "COMBINES", "OPS",
+           "HashWaveError"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhashwave.so")
@@ -131,6 +132,7 @@ def _bind(L):
         "hwave_multi_run": (I, [P, P, ctypes.c_uint32, P, P, P, P, P]),
         "hwave_multi_clear": (I, [P, P]),
         "hwave_multi_upsert": (I, [P, P, P, P, I, P, P]),
+        "hwave_multi_upsert_tables": (I, [P, ctypes.c_uint32, P, P, P, I, P, P]),
         "hwave_server_create": (I, [ctypes.POINTER(P), P, ctypes.c_uint32, ctypes.POINTER(_ServerCfg)]),
         "hwave_server_submit": (I, [P, ctypes.POINTER(_Request), ctypes.c_double, ctypes.POINTER(U64)]),
         "hwave_server_poll": (I, [P, U64, ctypes.POINTER(I)]),
@@ -383,6 +385,20 @@ class Multi:
         _check(lib().hwave_multi_upsert(self.h, ctypes.cast(offs, ctypes.c_void_p), _ptr(keys), _ptr(vals),
                                         COMBINES[combine], _ptr(status), _stream(stream)))
         return status
+
+
+def multi_upsert_tables(tables, d_offsets, keys, vals, combine="sum", status=None, stream=None):
+    """hwave_multi_upsert_tables: table i receives ops [d_offsets[i], d_offsets[i+1])
+    of the shared arrays as one upsert, in one persistent launch; d_offsets is an
+    int64 device tensor of len(tables) + 1 entries."""
+    import torch
+    n = keys.numel()
+    status = torch.empty(n, dtype=torch.uint8, device=keys.device) if status is None else status
+    arr = (ctypes.c_void_p * len(tables))(*[t.h.value for t in tables])
+    _check(lib().hwave_multi_upsert_tables(ctypes.cast(arr, ctypes.c_void_p), len(tables), _ptr(d_offsets),
+                                           _ptr(keys), _ptr(vals), COMBINES[combine], _ptr(status),
+                                           _stream(stream)))
+    return status
 
 
 class Server:

@@ -4,6 +4,7 @@
 // (initialisation, counting, export, primary-bucket lookup).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <mutex>
@@ -14,6 +15,8 @@
 #include "hw_multi.hpp"
 
 using namespace hw;
+
+static void drop_groups_of(hwave_table* t);
 
 struct hwave_table {
   int device;
@@ -446,6 +449,7 @@ int hwave_create_in(hwave_table** out, void* d_buffer, uint64_t buffer_bytes, ui
 
 int hwave_destroy(hwave_table* t) {
   if (!t) return HWAVE_EINVAL;
+  drop_groups_of(t);
   hipError_t e = hipDeviceSynchronize();
   int rc = e == hipSuccess ? HWAVE_OK : hip_fail(e);
   if (t->la.tv.probe_ctr) (void)hipFree(t->la.tv.probe_ctr);
@@ -855,6 +859,59 @@ int hwave_multi_upsert(hwave_multi* m, const uint64_t* h_offsets, const void* d_
                                h_offsets[i + 1]});
   }
   return hwave_multi_run(m, items.data(), (uint32_t)items.size(), d_keys, d_vals, nullptr, d_status, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Groups made by hwave_multi_upsert_tables, one per distinct table list, kept
+// until one of their tables is destroyed.
+std::mutex g_groups_mu;
+std::vector<std::pair<std::vector<hwave_table*>, hwave_multi*>> g_groups;
+
+}  // namespace
+
+// Called by hwave_destroy: groups that hold `t` go with it.
+static void drop_groups_of(hwave_table* t) {
+  std::lock_guard<std::mutex> g(g_groups_mu);
+  for (size_t i = 0; i < g_groups.size();) {
+    const auto& v = g_groups[i].first;
+    if (std::find(v.begin(), v.end(), t) != v.end()) {
+      hwave_multi_destroy(g_groups[i].second);
+      g_groups.erase(g_groups.begin() + (long)i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+extern "C" {
+
+int hwave_multi_upsert_tables(hwave_table* const* tables, uint32_t n_tables, const uint64_t* d_offsets,
+                              const void* d_keys, const void* d_vals, hwave_combine combine, uint8_t* d_status,
+                              void* stream) {
+  if (!tables || n_tables == 0 || !d_offsets || (int)combine < HWAVE_SUM || (int)combine > HWAVE_MAX)
+    return HWAVE_EINVAL;
+  std::vector<hwave_table*> key(tables, tables + n_tables);
+  hwave_multi* m = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_groups_mu);
+    for (auto& e : g_groups)
+      if (e.first == key) m = e.second;
+    if (!m) {
+      const int rc = hwave_multi_create(&m, tables, n_tables, stream);
+      if (rc) return rc;
+      g_groups.emplace_back(key, m);
+    }
+  }
+  std::vector<uint64_t> h(n_tables + 1);
+  hipError_t e = hipMemcpyAsync(h.data(), d_offsets, h.size() * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e);
+  if (h[0] != 0) return HWAVE_EINVAL;
+  return hwave_multi_upsert(m, h.data(), d_keys, d_vals, combine, d_status, stream);
 }
 
 int hwave_stream_sync(void* stream) {

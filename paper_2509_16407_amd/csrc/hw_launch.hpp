@@ -309,7 +309,7 @@ struct Launch {
     for (uint64_t off = 0; off < n; off += ws->chunk) {
       const uint64_t m = n - off < ws->chunk ? n - off : ws->chunk;
       const unsigned gb = (unsigned)((m + MERGE_BLOCK_OPS - 1) / MERGE_BLOCK_OPS);
-      hipLaunchKernelGGL((k_merge_build<K>), dim3(gb < a.max_blocks ? gb : a.max_blocks), dim3(256), 0, s, *ws,
+      hipLaunchKernelGGL((k_merge_build<K>), dim3(gb < a.max_blocks ? gb : a.max_blocks), dim3(MERGE_THREADS), 0, s, *ws,
                          ops + off, k + off, v + off, m, combine);
       mixed_launch<true>(a, ops + off, k + off, v + off, m, combine, o ? o + off : nullptr,
                          status ? status + off : nullptr, *ws, s);

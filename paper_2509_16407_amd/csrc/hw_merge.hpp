@@ -37,6 +37,7 @@ constexpr uint32_t MERGE_CHUNK = 1u << 20;        // operations per pass (librar
 constexpr uint32_t MERGE_NONE = 0xFFFFFFFFu;      // op_ent of an operation that is not merged
 constexpr uint32_t MERGE_FOLLOWER = 0x80000000u;  // op_ent flag set by a follower in pass 2
 constexpr int MERGE_BLOCK_OPS = 4096;             // operations per block window of pass 1
+constexpr int MERGE_THREADS = 1024;               // threads per block of pass 1 (16 waves: latency hiding)
 constexpr int MERGE_LDS = 2048;                   // LDS entries per block (upserts <= 30% of 4096 in
                                                   // mixed batches; more spill to the global table)
 
@@ -92,8 +93,7 @@ __device__ __forceinline__ uint32_t merge_slot(const MergeWs& ws, uint64_t k) {
   const uint64_t k1 = k + 1;
   uint32_t h = (uint32_t)fmix64(k ^ MERGE_SALT) & ws.ne_mask;
   while (true) {
-    uint64_t cur = ld(ws.key + h);
-    if (cur == 0) cur = cas(ws.key + h, (uint64_t)0, k1);  // 0: we claimed it
+    const uint64_t cur = cas(ws.key + h, (uint64_t)0, k1);  // returns 0 when we claimed it
     if (cur == 0 || cur == k1) return h;
     h = (h + 1) & ws.ne_mask;
   }
@@ -102,17 +102,17 @@ __device__ __forceinline__ uint32_t merge_slot(const MergeWs& ws, uint64_t k) {
 // Pass 1 over ops [0, n) (n <= ws.chunk): upserts (ops[i] == OP_UPSERT, valid key)
 // are merged; op_ent receives each operation's entry or MERGE_NONE.
 template <typename K>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(MERGE_THREADS)
 k_merge_build(MergeWs ws, const uint8_t* __restrict__ ops, const K* __restrict__ keys,
               const K* __restrict__ vals, uint64_t n, int combine) {
   __shared__ uint64_t lkey[MERGE_LDS];
   __shared__ uint64_t lacc[MERGE_LDS];
   __shared__ uint32_t llead[MERGE_LDS];
   __shared__ uint32_t lgent[MERGE_LDS];
-  constexpr int PER = MERGE_BLOCK_OPS / 256;
+  constexpr int PER = MERGE_BLOCK_OPS / MERGE_THREADS;
   const uint32_t tid = threadIdx.x;
   for (uint64_t c0 = (uint64_t)blockIdx.x * MERGE_BLOCK_OPS; c0 < n; c0 += (uint64_t)gridDim.x * MERGE_BLOCK_OPS) {
-    for (uint32_t e = tid; e < MERGE_LDS; e += 256) {
+    for (uint32_t e = tid; e < MERGE_LDS; e += MERGE_THREADS) {
       lkey[e] = ~0ull;
       lacc[e] = 0;
       llead[e] = 0;
@@ -123,7 +123,7 @@ k_merge_build(MergeWs ws, const uint8_t* __restrict__ ops, const K* __restrict__
     int32_t le[PER];
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const uint64_t i = c0 + (uint64_t)r * 256 + tid;
+      const uint64_t i = c0 + (uint64_t)r * MERGE_THREADS + tid;
       le[r] = -1;
       if (i >= n || ops[i] != OP_UPSERT) continue;
       const K kk = keys[i];
@@ -157,7 +157,7 @@ k_merge_build(MergeWs ws, const uint8_t* __restrict__ ops, const K* __restrict__
       }
     }
     __syncthreads();
-    for (uint32_t e = tid; e < MERGE_LDS; e += 256) {
+    for (uint32_t e = tid; e < MERGE_LDS; e += MERGE_THREADS) {
       const uint64_t k = lkey[e];
       if (k == ~0ull) continue;
       const uint32_t g = merge_slot(ws, k);
@@ -166,11 +166,15 @@ k_merge_build(MergeWs ws, const uint8_t* __restrict__ ops, const K* __restrict__
       __hip_atomic_fetch_max(&ws.ent[g].lead, llead[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
+    // an operation that did not lead its key in this block follows for sure:
+    // marked now, it skips the merge table in pass 2
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const uint64_t i = c0 + (uint64_t)r * 256 + tid;
+      const uint64_t i = c0 + (uint64_t)r * MERGE_THREADS + tid;
       if (i >= n || le[r] == -2) continue;
-      ws.op_ent[i] = le[r] >= 0 ? lgent[le[r]] : MERGE_NONE;
+      uint32_t v = MERGE_NONE;
+      if (le[r] >= 0) v = lgent[le[r]] | (llead[le[r]] == merge_lead_code(ws, i) ? 0u : MERGE_FOLLOWER);
+      ws.op_ent[i] = v;
     }
     __syncthreads();
   }
@@ -185,6 +189,7 @@ __device__ __forceinline__ bool merge_take(const MergeWs& ws, const Tile<T>& til
   const uint32_t e = ws.op_ent[j];
   *entry = e;
   if (e == MERGE_NONE) return true;  // not merged (invalid key): the table op reports it
+  if (e & MERGE_FOLLOWER) return false;  // marked in pass 1
   const MergeEntry m = ws.ent[e];
   if (m.lead != merge_lead_code(ws, j)) {
     if (tile.leader()) ws.op_ent[j] = e | MERGE_FOLLOWER;

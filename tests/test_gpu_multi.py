@@ -37,6 +37,32 @@ def test_menus_match_library():
     assert not hw.multi_supported(32, "CUCKOO", 8, 4)
 
 
+def test_multi_upsert_tables_with_device_offsets():
+    """The table-array form with device offsets (hwave_multi_upsert_tables): the
+    same group-by as a group's call, twice in a row on the same tables (the
+    library reuses its group), equal to the oracle's sums table by table."""
+    n = 12
+    exps = w.table_exponents(n, 9, 13, workload_id=43)
+    cfgs = [MENU32[i % len(MENU32)] for i in range(n)]
+    offsets, keys, vals = w.groupby_tables(exps, 0.6, workload_id=43)
+    A = [hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t) for e, (d, b, t) in zip(exps, cfgs)]
+    kd = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    od = torch.from_numpy(np.asarray(offsets, dtype=np.int64)).cuda()
+    for rnd in range(2):
+        st = u8(hw.multi_upsert_tables(A, od, kd, vd, combine="sum"))
+        assert ((st == hw.ST_DONE) | (st == hw.ST_EXISTED)).all()
+    for i in range(n):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        om = oracle.OracleMap(key_bits=32)
+        kk, vv = keys[a:b].astype(np.uint64), vals[a:b].astype(np.uint64)
+        om.upsert(kk, vv)
+        om.upsert(kk, vv)
+        k, v = _dump(A[i])
+        ok, ov = om.dump()
+        assert np.array_equal(k, ok) and np.array_equal(v, ov), i
+
+
 @pytest.mark.parametrize("flags", [0, hw.F_NO_ERASE], ids=["locked", "noerase"])
 def test_multi_groupby_equals_plain_and_oracle(flags):
     n = 2 * len(MENU32) * 3
