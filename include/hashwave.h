@@ -94,7 +94,8 @@ enum {
   HWAVE_ENOMEM = -2,      /* device allocation failed or buffer too small          */
   HWAVE_EDEVICE = -3,     /* a HIP call failed; see hwave_last_hip_error()         */
   HWAVE_EUNSUPPORTED = -4, /* no kernel instance for this design/width/bucket/tile */
-  HWAVE_EIO = -5           /* a file could not be opened, read or written, or is malformed */
+  HWAVE_EIO = -5,          /* a file could not be opened, read or written, or is malformed */
+  HWAVE_ETOOBIG = -6       /* batch larger than hwave_mixed_noalloc's fixed workspace  */
 };
 
 /* Flags of hwave_config.flags. */
@@ -249,6 +250,23 @@ int hwave_erase(hwave_table* t, const void* d_keys, uint64_t n, uint8_t* d_found
 int hwave_mixed(hwave_table* t, const uint8_t* d_ops, const void* d_keys, const void* d_vals,
                 uint64_t n, hwave_combine combine, void* d_vals_out, uint8_t* d_status,
                 void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): hwave_mixed with the
+ * upserts merged by key as on a HWAVE_F_MERGE_MIXED table, whatever the table's
+ * flags, using a workspace in a fixed device array instead of one the library
+ * allocates.  Calls no allocating routine.  Limit: n <= 262,144 (2^18)
+ * operations, else HWAVE_ETOOBIG and nothing is enqueued.  The array (14 MiB:
+ * 2^19 merge entries of 24 bytes and a 4-byte word per operation) is held by
+ * each device the library runs on until the process ends; the first call on a
+ * device looks up its address.  Every call on a device shares that array and
+ * clears it (with a kernel) before use: calls on one device that overlap in
+ * time (other streams, other host threads) race and must not be issued.  The
+ * table's device must be current.  Results equal those of hwave_mixed on a
+ * table with HWAVE_F_MERGE_MIXED. */
+int hwave_mixed_noalloc(hwave_table* t, const uint8_t* d_ops, const void* d_keys, const void* d_vals,
+                        uint64_t n, hwave_combine combine, void* d_vals_out, uint8_t* d_status,
+                        void* stream);
 
 /* Writes the number of live keys to *d_count (one uint64_t on the device). */
 int hwave_size(hwave_table* t, uint64_t* d_count, void* stream);

@@ -116,6 +116,7 @@ def _bind(L):
         "hwave_query": (I, [P, P, U64, P, P, P]),
         "hwave_erase": (I, [P, P, U64, P, P]),
         "hwave_mixed": (I, [P, P, P, P, U64, I, P, P, P]),
+        "hwave_mixed_noalloc": (I, [P, P, P, P, U64, I, P, P, P]),
         "hwave_size": (I, [P, P, P]),
         "hwave_export": (I, [P, P, P, P, P]),
         "hwave_num_buckets": (U64, [P]),
@@ -279,6 +280,17 @@ class Table:
         _check(self._L.hwave_mixed(self.h, _ptr(ops), _ptr(self._keys(keys)),
                                  None if vals is None else _ptr(self._keys(vals)), n,
                                  COMBINES[combine], _ptr(out), _ptr(status), _stream(stream)))
+        return status, out
+
+    def mixed_noalloc(self, ops, keys, vals, combine="sum", out=None, status=None, stream=None):
+        """hwave_mixed_noalloc: a mixed call with upserts merged by key in the
+        library's fixed device workspace (at most 2^18 operations)."""
+        n = keys.numel()
+        out = self._empty(n) if out is None else out
+        status = self._u8(n) if status is None else status
+        _check(self._L.hwave_mixed_noalloc(self.h, _ptr(ops), _ptr(self._keys(keys)),
+                                         None if vals is None else _ptr(self._keys(vals)), n,
+                                         COMBINES[combine], _ptr(out), _ptr(status), _stream(stream)))
         return status, out
 
     def size(self, stream=None) -> int:

@@ -520,6 +520,79 @@ int hwave_mixed(hwave_table* t, const uint8_t* d_ops, const void* d_keys, const 
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The workspace of hwave_mixed_noalloc: one merge workspace (hw_merge.hpp) for
+// chunks of NOALLOC_OPS operations, in a fixed device array that each device
+// holds for the life of the process.  In host code `scratch` names a host-side
+// stand-in, never the device memory: its device address comes from
+// hipGetSymbolAddress, once per device (noalloc_ws), and only that address is
+// ever given to kernels.
+constexpr uint32_t NOALLOC_OPS = 1u << 18;
+constexpr uint64_t NOALLOC_ENTRIES = 2ull * NOALLOC_OPS;
+constexpr uint64_t NOALLOC_ZERO_BYTES = NOALLOC_ENTRIES * (8 + sizeof(MergeEntry));  // key words + entries
+constexpr uint64_t NOALLOC_BYTES = NOALLOC_ZERO_BYTES + (uint64_t)NOALLOC_OPS * 4;  // + per-op words
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64];
+
+// Device address of this device's `scratch`, looked up on the first call per
+// device (with that device current).  NULL on failure (*err set).
+uint8_t* noalloc_base(int device, hipError_t* err) {
+  if (device < 0 || device >= 64) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    g_noalloc_ptr[device] = ptr;
+  }
+  return (uint8_t*)g_noalloc_ptr[device];
+}
+
+}  // namespace
+
+extern "C" {
+
+int hwave_mixed_noalloc(hwave_table* t, const uint8_t* d_ops, const void* d_keys, const void* d_vals, uint64_t n,
+                        hwave_combine combine, void* d_vals_out, uint8_t* d_status, void* stream) {
+  if (!t || (int)combine < HWAVE_SUM || (int)combine > HWAVE_MAX) return HWAVE_EINVAL;
+  if (n > NOALLOC_OPS) return HWAVE_ETOOBIG;
+  if (n == 0) return HWAVE_OK;
+  if (bad_ptr(d_ops) || bad_ptr(d_keys)) return HWAVE_EINVAL;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e);
+  if (cur != t->device) return HWAVE_EINVAL;  // the table's device must be current
+  uint8_t* base = noalloc_base(cur, &e);
+  if (!base) return hip_fail(e);
+  MergeWs ws;
+  ws.key = (uint64_t*)base;
+  ws.ent = (MergeEntry*)(base + NOALLOC_ENTRIES * 8);
+  ws.op_ent = (uint32_t*)(base + NOALLOC_ZERO_BYTES);
+  ws.ne_mask = (uint32_t)(NOALLOC_ENTRIES - 1);
+  ws.chunk = NOALLOC_OPS;
+  hipStream_t s = (hipStream_t)stream;
+  // the array keeps the last call's contents: the entries must start empty (all
+  // zero); a fill kernel, not a memset, so the call can be captured in a graph
+  hipLaunchKernelGGL(k_fill16, dim3(stream_grid(NOALLOC_ZERO_BYTES / 16, cur)), dim3(256), 0, s, (uint4*)base,
+                     NOALLOC_ZERO_BYTES / 16, 0u);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  const void* vals = d_vals ? d_vals : d_keys;
+  e = t->ks->mixed(t->la, d_ops, d_keys, vals, n, (int)combine, d_vals_out, d_status, &ws, s);
+  return e == hipSuccess ? HWAVE_OK : hip_fail(e);
+}
+
 int hwave_size(hwave_table* t, uint64_t* d_count, void* stream) {
   if (!t || !d_count) return HWAVE_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -629,6 +702,7 @@ const char* hwave_strerror(int code) {
     case HWAVE_EDEVICE: return "HIP error (see hwave_last_hip_error)";
     case HWAVE_EUNSUPPORTED: return "no kernel instance for this configuration";
     case HWAVE_EIO: return "file could not be read or written, or is malformed";
+    case HWAVE_ETOOBIG: return "batch larger than the allocation-free call's fixed workspace";
   }
   return "unknown error";
 }
