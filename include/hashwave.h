@@ -82,9 +82,9 @@ enum {
                             lock_timeout_us for the key's bucket lock, or saw
                             that another operation of the table had; the op
                             had no effect.  A failure report, not a result: the
-                            abandoned ticket leaves that bucket's lock unusable,
-                            so later writers of the bucket time out as well,
-                            until hwave_clear empties the table               */
+                            abandoned ticket blocks its lock queue, so later
+                            writers that find a bucket of that queue busy time
+                            out as well, until hwave_clear empties the table  */
 };
 
 /* Return codes. */
@@ -182,18 +182,18 @@ typedef struct {
   uint32_t flags;        /* HWAVE_F_*                                         */
   uint32_t lock_timeout_us; /* longest wait of one operation for its bucket's
                            lock, in microseconds (0 = 10 s; at most 40 s, else
-                           HWAVE_EINVAL).  Bucket locks are FIFO ticket locks
-                           (Section 4.1 serialises a key's writers on its
-                           primary bucket's lock), so a wait is bounded by the
-                           operations queued ahead times one critical section;
-                           an operation still waiting at the limit gives up
-                           with HWAVE_ST_TIMEOUT (see there)                   */
+                           HWAVE_EINVAL).  Section 4.1 serialises a key's
+                           writers on its primary bucket's lock; writers that
+                           find it held wait in a FIFO ticket queue, so a wait
+                           is bounded by the operations queued ahead times one
+                           critical section; an operation still waiting at the
+                           limit gives up with HWAVE_ST_TIMEOUT (see there)    */
 } hwave_config;
 
 /* Fills *out with the design's defaults.  Returns HWAVE_OK or HWAVE_EINVAL. */
 int hwave_config_default(hwave_design design, hwave_config* out);
 
-/* Device bytes a table needs (slots + tags + lock words + control word) for a
+/* Device bytes a table needs (slots + tags + lock bytes and queues + control words) for a
  * capacity rounded up to bucket_slots * 2^k slots.  Host-only arithmetic. */
 int hwave_table_bytes(uint64_t capacity_slots, hwave_design design, const hwave_config* cfg,
                       uint64_t* bytes);
@@ -303,9 +303,14 @@ typedef struct {
                            8 16-byte units, unit 7 the link (empty key word,
                            next node index or all-ones in the value word)     */
   uint16_t* tags;       /* capacity 16-bit tags, or NULL without tags             */
-  uint32_t* locks;      /* bucket b's lock: 32-bit words 2b (ticket being served)
-                           and 2b + 1 (next ticket); free when equal           */
-  uint64_t n_lock_words; /* 32-bit words: 2 per bucket                           */
+  uint32_t* locks;      /* bucket b's lock: byte b (byte b % 4 of 32-bit word
+                           b / 4), nonzero while held (Section 5.1)            */
+  uint64_t n_lock_words; /* 32-bit words of lock bytes: ceil(buckets / 4)        */
+  uint64_t* lock_queues; /* ticket queues of contended acquires: per word, next
+                           ticket (high 32 bits) and ticket being served (low
+                           32 bits); idle when equal.  Bucket b queues on word
+                           b mod n_lock_queues                                 */
+  uint64_t n_lock_queues; /* a power of two                                     */
   uint64_t num_buckets;
   uint32_t bucket_slots, tile, kv_bits, design;
   uint64_t slot_bytes;  /* bytes of the slot region (chaining: every node)     */

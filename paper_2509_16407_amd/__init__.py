@@ -76,7 +76,8 @@ class _ServeStats(ctypes.Structure):
 
 class _Raw(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_void_p), ("tags", ctypes.c_void_p), ("locks", ctypes.c_void_p),
-                ("n_lock_words", ctypes.c_uint64), ("num_buckets", ctypes.c_uint64),
+                ("n_lock_words", ctypes.c_uint64), ("lock_queues", ctypes.c_void_p),
+                ("n_lock_queues", ctypes.c_uint64), ("num_buckets", ctypes.c_uint64),
                 ("bucket_slots", ctypes.c_uint32), ("tile", ctypes.c_uint32),
                 ("kv_bits", ctypes.c_uint32), ("design", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint64)]
 
@@ -332,7 +333,8 @@ class Table:
         return {"queries": c.queries, "bucket_lines": c.bucket_lines, "slot_lines": c.slot_lines}
 
     def raw(self):
-        """Views of the raw device image: dict(slots=uint8, tags=int16 or None, locks=int32)."""
+        """Views of the raw device image: dict(slots=uint8, tags=int16 or None, locks=int32 words of
+        lock bytes, lock_queues=int64 ticket words)."""
         import torch
         base = self.buffer.data_ptr()
         r = self._raw
@@ -345,6 +347,8 @@ class Table:
             out["tags"] = None
         off = r.locks - base
         out["locks"] = self.buffer[off: off + 4 * r.n_lock_words].view(torch.int32)
+        off = r.lock_queues - base
+        out["lock_queues"] = self.buffer[off: off + 8 * r.n_lock_queues].view(torch.int64)
         return out
 
 

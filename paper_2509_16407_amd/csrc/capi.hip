@@ -51,9 +51,23 @@ uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   uint64_t nb, capacity, units, pool;
-  uint64_t off_tags, off_locks, off_ctrl, off_pool_ctr, off_hot, off_merge, total;
-  uint64_t n_lock_words;
+  uint64_t off_tags, off_locks, off_lockq, off_ctrl, off_pool_ctr, off_hot, off_merge, total;
+  uint64_t n_lock_words;  // 32-bit words of lock bytes (one byte per bucket)
+  uint64_t n_lockq;       // lock queues (hw_device.hpp): a power of two
 };
+
+// Lock bytes, then the lock queues: the largest power of two <= nb, at most
+// LOCK_QUEUES_MAX.  Returns the offset after them.
+uint64_t place_locks(uint64_t nb, uint64_t off, Layout* L) {
+  L->off_locks = off;
+  L->n_lock_words = (nb + 3) / 4;
+  off += round_up(L->n_lock_words * 4, ALIGN);
+  uint64_t nq = 1;
+  while (nq * 2 <= nb && nq * 2 <= LOCK_QUEUES_MAX) nq *= 2;
+  L->off_lockq = off;
+  L->n_lockq = nq;
+  return off + round_up(nq * 8, ALIGN);
+}
 
 // Hot-key accumulators (hw_ops.hpp, HOT_ROWS): tables that merge duplicates and
 // never erase, except cuckoo (it moves keys) and the phased variant.
@@ -169,9 +183,7 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
     L->capacity = (nb + pool) * 7;
     uint64_t off = round_up(L->units * 16, ALIGN);
     L->off_tags = off;
-    L->off_locks = off;
-    L->n_lock_words = 2 * nb;  // one 64-bit ticket-lock word per bucket
-    off += round_up(L->n_lock_words * 4, ALIGN);
+    off = place_locks(nb, off, L);
     L->off_ctrl = off;
     off += ALIGN;
     L->off_pool_ctr = off;  // POOL_PARTS allocation counters, one per 128-byte line
@@ -192,9 +204,7 @@ int layout_of(uint64_t capacity, hwave_design design, const hwave_config& c, Lay
   uint64_t off = round_up(L->capacity * slot_bytes, ALIGN);
   L->off_tags = off;
   if (design_tags(design)) off += round_up(L->capacity * 2, ALIGN);
-  L->off_locks = off;
-  L->n_lock_words = 2 * nb;  // one 64-bit ticket-lock word per bucket
-  off += round_up(L->n_lock_words * 4, ALIGN);
+  off = place_locks(nb, off, L);
   L->off_ctrl = off;
   off += ALIGN;
   L->total = place_hot(design, c, off, L);
@@ -320,7 +330,9 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   TableDev& tv = t->la.tv;
   tv.slots = b;
   tv.tagw = design_tags(design) ? (uint32_t*)(b + L.off_tags) : nullptr;
-  tv.locks = (uint64_t*)(b + L.off_locks);
+  tv.locks = (uint32_t*)(b + L.off_locks);
+  tv.lockq = (uint64_t*)(b + L.off_lockq);
+  tv.lockq_mask = (uint32_t)(L.n_lockq - 1);
   tv.ctrl = (uint32_t*)(b + L.off_ctrl);
   tv.bucket_mask = (uint32_t)(L.nb - 1);
   tv.nb_front = design_iceberg(design) ? (uint32_t)iceberg_front(L.nb) : (uint32_t)L.nb;
@@ -685,6 +697,8 @@ int hwave_raw(const hwave_table* t, hwave_raw_view* out) {
   out->tags = (uint16_t*)t->la.tv.tagw;
   out->locks = (uint32_t*)t->la.tv.locks;
   out->n_lock_words = t->n_lock_words;
+  out->lock_queues = t->la.tv.lockq;
+  out->n_lock_queues = (uint64_t)t->la.tv.lockq_mask + 1;
   out->num_buckets = t->nb;
   out->bucket_slots = t->cfg.bucket_slots;
   out->tile = t->cfg.tile;

@@ -175,121 +175,137 @@ __device__ __forceinline__ X cas(X* p, X expected, X desired) {
 
 // ------------------------------------------------------------------ locks
 //
-// One lock per bucket (the paper keeps one lock bit per bucket in an external
-// array, Section 5.1), here a ticket lock with proportional back-off
-// (Mellor-Crummey and Scott, ACM TOCS 9(1), 1991) in one 64-bit word per bucket:
-// the high half is the next ticket, the low half the ticket being served, and
-// the lock is free when the two are equal.
+// One lock byte per bucket in an external array (the paper keeps one lock bit
+// per bucket there, Section 5.1; a byte makes the release a plain store): byte
+// b % 4 of 32-bit word b / 4, nonzero while held.  The array is small (1 byte
+// per 32 slots at bucket size 32: 8 MB for 2^28 slots), so most of it stays in
+// the last-level cache between operations; per-bucket 64-bit ticket words would
+// take 8 bytes per bucket and cost ~8% of a write-heavy batch's time in lock
+// misses.
 //
-//  * Taking the lock is one 64-bit atomic add of 2^32: it returns the word as it
-//    was, so an uncontended acquire costs one atomic, as a test-and-set would.
-//    Carries out of the high half fall off the word; they never reach the low one.
-//  * Releasing it is a 32-bit store of (own ticket + 1) into the low half, after
-//    every write of the critical section has completed.  Only the holder writes
-//    the low half.
-//  * A waiter d tickets behind the one being served reads the low half again
-//    after about d - 1 critical sections, so the waiters' reads stay spread out.
+//  * Uncontended acquire: one atomic OR of the bucket's bit pattern into its
+//    word.  It returns the word as it was: the byte was clear, so the lock is
+//    ours.  Release: a byte store of 0, after every write of the critical
+//    section has completed.
+//  * Contended acquire (the OR found the byte set): the tile retries a few
+//    times (LOCK_SPINS), each after a growing pause and only when the byte
+//    reads clear -- a lock held by one other tile is usually free within a
+//    critical section.  Then it queues on one of the table's lock queues,
+//    ticket locks with proportional back-off
+//    (Mellor-Crummey and Scott, ACM TOCS 9(1), 1991) in 64-bit words (high
+//    half: next ticket; low half: ticket being served), queue b mod the queue
+//    count.  A waiter d tickets behind the one being served reads the serving
+//    half again after about d - 1 critical sections.  When its turn comes it is
+//    the only queued tile of that queue: it tries the OR on its bucket's byte
+//    every LOCK_FIRST_TICKS until the byte was clear, and then passes the queue
+//    on at once (stores its ticket + 1), so that the next tile in line polls
+//    during its critical section and takes the byte soon after the release.
 //
-// Why not test-and-set: one address of MI355X memory serves ~80 M requests per
-// second.  With test-and-set every waiter keeps an atomic (or, polling, a load)
-// queued at the lock word, and each release waits behind all of them: with 2^16
-// tiles on one bucket a hand-off costs ~0.8 ms.  Ticket waiters issue no
-// read-modify-write and poll rarely, so a hand-off costs one critical section
-// plus a short poll delay, and service is first come first served.
+// Why queue at all: one address of MI355X memory serves ~80 M requests per
+// second.  If every waiter kept retrying the byte (test-and-set, even with
+// back-off), its requests would queue at the lock word ahead of each release:
+// with 2^16 tiles on one bucket a hand-off costs ~0.8 ms.  Queued waiters
+// issue no read-modify-write and poll rarely; one tile per queue polls the
+// byte, so a hand-off costs one critical section plus a short poll delay, in
+// arrival order (new arrivals may take a free byte ahead of the queue during
+// their few retries).
 //
-// A ticket cannot be given back, so a waiter never leaves the queue -- except
-// when its wait exceeds the table's time limit, a failure that the lock protocol
-// itself never produces (FIFO service bounds every wait by the waiters ahead of
-// it times one critical section).  Such an operation reports ST_TIMEOUT and sets
+// A ticket cannot be given back, so a queued waiter never leaves the queue --
+// except when its wait exceeds the table's time limit, a failure that the lock
+// protocol itself never produces (a wait is bounded by the waiters ahead of it
+// times one critical section).  Such an operation reports ST_TIMEOUT and sets
 // the table's failure flag; every waiter that sees the flag gives up too, so the
-// kernel still ends.  The table's lock state is then undefined.
+// kernel still ends.  The abandoned ticket blocks its queue until the table is
+// cleared; the lock bytes themselves are never abandoned (a tile holds one only
+// inside its critical section).
 
-// Wall clock of the chip: 100 MHz (s_memrealtime).
-__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+// Wall clock of the chip: 100 MHz (s_memrealtime), low 32 bits.  They wrap
+// every ~43 s; waits are compared as differences, and a wait never exceeds
+// the time limit (at most 40 s).
+__device__ __forceinline__ uint32_t now_ticks() { return (uint32_t)__builtin_amdgcn_s_memrealtime(); }
 
-constexpr uint32_t LOCK_UNIT_TICKS = 100;  // 1 us: assumed critical section per ticket ahead
-constexpr uint32_t LOCK_FIRST_TICKS = 25;  // 0.25 us: next in line polls this often
-constexpr uint32_t LOCK_FLAG_WORD = 32;    // ctrl word of the failure flag (its own 128-byte line)
+// Whether tick `t` has been reached at `now` (within 2^31 ticks of it).
+__device__ __forceinline__ bool ticks_reached(uint32_t now, uint32_t t) { return (int32_t)(now - t) >= 0; }
 
-__device__ __forceinline__ uint32_t* serving_of(uint64_t* locks, uint32_t b) { return (uint32_t*)(locks + b); }
+constexpr uint32_t LOCK_UNIT_TICKS = 100;   // 1 us: assumed critical section per ticket ahead
+constexpr uint32_t LOCK_FIRST_TICKS = 25;   // 0.25 us: the head of a queue tries its byte this often
+constexpr uint32_t LOCK_FLAG_WORD = 32;     // ctrl word of the failure flag (its own 128-byte line)
+constexpr uint32_t LOCK_QUEUES_MAX = 1u << 14;  // lock queues of a large table (128 KB)
+constexpr uint32_t LOCK_SPINS = 4;               // retries of a held byte before queueing
 
-// Leader lane takes a ticket for bucket b; every lane of the tile gets the
-// word as it was (high half: our ticket; low half: the ticket being served).
+__device__ __forceinline__ uint32_t lock_pattern(uint32_t b) { return 1u << ((b & 3u) * 8u); }
+
+// Leader lane ORs bucket b's lock byte; every lane learns whether it was clear
+// (then the tile holds the lock).
 template <int T>
-__device__ __forceinline__ uint64_t take_ticket(uint64_t* locks, uint32_t b, const Tile<T>& tile) {
-  uint64_t old = 0;
+__device__ __forceinline__ bool try_lock(uint32_t* locks, uint32_t b, const Tile<T>& tile) {
+  uint32_t old = 0;
   if (tile.leader()) {
 #ifdef HW_STRICT_ORDER
-    old = __hip_atomic_fetch_add(locks + b, (uint64_t)1 << 32, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    old = __hip_atomic_fetch_or(locks + (b >> 2), lock_pattern(b), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 #else
-    old = __hip_atomic_fetch_add(locks + b, (uint64_t)1 << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    old = __hip_atomic_fetch_or(locks + (b >> 2), lock_pattern(b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #endif
   }
+  return (tile.bcast(old, 0) & lock_pattern(b)) == 0;
+}
+
+// Whether bucket b's lock byte currently reads clear (a coherent load; no atomic).
+template <int T>
+__device__ __forceinline__ bool lock_looks_free(uint32_t* locks, uint32_t b, const Tile<T>& tile) {
+  uint32_t v = 0;
+  if (tile.leader()) v = ld((const uint8_t*)locks + b);
+  return tile.bcast(v, 0) == 0;
+}
+
+// Leader lane clears bucket b's lock byte.  The caller has waited for the
+// critical section's writes (wait_mem), or uses the strict-order build.
+__device__ __forceinline__ void release_try_lock(uint32_t* locks, uint32_t b) {
+#ifdef HW_STRICT_ORDER
+  __hip_atomic_store((uint8_t*)locks + b, (uint8_t)0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+#else
+  st((uint8_t*)locks + b, (uint8_t)0);
+#endif
+}
+
+// Leader lane takes a ticket of lock queue q; every lane of the tile gets the
+// word as it was (high half: our ticket; low half: the ticket being served).
+template <int T>
+__device__ __forceinline__ uint64_t take_ticket(uint64_t* queues, uint32_t q, const Tile<T>& tile) {
+  uint64_t old = 0;
+  if (tile.leader())
+    old = __hip_atomic_fetch_add(queues + q, (uint64_t)1 << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return tile.bcast(old, 0);
 }
 
-// The ticket bucket b is serving now (a coherent load; no atomic).
+// The ticket queue q is serving now (a coherent load; no atomic).
 template <int T>
-__device__ __forceinline__ uint32_t read_serving(uint64_t* locks, uint32_t b, const Tile<T>& tile) {
+__device__ __forceinline__ uint32_t read_serving(uint64_t* queues, uint32_t q, const Tile<T>& tile) {
   uint32_t s = 0;
-  if (tile.leader()) {
-#ifdef HW_STRICT_ORDER
-    s = __hip_atomic_load(serving_of(locks, b), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-#else
-    s = ld(serving_of(locks, b));
-#endif
-  }
+  if (tile.leader()) s = ld((const uint32_t*)(queues + q));
   return tile.bcast(s, 0);
+}
+
+// Passes queue q on to the ticket after `mine` (leader lane).
+__device__ __forceinline__ void pass_queue(uint64_t* queues, uint32_t q, uint32_t mine) {
+  st((uint32_t*)(queues + q), mine + 1);
 }
 
 // When a waiter d tickets behind should look again: after d - 1 assumed
 // critical sections, but at least every LOCK_MAX_GAP_TICKS, so that the time
 // limit is checked even far back in a long queue.
-constexpr uint64_t LOCK_MAX_GAP_TICKS = 1u << 20;  // ~10 ms
-__device__ __forceinline__ uint64_t next_look(uint64_t now, uint32_t d) {
-  const uint64_t gap = (uint64_t)(d - 1) * LOCK_UNIT_TICKS;
-  return now + (gap < LOCK_MAX_GAP_TICKS ? gap : LOCK_MAX_GAP_TICKS) + LOCK_FIRST_TICKS;
-}
-
-// Releases bucket b, held with ticket `mine`, after every write of the critical
-// section has completed.
-template <int T>
-__device__ __forceinline__ void unlock(uint64_t* locks, uint32_t b, uint32_t mine, const Tile<T>& tile) {
-#ifdef HW_STRICT_ORDER
-  if (tile.leader())
-    __hip_atomic_store(serving_of(locks, b), mine + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-#else
-  wait_mem();
-  if (tile.leader()) st(serving_of(locks, b), mine + 1);
-#endif
+constexpr uint32_t LOCK_MAX_GAP_TICKS = 1u << 20;  // ~10 ms
+__device__ __forceinline__ uint32_t next_look(uint32_t now, uint32_t d) {
+  const uint32_t ahead = d - 1;
+  const uint32_t gap = ahead < LOCK_MAX_GAP_TICKS / LOCK_UNIT_TICKS ? ahead * LOCK_UNIT_TICKS : LOCK_MAX_GAP_TICKS;
+  return now + gap + LOCK_FIRST_TICKS;
 }
 
 // Cuckoo operations hold all three of their buckets' locks at once and take
-// them with try-locks (test-and-set on the low half of the lock word: bit 0 set
-// = held; the high half stays 0), so a tile that misses one releases the others
-// and never waits while holding a lock.  A waiting tile reads the word first and
-// tries the atomic only when it reads free (or on every 256th attempt).
-
-// Leader lane sets bucket b's lock bit; every lane learns whether it was free.
-template <int T>
-__device__ __forceinline__ bool try_lock(uint64_t* locks, uint32_t b, const Tile<T>& tile) {
-  uint32_t old = 0;
-  if (tile.leader())
-    old = __hip_atomic_fetch_or(serving_of(locks, b), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return (tile.bcast(old, 0) & 1u) == 0;
-}
-
-// Whether bucket b's try-lock currently reads free (a coherent load; no atomic).
-template <int T>
-__device__ __forceinline__ bool lock_looks_free(uint64_t* locks, uint32_t b, const Tile<T>& tile) {
-  uint32_t w = 0;
-  if (tile.leader()) w = ld(serving_of(locks, b));
-  return tile.bcast(w, 0) == 0;
-}
-
-// Releases a try-lock (leader lane), after the caller has waited for the
-// critical section's writes.
-__device__ __forceinline__ void release_try_lock(uint64_t* locks, uint32_t b) { st(serving_of(locks, b), 0u); }
+// them with try_lock alone (no queue), so a tile that misses one releases the
+// others and never waits while holding a lock.  A waiting tile reads the bytes
+// first and tries the atomics only when they read clear (or on every 256th
+// attempt).
 
 // Back-off between failed try-lock attempts: a pause that doubles from 128
 // cycles up to ~3.4 us (64 x 128 cycles).

@@ -71,7 +71,8 @@ enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, 
 struct TableDev {
   void* slots;           // (key, value) pairs, bucket-major
   uint32_t* tagw;        // 16-bit tags viewed as 32-bit words; null without tags
-  uint64_t* locks;       // one ticket-lock word per bucket (hw_device.hpp)
+  uint32_t* locks;       // one lock byte per bucket (hw_device.hpp)
+  uint64_t* lockq;       // lock queues: lockq_mask + 1 ticket words
   uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice, iceberg);
                          // ctrl[LOCK_FLAG_WORD]: a lock wait timed out
   uint32_t bucket_mask;  // buckets - 1 (a power of two minus one)
@@ -84,6 +85,7 @@ struct TableDev {
   uint32_t no_erase;     // table never erases: present keys are combined without the lock
   uint32_t aggregate;    // merge duplicate keys of a write batch first (hw_agg.hpp)
   uint32_t lock_limit;   // longest wait for a bucket lock, in 100 MHz ticks
+  uint32_t lockq_mask;   // lock queues - 1 (a power of two minus one); bucket b queues on b & lockq_mask
   uint64_t* hot_tag;     // HOT_N entry tags, or null (see HOT_ROWS)
   uint64_t* hot_acc;     // HOT_N accumulators
   unsigned long long* probe_ctr;  // instrumented builds: PROBE_STRIPES query probe counters; else null
@@ -901,48 +903,73 @@ struct Ops {
   // ST_TIMEOUT when the wait outlasted the table's limit or another waiter of
   // the table reported such a failure (checked on every 16th look).
   //
-  // The tile takes a ticket, then looks at the serving counter at times spaced
-  // by its place in the queue.  The critical section runs inside the waiting
-  // loop, in the iteration whose look found the tile's turn, so tiles of one
-  // wave that wait on each other cannot deadlock: lanes of a wave run in
-  // lockstep, and a tile whose turn has come finishes and releases in the same
-  // iteration as the others go on waiting.
+  // The tile tries the lock byte; if it is held, it retries up to LOCK_SPINS
+  // times, each after a growing pause and only when the byte reads clear (a
+  // lock held by one other tile is usually free again within a critical
+  // section).  Then it takes a ticket of the bucket's lock queue, looks at the
+  // serving counter at times spaced by its place in the queue, and once at the
+  // head tries the byte until it takes it, then passes the queue on.
+  //
+  // Lanes of a wave run in lockstep, so every tile of the wave goes round this
+  // loop until the last one is done.  The critical section comes first in each
+  // round: a tile that holds the lock runs it and releases before any waiting
+  // step of the round, so its lock is not held across other tiles' pauses and
+  // round trips (the retries, the most common wait, come last in the round),
+  // and tiles of one wave that wait on each other cannot deadlock.
   template <class F>
   __device__ static uint8_t locked(const TableDev& tv, const Tile<T>& tile, uint32_t b, F&& cs) {
-    const uint64_t w = take_ticket(tv.locks, b, tile);
-    const uint32_t mine = (uint32_t)(w >> 32);
-    uint32_t served = (uint32_t)w;
-    uint64_t since = 0, look = 0;
-    if (served != mine) {
-      since = now_ticks();
-      look = next_look(since, mine - served);
-    }
-    uint32_t looks = 0;
+    const uint32_t q = b & tv.lockq_mask;
+    bool have = try_lock(tv.locks, b, tile);
+    bool queued = false, head = false;
+    uint32_t spins = 0, mine = 0, served = 0, since = 0, look = 0, looks = 0;
+    Backoff bo;
     uint8_t status = ST_TIMEOUT;
     bool pending = true;
     while (pending) {
-      bool go = served == mine;
-      if (!go) {
-        const uint64_t now = now_ticks();
-        if (now >= look) {
-          served = read_serving(tv.locks, b, tile);
-          go = served == mine;
-          if (!go) {
-            if (now - since > tv.lock_limit || ((++looks & 15) == 0 && lock_failed(tv, tile))) {
-              if (tile.leader()) st(tv.ctrl + LOCK_FLAG_WORD, 1u);
-              pending = false;  // status stays ST_TIMEOUT
+      if (have) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // critical-section accesses after the lock's
+        status = cs();
+#ifndef HW_STRICT_ORDER
+        wait_mem();  // every write of the critical section has completed
+#endif
+        if (tile.leader()) release_try_lock(tv.locks, b);
+        pending = false;
+      } else if (queued) {
+        const uint32_t now = now_ticks();
+        if (ticks_reached(now, look)) {
+          if (!head) {
+            served = read_serving(tv.lockq, q, tile);
+            head = served == mine;
+            if (!head) look = next_look(now, mine - served);
+          }
+          if (head) {
+            have = try_lock(tv.locks, b, tile);
+            if (have) {
+              if (tile.leader()) pass_queue(tv.lockq, q, mine);  // the next head polls during our section
+            } else {
+              look = now + LOCK_FIRST_TICKS;
             }
-            look = next_look(now, mine - served);
+          }
+          if (!have && (now - since > tv.lock_limit || ((++looks & 15) == 0 && lock_failed(tv, tile)))) {
+            if (tile.leader()) st(tv.ctrl + LOCK_FLAG_WORD, 1u);
+            pending = false;  // status stays ST_TIMEOUT
           }
         } else {
           __builtin_amdgcn_s_sleep(2);
         }
-      }
-      if (go) {
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // critical-section accesses after the lock's
-        status = cs();
-        unlock(tv.locks, b, mine, tile);
-        pending = false;
+      } else {
+        bo.grow();
+        bo.pause();
+        have = lock_looks_free(tv.locks, b, tile) && try_lock(tv.locks, b, tile);
+        if (!have && ++spins == LOCK_SPINS) {
+          const uint64_t w = take_ticket(tv.lockq, q, tile);
+          queued = true;
+          mine = (uint32_t)(w >> 32);
+          served = (uint32_t)w;
+          since = now_ticks();
+          head = served == mine;
+          look = head ? since : next_look(since, mine - served);
+        }
       }
     }
     return status;

@@ -23,15 +23,19 @@ def u8(t):
     return t.detach().cpu().numpy().astype(np.uint8)
 
 
-def held_lock_bitmap(lock_words32):
-    """Ticket-lock words (per bucket: the ticket being served, then the next
-    ticket) -> the layout checker's bitmap of held locks (bit b % 64 of 64-bit
-    word b // 64 set when bucket b's lock is held, i.e. the two differ)."""
-    w = np.ascontiguousarray(lock_words32, dtype=np.uint32).reshape(-1, 2)
-    held = w[:, 0] != w[:, 1]
-    packed = np.packbits(held, bitorder="little")
+def held_lock_bitmap(lock_words32, num_buckets):
+    """Lock bytes (byte b of the array: bucket b, nonzero while held) -> the
+    layout checker's bitmap of held locks (bit b % 64 of 64-bit word b // 64)."""
+    by = np.ascontiguousarray(lock_words32, dtype=np.uint32).view(np.uint8)[:num_buckets]
+    packed = np.packbits(by != 0, bitorder="little")
     packed = np.concatenate([packed, np.zeros(-len(packed) % 8, np.uint8)])
     return packed.view(np.uint64)
+
+
+def busy_lock_queues(table):
+    """Number of lock queues with a ticket not yet served (next != serving)."""
+    q = table.raw()["lock_queues"].cpu().numpy().view(np.uint64)
+    return int(((q >> np.uint64(32)) != (q & np.uint64(0xFFFFFFFF))).sum())
 
 
 def image(table):
@@ -40,7 +44,7 @@ def image(table):
     r = table.raw()
     slots = r["slots"].cpu().numpy()
     tags = None if r["tags"] is None else r["tags"].cpu().numpy().view(np.uint16)
-    return slots, tags, held_lock_bitmap(r["locks"].cpu().numpy().view(np.uint32))
+    return slots, tags, held_lock_bitmap(r["locks"].cpu().numpy().view(np.uint32), table.num_buckets)
 
 
 def per_key_counts(keys, status, code):

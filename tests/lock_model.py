@@ -28,6 +28,17 @@ Protocols (`proto`):
                 seconds (at most max_gap + first); the release stores
                 serving + 1.  Waiters never issue a
                 read-modify-write while waiting.
+* "queued"   -- the kernels' lock: a lock byte per bucket plus a ticket queue
+                on a second word.  An atomic OR on the byte; when it finds the
+                byte held, up to `spins` retries (pause as in "poll", a load,
+                the OR when the load reads clear); then a ticket of the queue,
+                waited for as in "ticket"; at the head of the queue, the OR
+                every `first` seconds until it finds the byte clear (one
+                tile per queue does this).  A tile that took the byte through
+                the queue stores serving + 1 into the queue word at once, so
+                the next head polls during its critical section; the release
+                is a store to the byte.  The two words are separate addresses,
+                each with its own service queue.
 
 In the first three the waiters' own requests queue at the address ahead of the
 holder's release, so each hand-off costs about (requests in the queue) / mu; in
@@ -55,14 +66,15 @@ class Result:
 
 
 def simulate(proto: str, waiters: int, ops_per_waiter: int = 1, mu: float = 80e6, lat: float = 0.5e-6,
-             cs: float = 3e-6, unit: float = 1e-6, first: float = 0.25e-6, max_gap: float = 10.48576e-3) -> Result:
+             cs: float = 3e-6, unit: float = 1e-6, first: float = 0.25e-6, max_gap: float = 10.48576e-3,
+             spins: int = 4) -> Result:
     """Runs `waiters` tiles, each doing `ops_per_waiter` locked operations on one
     lock, all starting at time 0, and returns what it took."""
-    assert proto in ("spin", "spin_bo", "poll", "ticket")
+    assert proto in ("spin", "spin_bo", "poll", "ticket", "queued")
     svc = 1.0 / mu
     ev: list = []            # (time, seq, kind, tile, value)
     seq = 0
-    server_free = 0.0
+    server_free = {"byte": 0.0, "queue": 0.0}
     # lock word state, as the address sees it
     held = False
     ticket = 0
@@ -73,8 +85,9 @@ def simulate(proto: str, waiters: int, ops_per_waiter: int = 1, mu: float = 80e6
     attempt = [0] * waiters
     my_ticket = [0] * waiters
     wait_from = [0.0] * waiters
+    via_queue = [False] * waiters
     # queue-length bookkeeping: completion times of requests in service order
-    in_queue: list = []
+    in_queue = {"byte": [], "queue": []}
     peak = 0
     served = 0
     acquisitions = 0
@@ -101,6 +114,7 @@ def simulate(proto: str, waiters: int, ops_per_waiter: int = 1, mu: float = 80e6
         steps[tile] = 0
         attempt[tile] = 0
         wait_from[tile] = t
+        via_queue[tile] = False
         if proto == "ticket":
             request(t, "take", tile)
         else:
@@ -111,6 +125,10 @@ def simulate(proto: str, waiters: int, ops_per_waiter: int = 1, mu: float = 80e6
         nonlocal acquisitions, max_wait
         acquisitions += 1
         max_wait = max(max_wait, t - wait_from[tile])
+        # a tile that came through the queue passes it on at once: the next
+        # head then polls the byte during this critical section
+        if proto == "queued" and via_queue[tile]:
+            request(t, "pass", tile, my_ticket[tile] + 1)
         # critical section, then the release store
         request(t + cs, "release", tile, my_ticket[tile] + 1)
 
@@ -121,21 +139,25 @@ def simulate(proto: str, waiters: int, ops_per_waiter: int = 1, mu: float = 80e6
         t, _, kind, tile, value = heapq.heappop(ev)
         if kind.startswith("arrive:"):
             op = kind[7:]
-            start = max(t, server_free)
-            server_free = start + svc
+            addr = "queue" if (proto == "queued" and op in ("take", "poll", "pass")) else "byte"
+            start = max(t, server_free[addr])
+            server_free[addr] = start + svc
             served += 1
-            while in_queue and in_queue[0] <= t:
-                heapq.heappop(in_queue)
-            heapq.heappush(in_queue, server_free)
-            peak = max(peak, len(in_queue))
-            done = server_free
+            iq = in_queue[addr]
+            while iq and iq[0] <= t:
+                heapq.heappop(iq)
+            heapq.heappush(iq, server_free[addr])
+            peak = max(peak, len(iq))
+            done = server_free[addr]
             # the effect happens in service order, which is arrival order
-            if op == "or":
+            if op in ("or", "hor"):
                 old = held
                 held = True
-                push(done + lat, "ans:or", tile, int(old))
-            elif op == "load":
-                push(done + lat, "ans:load", tile, int(held))
+                push(done + lat, "ans:" + op, tile, int(old))
+            elif op in ("load", "hload"):
+                push(done + lat, "ans:" + op, tile, int(held))
+            elif op == "pass":
+                serving = value
             elif op == "take":
                 my_ticket[tile] = ticket
                 ticket += 1
@@ -156,6 +178,31 @@ def simulate(proto: str, waiters: int, ops_per_waiter: int = 1, mu: float = 80e6
             continue
         if kind == "next":
             start_op(t, tile)
+            continue
+        if proto == "queued":
+            if kind in ("ans:or", "ans:load"):
+                if kind == "ans:or" and value == 0:
+                    acquired(t, tile)
+                elif kind == "ans:load" and value == 0:
+                    request(t, "or", tile)
+                elif attempt[tile] > spins:
+                    request(t, "take", tile)
+                else:
+                    attempt[tile] += 1
+                    grow(tile)
+                    request(t + pause_of(tile), "load", tile)
+            elif kind in ("ans:take", "ans:poll"):
+                d = my_ticket[tile] - value
+                if d == 0:
+                    request(t, "hor", tile)
+                else:
+                    request(t + min((d - 1) * unit, max_gap) + first, "poll", tile)
+            elif kind == "ans:hor":
+                if value == 0:
+                    via_queue[tile] = True
+                    acquired(t, tile)
+                else:
+                    request(t + first, "hor", tile)
             continue
         if proto in ("spin", "spin_bo", "poll"):
             if kind == "ans:or":

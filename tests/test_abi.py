@@ -38,24 +38,26 @@ def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0, flags=0):
                                                     (4, 16, 32), (5, 18, 32)])
 def test_space_per_slot_matches_section_6_1(design, per_slot, bucket):
     """16 bytes per key-value slot, plus 2 bytes of tag in the metadata designs
-    (Section 6.1); on top, one 8-byte ticket-lock word per bucket and a 256-byte
-    control word."""
+    (Section 6.1); on top, one lock byte per bucket (Section 5.1 keeps one lock
+    bit per bucket in an external array), 2^14 eight-byte lock queues and a
+    256-byte control word."""
     slots = 1 << 28
     rc, b = _bytes(slots, design)
     assert rc == 0
-    locks = 8 * (slots // bucket)
-    assert b == slots * per_slot + locks + 256
+    locks = slots // bucket
+    assert b == slots * per_slot + locks + 8 * (1 << 14) + 256
 
 
 def test_chaining_space():
     """Chaining: ceil(capacity / 7) bucket nodes and twice as many pool nodes, 128
-    bytes each (7 pairs and a link, Section 5), one 8-byte ticket-lock word per
-    bucket, and 1024 pool-partition counters, one per 128-byte line."""
+    bytes each (7 pairs and a link, Section 5), one lock byte per bucket, lock
+    queues (the largest power of two <= the bucket count, 8 bytes each), and
+    1024 pool-partition counters, one per 128-byte line."""
     rc, b = _bytes(7 * 1000, 6)
     assert rc == 0
     nb, pool = 1000, 2000
     node_bytes = -(-(nb + pool) * 128 // 256) * 256
-    lock_bytes = -(-(8 * nb) // 256) * 256
+    lock_bytes = -(-nb // 256) * 256 + 512 * 8
     assert b == node_bytes + lock_bytes + 256 + 1024 * 128
     assert _bytes(7 * 1000, 6, kv_bits=32)[0] == -4  # 64-bit keys only
 

@@ -6,11 +6,12 @@ one launch.
   insert Y, whose primary (iceberg: front-yard) bucket is the same bucket and
   whose other candidate bucket has room.  Exactly one copy of Y may result.
 * Same-key storm: 2^16 SUM upserts over 16 keys that all share one primary
-  bucket (every tile of every wave queues for one ticket lock): the launch ends
-  and every sum is exact.  With test-and-set locks this case never finished:
-  the waiters' requests queued at the lock word delayed every release (the CPU
-  model in lock_model.py reproduces it); ticket waiters issue no
-  read-modify-write and poll rarely.
+  bucket (every tile of every wave finds the lock byte held and queues in the
+  bucket's ticket queue): the launch ends and every sum is exact.  With
+  test-and-set locks alone this case never finished: the waiters' requests
+  queued at the lock word delayed every release (the CPU model in
+  lock_model.py reproduces it); queued waiters issue no read-modify-write and
+  poll rarely, and one tile per queue polls the byte.
 * Lock time limit forced from the host: with a 1 us limit, waiters of a storm
   give up with TIMEOUT, the launch ends, and exactly the operations that did
   not time out took effect.
@@ -26,7 +27,7 @@ import torch
 import oracle
 import paper_2509_16407_amd as hw
 from paper_2509_16407_amd import workloads as w
-from gpu_util import dev, host, image, u8
+from gpu_util import busy_lock_queues, dev, host, image, u8
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +48,7 @@ def _layout_ok(t):
     nv, rep = oracle.layout_check(ODESIGN[t.design], t.kv_bits, t.num_buckets, t.bucket_slots,
                                   slots, tags, locks)
     assert nv == 0, rep
+    assert busy_lock_queues(t) == 0  # every ticket taken was served
     return rep
 
 
@@ -179,11 +181,17 @@ def test_lock_time_limit_forced_from_the_host(design):
     o = np.argsort(k)
     okeys, ovals = om.dump()
     assert np.array_equal(k[o], okeys) and np.array_equal(v[o], ovals)
-    # the storm's bucket now holds abandoned tickets: a lone upsert there times
-    # out; after hwave_clear (locks and failure flag reset) it inserts
+    # the storm's queue now holds abandoned tickets, but no lock byte is left
+    # held (a tile holds one only inside its critical section): a lone upsert
+    # takes the byte at once.  hwave_clear resets the queues and the flag.
+    slots, tags, locks = image(t)
+    assert not locks.any()
+    assert busy_lock_queues(t) > 0
     one, v1 = dev(ks[:1]), dev(vs[:1])
-    assert u8(t.upsert(one, v1, combine="sum"))[0] == hw.ST_TIMEOUT
+    present = bool(np.isin(ks[:1], okeys)[0])
+    assert u8(t.upsert(one, v1, combine="sum"))[0] == (hw.ST_EXISTED if present else hw.ST_DONE)
     t.clear()
+    assert busy_lock_queues(t) == 0
     assert u8(t.upsert(one, v1, combine="sum"))[0] == hw.ST_DONE
 
 

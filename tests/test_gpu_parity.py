@@ -14,7 +14,7 @@ import pytest
 import oracle
 import paper_2509_16407_amd as hw
 from paper_2509_16407_amd import workloads as w
-from gpu_util import dev, full_is_genuine, host, image, per_key_counts, u8
+from gpu_util import busy_lock_queues, dev, full_is_genuine, host, image, per_key_counts, u8
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +29,7 @@ def check_layout(t, neg_keys=None, tile_bytes=None):
     nv, rep = oracle.layout_check(ODESIGN[t.design], t.kv_bits, t.num_buckets, t.bucket_slots,
                                   slots, tags, locks, neg_keys=neg_keys, tile_bytes=tb)
     assert nv == 0, rep
+    assert busy_lock_queues(t) == 0  # every ticket taken was served
     return rep
 
 

@@ -12,6 +12,9 @@ address of MI355X memory serves ~80 M requests per second.
 * The ticket lock with proportional back-off keeps the queue short: the batch
   takes ~0.3 s, one critical section plus a few hundred nanoseconds per hand-off,
   whatever the number of waiters.
+* The kernels' lock -- a byte per bucket, taken with one atomic when free, and a
+  ticket queue for tiles that find it held -- hands off as fast as the ticket
+  lock, with one poller per queue.
 
 The old protocols are simulated at 2^16 / 128 waiters with the service rate
 divided by 128 as well: while waiters keep requests queued, a hand-off costs
@@ -79,4 +82,30 @@ def test_grid_stride_tiles_each_hold_one_ticket_at_a_time():
     # 2^12 tiles with 4 operations each: FIFO per operation, 2^14 hand-offs
     r = lm.simulate("ticket", 1 << 12, ops_per_waiter=4)
     assert r.handoffs == 1 << 14
+    assert r.mean_handoff_s < 3e-6 + 2.5e-6
+
+
+def test_queued_lock_bounds_the_storm():
+    """The kernels' lock (byte plus ticket queue) in a 2^14-tile storm: a
+    hand-off costs one critical section plus about a round trip, as in the ticket
+    lock, and the two words see far fewer requests than they could serve."""
+    w = 1 << 14
+    r = lm.simulate("queued", w, mu=MU)
+    assert r.handoffs == w
+    assert r.mean_handoff_s < 3e-6 + 2 * 0.5e-6 + 1.5e-6, r.mean_handoff_s
+    assert r.requests / r.total_s < 0.25 * MU
+    t = lm.simulate("ticket", w, mu=MU)
+    assert abs(r.mean_handoff_s - t.mean_handoff_s) < 0.1 * t.mean_handoff_s
+
+
+def test_queued_lock_uncontended_costs_one_atomic_and_one_store():
+    r = lm.simulate("queued", 1)
+    assert r.handoffs == 1 and r.requests == 2
+    # a second tile arriving while the first holds the byte retries, then gets it
+    r = lm.simulate("queued", 2, cs=1e-6)
+    assert r.handoffs == 2
+
+
+def test_queued_lock_without_retries_still_bounded():
+    r = lm.simulate("queued", 1 << 12, spins=0)
     assert r.mean_handoff_s < 3e-6 + 2.5e-6
