@@ -109,13 +109,14 @@ k_erase(TableDev tv, const typename C::K* __restrict__ keys, uint64_t n, uint8_t
 // paths need the registers the grouping takes.
 //
 // MERGED: the call's upserts were merged by key (hw_merge.hpp); only each key's
-// leader runs its table upsert, and a follower's status is written later.
+// leader runs its table upsert, and a follower's status is written later.  `oe`
+// is the operation's op_ent word (read by the caller; unused unless MERGED).
 template <class C, bool MERGED = false>
 __device__ __forceinline__ void mixed_op(const TableDev& tv, const Tile<C::T>& tile, const uint8_t* __restrict__ ops,
                                          const typename C::K* __restrict__ keys,
                                          const typename C::K* __restrict__ vals, uint64_t j, int combine,
                                          typename C::K* __restrict__ out, uint8_t* __restrict__ status,
-                                         const MergeWs& ws) {
+                                         const MergeWs& ws, uint32_t oe) {
   using K = typename C::K;
   const int op = ops[j];
   const K key = keys[j];
@@ -131,7 +132,10 @@ __device__ __forceinline__ void mixed_op(const TableDev& tv, const Tile<C::T>& t
     const int cmb = op == OP_INSERT ? C_KEEP : combine;
     uint32_t e = MERGE_NONE;
     if constexpr (MERGED) {
-      if (op == OP_UPSERT) report = merge_take<K>(ws, tile, j, cmb, &val, &e);
+      if (op == OP_UPSERT) {
+        e = oe;
+        report = merge_take<K>(ws, tile, j, oe, cmb, &val);
+      }
     }
     st = ST_EXISTED;
     if (report) {
@@ -154,42 +158,57 @@ __device__ __forceinline__ void mixed_body(const TableDev& tv, const uint8_t* __
                                            const typename C::K* __restrict__ keys,
                                            const typename C::K* __restrict__ vals, uint64_t n, int combine,
                                            typename C::K* __restrict__ out, uint8_t* __restrict__ status,
-                                           uint8_t* order_lds, const MergeWs& ws) {
+                                           uint8_t* order_lds, uint32_t* oent_lds, const MergeWs& ws) {
   const Tile<C::T> tile;
   if constexpr (C::CUCKOO) {
     const uint64_t stride = (uint64_t)gridDim.x * (BLOCK / C::T);
     for (uint64_t i = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) / C::T; i < n; i += stride)
-      mixed_op<C, MERGED>(tv, tile, ops, keys, vals, i, combine, out, status, ws);
+      mixed_op<C, MERGED>(tv, tile, ops, keys, vals, i, combine, out, status, ws, MERGED ? ws.op_ent[i] : MERGE_NONE);
     return;
   }
   // wave-uniform values made scalar, so they take no vector registers
   const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   uint8_t* order = order_lds + wid * 64;  // this wave's 64 entries
+  uint32_t* oent = oent_lds + (MERGED ? wid * 64 : 0);
   const uint32_t lane = __lane_id();
   const uint64_t wave = (uint64_t)blockIdx.x * (BLOCK / 64) + wid;
   const uint64_t n_waves = (uint64_t)gridDim.x * (BLOCK / 64);
   for (uint64_t base = wave * 64; base < n; base += n_waves * 64) {
     // rank of the lane's operation: query 0, insert/upsert 1, erase 2, other 3,
-    // past the end 4; its place = lanes of lower rank + lower lanes of its rank
+    // nothing to do 4 (an upsert that the merge's build pass found to follow
+    // another: the finishing pass reports it), past the end 5; its place =
+    // lanes of lower rank + lower lanes of its rank
     const uint64_t i = base + lane;
-    int r = 4;
+    int r = 5;
+    uint32_t oe = MERGE_NONE;
     if (i < n) {
       const int op = ops[i];
       r = op == OP_QUERY ? 0 : (op == OP_INSERT || op == OP_UPSERT) ? 1 : op == OP_ERASE ? 2 : 3;
+      if constexpr (MERGED) {
+        if (op == OP_UPSERT) {
+          oe = ws.op_ent[i];
+          if (oe != MERGE_NONE && (oe & MERGE_FOLLOWER)) {
+            r = 4;
+            if (out) out[i] = 0;
+          }
+        }
+      }
     }
     uint32_t place = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
       const uint64_t m = __ballot(r == k);
       if (k < r) place += (uint32_t)__popcll(m);
       if (k == r) place += (uint32_t)__popcll(m & ((1ull << lane) - 1));
     }
-    if (r == 4) place = lane;  // past-end lanes are the highest ones
+    if (r == 5) place = lane;  // past-end lanes are the highest ones
     order[place] = (uint8_t)lane;
+    if constexpr (MERGED) oent[place] = oe;
+    const uint32_t cnt = (uint32_t)__popcll(__ballot(r < 4));
     wave_sync();
-    const uint32_t cnt = n - base < 64 ? (uint32_t)(n - base) : 64u;
     for (uint32_t s = lane / C::T; s < cnt; s += 64 / C::T)
-      mixed_op<C, MERGED>(tv, tile, ops, keys, vals, base + order[s], combine, out, status, ws);
+      mixed_op<C, MERGED>(tv, tile, ops, keys, vals, base + order[s], combine, out, status, ws,
+                          MERGED ? oent[s] : MERGE_NONE);
     wave_sync();  // the next window rewrites `order`
   }
 }
@@ -200,7 +219,8 @@ k_mixed(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __res
         const typename C::K* __restrict__ vals, uint64_t n, int combine, typename C::K* __restrict__ out,
         uint8_t* __restrict__ status, MergeWs ws) {
   __shared__ uint8_t order_lds[BLOCK];
-  mixed_body<C, MERGED>(tv, ops, keys, vals, n, combine, out, status, order_lds, ws);
+  __shared__ uint32_t oent_lds[MERGED ? BLOCK : 1];
+  mixed_body<C, MERGED>(tv, ops, keys, vals, n, combine, out, status, order_lds, oent_lds, ws);
 }
 
 // With an occupancy bound of W waves per SIMD: the grouping's registers would
@@ -214,7 +234,8 @@ k_mixed_w(TableDev tv, const uint8_t* __restrict__ ops, const typename C::K* __r
            const typename C::K* __restrict__ vals, uint64_t n, int combine, typename C::K* __restrict__ out,
            uint8_t* __restrict__ status, MergeWs ws) {
   __shared__ uint8_t order_lds[BLOCK];
-  mixed_body<C, MERGED>(tv, ops, keys, vals, n, combine, out, status, order_lds, ws);
+  __shared__ uint32_t oent_lds[MERGED ? BLOCK : 1];
+  mixed_body<C, MERGED>(tv, ops, keys, vals, n, combine, out, status, order_lds, oent_lds, ws);
 }
 
 // Host side ------------------------------------------------------------------

@@ -180,15 +180,14 @@ k_merge_build(MergeWs ws, const uint8_t* __restrict__ ops, const K* __restrict__
   }
 }
 
-// Pass 2 helper, called for an upsert by every lane of its tile: whether this
-// operation runs its table upsert, and with which value.  A follower marks
-// itself (leader lane) and does not touch the table.
+// Pass 2 helper, called for an upsert by every lane of its tile with the
+// operation's op_ent word e: whether this operation runs its table upsert, and
+// with which value.  A follower marks itself (leader lane) and does not touch
+// the table.
 template <typename K, int T>
-__device__ __forceinline__ bool merge_take(const MergeWs& ws, const Tile<T>& tile, uint64_t j, int combine,
-                                           K* val, uint32_t* entry) {
-  const uint32_t e = ws.op_ent[j];
-  *entry = e;
-  if (e == MERGE_NONE) return true;  // not merged (invalid key): the table op reports it
+__device__ __forceinline__ bool merge_take(const MergeWs& ws, const Tile<T>& tile, uint64_t j, uint32_t e,
+                                           int combine, K* val) {
+  if (e == MERGE_NONE) return true;      // not merged (invalid key): the table op reports it
   if (e & MERGE_FOLLOWER) return false;  // marked in pass 1
   const MergeEntry m = ws.ent[e];
   if (m.lead != merge_lead_code(ws, j)) {
