@@ -190,11 +190,14 @@ typedef struct {
                            limit gives up with HWAVE_ST_TIMEOUT (see there)    */
 } hwave_config;
 
-/* Fills *out with the design's defaults.  Returns HWAVE_OK or HWAVE_EINVAL. */
+/* Fills *out with the design's defaults: the bucket size and tile width of the
+ * paper's configuration of that design (Section 5).  Returns HWAVE_OK or
+ * HWAVE_EINVAL. */
 int hwave_config_default(hwave_design design, hwave_config* out);
 
 /* Device bytes a table needs (slots + tags + lock bytes and queues + control words) for a
- * capacity rounded up to bucket_slots * 2^k slots.  Host-only arithmetic. */
+ * capacity rounded up to bucket_slots * 2^k slots: the space accounting of
+ * Section 6.1 plus the locks (Section 5.1).  Host-only arithmetic. */
 int hwave_table_bytes(uint64_t capacity_slots, hwave_design design, const hwave_config* cfg,
                       uint64_t* bytes);
 
@@ -205,18 +208,20 @@ int hwave_table_bytes(uint64_t capacity_slots, hwave_design design, const hwave_
 int hwave_create(hwave_table** out, uint64_t capacity_slots, hwave_design design,
                  const hwave_config* cfg, void* stream);
 
-/* Same as hwave_create but in caller-owned device memory (e.g. a torch tensor)
- * of buffer_bytes >= hwave_table_bytes(); d_buffer must be 256-byte aligned and
- * outlive the table. */
+/* Same as hwave_create (fixed capacity, Section 3.2) but in caller-owned device
+ * memory (e.g. a torch tensor) of buffer_bytes >= hwave_table_bytes(); d_buffer
+ * must be 256-byte aligned and outlive the table; HWAVE_EINVAL otherwise. */
 int hwave_create_in(hwave_table** out, void* d_buffer, uint64_t buffer_bytes,
                     uint64_t capacity_slots, hwave_design design, const hwave_config* cfg,
                     void* stream);
 
-/* Synchronises the device, then frees the table (and its memory if owned). */
+/* Synchronises the device, then frees the table (and its memory if owned).  Not
+ * a paper operation: table lifetime. */
 int hwave_destroy(hwave_table* t);
 
-/* Empties the table (every slot empty, tags empty, locks free, the lock
- * failure flag of HWAVE_ST_TIMEOUT cleared) on `stream`. */
+/* Empties the table (every slot empty, tags empty, locks and lock queues free,
+ * the lock failure flag of HWAVE_ST_TIMEOUT cleared) on `stream`: the empty
+ * table every benchmark run of Section 6 starts from. */
 int hwave_clear(hwave_table* t, void* stream);
 
 /* Insert = Upsert with KEEP (Section 5.1).  d_vals may not be NULL.  d_status
@@ -268,12 +273,15 @@ int hwave_mixed_noalloc(hwave_table* t, const uint8_t* d_ops, const void* d_keys
                         uint64_t n, hwave_combine combine, void* d_vals_out, uint8_t* d_status,
                         void* stream);
 
-/* Writes the number of live keys to *d_count (one uint64_t on the device). */
+/* Writes the number of live keys to *d_count (one uint64_t on the device).  Not
+ * a paper operation: the size check of the benchmarks' verification (live keys =
+ * successful inserts - successful erases). */
 int hwave_size(hwave_table* t, uint64_t* d_count, void* stream);
 
 /* Copies every live (key, value) pair to d_keys/d_vals (capacity elements
  * each, in slot order) and their number to *d_count.  Meant for a quiescent
- * table (checkpoint dump, tests). */
+ * table (checkpoint dump, tests).  Not a paper operation: the dump that the
+ * verification compares with the oracle's map. */
 int hwave_export(hwave_table* t, void* d_keys, void* d_vals, uint64_t* d_count, void* stream);
 
 /* Number of buckets (host call), and the primary bucket of each key (device
@@ -294,10 +302,11 @@ int hwave_primary_bucket(hwave_table* t, const void* d_keys, uint64_t n, uint64_
 int hwave_candidate_buckets(hwave_table* t, const void* d_keys, uint64_t n, uint64_t* d_out,
                             void* stream);
 
-/* Slot capacity after rounding. */
+/* Slot capacity after rounding (bucket_slots * 2^k, Section 3.2). */
 uint64_t hwave_capacity(const hwave_table* t);
 
-/* Device pointers and geometry of a table, for tests that inspect its raw image. */
+/* Device pointers and geometry of a table, for tests that inspect its raw image
+ * against the layouts of Section 2.2 (the oracle's layout checker). */
 typedef struct {
   void* slots;          /* slots of (key, value), bucket-major; chaining: nodes of
                            8 16-byte units, unit 7 the link (empty key word,
@@ -318,7 +327,9 @@ typedef struct {
 int hwave_raw(const hwave_table* t, hwave_raw_view* out);
 
 /* ------------------------------------------------------------------------
- * Batched form: one persistent launch over many tables.
+ * Batched form: one persistent launch over many tables.  Not a paper operation:
+ * the paper runs one table per launch; each item here is one of its bulk
+ * operations (Section 5.1) on one table.
  *
  * A hwave_multi groups tables of one key width (any designs and sizes whose
  * configuration is in the multi-table menu: hwave_multi_supported).  Each call
@@ -424,7 +435,8 @@ int hwave_tune_load(const char* path, uint32_t* log2_capacity, hwave_tune_result
                     uint32_t* n);
 
 /* ------------------------------------------------------------------------
- * Served form: a request loop over resident tables (continuous batching).
+ * Served form: a request loop over resident tables (continuous batching).  Not
+ * a paper operation: each request is one of its bulk operations (Section 5.1).
  *
  * A request is one operation kind on n keys of one table, with its arrays in
  * host memory; they must stay valid until the request completes.  In batched
