@@ -125,11 +125,11 @@ __device__ __forceinline__ void mixed_op(const TableDev& tv, const Tile<C::T>& t
   bool report = true;
   if (op == OP_QUERY) {
     st = Ops<C>::query(tv, tile, key, &v);
-  } else if (op == OP_ERASE) {
-    st = Ops<C>::erase(tv, tile, key);
-  } else if (op == OP_INSERT || op == OP_UPSERT) {
-    K val = vals[j];
-    const int cmb = op == OP_INSERT ? C_KEEP : combine;
+  } else if (op == OP_ERASE || op == OP_INSERT || op == OP_UPSERT) {
+    // erases and upserts share one inlined lock loop (Ops::write)
+    const bool erase = op == OP_ERASE;
+    K val = erase ? K(0) : vals[j];
+    const int cmb = op == OP_UPSERT ? combine : C_KEEP;
     uint32_t e = MERGE_NONE;
     if constexpr (MERGED) {
       if (op == OP_UPSERT) {
@@ -139,7 +139,7 @@ __device__ __forceinline__ void mixed_op(const TableDev& tv, const Tile<C::T>& t
     }
     st = ST_EXISTED;
     if (report) {
-      st = Ops<C>::upsert(tv, tile, key, val, cmb);
+      st = Ops<C>::write(tv, tile, key, val, cmb, erase);
       if constexpr (MERGED) {
         if (e != MERGE_NONE && tile.leader()) ws.ent[e].stat = st;
       }

@@ -993,13 +993,34 @@ struct Ops {
   // instead of the value word.
   __device__ static uint8_t upsert(const TableDev& tv, const Tile<T>& tile, K key, K val,
                                    int combine, int hot_row = -1) {
-    if (key >= Keys<K>::FIRST_INVALID) return ST_INVALID;
-    if constexpr (C::CUCKOO) return cuckoo_upsert(tv, tile, key, val, combine);
+    return write(tv, tile, key, val, combine, false, hot_row);
+  }
+
+  // Upsert (erase false) or erase (erase true) of one key.  Both kinds take the
+  // primary bucket's lock through ONE lock loop, so a kernel that runs both
+  // (the mixed kernels) inlines the loop once; where `erase` is a constant the
+  // other kind's code folds away.
+  __device__ static uint8_t write(const TableDev& tv, const Tile<T>& tile, K key, K val, int combine, bool erase,
+                                  int hot_row = -1) {
+    if (key >= Keys<K>::FIRST_INVALID || (erase && tv.no_erase)) return ST_INVALID;
+    if constexpr (C::CUCKOO) {
+      K unused;
+      return erase ? cuckoo_locked(tv, tile, key, true, &unused) : cuckoo_upsert(tv, tile, key, val, combine);
+    }
     const Home h = home_of(tv, key);
     const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
+    if constexpr (!C::DOUBLE) {
+      // an erase marks the table first: the two-choice shortcut and iceberg's
+      // front-yard rule hold only while nothing was ever erased
+      if (erase && tile.leader() && ld(tv.ctrl) == 0) {
+        st(tv.ctrl, 1u);
+        wait_mem();
+      }
+    }
     // Phased chaining keeps its write locks: appending a node is not safe for
     // two writers of one chain (only its queries differ, Table 1's phased column).
     if constexpr (C::BSP && !C::CHAIN) {
+      if (erase) return erase_locked(tv, tile, h, key, tag);
       if constexpr (C::ICEBERG)
         return upsert_iceberg_locked(tv, tile, h, key, val, tag, combine);
       else if constexpr (C::DOUBLE)
@@ -1007,7 +1028,7 @@ struct Ops {
       else
         return upsert_p2_locked(tv, tile, h, key, val, tag, combine);
     }
-    if (tv.no_erase) {
+    if (!erase && tv.no_erase) {
       K cur;
       const int64_t s = find(tv, tile, h, key, tag, &cur);
       if (s >= 0) {
@@ -1020,6 +1041,7 @@ struct Ops {
       }
     }
     return locked(tv, tile, h.b1, [&]() -> uint8_t {
+      if (erase) return erase_locked(tv, tile, h, key, tag);
       if constexpr (C::CHAIN)
         return upsert_chain_locked(tv, tile, h, key, val, combine);
       else if constexpr (C::ICEBERG)
@@ -1185,21 +1207,7 @@ struct Ops {
   // Erase under the primary lock (none in the phased variant).  ST_DONE if
   // removed, ST_MISS if absent.
   __device__ static uint8_t erase(const TableDev& tv, const Tile<T>& tile, K key) {
-    if (key >= Keys<K>::FIRST_INVALID || tv.no_erase) return ST_INVALID;
-    if constexpr (C::CUCKOO) {
-      K unused;
-      return cuckoo_locked(tv, tile, key, true, &unused);
-    }
-    const Home h = home_of(tv, key);
-    const uint32_t tag = C::TAGS ? tag_of((uint64_t)key) : 0u;
-    if constexpr (!C::DOUBLE) {
-      if (tile.leader() && ld(tv.ctrl) == 0) {
-        st(tv.ctrl, 1u);
-        wait_mem();
-      }
-    }
-    if constexpr (C::BSP && !C::CHAIN) return erase_locked(tv, tile, h, key, tag);
-    return locked(tv, tile, h.b1, [&]() -> uint8_t { return erase_locked(tv, tile, h, key, tag); });
+    return write(tv, tile, key, K(0), C_KEEP, true);
   }
 
   // Finds and removes `key` among its candidate buckets.
