@@ -173,6 +173,10 @@ __device__ __forceinline__ X cas(X* p, X expected, X desired) {
   return expected;  // the value found (== the argument on success)
 }
 
+// Threads per block of every kernel that operates on a table (the per-tile
+// lock-wait state below is sized by it).
+constexpr int BLOCK = 256;
+
 // ------------------------------------------------------------------ locks
 //
 // One lock byte per bucket in an external array (the paper keeps one lock bit

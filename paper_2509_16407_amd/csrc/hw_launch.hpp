@@ -14,8 +14,6 @@
 
 namespace hw {
 
-constexpr int BLOCK = 256;
-
 template <class C>
 __global__ void __launch_bounds__(BLOCK)
 k_upsert(TableDev tv, const typename C::K* __restrict__ keys, const typename C::K* __restrict__ vals,

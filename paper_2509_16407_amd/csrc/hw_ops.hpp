@@ -918,57 +918,70 @@ struct Ops {
   // and tiles of one wave that wait on each other cannot deadlock.
   template <class F>
   __device__ static uint8_t locked(const TableDev& tv, const Tile<T>& tile, uint32_t b, F&& cs) {
-    const uint32_t q = b & tv.lockq_mask;
-    bool have = try_lock(tv.locks, b, tile);
-    bool queued = false, head = false;
-    uint32_t spins = 0, mine = 0, served = 0, since = 0, look = 0, looks = 0;
-    Backoff bo;
+    // The waiting state (ticket, start of the wait, next look, retries or
+    // looks) lives in LDS, one slot per tile of the block: it is touched only
+    // while waiting, and kept out of registers it leaves them to the critical
+    // section inlined below.  Every lane of a tile writes the same values.
+    __shared__ uint32_t wait_lds[4 * (BLOCK / T)];
+    uint32_t* const ws = wait_lds + 4 * (threadIdx.x / T);
+    enum : uint32_t { HAVE = 0, RETRY = 1, QUEUED = 2, HEAD = 3, DONE = 4 };
+    uint32_t stage = try_lock(tv.locks, b, tile) ? HAVE : RETRY;
+    if (stage == RETRY) ws[3] = 0;
     uint8_t status = ST_TIMEOUT;
-    bool pending = true;
-    while (pending) {
-      if (have) {
+    while (stage != DONE) {
+      if (stage == HAVE) {
         __atomic_signal_fence(__ATOMIC_SEQ_CST);  // critical-section accesses after the lock's
         status = cs();
 #ifndef HW_STRICT_ORDER
         wait_mem();  // every write of the critical section has completed
 #endif
         if (tile.leader()) release_try_lock(tv.locks, b);
-        pending = false;
-      } else if (queued) {
+        stage = DONE;
+      } else if (stage != RETRY) {
         const uint32_t now = now_ticks();
-        if (ticks_reached(now, look)) {
-          if (!head) {
-            served = read_serving(tv.lockq, q, tile);
-            head = served == mine;
-            if (!head) look = next_look(now, mine - served);
+        if (ticks_reached(now, ws[2])) {
+          const uint32_t mine = ws[0];
+          uint32_t look = ws[2];
+          if (stage == QUEUED) {
+            const uint32_t served = read_serving(tv.lockq, b & tv.lockq_mask, tile);
+            if (served == mine) stage = HEAD;
+            else look = next_look(now, mine - served);
           }
-          if (head) {
-            have = try_lock(tv.locks, b, tile);
-            if (have) {
-              if (tile.leader()) pass_queue(tv.lockq, q, mine);  // the next head polls during our section
+          if (stage == HEAD) {
+            if (try_lock(tv.locks, b, tile)) {
+              stage = HAVE;
+              if (tile.leader()) pass_queue(tv.lockq, b & tv.lockq_mask, mine);  // the next head polls during our section
             } else {
               look = now + LOCK_FIRST_TICKS;
             }
           }
-          if (!have && (now - since > tv.lock_limit || ((++looks & 15) == 0 && lock_failed(tv, tile)))) {
+          const uint32_t looks = ws[3] + 1;
+          if (stage != HAVE && (now - ws[1] > tv.lock_limit || ((looks & 15) == 0 && lock_failed(tv, tile)))) {
             if (tile.leader()) st(tv.ctrl + LOCK_FLAG_WORD, 1u);
-            pending = false;  // status stays ST_TIMEOUT
+            stage = DONE;  // status stays ST_TIMEOUT
           }
+          ws[2] = look;
+          ws[3] = looks;
         } else {
           __builtin_amdgcn_s_sleep(2);
         }
       } else {
-        bo.grow();
-        bo.pause();
-        have = lock_looks_free(tv.locks, b, tile) && try_lock(tv.locks, b, tile);
-        if (!have && ++spins == LOCK_SPINS) {
-          const uint64_t w = take_ticket(tv.lockq, q, tile);
-          queued = true;
-          mine = (uint32_t)(w >> 32);
-          served = (uint32_t)w;
-          since = now_ticks();
-          head = served == mine;
-          look = head ? since : next_look(since, mine - served);
+        // retry: a pause of 2^retries steps of 128 cycles, then a look at the
+        // byte and the OR if it reads clear
+        const uint32_t retries = ws[3];
+        for (uint32_t i = 0; i < (1u << retries); ++i) __builtin_amdgcn_s_sleep(2);
+        if (lock_looks_free(tv.locks, b, tile) && try_lock(tv.locks, b, tile)) {
+          stage = HAVE;
+        } else if (retries + 1 == LOCK_SPINS) {
+          const uint64_t w = take_ticket(tv.lockq, b & tv.lockq_mask, tile);
+          const uint32_t mine = (uint32_t)(w >> 32), since = now_ticks();
+          stage = (uint32_t)w == mine ? HEAD : QUEUED;
+          ws[0] = mine;
+          ws[1] = since;
+          ws[2] = stage == HEAD ? since : next_look(since, mine - (uint32_t)w);
+          ws[3] = 0;
+        } else {
+          ws[3] = retries + 1;
         }
       }
     }
