@@ -195,7 +195,7 @@ typedef struct {
  * HWAVE_EINVAL. */
 int hwave_config_default(hwave_design design, hwave_config* out);
 
-/* Device bytes a table needs (slots + tags + lock bytes and queues + control words) for a
+/* Device bytes a table needs (slots + tags + lock array and queues + control words) for a
  * capacity rounded up to bucket_slots * 2^k slots: the space accounting of
  * Section 6.1 plus the locks (Section 5.1).  Host-only arithmetic. */
 int hwave_table_bytes(uint64_t capacity_slots, hwave_design design, const hwave_config* cfg,
@@ -312,9 +312,10 @@ typedef struct {
                            8 16-byte units, unit 7 the link (empty key word,
                            next node index or all-ones in the value word)     */
   uint16_t* tags;       /* capacity 16-bit tags, or NULL without tags             */
-  uint32_t* locks;      /* bucket b's lock: byte b (byte b % 4 of 32-bit word
-                           b / 4), nonzero while held (Section 5.1)            */
-  uint64_t n_lock_words; /* 32-bit words of lock bytes: ceil(buckets / 4)        */
+  uint32_t* locks;      /* bucket b's lock: byte b * lock_stride of this array
+                           (Section 5.1), nonzero while held                   */
+  uint64_t n_lock_words; /* 32-bit words of the lock array:
+                           ceil(buckets * lock_stride / 4)                     */
   uint64_t* lock_queues; /* ticket queues of contended acquires: per word, next
                            ticket (high 32 bits) and ticket being served (low
                            32 bits); idle when equal.  Bucket b queues on word
@@ -323,6 +324,8 @@ typedef struct {
   uint64_t num_buckets;
   uint32_t bucket_slots, tile, kv_bits, design;
   uint64_t slot_bytes;  /* bytes of the slot region (chaining: every node)     */
+  uint32_t lock_stride; /* bytes per bucket lock: clamp(2^23 / buckets, 1, 8),
+                           a power of two                                      */
 } hwave_raw_view;
 int hwave_raw(const hwave_table* t, hwave_raw_view* out);
 

@@ -79,7 +79,8 @@ class _Raw(ctypes.Structure):
                 ("n_lock_words", ctypes.c_uint64), ("lock_queues", ctypes.c_void_p),
                 ("n_lock_queues", ctypes.c_uint64), ("num_buckets", ctypes.c_uint64),
                 ("bucket_slots", ctypes.c_uint32), ("tile", ctypes.c_uint32),
-                ("kv_bits", ctypes.c_uint32), ("design", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint64)]
+                ("kv_bits", ctypes.c_uint32), ("design", ctypes.c_uint32), ("slot_bytes", ctypes.c_uint64),
+                ("lock_stride", ctypes.c_uint32)]
 
 
 _lib = None
@@ -347,6 +348,7 @@ class Table:
             out["tags"] = None
         off = r.locks - base
         out["locks"] = self.buffer[off: off + 4 * r.n_lock_words].view(torch.int32)
+        out["lock_stride"] = int(r.lock_stride)
         off = r.lock_queues - base
         out["lock_queues"] = self.buffer[off: off + 8 * r.n_lock_queues].view(torch.int64)
         return out

@@ -52,15 +52,19 @@ uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 struct Layout {
   uint64_t nb, capacity, units, pool;
   uint64_t off_tags, off_locks, off_lockq, off_ctrl, off_pool_ctr, off_hot, off_merge, total;
-  uint64_t n_lock_words;  // 32-bit words of lock bytes (one byte per bucket)
+  uint64_t n_lock_words;  // 32-bit words of the lock array (one byte per bucket, at a stride)
+  uint32_t lock_shift;    // log2 of the lock stride in bytes
   uint64_t n_lockq;       // lock queues (hw_device.hpp): a power of two
 };
 
-// Lock bytes, then the lock queues: the largest power of two <= nb, at most
-// LOCK_QUEUES_MAX.  Returns the offset after them.
+// Lock bytes at a stride of 1 << lock_shift bytes (hw_device.hpp, LockArray:
+// clamp(2^23 / nb, 1, 8) bytes), then the lock queues: the largest power of
+// two <= nb, at most LOCK_QUEUES_MAX.  Returns the offset after them.
 uint64_t place_locks(uint64_t nb, uint64_t off, Layout* L) {
+  L->lock_shift = 0;
+  while (L->lock_shift < 3 && (nb << (L->lock_shift + 1)) <= (1ull << 23)) ++L->lock_shift;
   L->off_locks = off;
-  L->n_lock_words = (nb + 3) / 4;
+  L->n_lock_words = ((nb << L->lock_shift) + 3) / 4;
   off += round_up(L->n_lock_words * 4, ALIGN);
   uint64_t nq = 1;
   while (nq * 2 <= nb && nq * 2 <= LOCK_QUEUES_MAX) nq *= 2;
@@ -330,7 +334,8 @@ int init_table(hwave_table* t, void* base, uint64_t bytes, const Layout& L, hwav
   TableDev& tv = t->la.tv;
   tv.slots = b;
   tv.tagw = design_tags(design) ? (uint32_t*)(b + L.off_tags) : nullptr;
-  tv.locks = (uint32_t*)(b + L.off_locks);
+  tv.locks.words = (uint32_t*)(b + L.off_locks);
+  tv.locks.shift = L.lock_shift;
   tv.lockq = (uint64_t*)(b + L.off_lockq);
   tv.lockq_mask = (uint32_t)(L.n_lockq - 1);
   tv.ctrl = (uint32_t*)(b + L.off_ctrl);
@@ -478,12 +483,12 @@ int hwave_clear(hwave_table* t, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   // Every region size is a multiple of 256 bytes.  Slots and tags: all-ones
   // (empty); locks and control word: zero.
-  const uint64_t fill_end = (uint64_t)((uint8_t*)t->la.tv.locks - (uint8_t*)t->base);
+  const uint64_t fill_end = (uint64_t)((uint8_t*)t->la.tv.locks.words - (uint8_t*)t->base);
   hipLaunchKernelGGL(k_fill16, dim3(stream_grid(fill_end / 16, t->device)), dim3(256), 0, s,
                      (uint4*)t->base, fill_end / 16, 0xFFFFFFFFu);
   const uint64_t zero_bytes = t->bytes - fill_end;
   hipLaunchKernelGGL(k_fill16, dim3(stream_grid(zero_bytes / 16, t->device)), dim3(256), 0, s,
-                     (uint4*)t->la.tv.locks, zero_bytes / 16, 0u);
+                     (uint4*)t->la.tv.locks.words, zero_bytes / 16, 0u);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);
 }
@@ -695,8 +700,9 @@ int hwave_raw(const hwave_table* t, hwave_raw_view* out) {
   if (!t || !out) return HWAVE_EINVAL;
   out->slots = t->la.tv.slots;
   out->tags = (uint16_t*)t->la.tv.tagw;
-  out->locks = (uint32_t*)t->la.tv.locks;
+  out->locks = t->la.tv.locks.words;
   out->n_lock_words = t->n_lock_words;
+  out->lock_stride = 1u << t->la.tv.locks.shift;
   out->lock_queues = t->la.tv.lockq;
   out->n_lock_queues = (uint64_t)t->la.tv.lockq_mask + 1;
   out->num_buckets = t->nb;
@@ -811,7 +817,7 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
     h[i].tv = t->la.tv;
     h[i].cls = (uint32_t)cls;
     h[i].pad = 0;
-    const uint64_t locks_off = (uint64_t)((uint8_t*)t->la.tv.locks - (uint8_t*)t->base);
+    const uint64_t locks_off = (uint64_t)((uint8_t*)t->la.tv.locks.words - (uint8_t*)t->base);
     h[i].fill_words = locks_off / 16;
     h[i].zero_words = (t->bytes - locks_off) / 16;
   }

@@ -124,7 +124,6 @@ __device__ __forceinline__ void mixed_op(const TableDev& tv, const Tile<C::T>& t
   if (op == OP_QUERY) {
     st = Ops<C>::query(tv, tile, key, &v);
   } else if (op == OP_ERASE || op == OP_INSERT || op == OP_UPSERT) {
-    // erases and upserts share one inlined lock loop (Ops::write)
     const bool erase = op == OP_ERASE;
     K val = erase ? K(0) : vals[j];
     const int cmb = op == OP_UPSERT ? combine : C_KEEP;
@@ -137,7 +136,9 @@ __device__ __forceinline__ void mixed_op(const TableDev& tv, const Tile<C::T>& t
     }
     st = ST_EXISTED;
     if (report) {
-      st = Ops<C>::write(tv, tile, key, val, cmb, erase);
+      // two call sites, each with `erase` constant: one lock loop holding both
+      // critical sections measured 3-4% slower in aging launches
+      st = erase ? Ops<C>::erase(tv, tile, key) : Ops<C>::upsert(tv, tile, key, val, cmb);
       if constexpr (MERGED) {
         if (e != MERGE_NONE && tile.leader()) ws.ent[e].stat = st;
       }

@@ -71,7 +71,7 @@ enum : int { D_DOUBLE = 0, D_DOUBLE_M = 1, D_P2 = 2, D_P2_M = 3, D_ICEBERG = 4, 
 struct TableDev {
   void* slots;           // (key, value) pairs, bucket-major
   uint32_t* tagw;        // 16-bit tags viewed as 32-bit words; null without tags
-  uint32_t* locks;       // one lock byte per bucket (hw_device.hpp)
+  LockArray locks;       // one lock byte per bucket, at a stride (hw_device.hpp)
   uint64_t* lockq;       // lock queues: lockq_mask + 1 ticket words
   uint32_t* ctrl;        // ctrl[0]: an erase has happened (power-of-two-choice, iceberg);
                          // ctrl[LOCK_FLAG_WORD]: a lock wait timed out
@@ -1009,10 +1009,9 @@ struct Ops {
     return write(tv, tile, key, val, combine, false, hot_row);
   }
 
-  // Upsert (erase false) or erase (erase true) of one key.  Both kinds take the
-  // primary bucket's lock through ONE lock loop, so a kernel that runs both
-  // (the mixed kernels) inlines the loop once; where `erase` is a constant the
-  // other kind's code folds away.
+  // Upsert (erase false) or erase (erase true) of one key: the write path both
+  // share.  Callers pass a constant `erase`, so the other kind's code folds
+  // away.
   __device__ static uint8_t write(const TableDev& tv, const Tile<T>& tile, K key, K val, int combine, bool erase,
                                   int hot_row = -1) {
     if (key >= Keys<K>::FIRST_INVALID || (erase && tv.no_erase)) return ST_INVALID;

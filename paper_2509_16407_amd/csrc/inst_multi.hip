@@ -50,7 +50,7 @@ __global__ void k_multi_clear(const MultiTable* __restrict__ tables, uint32_t n_
     uint4* a = (uint4*)m.tv.slots;
     const uint4 ones = make_uint4(~0u, ~0u, ~0u, ~0u);
     for (uint64_t i = threadIdx.x; i < m.fill_words; i += blockDim.x) a[i] = ones;
-    uint4* z = (uint4*)m.tv.locks;
+    uint4* z = (uint4*)m.tv.locks.words;
     const uint4 zero = make_uint4(0, 0, 0, 0);
     for (uint64_t i = threadIdx.x; i < m.zero_words; i += blockDim.x) z[i] = zero;
   }

@@ -23,10 +23,10 @@ def u8(t):
     return t.detach().cpu().numpy().astype(np.uint8)
 
 
-def held_lock_bitmap(lock_words32, num_buckets):
-    """Lock bytes (byte b of the array: bucket b, nonzero while held) -> the
+def held_lock_bitmap(lock_words32, num_buckets, stride=1):
+    """Lock array (byte b * stride: bucket b, nonzero while held) -> the
     layout checker's bitmap of held locks (bit b % 64 of 64-bit word b // 64)."""
-    by = np.ascontiguousarray(lock_words32, dtype=np.uint32).view(np.uint8)[:num_buckets]
+    by = np.ascontiguousarray(lock_words32, dtype=np.uint32).view(np.uint8)[::stride][:num_buckets]
     packed = np.packbits(by != 0, bitorder="little")
     packed = np.concatenate([packed, np.zeros(-len(packed) % 8, np.uint8)])
     return packed.view(np.uint64)
@@ -44,7 +44,8 @@ def image(table):
     r = table.raw()
     slots = r["slots"].cpu().numpy()
     tags = None if r["tags"] is None else r["tags"].cpu().numpy().view(np.uint16)
-    return slots, tags, held_lock_bitmap(r["locks"].cpu().numpy().view(np.uint32), table.num_buckets)
+    return slots, tags, held_lock_bitmap(r["locks"].cpu().numpy().view(np.uint32), table.num_buckets,
+                                         r["lock_stride"])
 
 
 def per_key_counts(keys, status, code):

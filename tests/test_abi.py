@@ -39,25 +39,39 @@ def _bytes(capacity, design, kv_bits=64, bucket=0, tile=0, flags=0):
 def test_space_per_slot_matches_section_6_1(design, per_slot, bucket):
     """16 bytes per key-value slot, plus 2 bytes of tag in the metadata designs
     (Section 6.1); on top, one lock byte per bucket (Section 5.1 keeps one lock
-    bit per bucket in an external array), 2^14 eight-byte lock queues and a
-    256-byte control word."""
+    bit per bucket in an external array) at a stride of clamp(2^23 / buckets, 1,
+    8) bytes, 2^14 eight-byte lock queues and a 256-byte control word."""
     slots = 1 << 28
     rc, b = _bytes(slots, design)
     assert rc == 0
-    locks = slots // bucket
-    assert b == slots * per_slot + locks + 8 * (1 << 14) + 256
+    nb = slots // bucket
+    stride = max(1, min(8, (1 << 23) // nb))
+    assert b == slots * per_slot + nb * stride + 8 * (1 << 14) + 256
+
+
+@pytest.mark.parametrize("log2nb,stride", [(10, 8), (20, 8), (21, 4), (22, 2), (23, 1), (26, 1)])
+def test_lock_stride_spreads_locks_within_8_mib(log2nb, stride):
+    """The lock array: buckets x stride bytes, the stride the largest power of two
+    <= 8 that keeps the array within 2^23 bytes (P2HT(M), bucket 32; tags 2 bytes
+    per slot; queues min(2^14, buckets) words)."""
+    nb = 1 << log2nb
+    rc, b = _bytes(nb * 32, 3)
+    assert rc == 0
+    r256 = lambda x: -(-x // 256) * 256
+    assert b == nb * 32 * 18 + r256(nb * stride) + r256(8 * min(nb, 1 << 14)) + 256
 
 
 def test_chaining_space():
     """Chaining: ceil(capacity / 7) bucket nodes and twice as many pool nodes, 128
-    bytes each (7 pairs and a link, Section 5), one lock byte per bucket, lock
+    bytes each (7 pairs and a link, Section 5), one lock byte per bucket (at a
+    stride of 8 bytes in a table this small), lock
     queues (the largest power of two <= the bucket count, 8 bytes each), and
     1024 pool-partition counters, one per 128-byte line."""
     rc, b = _bytes(7 * 1000, 6)
     assert rc == 0
     nb, pool = 1000, 2000
     node_bytes = -(-(nb + pool) * 128 // 256) * 256
-    lock_bytes = -(-nb // 256) * 256 + 512 * 8
+    lock_bytes = -(-(8 * nb) // 256) * 256 + 512 * 8  # stride 8: 1000 buckets << 2^23
     assert b == node_bytes + lock_bytes + 256 + 1024 * 128
     assert _bytes(7 * 1000, 6, kv_bits=32)[0] == -4  # 64-bit keys only
 
