@@ -281,3 +281,33 @@ def test_publish_litmus_replace_vs_query(design):
         t.upsert(dev(base), dev(w.value_of(base) + np.uint64(10 * (rnd + 1))), combine="replace")
     assert bad == 0
     _layout_ok(t)
+
+
+@pytest.mark.parametrize("design,cap", [("P2_M", 1 << 16), ("DOUBLE", 1 << 26)])
+def test_lock_byte_at_its_stride_holds_off_writers(design, cap):
+    """The lock array's layout, pinned from the host: bucket b's lock is byte
+    b * lock_stride, stride = clamp(2^23 / buckets, 1, 8) (8 for the small table,
+    1 for 2^23 buckets).  With that byte set from the host, the writers of bucket
+    b wait, reach the table's 1 ms limit and report TIMEOUT without effect, while
+    keys of other buckets (one per bucket, so none waits) insert.  Clearing the
+    table frees the lock again."""
+    t = hw.Table(cap, design, lock_timeout_us=1000)
+    r = t.raw()
+    stride = r["lock_stride"]
+    assert stride == max(1, min(8, (1 << 23) // t.num_buckets))
+    cand = w.distinct_keys(w.stream_seed(90, ODESIGN[design]), 4096)
+    prim = t.primary_bucket(dev(cand)).cpu().numpy()
+    b = int(np.bincount(prim).argmax())
+    on_b = cand[prim == b][:8]
+    _, first = np.unique(prim, return_index=True)
+    others = np.array([cand[i] for i in first if prim[i] != b][:56], dtype=np.uint64)
+    keys = np.concatenate([on_b, others])
+    vals = w.value_of(keys)
+    r["locks"].view(torch.uint8)[b * stride] = 1  # bucket b's lock, held by nobody
+    st = u8(t.upsert(dev(keys), dev(vals), combine="sum"))
+    assert (st[: len(on_b)] == hw.ST_TIMEOUT).all()
+    assert (st[len(on_b):] == hw.ST_DONE).all()
+    f, _ = t.query(dev(on_b))
+    assert (u8(f) == hw.ST_MISS).all()  # timed-out writes had no effect
+    t.clear()
+    assert (u8(t.upsert(dev(keys), dev(vals), combine="sum")) == hw.ST_DONE).all()

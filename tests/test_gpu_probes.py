@@ -126,7 +126,12 @@ def test_tag_false_positives_exactly_and_at_the_paper_rate(design):
     n = int(0.9 * cap)
     pool = w.distinct_keys(seed, n + (1 << 18))
     keys, neg = pool[:n], pool[n:]
-    assert (u8(t.insert(dev(keys), dev(w.value_of(keys)))) == hw.ST_DONE).all()
+    st = u8(t.insert(dev(keys), dev(w.value_of(keys))))
+    full = st == hw.ST_FULL
+    assert ((st == hw.ST_DONE) | full).all()
+    if full.any():  # a legal concurrent-placement FULL at 0.9 (both candidate buckets full)
+        assert design in ("P2_M", "ICEBERG_M"), design
+        full_is_genuine(t, keys[full])
     slots, tags, _ = image(t)
     nb = t.num_buckets
     tags = tags.reshape(nb, t.bucket_slots)
