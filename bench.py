@@ -398,6 +398,9 @@ PAPER_AGED_PROBES = {"DOUBLE": (1.61, 80.00), "DOUBLE_M": (2.10, 19.39), "P2": (
 
 
 # Table 1's load query probes at 0.9 (A40)
+# Table 1, "Average load probes", columns Insert and Delete (paper, A40).
+PAPER_WRITE_PROBES = {"DOUBLE": (5.44, 4.22), "DOUBLE_M": (5.12, 6.07), "P2": (6.34, 5.83), "P2_M": (5.25, 6.15),
+                      "ICEBERG": (6.53, 5.97), "ICEBERG_M": (5.24, 6.19)}
 PAPER_LOAD_PROBES = {"DOUBLE": 1.22, "DOUBLE_M": 2.05, "P2": 2.83, "P2_M": 2.13, "ICEBERG": 2.97,
                      "ICEBERG_M": 2.16, "CHAINING": 1.16}
 
@@ -416,18 +419,39 @@ def load_probes(designs, log2cap=22):
     res = {}
     for des in designs:
         t = hw.Table(n if des == "CHAINING" else 1 << log2cap, des, instrumented=True)
-        ins = t.insert(keys, keys * 3 + 1)
-        ok = ins == 1
         t.probe_counters(reset=True)
+        # nine insert batches (0.1 load each), the same fill as one
+        ins = torch.cat([t.insert(part, part * 3 + 1) for part in torch.tensor_split(keys, 9)])
+        wc = t.probe_counters(reset=True)
+        ok = ins == 1
         f, _ = t.query(keys, out=out, found=st)
         assert bool((f == ok.to(torch.uint8)).all()), "load probes %s: queries" % des
         c = t.probe_counters(reset=True)
-        res[des] = {"positive": round((c["bucket_lines"] + c["slot_lines"]) / max(1, c["queries"]), 3),
-                    "full_inserts": int((~ok).sum().item()), "paper_a40": PAPER_LOAD_PROBES.get(des)}
+        pos = (c["bucket_lines"] + c["slot_lines"]) / max(1, c["queries"])
+        r = {"positive": round(pos, 3), "full_inserts": int((~ok).sum().item()),
+             "paper_a40": PAPER_LOAD_PROBES.get(des)}
+        if des in PAPER_WRITE_PROBES:
+            # Table 1's delete column as accesses: the search (a positive query),
+            # the lock's acquire and release, and the removal's writes (the key;
+            # with tags the tag too)
+            r["delete_model"] = round(pos + 2 + (2 if des.endswith("_M") else 1), 3)
+            r["paper_a40_delete"] = PAPER_WRITE_PROBES[des][1]
+        if des.endswith("_M") and wc["writes"]:
+            # and its insert column: one tag line per bucket visited, the lock's
+            # two accesses, the claim and the publish
+            visits = wc["write_visits"] / wc["writes"]
+            r["insert_visits"] = round(visits, 4)
+            r["insert_model"] = round(visits + 4, 3)
+            r["paper_a40_insert"] = PAPER_WRITE_PROBES[des][0]
+        res[des] = r
         del t
         torch.cuda.empty_cache()
     log("load probes at 0.9 (GPU-counted, 2^%d slots): %s" % (log2cap, ", ".join(
         "%s %.2f (Table 1: %s)" % (d, r["positive"], r["paper_a40"]) for d, r in res.items())))
+    log("insert/delete probes as accesses (GPU-counted search + lock + writes): %s" % ", ".join(
+        "%s %s/%s (Table 1: %s/%s)" % (d, r.get("insert_model", "-"), r.get("delete_model", "-"),
+                                       r.get("paper_a40_insert", "-"), r.get("paper_a40_delete", "-"))
+        for d, r in res.items() if "delete_model" in r))
     return res
 
 

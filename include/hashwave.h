@@ -514,13 +514,18 @@ double hwave_now(void);
  * queries counted, lines of buckets / tag buckets / chain nodes they read
  * (each bucket's lines counted once; slot designs count the lines of the
  * tile-width steps read up to a hit), and key/value slots read after a tag
- * match.  Cuckoo queries are not counted.  Synchronises `stream`; reset != 0
- * zeroes the counters afterwards (on `stream`).  Other builds return
- * HWAVE_EUNSUPPORTED with *out zeroed. */
+ * match.  Cuckoo queries are not counted.  Also the upserts and inserts that
+ * searched under their bucket lock (double hashing, power-of-two-choice,
+ * iceberg) and the buckets those searches looked at before deciding: in the tag
+ * designs one tag line each, the search part of Table 1's insert column.
+ * Synchronises `stream`; reset != 0 zeroes the counters afterwards (on
+ * `stream`).  Other builds return HWAVE_EUNSUPPORTED with *out zeroed. */
 typedef struct {
   uint64_t queries;
   uint64_t bucket_lines;
   uint64_t slot_lines;
+  uint64_t writes;
+  uint64_t write_visits;
 } hwave_probe_stats;
 int hwave_probe_counters(hwave_table* t, hwave_probe_stats* out, int reset, void* stream);
 

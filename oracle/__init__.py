@@ -105,7 +105,7 @@ def _bind(lib):
     lib.orc_image_pairs.argtypes = [ctypes.c_int, U64, P, P, P]
     lib.orc_sim_insert.restype = U64
     lib.orc_sim_insert.argtypes = [ctypes.c_int, ctypes.c_int, U64, U64, P, P, P, P, U64,
-                                   ctypes.c_int, ctypes.c_int]
+                                   ctypes.c_int, ctypes.c_int, P]
     lib.orc_chain_bucket.restype = U64
     lib.orc_chain_bucket.argtypes = [U64, U64]
     lib.orc_chain_check.restype = U64
@@ -217,10 +217,11 @@ def image_pairs(key_bits, slots):
 
 
 def sim_insert(design, key_bits, nb, bucket_slots, keys, vals=None, shortcut=True,
-               slots=None, tags=None):
+               slots=None, tags=None, visits=False):
     """Sequential placement of `keys` (Section 2.2 rules) into a fresh image.
 
-    Returns (slots uint8 array, tags uint16 array or None, n_failed)."""
+    Returns (slots uint8 array, tags uint16 array or None, n_failed), and with
+    visits=True also each insert's bucket visits (uint32 array)."""
     lib = load()
     sb = 16 if key_bits == 64 else 8
     init = slots is None
@@ -230,9 +231,32 @@ def sim_insert(design, key_bits, nb, bucket_slots, keys, vals=None, shortcut=Tru
             tags = np.empty(nb * bucket_slots, dtype=np.uint16)
     keys = _u64(keys)
     vals = _u64(vals)
+    vis = np.zeros(len(keys), dtype=np.uint32) if visits else None
     failed = lib.orc_sim_insert(design, key_bits, nb, bucket_slots, _ptr(slots), _ptr(tags),
-                                _ptr(keys), _ptr(vals), len(keys), int(bool(shortcut)), int(init))
+                                _ptr(keys), _ptr(vals), len(keys), int(bool(shortcut)), int(init), _ptr(vis))
+    if visits:
+        return slots, tags, int(failed), vis
     return slots, tags, int(failed)
+
+
+# Table 1's insert and delete columns, as accesses (reading 13): every access
+# to a cache line counts, the lock's acquire and release included.
+LOCK_ACCESSES = 2       # acquire and release of the primary bucket's lock
+INSERT_WRITES = 2       # the claim (compare-and-swap) and the key-value publish
+
+
+def insert_probes_tags(visits):
+    """Mean insert probes of a tag design from its inserts' bucket visits: one tag
+    line per visit, the lock's two accesses and the two writes of the placement."""
+    return float(np.mean(visits)) + LOCK_ACCESSES + INSERT_WRITES
+
+
+def delete_probes(design, query_probes):
+    """Mean delete probes from the positive-query probes of the same keys: the
+    search reads what a query reads, then the lock's two accesses and the
+    removal's writes (the key; in the tag designs the tag too)."""
+    writes = 2 if design in (DOUBLE_M, P2_M, ICEBERG_M) else 1
+    return query_probes + LOCK_ACCESSES + writes
 
 
 def tag_of(key: int) -> int:

@@ -525,10 +525,17 @@ uint64_t orc_image_pairs(int key_bits, uint64_t nslots, const void* slots, uint6
 //     alternate, ties to the primary; full when both are full.
 //   iceberg: the front bucket while it has a free slot; else the less loaded of
 //     the two backyard choices, ties to the first; full when both are full.
+// `visits` (nullable, n entries): for each key, the buckets its insert looks at
+// before placing it -- double hashing: every bucket up to the one it goes to;
+// power-of-two-choice: the primary, plus the alternate when the shortcut does
+// not apply and the two differ; iceberg: the front bucket, plus both backyard
+// choices (one if they coincide) when the front is full.  In the tag designs a
+// visit reads one tag bucket, a line of its own (reading 13, Table 1's insert
+// column).
 // Returns the number of keys that could not be placed.
 uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_slots,
                         void* slots, uint16_t* tags, const uint64_t* keys, const uint64_t* vals,
-                        uint64_t n, int shortcut, int init) {
+                        uint64_t n, int shortcut, int init, uint32_t* visits) {
   const uint64_t nslots = nb * bucket_slots;
   const uint64_t sb = key_bits == 64 ? 16 : 8;
   uint8_t* S = (uint8_t*)slots;
@@ -565,17 +572,21 @@ uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_s
     uint64_t v = vals ? vals[i] : 0;
     if (design_is_double(design)) {
       bool placed = false;
-      for (uint64_t p = 0; p < nb; p++) {
+      uint64_t p = 0;
+      for (; p < nb; p++) {
         uint64_t b = orc_double_bucket(h, nb, p);
         if (fill[b] < bucket_slots) { put(b, keys[i], v); placed = true; break; }
       }
+      if (visits) visits[i] = (uint32_t)(placed ? p + 1 : nb);
       if (!placed) failed++;
     } else if (design_is_iceberg(design)) {
       orc_iceberg ib = orc_iceberg_of(keys[i], nb);
       if (fill[ib.front] < bucket_slots) {
+        if (visits) visits[i] = 1;
         put(ib.front, keys[i], v);
         continue;
       }
+      if (visits) visits[i] = ib.back1 == ib.back2 ? 2 : 3;
       uint64_t b = ORC_MUTANT == 14 ? (fill[ib.back2] <= fill[ib.back1] ? ib.back2 : ib.back1)
                                     : (fill[ib.back2] < fill[ib.back1] ? ib.back2 : ib.back1);
       if (fill[b] >= bucket_slots) { failed++; continue; }
@@ -583,9 +594,11 @@ uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_s
     } else {
       uint64_t b1 = h.b1, b2 = orc_p2_alt(h, nb);
       if (shortcut && (ORC_MUTANT == 7 ? 2 * fill[b1] < bucket_slots : 4 * fill[b1] < 3 * bucket_slots)) {
+        if (visits) visits[i] = 1;
         put(b1, keys[i], v);
         continue;
       }
+      if (visits) visits[i] = b1 == b2 ? 1 : 2;
       uint64_t b = ORC_MUTANT == 8 ? (fill[b2] <= fill[b1] ? b2 : b1) : (fill[b2] < fill[b1] ? b2 : b1);
       if (fill[b] >= bucket_slots) { failed++; continue; }
       put(b, keys[i], v);

@@ -53,7 +53,8 @@ class _Tune(ctypes.Structure):
 
 
 class _Probe(ctypes.Structure):
-    _fields_ = [("queries", ctypes.c_uint64), ("bucket_lines", ctypes.c_uint64), ("slot_lines", ctypes.c_uint64)]
+    _fields_ = [("queries", ctypes.c_uint64), ("bucket_lines", ctypes.c_uint64), ("slot_lines", ctypes.c_uint64),
+                ("writes", ctypes.c_uint64), ("write_visits", ctypes.c_uint64)]
 
 
 class _Request(ctypes.Structure):
@@ -328,10 +329,12 @@ class Table:
         return out.view(n, 3)
 
     def probe_counters(self, reset: bool = False, stream=None) -> dict:
-        """Query probe counters (instrumented tables only, C-ABI hwave_probe_counters)."""
+        """Probe counters (instrumented tables only, C-ABI hwave_probe_counters): queries and the
+        lines they read, and the locked upserts and the buckets their searches looked at."""
         c = _Probe()
         _check(self._L.hwave_probe_counters(self.h, ctypes.byref(c), int(bool(reset)), _stream(stream)))
-        return {"queries": c.queries, "bucket_lines": c.bucket_lines, "slot_lines": c.slot_lines}
+        return {"queries": c.queries, "bucket_lines": c.bucket_lines, "slot_lines": c.slot_lines,
+                "writes": c.writes, "write_visits": c.write_visits}
 
     def raw(self):
         """Views of the raw device image: dict(slots=uint8, tags=int16 or None, locks=int32 words of

@@ -687,6 +687,8 @@ int hwave_probe_counters(hwave_table* t, hwave_probe_stats* out, int reset, void
     out->bucket_lines += h[i * 16 + PC_BUCKET];
     out->slot_lines += h[i * 16 + PC_SLOT];
     out->queries += h[i * 16 + PC_QUERY];
+    out->writes += h[i * 16 + PC_WRITE];
+    out->write_visits += h[i * 16 + PC_VISIT];
   }
   if (reset) {
     hipLaunchKernelGGL(k_fill16, dim3(1), dim3(256), 0, s, (uint4*)d, h.size() * sizeof(unsigned long long) / 16, 0u);

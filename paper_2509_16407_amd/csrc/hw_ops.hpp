@@ -95,9 +95,11 @@ struct TableDev {
 // stripes of 16 words, one 128-byte line each, picked by wave; word PC_BUCKET
 // counts the unique 128-byte lines of buckets, tag buckets and chain nodes a
 // query reads, PC_SLOT the key/value slots it reads after a tag match, PC_QUERY
-// the queries.  Other builds compile the counting out.
+// the queries; PC_WRITE the upserts that search under the lock and PC_VISIT the
+// buckets those searches look at before deciding (rescans after a lost claim
+// not counted).  Other builds compile the counting out.
 constexpr uint32_t PROBE_STRIPES = 64;
-enum : int { PC_BUCKET = 0, PC_SLOT = 1, PC_QUERY = 2 };
+enum : int { PC_BUCKET = 0, PC_SLOT = 1, PC_QUERY = 2, PC_WRITE = 3, PC_VISIT = 4 };
 
 __device__ __forceinline__ void probe_add(const TableDev& tv, int word, uint64_t n) {
 #ifdef HW_INSTRUMENT
@@ -1073,8 +1075,10 @@ struct Ops {
     first_free.free = -1;
     uint32_t free_i = 0, free_b = 0;
     uint32_t b = h.b1;
+    if (tile.leader()) probe_add(tv, PC_WRITE, 1);
     for (uint32_t i = 0; i < tv.probe_cap; ++i, b = (b + step) & tv.bucket_mask) {
       BucketScan<K> r = scan<true>(tv, tile, b, key, tag);
+      if (tile.leader()) probe_add(tv, PC_VISIT, 1);
       if (r.hit >= 0) {
         combine_at(tv, tile, (uint64_t)b * B + r.hit, val, combine);
         return ST_EXISTED;
@@ -1103,7 +1107,9 @@ struct Ops {
                                              int combine) {
     const uint32_t b1 = h.b1;
     const uint32_t b2 = h.h2 & tv.bucket_mask;
+    if (tile.leader()) probe_add(tv, PC_WRITE, 1);
     BucketScan<K> r1 = scan<true>(tv, tile, b1, key, tag);
+    if (tile.leader()) probe_add(tv, PC_VISIT, 1);
     if (r1.hit >= 0) {
       combine_at(tv, tile, (uint64_t)b1 * B + r1.hit, val, combine);
       return ST_EXISTED;
@@ -1120,6 +1126,7 @@ struct Ops {
       return claim_in_bucket(tv, tile, b1, r1, key, val, tag) >= 0 ? ST_DONE : ST_FULL;
     }
     BucketScan<K> r2 = scan<true>(tv, tile, b2, key, tag);
+    if (tile.leader()) probe_add(tv, PC_VISIT, 1);
     if (r2.hit >= 0) {
       combine_at(tv, tile, (uint64_t)b2 * B + r2.hit, val, combine);
       return ST_EXISTED;
@@ -1157,7 +1164,9 @@ struct Ops {
   __device__ static uint8_t upsert_iceberg_locked(const TableDev& tv, const Tile<T>& tile,
                                                   const Home& h, K key, K val, uint32_t tag,
                                                   int combine) {
+    if (tile.leader()) probe_add(tv, PC_WRITE, 1);
     BucketScan<K> rf = scan<true>(tv, tile, h.b1, key, tag);
+    if (tile.leader()) probe_add(tv, PC_VISIT, 1);
     if (rf.hit >= 0) {
       combine_at(tv, tile, (uint64_t)h.b1 * B + rf.hit, val, combine);
       return ST_EXISTED;
@@ -1169,6 +1178,7 @@ struct Ops {
       rf = scan<false>(tv, tile, h.b1, key, tag);  // phased variant: lost the slot to another key
     }
     BucketScan<K> r1 = scan<true>(tv, tile, h.h2, key, tag);
+    if (tile.leader()) probe_add(tv, PC_VISIT, 1);
     if (r1.hit >= 0) {
       combine_at(tv, tile, (uint64_t)h.h2 * B + r1.hit, val, combine);
       return ST_EXISTED;
@@ -1176,6 +1186,7 @@ struct Ops {
     BucketScan<K> r2 = r1;
     if (h.b3 != h.h2) {
       r2 = scan<true>(tv, tile, h.b3, key, tag);
+      if (tile.leader()) probe_add(tv, PC_VISIT, 1);
       if (r2.hit >= 0) {
         combine_at(tv, tile, (uint64_t)h.b3 * B + r2.hit, val, combine);
         return ST_EXISTED;

@@ -152,3 +152,35 @@ def test_tag_false_positives_exactly_and_at_the_paper_rate(design):
     c = t.probe_counters(reset=True)
     exp_pos = sum(_tag_matches(design, k, nb, tags, slots_keys=sk)[0] for k in sample.tolist())
     assert c["slot_lines"] == exp_pos
+
+
+@pytest.mark.parametrize("design", ["P2_M", "DOUBLE_M", "ICEBERG_M"])
+def test_insert_visits_match_the_sequential_model(design):
+    """Table 1's insert column, search part, counted by the GPU: the buckets an
+    insert looks at under its lock before placing the key (one tag line each in
+    these designs).  A 2^20-slot table is filled to 0.9 in nine batches; the
+    counted mean equals the oracle's sequential placement of the same keys within
+    1% (concurrent inserts decide on slightly staler fills), and with the lock's
+    two accesses and the two writes it lands within 0.1 of Table 1."""
+    cap = 1 << 20
+    t = hw.Table(cap, design, instrumented=True)
+    seed = w.stream_seed(152, hw.DESIGNS[design])
+    n = int(0.9 * cap)
+    keys = w.distinct_keys(seed, n)
+    t.probe_counters(reset=True)
+    for part in np.array_split(keys, 9):
+        st = u8(t.insert(dev(part), dev(w.value_of(part))))
+        full = st == hw.ST_FULL
+        assert ((st == hw.ST_DONE) | full).all()
+        if full.any():
+            full_is_genuine(t, part[full])
+    c = t.probe_counters(reset=True)
+    assert c["writes"] == n
+    gpu = c["write_visits"] / c["writes"]
+    _, _, failed, vis = oracle.sim_insert(ODESIGN[design], 64, t.num_buckets, t.bucket_slots, keys, visits=True)
+    assert failed == 0
+    model = float(vis.mean())
+    print("%s: insert visits GPU %.4f, sequential model %.4f" % (design, gpu, model), flush=True)
+    assert abs(gpu - model) <= 0.01 * model, (gpu, model)
+    paper = {"P2_M": 5.25, "DOUBLE_M": 5.12, "ICEBERG_M": 5.24}[design]
+    assert abs(oracle.insert_probes_tags(np.array([gpu])) - paper) <= 0.1

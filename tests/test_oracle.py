@@ -194,6 +194,44 @@ def test_table1_load_query_probes(row):
     assert abs(probes - paper) <= 0.01, (name, probes, paper)
 
 
+def _load_to_09(name, bucket, visits=False):
+    cap = 1 << 21
+    nb = cap // bucket
+    n = int(0.9 * cap)
+    keys = w.distinct_keys(w.stream_seed(40, DESIGNS[name]), n)
+    out = oracle.sim_insert(DESIGNS[name], 64, nb, bucket, keys, shortcut=True, visits=visits)
+    assert out[2] == 0
+    return nb, n, out
+
+
+@pytest.mark.parametrize("row", _read_golden("table1_write_probes.txt"), ids=lambda r: r[0])
+def test_table1_load_delete_probes(row):
+    """Table 1's delete column, as accesses (reading 13): what a positive query
+    of the key reads, the lock's acquire and release, and the removal's writes
+    (the key; with tags the tag too).  Within 0.05 for all six designs."""
+    name, bucket, paper = row[0], int(row[1]), float(row[3])
+    tile_bytes = {"DOUBLE_M": 64, "P2_M": 64, "ICEBERG_M": 64}.get(name, 128)
+    nb, n, (slots, tags, _) = _load_to_09(name, bucket)
+    nv, rep = oracle.layout_check(DESIGNS[name], 64, nb, bucket, slots, tags, tile_bytes=tile_bytes)
+    assert nv == 0 and rep["live"] == n
+    model = oracle.delete_probes(DESIGNS[name], rep["pos_probe_sum"] / rep["live"])
+    assert abs(model - paper) <= 0.05, (name, model, paper)
+
+
+@pytest.mark.parametrize("row", [r for r in _read_golden("table1_write_probes.txt") if r[0].endswith("_M")],
+                         ids=lambda r: r[0])
+def test_table1_load_insert_probes_tag_designs(row):
+    """Table 1's insert column for the tag designs (reading 13): one tag line per
+    bucket the insert looks at (the shortcut and front-yard rules decide how
+    many), the lock's two accesses, the claim and the publish.  Within 0.1 (the
+    double-hashing variant is 0.07 under the paper)."""
+    name, bucket, paper = row[0], int(row[1]), float(row[2])
+    nb, n, (slots, tags, _, vis) = _load_to_09(name, bucket, visits=True)
+    assert len(vis) == n and vis.min() >= 1
+    model = oracle.insert_probes_tags(vis)
+    assert abs(model - paper) <= 0.1, (name, model, paper)
+
+
 def test_p2_without_shortcut_misses_table1():
     """The 75% shortcut is what the Table 1 power-of-two-choice numbers need."""
     cap = 1 << 21
