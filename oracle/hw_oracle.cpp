@@ -594,7 +594,7 @@ uint64_t orc_sim_insert(int design, int key_bits, uint64_t nb, uint64_t bucket_s
     } else {
       uint64_t b1 = h.b1, b2 = orc_p2_alt(h, nb);
       if (shortcut && (ORC_MUTANT == 7 ? 2 * fill[b1] < bucket_slots : 4 * fill[b1] < 3 * bucket_slots)) {
-        if (visits) visits[i] = 1;
+        if (visits) visits[i] = ORC_MUTANT == 18 ? 2 : 1;
         put(b1, keys[i], v);
         continue;
       }
