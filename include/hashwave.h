@@ -361,9 +361,19 @@ typedef struct {
 int hwave_multi_supported(uint32_t kv_bits, hwave_design design, uint32_t bucket_slots, uint32_t tile);
 
 /* Creates a group over n_tables existing tables (same device and key width).
- * The tables must outlive the group.  Uploads their descriptors on `stream`. */
+ * The tables must outlive the group.  Uploads their descriptors on `stream`.
+ * When every table has the same base-menu configuration, the group runs on that
+ * configuration's own kernel (fewer registers, no switch over the menu); 64-bit
+ * groups with a HWAVE_F_AGGREGATE table take its variant with the merging path. */
 int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n_tables, void* stream);
 int hwave_multi_destroy(hwave_multi* m);
+
+/* Which kernel a group runs on.  *kernel: HWAVE_MULTI_MENU (the key width's base
+ * menu), HWAVE_MULTI_EXTENDED (64-bit extended menu) or HWAVE_MULTI_SOLO (one
+ * configuration); *waves: its occupancy target, waves per SIMD, which sizes the
+ * persistent grid.  Either pointer may be null.  HWAVE_EINVAL if m is null. */
+enum { HWAVE_MULTI_MENU = 0, HWAVE_MULTI_EXTENDED = 1, HWAVE_MULTI_SOLO = 2 };
+int hwave_multi_kernel(const hwave_multi* m, uint32_t* kernel, uint32_t* waves);
 
 /* Runs n_items host-described items in one launch.  d_vals is read by insert
  * and upsert items (nullable if there are none); d_vals_out (nullable) receives

@@ -133,6 +133,7 @@ def _bind(L):
         "hwave_multi_supported": (I, [ctypes.c_uint32, I, ctypes.c_uint32, ctypes.c_uint32]),
         "hwave_multi_create": (I, [ctypes.POINTER(P), P, ctypes.c_uint32, P]),
         "hwave_multi_destroy": (I, [P]),
+        "hwave_multi_kernel": (I, [P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]),
         "hwave_multi_run": (I, [P, P, ctypes.c_uint32, P, P, P, P, P]),
         "hwave_multi_clear": (I, [P, P]),
         "hwave_multi_upsert": (I, [P, P, P, P, I, P, P]),
@@ -370,6 +371,13 @@ class Multi:
         _check(lib().hwave_multi_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p),
                                         len(self.tables), _stream(stream)))
         self.h = h
+
+    def kernel(self):
+        """(kind, waves per SIMD) of the kernel the group runs on; kind is 'menu',
+        'extended' or 'solo' (every table on one configuration)."""
+        k, wv = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().hwave_multi_kernel(self.h, ctypes.byref(k), ctypes.byref(wv)))
+        return ("menu", "extended", "solo")[k.value], wv.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -18,7 +18,7 @@ OBJ = os.path.join(HERE, "_build")
 OBJ_INSTR = os.path.join(HERE, "_build_instr")
 
 SOURCES = ["capi.hip", "inst_u64_double.hip", "inst_u64_p2.hip", "inst_u64_iceberg.hip", "inst_u64_chain.hip", "inst_u64_cuckoo.hip", "inst_u32_double.hip",
-           "inst_u32_p2.hip", "inst_u32_iceberg.hip", "inst_u64_bsp.hip", "inst_multi.hip", "autotune.hip",
+           "inst_u32_p2.hip", "inst_u32_iceberg.hip", "inst_u64_bsp.hip", "inst_multi.hip", "inst_multi_solo.hip", "autotune.hip",
            "server.hip"]
 HEADERS = ["hw_device.hpp", "hw_ops.hpp", "hw_launch.hpp", "hw_multi.hpp"]
 

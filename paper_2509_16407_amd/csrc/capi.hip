@@ -738,7 +738,9 @@ int hwave_last_hip_error(void) { return g_last_hip_error; }
 struct hwave_multi {
   int device;
   int kv_bits;
-  int menu;  // MENU_BASE or MENU_EXT
+  int menu;  // MENU_BASE, MENU_EXT or MENU_SOLO
+  int solo;  // base-menu entry shared by every table (MENU_SOLO), else -1
+  bool agg;  // some table merges duplicate keys (64-bit solo kernels: the merging path)
   uint32_t n_tables;
   std::vector<uint64_t> table_bytes;  // footprint per table (queue placement)
   MultiTable* d_tables = nullptr;
@@ -823,10 +825,24 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
     h[i].fill_words = locks_off / 16;
     h[i].zero_words = (t->bytes - locks_off) / 16;
   }
+  // every table on one base-menu configuration: that configuration's own kernel
+  int solo = -1;
+  if (menu == MENU_BASE) {
+    solo = (int)h[0].cls;
+    for (uint32_t i = 1; i < n_tables && solo >= 0; i++)
+      if ((int)h[i].cls != solo) solo = -1;
+    if (solo >= 0) {
+      menu = MENU_SOLO;
+      for (uint32_t i = 0; i < n_tables; i++) h[i].cls = 0;
+    }
+  }
   hwave_multi* m = new hwave_multi;
   m->device = dev;
   m->kv_bits = kv;
   m->menu = menu;
+  m->solo = solo;
+  m->agg = false;
+  for (uint32_t i = 0; i < n_tables; i++) m->agg = m->agg || tables[i]->la.tv.aggregate;
   m->n_tables = n_tables;
   for (uint32_t i = 0; i < n_tables; i++) m->table_bytes.push_back(tables[i]->bytes);
   // only the 64-bit menu carries the merging path that fills the accumulators
@@ -851,9 +867,17 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
   // Persistent grid: full occupancy of the multi-table kernel.
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-  const int waves = menu == MENU_EXT ? MenuU64X::WAVES : HW_MULTI_WAVES;
-  m->grid = (unsigned)cus * (4 * waves * 64 / BLOCK);
+  m->grid = (unsigned)cus * (4 * multi_waves(kv, menu, m->agg) * 64 / BLOCK);
   *out = m;
+  return HWAVE_OK;
+}
+
+int hwave_multi_kernel(const hwave_multi* m, uint32_t* kernel, uint32_t* waves) {
+  if (!m) return HWAVE_EINVAL;
+  static_assert(HWAVE_MULTI_MENU == MENU_BASE && HWAVE_MULTI_EXTENDED == MENU_EXT && HWAVE_MULTI_SOLO == MENU_SOLO,
+                "kernel codes");
+  if (kernel) *kernel = (uint32_t)m->menu;
+  if (waves) *waves = (uint32_t)multi_waves(m->kv_bits, m->menu, m->agg);
   return HWAVE_OK;
 }
 
@@ -930,7 +954,7 @@ int hwave_multi_run(hwave_multi* m, const hwave_item* h_items, uint32_t n_items,
   if (e == hipSuccess) e = hipEventRecord(m->staged, s);
   if (e != hipSuccess) return hip_fail(e);
   m->staged_pending = true;
-  e = launch_multi(m->kv_bits, m->menu, m->grid, m->d_tables, m->d_items, qs, m->d_heads, d_keys,
+  e = launch_multi(m->kv_bits, m->menu, m->solo, m->agg, m->grid, m->d_tables, m->d_items, qs, m->d_heads, d_keys,
                    d_vals ? d_vals : d_keys, d_vals_out, d_status, s);
   if (e == hipSuccess && merging) e = launch_multi_hot_flush(m->kv_bits, m->d_tables, m->d_hot, m->n_hot, s);
   return e == hipSuccess ? HWAVE_OK : hip_fail(e);

@@ -26,6 +26,12 @@ constexpr int HEAD_STRIDE = 32;
 #ifndef HW_MULTI_WAVES
 #define HW_MULTI_WAVES 6  // occupancy target of the multi-table kernel (waves per SIMD)
 #endif
+#ifndef HW_SOLO_WAVES
+#define HW_SOLO_WAVES 8   // occupancy target of its single-configuration instances
+#endif
+#ifndef HW_SOLO_AGG_WAVES
+#define HW_SOLO_AGG_WAVES 6  // the same with the merging path compiled in (~80 VGPRs)
+#endif
 
 struct MultiItem {
   uint32_t table;
@@ -54,6 +60,15 @@ struct Menu {
   using K = typename C0::K;               // one key width per menu
   // occupancy target: cuckoo's three-lock paths need more registers
   static constexpr int WAVES = (C0::CUCKOO || ... || Cs::CUCKOO) ? 4 : HW_MULTI_WAVES;
+};
+
+// A menu of one configuration with its own occupancy target.  A group whose
+// tables all share one configuration runs on it: the switch over the menu and
+// the other configurations' inlined paths cost the full menu's kernel registers
+// and spills, and with them two of its eight waves per SIMD.
+template <class M, int W>
+struct Solo : M {
+  static constexpr int WAVES = W;
 };
 
 // Runs ops [m.begin, m.end) of one table with configuration C on this wave.
@@ -164,11 +179,20 @@ inline const MenuEntry* menu_entries(Menu<AGG, Cs...>, int* n) {
 
 // Host launchers (inst_multi.hip).
 hipError_t launch_multi_clear(unsigned grid, const MultiTable* tables, uint32_t n_tables, hipStream_t s);
-// menu: MENU_BASE or MENU_EXT (64-bit keys only).
-enum : int { MENU_BASE = 0, MENU_EXT = 1 };
-hipError_t launch_multi(int kv_bits, int menu, unsigned grid, const MultiTable* tables, const MultiItem* items,
-                        const MultiQueues& qs, uint32_t* heads, const void* keys, const void* vals, void* out,
-                        uint8_t* status, hipStream_t s);
+// menu: MENU_BASE, MENU_EXT (64-bit keys only) or MENU_SOLO, the one-entry menu
+// of base-menu entry `solo` (every table's `cls` is then 0).  `agg`: a 64-bit
+// solo kernel with the merging path (some table of the group merges duplicates).
+enum : int { MENU_BASE = 0, MENU_EXT = 1, MENU_SOLO = 2 };
+hipError_t launch_multi(int kv_bits, int menu, int solo, bool agg, unsigned grid, const MultiTable* tables,
+                        const MultiItem* items, const MultiQueues& qs, uint32_t* heads, const void* keys,
+                        const void* vals, void* out, uint8_t* status, hipStream_t s);
+// Single-configuration instances (inst_multi_solo.hip): entry `solo` of the key
+// width's base menu, with or without the merging path (64-bit keys only).
+hipError_t launch_multi_solo(int kv_bits, int solo, bool agg, unsigned grid, const MultiTable* tables,
+                             const MultiItem* items, const MultiQueues& qs, uint32_t* heads, const void* keys,
+                             const void* vals, void* out, uint8_t* status, hipStream_t s);
+// Occupancy target (waves per SIMD) of a menu's kernel, for the persistent grid.
+int multi_waves(int kv_bits, int menu, bool agg);
 // Folds the hot-key accumulators of the n_hot tables listed in `hot` (device
 // array of table indices); a no-op for n_hot == 0.
 hipError_t launch_multi_hot_flush(int kv_bits, const MultiTable* tables, const uint32_t* hot, uint32_t n_hot,

@@ -7,10 +7,12 @@ __global__ void k_zero_heads(uint32_t* heads) {
   if (threadIdx.x < NQ) heads[threadIdx.x * HEAD_STRIDE] = 0;
 }
 
-hipError_t launch_multi(int kv_bits, int menu, unsigned grid, const MultiTable* tables, const MultiItem* items,
-                        const MultiQueues& qs, uint32_t* heads, const void* keys, const void* vals, void* out,
-                        uint8_t* status, hipStream_t s) {
+hipError_t launch_multi(int kv_bits, int menu, int solo, bool agg, unsigned grid, const MultiTable* tables,
+                        const MultiItem* items, const MultiQueues& qs, uint32_t* heads, const void* keys,
+                        const void* vals, void* out, uint8_t* status, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_heads, dim3(1), dim3(64), 0, s, heads);
+  if (menu == MENU_SOLO)
+    return launch_multi_solo(kv_bits, solo, agg, grid, tables, items, qs, heads, keys, vals, out, status, s);
   if (kv_bits == 64 && menu == MENU_EXT)
     hipLaunchKernelGGL((k_multi<MenuU64X>), dim3(grid), dim3(BLOCK), 0, s, tables, items, qs, heads, keys, vals,
                        out, status);
@@ -61,9 +63,16 @@ hipError_t launch_multi_clear(unsigned grid, const MultiTable* tables, uint32_t 
   return hipGetLastError();
 }
 
+int multi_waves(int kv_bits, int menu, bool agg) {
+  if (menu == MENU_SOLO) return kv_bits == 64 && agg ? HW_SOLO_AGG_WAVES : HW_SOLO_WAVES;
+  if (kv_bits == 64 && menu == MENU_EXT) return MenuU64X::WAVES;
+  return kv_bits == 64 ? MenuU64::WAVES : MenuU32::WAVES;
+}
+
 int multi_menu_index(int kv_bits, int menu, int design, int bucket, int tile) {
   int n = 0;
-  if (kv_bits != 64 && menu != MENU_BASE) return -1;
+  if (kv_bits != 64 && menu == MENU_EXT) return -1;
+  if (menu == MENU_SOLO) menu = MENU_BASE;
   const MenuEntry* e = kv_bits != 64        ? menu_entries(MenuU32{}, &n)
                        : menu == MENU_EXT ? menu_entries(MenuU64X{}, &n)
                                           : menu_entries(MenuU64{}, &n);

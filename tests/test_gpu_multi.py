@@ -103,8 +103,25 @@ def test_multi_mixed_items_u64(menu):
     item per table per launch, so every output is deterministic; a third launch
     erases."""
     tabs = [hw.Table(1 << 14, d, bucket=b, tile=t) for d, b, t in (MENU64 if menu == "base" else MENU64X)]
-    oms = [oracle.OracleMap() for _ in tabs]
     m = hw.Multi(tabs)
+    assert m.kernel() == (("menu", 6) if menu == "base" else ("extended", 4))
+    _mixed_items_u64(tabs, m)
+
+
+@pytest.mark.parametrize("cfg", MENU64, ids=["%s-b%d-t%d" % c for c in MENU64])
+def test_multi_solo_mixed_items_u64(cfg):
+    """A group whose tables share one configuration runs on that configuration's
+    own kernel (eight waves per SIMD): the same three launches as above, on four
+    tables of uneven capacities."""
+    d, b, t = cfg
+    tabs = [hw.Table(1 << e, d, bucket=b, tile=t) for e in (14, 15, 14, 16)]
+    m = hw.Multi(tabs)
+    assert m.kernel() == ("solo", 8)
+    _mixed_items_u64(tabs, m)
+
+
+def _mixed_items_u64(tabs, m):
+    oms = [oracle.OracleMap() for _ in tabs]
     pool = [w.distinct_keys(w.stream_seed(42, i), 20000) for i in range(len(tabs))]
     # launch 1: insert 10000 keys per table
     keys = np.concatenate([p[:10000] for p in pool])
@@ -153,6 +170,68 @@ def test_multi_mixed_items_u64(menu):
         ok, ov = oms[i].dump()
         k, v = _dump(t)
         assert np.array_equal(k, ok) and np.array_equal(v, ov)
+
+
+@pytest.mark.parametrize("cfg", MENU32, ids=["%s-b%d-t%d" % c for c in MENU32])
+def test_multi_solo_groupby_u32(cfg):
+    """Group-by SUM upserts on a group of 32-bit tables of one configuration (its
+    own kernel, eight waves per SIMD), twice in a row, equal to the oracle table
+    by table; the same tables with one of another configuration added run on the
+    menu's kernel."""
+    d, b, t = cfg
+    n = 9
+    exps = w.table_exponents(n, 9, 14, workload_id=45)
+    offsets, keys, vals = w.groupby_tables(exps, 0.65, workload_id=45)
+    A = [hw.Table(1 << int(e), d, kv_bits=32, bucket=b, tile=t) for e in exps]
+    m = hw.Multi(A)
+    assert m.kernel() == ("solo", 8)
+    other = next(c for c in MENU32 if c != cfg)
+    assert hw.Multi(A + [hw.Table(1 << 10, other[0], kv_bits=32, bucket=other[1], tile=other[2])]).kernel() == \
+        ("menu", 6)
+    kd = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    for rnd in range(2):
+        st = u8(m.upsert(offsets, kd, vd, combine="sum"))
+        assert ((st == hw.ST_DONE) | (st == hw.ST_EXISTED)).all()
+    for i in range(n):
+        a, b_ = int(offsets[i]), int(offsets[i + 1])
+        kk, vv = keys[a:b_].astype(np.uint64), vals[a:b_].astype(np.uint64)
+        om = oracle.OracleMap(key_bits=32)
+        om.upsert(kk, vv)
+        om.upsert(kk, vv)
+        k, v = _dump(A[i])
+        ok, ov = om.dump()
+        assert np.array_equal(k, ok) and np.array_equal(v, ov), i
+
+
+@pytest.mark.parametrize("cfg", [("P2_M", 32, 4), ("DOUBLE_M", 32, 4), ("DOUBLE", 8, 8)],
+                         ids=["P2_M-b32-t4", "DOUBLE_M-b32-t4", "DOUBLE-b8-t8"])
+def test_multi_solo_merging_u64(cfg):
+    """64-bit tables of one configuration that merge duplicate keys
+    (HWAVE_F_AGGREGATE, erase-free as in the served form) run on the solo kernel
+    with the merging path (six waves per SIMD); Zipf-skewed SUM upserts equal the
+    oracle's sums table by table."""
+    d, b, t = cfg
+    n = 6
+    tabs = [hw.Table(1 << 14, d, bucket=b, tile=t, flags=hw.F_NO_ERASE | hw.F_AGGREGATE) for _ in range(n)]
+    m = hw.Multi(tabs)
+    assert m.kernel() == ("solo", 6)
+    per = 12000
+    z = w.Zipf(4000, 0.99)
+    keys = np.concatenate([w.distinct_keys(w.stream_seed(46, 100 + i), 4000)[z.ranks(w.stream_seed(46, i), 0, per)]
+                           for i in range(n)])
+    vals = w.splitmix64(w.stream_seed(46, 99), 0, len(keys))
+    offsets = np.arange(n + 1, dtype=np.int64) * per
+    st = u8(m.upsert(offsets, dev(keys), dev(vals), combine="sum"))
+    assert ((st == hw.ST_DONE) | (st == hw.ST_EXISTED)).all()
+    for i in range(n):
+        a, b_ = int(offsets[i]), int(offsets[i + 1])
+        om = oracle.OracleMap()
+        ost = om.upsert(keys[a:b_], vals[a:b_])
+        assert (st[a:b_] == hw.ST_DONE).sum() == (ost == oracle.DONE).sum(), i
+        k, v = _dump(tabs[i])
+        ok, ov = om.dump()
+        assert np.array_equal(k, ok) and np.array_equal(v, ov), i
 
 
 @pytest.mark.parametrize("logcap", [10, 12])
