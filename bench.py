@@ -704,7 +704,11 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
     fills it to `load`.  Times one persistent multi-table launch (configuration
     autotuned per capacity class) against one plain launch per table (same
     configurations) and against one persistent launch with a fixed default
-    configuration.  Verifies every table's size and, on a sample of tables, every
+    configuration.  A group of one configuration runs on that configuration's own
+    kernel, a group of several on the menu's; so when the classes chose different
+    configurations, one launch with the single configuration of least estimated
+    time (from the tuner's rates) is timed too, and the faster group is the
+    batched result.  Verifies every table's size and, on a sample of tables, every
     key and value against the group-by sums computed directly with numpy."""
     import torch
     import paper_2509_16407_amd as hw
@@ -716,10 +720,10 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
     log("batched: %d tables, %d ops generated in %.1f s" % (n_tables, n_ops, time.time() - t0))
     t0 = time.time()
     classes = sorted(set(int(e) for e in exps))
-    tuned, rejected, tuned_ne = {}, {}, {}
+    tuned, rejected, tuned_ne, alls_ne = {}, {}, {}, {}
     for e in classes:
         tuned[e], rejected[e] = hw.autotune(32, 1 << e, load=load, reps=tune_reps)
-        tuned_ne[e], _ = hw.autotune(32, 1 << e, load=load, reps=tune_reps, flags=hw.F_NO_ERASE)
+        tuned_ne[e], alls_ne[e] = hw.autotune(32, 1 << e, load=load, reps=tune_reps, flags=hw.F_NO_ERASE)
     log("batched: autotuned %d classes (locking and erase-free tables) in %.1f s" % (len(classes), time.time() - t0))
     kd = torch.from_numpy(keys.view(np.int32)).cuda()
     vd = torch.from_numpy(vals.view(np.int32)).cuda()
@@ -782,26 +786,78 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
         torch.cuda.empty_cache()
         return ms_b, ms_p
 
+    def one_cfg(alls):
+        """The single configuration with the least time over the whole batch,
+        estimated from the tuner's per-class rates (none that left an op FULL)."""
+        ops_of = {e: int(sum(offsets[i + 1] - offsets[i] for i in range(n_tables) if exps[i] == e)) for e in classes}
+        key = lambda a: (a["design"], a["bucket"], a["tile"])
+        est = {}
+        for e in classes:
+            for a in alls[e]:
+                if a["full_ops"]:
+                    est[key(a)] = float("inf")
+                elif est.get(key(a), 0.0) != float("inf"):
+                    est[key(a)] = est.get(key(a), 0.0) + ops_of[e] / (a["gops"] * 1e9)
+        ok = [k for k in est if all(any(key(a) == k for a in alls[e]) for e in classes)]
+        return min(ok, key=lambda k: est[k])
+
+    def uniform_group(best_of, alls, flags):
+        """Per-class choices that differ put the group on the full menu's kernel; a
+        group of one configuration runs on that configuration's own.  Returns the
+        one-configuration alternative's (configuration, ms), or None when the
+        per-class choices already agree."""
+        if len({(v["design"], v["bucket"], v["tile"]) for v in best_of.values()}) == 1:
+            return None
+        c = one_cfg(alls)
+        tabs, m = make(lambda e: c, flags)
+        assert m.kernel()[0] == "solo"
+        ms = timed(lambda: m.upsert(offsets, kd, vd, status=st), m.clear)
+        verify(tabs)
+        del m, tabs
+        torch.cuda.empty_cache()
+        return c, ms
+
     ms_batched, ms_plain = batched_and_plain(tuned, 0)
+    uni = uniform_group(tuned, rejected, 0)
     log("batched: verified sizes of all tables and %d tables against their group-by sums" % len(pick))
     # group-by tables never erase: declared so, a repeated key is summed without its lock
     ms_batched_ne, ms_plain_ne = batched_and_plain(tuned_ne, hw.F_NO_ERASE)
-    log("batched: erase-free tables %.2f Gops/s in one launch vs %.2f Gops/s plain (verified)"
+    uni_ne = uniform_group(tuned_ne, alls_ne, hw.F_NO_ERASE)
+    log("batched: erase-free tables %.2f Gops/s in one launch (per-class configurations) vs %.2f Gops/s plain "
+        "(verified)"
         % (n_ops / ms_batched_ne / 1e6, n_ops / ms_plain_ne / 1e6))
     tabs_d, m_d = make(lambda e: ("P2_M", 32, 4))
     ms_default = timed(lambda: m_d.upsert(offsets, kd, vd, status=st), m_d.clear)
     del m_d, tabs_d, kd, vd, st
     torch.cuda.empty_cache()
     gops = lambda ms: round(n_ops / ms / 1e6, 3)
+    kernel_of = lambda cfg: "solo" if len({(v["design"], v["bucket"], v["tile"]) for v in cfg.values()}) == 1 else "menu"
+    one = lambda u: None if u is None else {"config": "%s/b%d/t%d" % u[0], "batched_ms": round(u[1], 3),
+                                            "batched_gops": gops(u[1])}
+    for name, u in (("locking", uni), ("erase-free", uni_ne)):
+        if u is not None:
+            log("batched (%s): the classes chose different configurations; one configuration (%s/b%d/t%d) for all "
+                "tables: %.2f Gops/s" % ((name,) + u[0] + (n_ops / u[1] / 1e6,)))
+    # the group step of the tuning: of the two groups timed, the faster is the
+    # batched form's result (per-class choices on the menu's kernel, or one
+    # configuration on its own kernel)
+    best = lambda ms, u: (ms, "per-class configurations") if u is None or ms <= u[1] else \
+        (u[1], "one configuration, %s/b%d/t%d" % u[0])
+    ms_best, policy = best(ms_batched, uni)
+    ms_best_ne, policy_ne = best(ms_batched_ne, uni_ne)
     return {"workload": "%d uint32 tables, capacities 2^e (e uniform %d..%d), group-by SUM upserts to %.2f load"
                         % (n_tables, e_min, e_max, load),
             "ops": n_ops, "slots": int((1 << exps.astype(np.int64)).sum()),
-            "batched_ms": round(ms_batched, 3), "batched_gops": gops(ms_batched),
+            "batched_ms": round(ms_best, 3), "batched_gops": gops(ms_best), "group": policy,
+            "per_class_ms": round(ms_batched, 3), "per_class_gops": gops(ms_batched),
             "plain_ms": round(ms_plain, 3), "plain_gops": gops(ms_plain),
             "default_cfg_batched_ms": round(ms_default, 3), "default_cfg_batched_gops": gops(ms_default),
-            "speedup_vs_plain": round(ms_plain / ms_batched, 3),
-            "erase_free": {"batched_ms": round(ms_batched_ne, 3), "batched_gops": gops(ms_batched_ne),
+            "speedup_vs_plain": round(ms_plain / ms_best, 3),
+            "per_class_kernel": kernel_of(tuned), "one_config": one(uni),
+            "erase_free": {"batched_ms": round(ms_best_ne, 3), "batched_gops": gops(ms_best_ne), "group": policy_ne,
+                           "per_class_ms": round(ms_batched_ne, 3), "per_class_gops": gops(ms_batched_ne),
                            "plain_ms": round(ms_plain_ne, 3), "plain_gops": gops(ms_plain_ne),
+                           "per_class_kernel": kernel_of(tuned_ne), "one_config": one(uni_ne),
                            "tuning": {str(e): "%s/b%d/t%d %.2f" % (v["design"], v["bucket"], v["tile"], v["gops"])
                                       for e, v in tuned_ne.items()}},
             "tuning": {str(e): "%s/b%d/t%d %.2f" % (v["design"], v["bucket"], v["tile"], v["gops"])
