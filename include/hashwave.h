@@ -362,7 +362,7 @@ int hwave_multi_supported(uint32_t kv_bits, hwave_design design, uint32_t bucket
 
 /* Creates a group over n_tables existing tables (same device and key width).
  * The tables must outlive the group.  Uploads their descriptors on `stream`.
- * When every table has the same base-menu configuration, the group runs on that
+ * When every table has the same configuration, the group runs on that
  * configuration's own kernel (fewer registers, no switch over the menu); 64-bit
  * groups with a HWAVE_F_AGGREGATE table take its variant with the merging path. */
 int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n_tables, void* stream);

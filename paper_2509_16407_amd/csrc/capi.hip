@@ -739,7 +739,7 @@ struct hwave_multi {
   int device;
   int kv_bits;
   int menu;  // MENU_BASE, MENU_EXT or MENU_SOLO
-  int solo;  // base-menu entry shared by every table (MENU_SOLO), else -1
+  int solo;  // menu entry shared by every table (MENU_SOLO), else -1
   bool agg;  // some table merges duplicate keys (64-bit solo kernels: the merging path)
   uint32_t n_tables;
   std::vector<uint64_t> table_bytes;  // footprint per table (queue placement)
@@ -825,16 +825,17 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
     h[i].fill_words = locks_off / 16;
     h[i].zero_words = (t->bytes - locks_off) / 16;
   }
-  // every table on one base-menu configuration: that configuration's own kernel
-  int solo = -1;
-  if (menu == MENU_BASE) {
-    solo = (int)h[0].cls;
-    for (uint32_t i = 1; i < n_tables && solo >= 0; i++)
-      if ((int)h[i].cls != solo) solo = -1;
-    if (solo >= 0) {
-      menu = MENU_SOLO;
-      for (uint32_t i = 0; i < n_tables; i++) h[i].cls = 0;
-    }
+  // every table on one configuration: that configuration's own kernel (its
+  // entry in the 32-bit menu or in the 64-bit extended menu)
+  int solo = (int)h[0].cls;
+  for (uint32_t i = 1; i < n_tables && solo >= 0; i++)
+    if ((int)h[i].cls != solo) solo = -1;
+  if (solo >= 0) {
+    const hwave_table* t = tables[0];
+    solo = multi_menu_index(kv, MENU_SOLO, (int)t->design, (int)t->cfg.bucket_slots, (int)t->cfg.tile);
+    if (solo < 0) return HWAVE_EUNSUPPORTED;
+    menu = MENU_SOLO;
+    for (uint32_t i = 0; i < n_tables; i++) h[i].cls = 0;
   }
   hwave_multi* m = new hwave_multi;
   m->device = dev;
@@ -867,7 +868,7 @@ int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n
   // Persistent grid: full occupancy of the multi-table kernel.
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-  m->grid = (unsigned)cus * (4 * multi_waves(kv, menu, m->agg) * 64 / BLOCK);
+  m->grid = (unsigned)cus * (4 * multi_waves(kv, menu, solo, m->agg) * 64 / BLOCK);
   *out = m;
   return HWAVE_OK;
 }
@@ -877,7 +878,7 @@ int hwave_multi_kernel(const hwave_multi* m, uint32_t* kernel, uint32_t* waves) 
   static_assert(HWAVE_MULTI_MENU == MENU_BASE && HWAVE_MULTI_EXTENDED == MENU_EXT && HWAVE_MULTI_SOLO == MENU_SOLO,
                 "kernel codes");
   if (kernel) *kernel = (uint32_t)m->menu;
-  if (waves) *waves = (uint32_t)multi_waves(m->kv_bits, m->menu, m->agg);
+  if (waves) *waves = (uint32_t)multi_waves(m->kv_bits, m->menu, m->solo, m->agg);
   return HWAVE_OK;
 }
 

@@ -71,6 +71,13 @@ struct Solo : M {
   static constexpr int WAVES = W;
 };
 
+// Occupancy target of configuration C's own kernel, with or without the merging
+// path compiled in.
+template <class C>
+constexpr int solo_waves(bool agg) {
+  return C::CUCKOO ? 4 : C::ICEBERG ? 6 : agg ? HW_SOLO_AGG_WAVES : HW_SOLO_WAVES;
+}
+
 // Runs ops [m.begin, m.end) of one table with configuration C on this wave.
 template <class C, bool AGG>
 __device__ __forceinline__ void run_item(const TableDev& tv, const MultiItem& m, const typename C::K* __restrict__ keys,
@@ -180,19 +187,22 @@ inline const MenuEntry* menu_entries(Menu<AGG, Cs...>, int* n) {
 // Host launchers (inst_multi.hip).
 hipError_t launch_multi_clear(unsigned grid, const MultiTable* tables, uint32_t n_tables, hipStream_t s);
 // menu: MENU_BASE, MENU_EXT (64-bit keys only) or MENU_SOLO, the one-entry menu
-// of base-menu entry `solo` (every table's `cls` is then 0).  `agg`: a 64-bit
+// of entry `solo` of the 32-bit menu or of the 64-bit extended menu (whose first
+// entries are the base menu's); every table's `cls` is then 0.  `agg`: a 64-bit
 // solo kernel with the merging path (some table of the group merges duplicates).
 enum : int { MENU_BASE = 0, MENU_EXT = 1, MENU_SOLO = 2 };
 hipError_t launch_multi(int kv_bits, int menu, int solo, bool agg, unsigned grid, const MultiTable* tables,
                         const MultiItem* items, const MultiQueues& qs, uint32_t* heads, const void* keys,
                         const void* vals, void* out, uint8_t* status, hipStream_t s);
-// Single-configuration instances (inst_multi_solo.hip): entry `solo` of the key
-// width's base menu, with or without the merging path (64-bit keys only).
+// Single-configuration instances (inst_multi_solo.hip): entry `solo` of the
+// 32-bit menu or the 64-bit extended menu, with or without the merging path
+// (64-bit keys only), and their occupancy targets.
+int multi_solo_waves(int kv_bits, int solo, bool agg);
 hipError_t launch_multi_solo(int kv_bits, int solo, bool agg, unsigned grid, const MultiTable* tables,
                              const MultiItem* items, const MultiQueues& qs, uint32_t* heads, const void* keys,
                              const void* vals, void* out, uint8_t* status, hipStream_t s);
 // Occupancy target (waves per SIMD) of a menu's kernel, for the persistent grid.
-int multi_waves(int kv_bits, int menu, bool agg);
+int multi_waves(int kv_bits, int menu, int solo, bool agg);
 // Folds the hot-key accumulators of the n_hot tables listed in `hot` (device
 // array of table indices); a no-op for n_hot == 0.
 hipError_t launch_multi_hot_flush(int kv_bits, const MultiTable* tables, const uint32_t* hot, uint32_t n_hot,

@@ -63,8 +63,8 @@ hipError_t launch_multi_clear(unsigned grid, const MultiTable* tables, uint32_t 
   return hipGetLastError();
 }
 
-int multi_waves(int kv_bits, int menu, bool agg) {
-  if (menu == MENU_SOLO) return kv_bits == 64 && agg ? HW_SOLO_AGG_WAVES : HW_SOLO_WAVES;
+int multi_waves(int kv_bits, int menu, int solo, bool agg) {
+  if (menu == MENU_SOLO) return multi_solo_waves(kv_bits, solo, agg);
   if (kv_bits == 64 && menu == MENU_EXT) return MenuU64X::WAVES;
   return kv_bits == 64 ? MenuU64::WAVES : MenuU32::WAVES;
 }
@@ -72,7 +72,7 @@ int multi_waves(int kv_bits, int menu, bool agg) {
 int multi_menu_index(int kv_bits, int menu, int design, int bucket, int tile) {
   int n = 0;
   if (kv_bits != 64 && menu == MENU_EXT) return -1;
-  if (menu == MENU_SOLO) menu = MENU_BASE;
+  if (menu == MENU_SOLO) menu = kv_bits == 64 ? MENU_EXT : MENU_BASE;
   const MenuEntry* e = kv_bits != 64        ? menu_entries(MenuU32{}, &n)
                        : menu == MENU_EXT ? menu_entries(MenuU64X{}, &n)
                                           : menu_entries(MenuU64{}, &n);

@@ -108,15 +108,15 @@ def test_multi_mixed_items_u64(menu):
     _mixed_items_u64(tabs, m)
 
 
-@pytest.mark.parametrize("cfg", MENU64, ids=["%s-b%d-t%d" % c for c in MENU64])
+@pytest.mark.parametrize("cfg", MENU64X, ids=["%s-b%d-t%d" % c for c in MENU64X])
 def test_multi_solo_mixed_items_u64(cfg):
     """A group whose tables share one configuration runs on that configuration's
-    own kernel (eight waves per SIMD): the same three launches as above, on four
-    tables of uneven capacities."""
+    own kernel (eight waves per SIMD; iceberg six, cuckoo four): the same three
+    launches as above, on four tables of uneven capacities."""
     d, b, t = cfg
     tabs = [hw.Table(1 << e, d, bucket=b, tile=t) for e in (14, 15, 14, 16)]
     m = hw.Multi(tabs)
-    assert m.kernel() == ("solo", 8)
+    assert m.kernel() == ("solo", {"ICEBERG": 6, "ICEBERG_M": 6, "CUCKOO": 4}.get(d, 8))
     _mixed_items_u64(tabs, m)
 
 
