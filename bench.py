@@ -895,7 +895,7 @@ def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3, swe
         bufs.append((k, v, o, st))
     offs = [r["t"] for r in reqs]
 
-    def run(mode):
+    def run(mode, arrivals=None):
         # the served kinds never erase: the tables are declared erase-free, so
         # present keys are combined without the lock, and merge duplicate keys
         # per window, so a Zipf-hot key reaches its value word once per window
@@ -909,7 +909,7 @@ def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3, swe
         torch.cuda.synchronize()
         srv = hw.Server(tabs, mode=mode, slots=slots, slot_ops=1 << 22)
         rs = [hw.Server.request(r["table"], OP[r["kind"]], *b) for r, b in zip(reqs, bufs)]
-        srv.replay(rs, offs)
+        srv.replay(rs, offs if arrivals is None else arrivals)
         srv.drain()
         st = srv.stats()
         srv.close()
@@ -925,18 +925,26 @@ def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3, swe
     st_p, res_p = run("plain")
     log("served plain: %.2f Gops/s, p50 %.2f ms, p99 %.2f ms"
         % (st_p["ops"] / st_p["wall_s"] / 1e9, st_p["p50_ms"], st_p["p99_ms"]))
-    # each request's results alone (plain, serial) and in the mix (batched) agree:
-    # query outputs exactly, write statuses as per-key counts
-    same = 0
-    for r, (ob, sb), (op_, sp) in zip(reqs, res_b, res_p):
-        if r["kind"] == "query":
-            ok = np.array_equal(ob, op_) and np.array_equal(sb, sp)
-        else:
-            ok = all(np.array_equal(np.unique(r["keys"][sb == c]), np.unique(r["keys"][sp == c]))
-                     and (sb == c).sum() == (sp == c).sum() for c in (1, 2))
-        same += int(ok)
-    assert same == len(reqs), "served results differ from the one-at-a-time replay"
-    log("served: all %d requests equal alone (plain replay) and in the mix" % len(reqs))
+    # closed loop: every request submitted at once, the batched form's saturation
+    st_c, res_c = run("batched", [0.0] * len(reqs))
+    log("served closed loop (all requests at once): %.2f Gops/s, %.1f requests/launch"
+        % (st_c["ops"] / st_c["wall_s"] / 1e9, st_c["mean_requests_per_batch"]))
+
+    # each request's results alone (plain, serial) and in the mix (batched, at the
+    # arrival rate and all at once) agree: query outputs exactly, write statuses as
+    # per-key counts
+    def same_as_plain(res):
+        same = 0
+        for r, (ob, sb), (op_, sp) in zip(reqs, res, res_p):
+            if r["kind"] == "query":
+                ok = np.array_equal(ob, op_) and np.array_equal(sb, sp)
+            else:
+                ok = all(np.array_equal(np.unique(r["keys"][sb == c]), np.unique(r["keys"][sp == c]))
+                         and (sb == c).sum() == (sp == c).sum() for c in (1, 2))
+            same += int(ok)
+        return same == len(reqs)
+    assert same_as_plain(res_b) and same_as_plain(res_c), "served results differ from the one-at-a-time replay"
+    log("served: all %d requests equal alone (plain replay) and in the mix (at the rate and all at once)" % len(reqs))
     f = lambda st: {"gops": round(st["ops"] / st["wall_s"] / 1e9, 3), "p50_ms": round(st["p50_ms"], 3),
                     "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
                     "wall_s": round(st["wall_s"], 4), "requests_per_launch": round(st["mean_requests_per_batch"], 2)}
@@ -944,7 +952,7 @@ def bench_served(n_tables=64, log2cap=26, n_req=2000, rate=20000.0, slots=3, swe
     out = {"workload": "%d P2HT(M) tables x 2^%d slots, %d Poisson requests at %.0f/s, sizes 2^U (U~U[8,20]), "
                        "query/upsert/insert 50/30/20, Zipf 0.99" % (n_tables, log2cap, n_req, rate),
            "ops": n_ops, "offered_gops": round(offered, 3), "batched": f(st_b), "plain": f(st_p),
-           "identical_results": True}
+           "closed_loop_batched": f(st_c), "identical_results": True}
     if sweep_rates:
         out["sweep"] = served_sweep(reqs, bufs, n_tables, cap, universe, sweep_rates, sweep_s, slots, OP, f)
     return out
