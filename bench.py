@@ -698,6 +698,29 @@ def bench_mixed_zipf(n_batches=256, log2cap=27, universe_log2=26, design="DOUBLE
     return res
 
 
+def one_config(alls, ops_of):
+    """The one configuration with the least estimated time over a whole batch:
+    alls[e] lists the tuner's results for capacity class e (dicts with design,
+    bucket, tile, gops and full_ops), ops_of[e] the batch's operations on tables
+    of class e.  The estimate is the sum over classes of ops / rate; a
+    configuration that left an operation FULL in any class, or was not timed in
+    every class, is never chosen.  Returns (design, bucket, tile)."""
+    key = lambda a: (a["design"], a["bucket"], a["tile"])
+    est, seen = {}, {}
+    for e, rows in alls.items():
+        for a in rows:
+            k = key(a)
+            seen[k] = seen.get(k, 0) + 1
+            if a["full_ops"] or a["gops"] <= 0:
+                est[k] = float("inf")
+            else:
+                est[k] = est.get(k, 0.0) + ops_of[e] / (a["gops"] * 1e9)
+    ok = [k for k in est if seen[k] == len(alls) and est[k] != float("inf")]
+    if not ok:
+        raise ValueError("no configuration held every class")
+    return min(ok, key=lambda k: est[k])
+
+
 def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_reps=2, n_verify=16):
     """The batched form: n_tables uint32 tables with capacities 2^e,
     e uniform in [e_min, e_max], each receiving a group-by SUM-upsert batch that
@@ -786,20 +809,8 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
         torch.cuda.empty_cache()
         return ms_b, ms_p
 
-    def one_cfg(alls):
-        """The single configuration with the least time over the whole batch,
-        estimated from the tuner's per-class rates (none that left an op FULL)."""
-        ops_of = {e: int(sum(offsets[i + 1] - offsets[i] for i in range(n_tables) if exps[i] == e)) for e in classes}
-        key = lambda a: (a["design"], a["bucket"], a["tile"])
-        est = {}
-        for e in classes:
-            for a in alls[e]:
-                if a["full_ops"]:
-                    est[key(a)] = float("inf")
-                elif est.get(key(a), 0.0) != float("inf"):
-                    est[key(a)] = est.get(key(a), 0.0) + ops_of[e] / (a["gops"] * 1e9)
-        ok = [k for k in est if all(any(key(a) == k for a in alls[e]) for e in classes)]
-        return min(ok, key=lambda k: est[k])
+    ops_of = {e: int(sum(offsets[i + 1] - offsets[i] for i in range(n_tables) if exps[i] == e)) for e in classes}
+    one_cfg = lambda alls: one_config(alls, ops_of)
 
     def uniform_group(best_of, alls, flags):
         """Per-class choices that differ put the group on the full menu's kernel; a

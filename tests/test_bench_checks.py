@@ -1,7 +1,8 @@
 """The bench's on-device check of the mixed concurrent workload (mixed_zipf_check),
 run on the CPU with the oracle standing in for the table: it must accept the
 oracle's outputs batch after batch, keep the model's size and value sum equal to
-the oracle's, and reject each kind of planted mistake."""
+the oracle's, and reject each kind of planted mistake.  Also the batched form's
+choice of one configuration for a whole group (one_config)."""
 import numpy as np
 import pytest
 import torch
@@ -70,3 +71,28 @@ def test_mixed_zipf_check_rejects_planted_mistakes(mistake):
     else:
         st[u[0]] = 3  # FULL is never a valid outcome here
     assert int(bench.mixed_zipf_check(present, val, done, ops, r, vd, st, out)) > 0
+
+
+def _row(design, bucket, tile, gops, full=0):
+    return {"design": design, "bucket": bucket, "tile": tile, "gops": gops, "full_ops": full}
+
+
+def test_one_config_minimises_the_estimated_batch_time():
+    """The batched form's group step: the one configuration with the least sum over
+    classes of ops / rate, never one that left an op FULL in some class or was not
+    timed in every class."""
+    ops = {10: 1_000_000, 20: 100_000_000}
+    alls = {10: [_row("DOUBLE", 16, 4, 6.0), _row("DOUBLE", 16, 8, 9.0), _row("P2_M", 16, 4, 20.0, full=3)],
+            20: [_row("DOUBLE", 16, 4, 8.0), _row("DOUBLE", 16, 8, 7.9), _row("P2_M", 16, 4, 30.0)]}
+    # per class, t8 wins class 10 and t4 class 20; over the batch, class 20 dominates
+    assert bench.one_config(alls, ops) == ("DOUBLE", 16, 4)
+    ops = {10: 100_000_000, 20: 1_000_000}
+    assert bench.one_config(alls, ops) == ("DOUBLE", 16, 8)
+    # a configuration timed in only one class is not a candidate
+    alls[20].append(_row("DOUBLE_M", 32, 4, 50.0))
+    assert bench.one_config(alls, ops) == ("DOUBLE", 16, 8)
+    # FULL anywhere excludes a configuration, even when it is fastest elsewhere
+    alls[10].append(_row("DOUBLE_M", 32, 4, 50.0, full=1))
+    assert bench.one_config(alls, ops) == ("DOUBLE", 16, 8)
+    with pytest.raises(ValueError):
+        bench.one_config({10: [_row("P2_M", 16, 4, 9.0, full=1)]}, {10: 1})
