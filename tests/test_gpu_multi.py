@@ -204,18 +204,21 @@ def test_multi_solo_groupby_u32(cfg):
         assert np.array_equal(k, ok) and np.array_equal(v, ov), i
 
 
-@pytest.mark.parametrize("cfg", [("P2_M", 32, 4), ("DOUBLE_M", 32, 4), ("DOUBLE", 8, 8)],
-                         ids=["P2_M-b32-t4", "DOUBLE_M-b32-t4", "DOUBLE-b8-t8"])
+SOLO_MERGING = [("P2_M", 32, 4), ("DOUBLE_M", 32, 4), ("DOUBLE", 8, 8), ("ICEBERG_M", 32, 4), ("CHAINING", 7, 8),
+                ("CUCKOO", 8, 4)]
+
+
+@pytest.mark.parametrize("cfg", SOLO_MERGING, ids=["%s-b%d-t%d" % c for c in SOLO_MERGING])
 def test_multi_solo_merging_u64(cfg):
     """64-bit tables of one configuration that merge duplicate keys
     (HWAVE_F_AGGREGATE, erase-free as in the served form) run on the solo kernel
-    with the merging path (six waves per SIMD); Zipf-skewed SUM upserts equal the
-    oracle's sums table by table."""
+    with the merging path (six waves per SIMD, cuckoo four); Zipf-skewed SUM
+    upserts equal the oracle's sums table by table."""
     d, b, t = cfg
     n = 6
     tabs = [hw.Table(1 << 14, d, bucket=b, tile=t, flags=hw.F_NO_ERASE | hw.F_AGGREGATE) for _ in range(n)]
     m = hw.Multi(tabs)
-    assert m.kernel() == ("solo", 6)
+    assert m.kernel() == ("solo", 4 if d == "CUCKOO" else 6)
     per = 12000
     z = w.Zipf(4000, 0.99)
     keys = np.concatenate([w.distinct_keys(w.stream_seed(46, 100 + i), 4000)[z.ranks(w.stream_seed(46, i), 0, per)]
