@@ -137,6 +137,10 @@ def test_bad_arguments_rejected_on_host():
     assert (c.kv_bits, c.bucket_slots, c.tile) == (64, 32, 4)
     assert L.hwave_num_buckets(None) == 0 and L.hwave_capacity(None) == 0
     assert L.hwave_destroy(None) == -1
+    k, wv = ctypes.c_uint32(7), ctypes.c_uint32(7)
+    assert L.hwave_multi_kernel(None, ctypes.byref(k), ctypes.byref(wv)) == -1
+    assert (k.value, wv.value) == (7, 7)                # untouched on error
+    assert L.hwave_multi_destroy(None) == -1
     for code in (0, -1, -2, -3, -4):
         assert L.hwave_strerror(code)
 
