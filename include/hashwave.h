@@ -368,7 +368,8 @@ int hwave_multi_supported(uint32_t kv_bits, hwave_design design, uint32_t bucket
 int hwave_multi_create(hwave_multi** out, hwave_table* const* tables, uint32_t n_tables, void* stream);
 int hwave_multi_destroy(hwave_multi* m);
 
-/* Which kernel a group runs on.  *kernel: HWAVE_MULTI_MENU (the key width's base
+/* Which kernel a group runs on (no paper operation: for callers that tune or
+ * profile the batched form).  *kernel: HWAVE_MULTI_MENU (the key width's base
  * menu), HWAVE_MULTI_EXTENDED (64-bit extended menu) or HWAVE_MULTI_SOLO (one
  * configuration); *waves: its occupancy target, waves per SIMD, which sizes the
  * persistent grid.  Either pointer may be null.  HWAVE_EINVAL if m is null. */
