@@ -819,7 +819,10 @@ def bench_batched(n_tables=4096, e_min=10, e_max=22, load=0.85, reps=3, tune_rep
         per-class choices already agree."""
         if len({(v["design"], v["bucket"], v["tile"]) for v in best_of.values()}) == 1:
             return None
-        c = one_cfg(alls)
+        try:
+            c = one_cfg(alls)
+        except ValueError:  # no configuration held every class
+            return None
         tabs, m = make(lambda e: c, flags)
         assert m.kernel()[0] == "solo"
         ms = timed(lambda: m.upsert(offsets, kd, vd, status=st), m.clear)
